@@ -1,0 +1,195 @@
+/*
+ * tfhe.h - C ABI of the MI355X (gfx950) NTT / HMULT library, an
+ * implementation of the hot path of TensorFHE (arXiv 2212.14191).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Moduli are primes q with 2^29 < q < 2^31 and q = 1 (mod 2N).
+ * - Residue arrays are uint32, canonical (each value in [0, q)), standard
+ *   (non-Montgomery) form, in the (limb, batch, N) layout the paper uses for
+ *   operation-level batching (Sec. IV-D): limb-major, then polynomial, then
+ *   coefficient.  Element (l, b, i) of an array with `batch` polynomials is
+ *   at index (l * batch + b) * N + i.
+ * - NTT-domain order is natural: index k holds the evaluation at psi^{2k+1}
+ *   (Eq. 4).  Both transform algorithms produce the same bits.
+ * - Device pointers are plain HIP device addresses (for example a torch
+ *   tensor's data_ptr()).  The caller owns every buffer it passes; the
+ *   library owns only what its *_create functions allocate.
+ * - Compute calls are asynchronous on `stream` (NULL = the default stream)
+ *   and validate their arguments synchronously.  A kernel fault surfaces as
+ *   TFHE_EHIP from a later call or from the caller's own synchronisation.
+ * - Host arrays passed to *_create are copied; the caller may free them.
+ * - Out-of-range inputs (values >= q) give unspecified results.
+ * - Every function returns a tfhe_status; on failure tfhe_last_error()
+ *   describes the cause (thread-local, valid until the next call on the
+ *   same thread).
+ */
+#ifndef TFHE_H_
+#define TFHE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TFHE_OK = 0,
+  TFHE_EINVAL = -1,      /* bad argument: null/unaligned pointer, size, level */
+  TFHE_ENOTNTT = -2,     /* modulus not prime, q != 1 mod 2N, q out of range,
+                            or psi not a primitive 2N-th root of unity */
+  TFHE_ENOMEM = -3,      /* device or host allocation failed */
+  TFHE_EHIP = -4,        /* a HIP runtime call failed */
+  TFHE_EUNSUPPORTED = -5 /* valid request this build does not implement */
+} tfhe_status;
+
+typedef enum {
+  TFHE_NTT_AUTO = 0,          /* the library's choice (tuned table, else MFMA
+                                 when available for N, else butterfly) */
+  TFHE_NTT_BUTTERFLY = 1,     /* radix-2 Cooley-Tukey / Gentleman-Sande
+                                 butterflies on the vector ALUs (Sec. II-A,
+                                 Fig. 2) */
+  TFHE_NTT_FOURSTEP_MFMA = 2  /* four-step NTT whose DFT stages are exact
+                                 INT8 matrix-core contractions over byte
+                                 slices (Sec. III-C, Eq. 8, Eq. 9) */
+} tfhe_ntt_algo;
+
+typedef struct tfhe_ntt_plan_s* tfhe_ntt_plan;
+typedef struct tfhe_ckks_ctx_s* tfhe_ckks_ctx;
+typedef struct ihipStream_t* tfhe_stream_t; /* binary-compatible with hipStream_t */
+
+/* ------------------------------------------------------------- utilities */
+
+/* Human-readable name of a status code (static string). */
+const char* tfhe_status_string(tfhe_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* tfhe_last_error(void);
+
+/* The `count` largest primes q < 2^bits with q = 1 (mod two_n), written in
+ * descending order to the host array out[count].  This is the modulus
+ * selection rule the library applies when a caller gives none (the paper
+ * leaves the choice open, Table 1).  bits in [30, 31]. */
+tfhe_status tfhe_find_primes(uint32_t bits, uint64_t two_n, uint32_t count, uint32_t* out);
+
+/* psi = g^{(q-1)/2N} for the smallest primitive root g of q (Sec. II-A);
+ * the root used when a plan is created with psi == NULL. */
+tfhe_status tfhe_default_psi(uint32_t q, uint32_t log_n, uint32_t* psi);
+
+/* -------------------------------------------------------------- NTT plan */
+
+/* Create an immutable plan for N = 2^log_n over n_limbs primes.
+ *   q[n_limbs], psi[n_limbs]: host arrays; psi may be NULL (default root).
+ *   algo: transform used by tfhe_ntt_fwd/inv; AUTO picks per N.
+ * Builds the twiddle tables of both algorithms on the device (Sec. III-B:
+ * "pre-computed in the initialization and reused").  Synchronous.
+ * log_n in [4, 16]; the MFMA algorithm covers log_n in {8, 12, 16}.
+ * Errors: TFHE_ENOTNTT for a bad modulus/root, TFHE_EINVAL, TFHE_ENOMEM. */
+tfhe_status tfhe_ntt_plan_create(tfhe_ntt_plan* out, uint32_t log_n, uint32_t n_limbs,
+                                 const uint32_t* q, const uint32_t* psi, tfhe_ntt_algo algo);
+tfhe_status tfhe_ntt_plan_destroy(tfhe_ntt_plan plan);
+
+/* Plan properties: modulus and root of limb `limb`, N, limb count, the
+ * algorithm AUTO resolved to. */
+tfhe_status tfhe_ntt_plan_info(tfhe_ntt_plan plan, uint32_t* log_n, uint32_t* n_limbs,
+                               tfhe_ntt_algo* algo);
+tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q, uint32_t* psi);
+
+/* Bytes of device workspace tfhe_ntt_fwd/inv need for `batch` polynomials
+ * of `limb_count` limbs (the transposed intermediate between the two
+ * passes).  0 is possible; the value never exceeds limb_count*batch*N*4. */
+tfhe_status tfhe_ntt_workspace_size(tfhe_ntt_plan plan, tfhe_ntt_algo algo, uint32_t limb_count,
+                                    uint32_t batch, size_t* bytes);
+
+/* Forward negacyclic NTT, Eq. (4): out_k = sum_n in_n psi^{(2k+1)n} mod q,
+ * for limbs [limb_begin, limb_begin+limb_count) of the plan and `batch`
+ * polynomials per limb.  in/out: device [limb_count][batch][N] uint32,
+ * 16-byte aligned; in == out allowed (no other overlap).  ws: device
+ * workspace of at least tfhe_ntt_workspace_size bytes, 256-byte aligned.
+ * algo: AUTO uses the plan's algorithm. */
+tfhe_status tfhe_ntt_fwd(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t* in, uint32_t* out,
+                         uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
+                         size_t ws_bytes, tfhe_stream_t stream);
+
+/* Inverse, Eq. (2) with the negacyclic twist of Eq. (3):
+ * out_n = N^{-1} psi^{-n} sum_k in_k psi^{-2nk} mod q.  Same arguments. */
+tfhe_status tfhe_ntt_inv(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t* in, uint32_t* out,
+                         uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
+                         size_t ws_bytes, tfhe_stream_t stream);
+
+/* Element-wise kernels of Sec. III-A over the same layout (a, b, c device,
+ * [limb_count][batch][N]; c may alias a or b):
+ *   Hada-Mult c = a o b mod q;  Ele-Add c = a + b mod q;  Ele-Sub c = a - b mod q. */
+tfhe_status tfhe_pointwise_mul(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
+                               uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
+                               uint32_t batch, tfhe_stream_t stream);
+tfhe_status tfhe_pointwise_add(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
+                               uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
+                               uint32_t batch, tfhe_stream_t stream);
+tfhe_status tfhe_pointwise_sub(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
+                               uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
+                               uint32_t batch, tfhe_stream_t stream);
+/* c = a o b for a b broadcast over the batch: b is [limb_count][N]. */
+tfhe_status tfhe_pointwise_mul_bcast(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
+                                     uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
+                                     uint32_t batch, tfhe_stream_t stream);
+
+/* ------------------------------------------------------------ CKKS context */
+
+/* RNS-CKKS context (Sec. II-B) with hybrid key switching: L q-limbs, K
+ * special p-limbs, dnum digits of alpha = L/dnum limbs (P must exceed every
+ * digit's modulus).  moduli[L+K]: q_0..q_{L-1} then p_0..p_{K-1} (host;
+ * NULL = tfhe_find_primes(31, 2^17, L+K) with the K largest as the p-limbs
+ * and the rest, descending, as q_0..q_{L-1}).  psi[L+K] may be NULL.
+ * Builds an NTT plan over all L+K moduli plus the basis-conversion
+ * constants of ModUp/ModDown for every level.  Synchronous. */
+tfhe_status tfhe_ckks_ctx_create(tfhe_ckks_ctx* out, uint32_t log_n, uint32_t L, uint32_t K,
+                                 uint32_t dnum, const uint32_t* moduli, const uint32_t* psi,
+                                 tfhe_ntt_algo algo);
+tfhe_status tfhe_ckks_ctx_destroy(tfhe_ckks_ctx ctx);
+
+/* The context's NTT plan (over the L+K moduli, q-limbs first); owned by the
+ * context, valid until tfhe_ckks_ctx_destroy. */
+tfhe_status tfhe_ckks_ctx_plan(tfhe_ckks_ctx ctx, tfhe_ntt_plan* plan);
+
+/* Device workspace (bytes) tfhe_hmult / tfhe_rotate need at this level and
+ * batch. */
+tfhe_status tfhe_hmult_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch,
+                                      size_t* bytes);
+
+/* HMULT (Sec. II-B; kernels of Table 2): for each of `batch` ciphertext
+ * pairs, ct_out = (d0, d1) + KeySwitch(d2) with d0 = c0c0', d1 = c0c1' +
+ * c1c0', d2 = c1c1'.  KeySwitch = INTT, Dcomp into digits, ModUp by fast
+ * basis conversion (no overflow correction), NTT, inner product with evk,
+ * ModDown (no rounding offset) (Sec. III-A).  No rescale.
+ *   ct_a, ct_b, ct_out: device [2][level][batch][N], NTT domain; ct_out may
+ *     alias ct_a or ct_b.
+ *   evk: device [dnum][2][L+K][N], NTT domain, evk[j] = (b_j, a_j) with
+ *     b_j = -a_j s + e_j + g_j s^2, g_j = [P]_{q_i} on the limbs of digit j.
+ *   level in [1, L]; ws: >= tfhe_hmult_workspace_size bytes, 256-aligned. */
+tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
+                       uint32_t* ct_out, const uint32_t* evk, uint32_t level, uint32_t batch,
+                       void* ws, size_t ws_bytes, tfhe_stream_t stream);
+
+/* HROTATE (Sec. II-B): ct_out = (sigma(c0), 0) + KeySwitch_rk(sigma(c1)),
+ * sigma the automorphism X -> X^galois_elt applied in the NTT domain as the
+ * FrobeniusMap permutation of Sec. III-A: out_j = in_{pi(j)},
+ * pi(j) = ((2j+1) galois_elt mod 2N - 1)/2.  galois_elt odd, < 2N (5^r mod
+ * 2N rotates the slots by r).  rotkey: device [dnum][2][L+K][N] for
+ * s' = sigma(s).  ct_in, ct_out: device [2][level][batch][N], must not alias. */
+tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,
+                        const uint32_t* rotkey, uint32_t galois_elt, uint32_t level,
+                        uint32_t batch, void* ws, size_t ws_bytes, tfhe_stream_t stream);
+
+/* FrobeniusMap alone (Sec. III-A): out_j = in_{pi(j)} on every polynomial of
+ * a [limb_count][batch][N] array (NTT domain).  out must not alias in. */
+tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t* out,
+                               uint32_t galois_elt, uint32_t limb_count, uint32_t batch,
+                               tfhe_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFHE_H_ */

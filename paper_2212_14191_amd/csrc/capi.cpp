@@ -1,0 +1,275 @@
+// C ABI entry points (include/tfhe.h): argument validation, error reporting
+// and dispatch to the kernels.  No exception crosses the ABI.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace tfhe {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+tfhe_status fail(tfhe_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+tfhe_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return TFHE_OK;
+  return fail(TFHE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+tfhe_status plan_build(tfhe_ntt_plan_s* p);
+void plan_free(tfhe_ntt_plan_s* p);
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Shared validation of a (plan, limb range, batch) compute call.
+static tfhe_status check_range(const tfhe_ntt_plan_s* p, uint32_t limb_begin, uint32_t limb_count,
+                               uint32_t batch) {
+  if (!p) return fail(TFHE_EINVAL, "null plan");
+  if ((uint64_t)limb_begin + limb_count > p->n_limbs)
+    return fail(TFHE_EINVAL, "limb range exceeds the plan's limbs");
+  if ((uint64_t)limb_count * batch * p->n > (1ull << 40))
+    return fail(TFHE_EINVAL, "batch too large");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(TFHE_EINVAL, "the plan's device is not the current device");
+  return TFHE_OK;
+}
+
+static tfhe_status check_ptr(const void* ptr, const char* name) {
+  if (!ptr) return fail(TFHE_EINVAL, std::string("null pointer: ") + name);
+  if (!aligned(ptr, 16)) return fail(TFHE_EINVAL, std::string("pointer not 16-byte aligned: ") + name);
+  return TFHE_OK;
+}
+
+static tfhe_ntt_algo resolve(const tfhe_ntt_plan_s* p, tfhe_ntt_algo a) {
+  return a == TFHE_NTT_AUTO ? p->algo : a;
+}
+
+}  // namespace tfhe
+
+using namespace tfhe;
+
+extern "C" {
+
+const char* tfhe_status_string(tfhe_status s) {
+  switch (s) {
+    case TFHE_OK: return "TFHE_OK";
+    case TFHE_EINVAL: return "TFHE_EINVAL";
+    case TFHE_ENOTNTT: return "TFHE_ENOTNTT";
+    case TFHE_ENOMEM: return "TFHE_ENOMEM";
+    case TFHE_EHIP: return "TFHE_EHIP";
+    case TFHE_EUNSUPPORTED: return "TFHE_EUNSUPPORTED";
+  }
+  return "TFHE_UNKNOWN";
+}
+
+const char* tfhe_last_error(void) { return g_last_error.c_str(); }
+
+tfhe_status tfhe_find_primes(uint32_t bits, uint64_t two_n, uint32_t count, uint32_t* out) {
+  if (!out || bits < 30 || bits > 31 || two_n < 2 || (two_n & (two_n - 1)))
+    return fail(TFHE_EINVAL, "find_primes: bits in [30,31], two_n a power of two, out non-null");
+  uint64_t q = ((1ull << bits) - 1) / two_n * two_n + 1;
+  if (q >= (1ull << bits)) q -= two_n;
+  uint32_t found = 0;
+  while (found < count && q > (1ull << 29)) {
+    if (is_prime_u32((uint32_t)q)) out[found++] = (uint32_t)q;
+    q -= two_n;
+  }
+  if (found < count) return fail(TFHE_EINVAL, "find_primes: not enough primes above 2^29");
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_default_psi(uint32_t q, uint32_t log_n, uint32_t* psi) {
+  if (!psi || log_n < 1 || log_n > 20) return fail(TFHE_EINVAL, "default_psi: bad argument");
+  uint32_t r = default_psi(q, log_n);
+  if (!r) return fail(TFHE_ENOTNTT, "default_psi: q is not a prime = 1 mod 2N");
+  *psi = r;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_plan_create(tfhe_ntt_plan* out, uint32_t log_n, uint32_t n_limbs,
+                                 const uint32_t* q, const uint32_t* psi, tfhe_ntt_algo algo) {
+  if (!out || !q) return fail(TFHE_EINVAL, "plan_create: null argument");
+  *out = nullptr;
+  if (log_n < 4 || log_n > 16) return fail(TFHE_EINVAL, "plan_create: log_n must be in [4, 16]");
+  if (n_limbs == 0 || n_limbs > 4096) return fail(TFHE_EINVAL, "plan_create: n_limbs in [1, 4096]");
+  if (algo != TFHE_NTT_AUTO && algo != TFHE_NTT_BUTTERFLY && algo != TFHE_NTT_FOURSTEP_MFMA)
+    return fail(TFHE_EINVAL, "plan_create: unknown algorithm");
+  const uint64_t two_n = 2ull << log_n;
+  tfhe_ntt_plan_s* p = new (std::nothrow) tfhe_ntt_plan_s();
+  if (!p) return fail(TFHE_ENOMEM, "plan_create: host allocation");
+  p->log_n = log_n;
+  p->n = 1u << log_n;
+  p->n_limbs = n_limbs;
+  for (uint32_t l = 0; l < n_limbs; ++l) {
+    uint32_t ql = q[l];
+    char msg[160];
+    if (ql <= (1u << 29) || ql >= (1u << 31) || !is_prime_u32(ql) || (ql - 1) % two_n != 0) {
+      snprintf(msg, sizeof msg, "limb %u: q=%u must be a prime in (2^29, 2^31) with q = 1 mod 2N", l, ql);
+      delete p;
+      return fail(TFHE_ENOTNTT, msg);
+    }
+    uint32_t s = psi ? psi[l] : default_psi(ql, log_n);
+    // primitive 2N-th root <=> s^N = -1 (2N is a power of two)
+    if (s == 0 || s >= ql || pow_mod(s, p->n, ql) != ql - 1) {
+      snprintf(msg, sizeof msg, "limb %u: psi=%u is not a primitive 2N-th root of unity mod %u", l, s, ql);
+      delete p;
+      return fail(TFHE_ENOTNTT, msg);
+    }
+    p->q.push_back(ql);
+    p->psi.push_back(s);
+  }
+  tfhe_status st = plan_build(p);
+  if (st != TFHE_OK) {
+    plan_free(p);
+    delete p;
+    return st;
+  }
+  if (algo == TFHE_NTT_FOURSTEP_MFMA && !p->has_mfma) {
+    plan_free(p);
+    delete p;
+    return fail(TFHE_EUNSUPPORTED, "plan_create: the MFMA four-step NTT does not cover this N");
+  }
+  p->algo = algo == TFHE_NTT_AUTO ? (p->has_mfma ? TFHE_NTT_FOURSTEP_MFMA : TFHE_NTT_BUTTERFLY) : algo;
+  *out = p;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_plan_destroy(tfhe_ntt_plan plan) {
+  if (!plan) return TFHE_OK;
+  plan_free(plan);
+  delete plan;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_plan_info(tfhe_ntt_plan plan, uint32_t* log_n, uint32_t* n_limbs,
+                               tfhe_ntt_algo* algo) {
+  if (!plan) return fail(TFHE_EINVAL, "null plan");
+  if (log_n) *log_n = plan->log_n;
+  if (n_limbs) *n_limbs = plan->n_limbs;
+  if (algo) *algo = plan->algo;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q, uint32_t* psi) {
+  if (!plan || limb >= plan->n_limbs) return fail(TFHE_EINVAL, "plan_modulus: bad plan or limb");
+  if (q) *q = plan->q[limb];
+  if (psi) *psi = plan->psi[limb];
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_workspace_size(tfhe_ntt_plan plan, tfhe_ntt_algo algo, uint32_t limb_count,
+                                    uint32_t batch, size_t* bytes) {
+  if (!plan || !bytes) return fail(TFHE_EINVAL, "workspace_size: null argument");
+  tfhe_ntt_algo a = resolve(plan, algo);
+  if (a == TFHE_NTT_FOURSTEP_MFMA && !plan->has_mfma)
+    return fail(TFHE_EUNSUPPORTED, "MFMA four-step not available for this plan");
+  *bytes = a == TFHE_NTT_FOURSTEP_MFMA ? fs_workspace_bytes(plan, limb_count, batch)
+                                       : bf_workspace_bytes(plan, limb_count, batch);
+  return TFHE_OK;
+}
+
+static tfhe_status ntt_dispatch(bool inverse, tfhe_ntt_plan plan, tfhe_ntt_algo algo,
+                                const uint32_t* in, uint32_t* out, uint32_t limb_begin,
+                                uint32_t limb_count, uint32_t batch, void* ws, size_t ws_bytes,
+                                tfhe_stream_t stream) {
+  tfhe_status st = check_range(plan, limb_begin, limb_count, batch);
+  if (st != TFHE_OK) return st;
+  if (limb_count == 0 || batch == 0) return TFHE_OK;
+  if ((st = check_ptr(in, "in")) != TFHE_OK || (st = check_ptr(out, "out")) != TFHE_OK) return st;
+  const tfhe_ntt_algo a = resolve(plan, algo);
+  if (a != TFHE_NTT_BUTTERFLY && a != TFHE_NTT_FOURSTEP_MFMA)
+    return fail(TFHE_EINVAL, "unknown algorithm");
+  if (a == TFHE_NTT_FOURSTEP_MFMA && !plan->has_mfma)
+    return fail(TFHE_EUNSUPPORTED, "MFMA four-step not available for this plan");
+  const size_t need = a == TFHE_NTT_FOURSTEP_MFMA ? fs_workspace_bytes(plan, limb_count, batch)
+                                                  : bf_workspace_bytes(plan, limb_count, batch);
+  if (need) {
+    if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "workspace missing or too small");
+    if (!aligned(ws, 256)) return fail(TFHE_EINVAL, "workspace not 256-byte aligned");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (a == TFHE_NTT_FOURSTEP_MFMA)
+    e = inverse ? fs_inverse(plan, in, out, ws, limb_begin, limb_count, batch, s)
+                : fs_forward(plan, in, out, ws, limb_begin, limb_count, batch, s);
+  else
+    e = inverse ? bf_inverse(plan, in, out, ws, limb_begin, limb_count, batch, s)
+                : bf_forward(plan, in, out, ws, limb_begin, limb_count, batch, s);
+  return hip_check(e, inverse ? "ntt_inv launch" : "ntt_fwd launch");
+}
+
+tfhe_status tfhe_ntt_fwd(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t* in, uint32_t* out,
+                         uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
+                         size_t ws_bytes, tfhe_stream_t stream) {
+  return ntt_dispatch(false, plan, algo, in, out, limb_begin, limb_count, batch, ws, ws_bytes, stream);
+}
+
+tfhe_status tfhe_ntt_inv(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t* in, uint32_t* out,
+                         uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
+                         size_t ws_bytes, tfhe_stream_t stream) {
+  return ntt_dispatch(true, plan, algo, in, out, limb_begin, limb_count, batch, ws, ws_bytes, stream);
+}
+
+static tfhe_status ew_dispatch(EwOp op, tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
+                               uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
+                               uint32_t batch, tfhe_stream_t stream) {
+  tfhe_status st = check_range(plan, limb_begin, limb_count, batch);
+  if (st != TFHE_OK) return st;
+  if (limb_count == 0 || batch == 0) return TFHE_OK;
+  if ((st = check_ptr(a, "a")) != TFHE_OK || (st = check_ptr(b, "b")) != TFHE_OK ||
+      (st = check_ptr(c, "c")) != TFHE_OK)
+    return st;
+  return hip_check(ew_launch(op, plan->d_mod + limb_begin, a, b, c, limb_count, batch, plan->n,
+                             (hipStream_t)stream),
+                   "element-wise launch");
+}
+
+tfhe_status tfhe_pointwise_mul(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b, uint32_t* c,
+                               uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                               tfhe_stream_t stream) {
+  return ew_dispatch(EW_MUL, plan, a, b, c, limb_begin, limb_count, batch, stream);
+}
+
+tfhe_status tfhe_pointwise_add(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b, uint32_t* c,
+                               uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                               tfhe_stream_t stream) {
+  return ew_dispatch(EW_ADD, plan, a, b, c, limb_begin, limb_count, batch, stream);
+}
+
+tfhe_status tfhe_pointwise_sub(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b, uint32_t* c,
+                               uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                               tfhe_stream_t stream) {
+  return ew_dispatch(EW_SUB, plan, a, b, c, limb_begin, limb_count, batch, stream);
+}
+
+tfhe_status tfhe_pointwise_mul_bcast(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
+                                     uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
+                                     uint32_t batch, tfhe_stream_t stream) {
+  return ew_dispatch(EW_MUL_BCAST, plan, a, b, c, limb_begin, limb_count, batch, stream);
+}
+
+tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t* out,
+                               uint32_t galois_elt, uint32_t limb_count, uint32_t batch,
+                               tfhe_stream_t stream) {
+  if (!plan) return fail(TFHE_EINVAL, "null plan");
+  if ((galois_elt & 1) == 0 || galois_elt >= 2 * plan->n)
+    return fail(TFHE_EINVAL, "frobenius_map: galois element must be odd and < 2N");
+  if (limb_count == 0 || batch == 0) return TFHE_OK;
+  tfhe_status st;
+  if ((st = check_ptr(in, "in")) != TFHE_OK || (st = check_ptr(out, "out")) != TFHE_OK) return st;
+  if (in == out) return fail(TFHE_EINVAL, "frobenius_map: out must not alias in");
+  return hip_check(frobenius_launch(in, out, galois_elt, limb_count * batch, plan->log_n,
+                                    (hipStream_t)stream),
+                   "frobenius launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,311 @@
+// RNS-CKKS context and the HMULT / HROTATE operations (Sec. II-B, Sec. III-A,
+// Table 2) as stream-ordered kernel sequences on the device.
+//
+// Key switching follows the hybrid method the paper adopts (Sec. II-B,
+// "Generalized Key-Switching"): Dcomp splits the limbs of the input into
+// digits of alpha = L/dnum limbs, ModUp extends each digit to Q_l * P by fast
+// basis conversion (no overflow correction), the inner product with the key
+// accumulates over the digits, and ModDown divides by P (no rounding offset).
+#include <string.h>
+
+#include <new>
+#include <set>
+
+#include "ckks_internal.hpp"
+
+namespace tfhe {
+
+tfhe_status plan_build(tfhe_ntt_plan_s* p);
+void plan_free(tfhe_ntt_plan_s* p);
+
+static uint32_t mulm(uint32_t a, uint32_t b, uint32_t q) { return (uint32_t)((uint64_t)a * b % q); }
+
+static uint2 with_companion(uint32_t w, uint32_t q) { return make_uint2(w, shoup_companion(w, q)); }
+
+// Forward/inverse NTT of `count` plan limbs starting at limb_begin, with the
+// plan's algorithm.
+static hipError_t ntt_call(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* in, uint32_t* out,
+                           uint32_t limb_begin, uint32_t count, uint32_t batch, void* ws,
+                           hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (p->algo == TFHE_NTT_FOURSTEP_MFMA)
+    return inverse ? fs_inverse(p, in, out, ws, limb_begin, count, batch, s)
+                   : fs_forward(p, in, out, ws, limb_begin, count, batch, s);
+  return inverse ? bf_inverse(p, in, out, ws, limb_begin, count, batch, s)
+                 : bf_forward(p, in, out, ws, limb_begin, count, batch, s);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace regions, in limb-planes of batch*N words.
+struct KsLayout {
+  size_t d2, x, up, acc, ntt, total;
+};
+
+static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t batch) {
+  const size_t plane = (size_t)batch * c->n * sizeof(uint32_t);
+  const uint32_t digits = (level + c->alpha - 1) / c->alpha;
+  const uint32_t ext = level + c->K;
+  KsLayout l;
+  size_t off = 0;
+  l.d2 = off; off += align256(plane * level);
+  l.x = off; off += align256(plane * level);
+  l.up = off; off += align256(plane * (size_t)digits * ext);
+  l.acc = off; off += align256(plane * 2 * ext);
+  l.ntt = off; off += align256(plane * std::max(level, c->K));
+  l.total = off;
+  return l;
+}
+
+// Key switching of d (NTT domain, [level][B][N]) with key [dnum][2][L+K][N];
+// out0 (+)= ModDown(acc0), out1 (+)= ModDown(acc1).
+static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const uint32_t* key,
+                             uint32_t* out0, uint32_t* out1, bool acc0_add, bool acc1_add,
+                             uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
+  const tfhe_ntt_plan_s* p = c->plan;
+  const KsLayout lay = ks_layout(c, level, batch);
+  const uint64_t plane = (uint64_t)batch * c->n;
+  const uint32_t ext = level + c->K;
+  const uint32_t digits = (level + c->alpha - 1) / c->alpha;
+  uint32_t* x = (uint32_t*)(ws + lay.x);
+  uint32_t* up = (uint32_t*)(ws + lay.up);
+  uint32_t* acc = (uint32_t*)(ws + lay.acc);
+  void* nws = ws + lay.ntt;
+  hipError_t e;
+  // INTT of the input, then Dcomp + ModUp + NTT per digit
+  if ((e = ntt_call(p, true, d, x, 0, level, batch, nws, s)) != hipSuccess) return e;
+  for (uint32_t j = 0; j < digits; ++j) {
+    const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
+    const uint32_t key_idx = d0 + nd - 1;
+    uint32_t* upj = up + (uint64_t)j * ext * plane;
+    if ((e = launch_modup(x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
+                          c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
+                          c->L, c->K, batch, c->n, s)) != hipSuccess)
+      return e;
+    // NTT the converted limbs: q-limbs before and after the digit, then the p-limbs
+    if ((e = ntt_call(p, false, upj, upj, 0, d0, batch, nws, s)) != hipSuccess) return e;
+    uint32_t* after = upj + (uint64_t)(d0 + nd) * plane;
+    if ((e = ntt_call(p, false, after, after, d0 + nd, level - d0 - nd, batch, nws, s)) != hipSuccess)
+      return e;
+    uint32_t* pl = upj + (uint64_t)level * plane;
+    if ((e = ntt_call(p, false, pl, pl, c->L, c->K, batch, nws, s)) != hipSuccess) return e;
+  }
+  uint32_t* a0 = acc;
+  uint32_t* a1 = acc + (uint64_t)ext * plane;
+  if ((e = launch_inner_product(d, up, key, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
+                                batch, c->log_n, s)) != hipSuccess)
+    return e;
+  // ModDown of both accumulators (the ModUp region is free again)
+  uint32_t* tp = up;
+  uint32_t* conv = x;
+  for (int comp = 0; comp < 2; ++comp) {
+    uint32_t* a = comp ? a1 : a0;
+    if ((e = ntt_call(p, true, a + (uint64_t)level * plane, tp, c->L, c->K, batch, nws, s)) != hipSuccess)
+      return e;
+    if ((e = launch_moddown_conv(tp, conv, p->d_mod, c->d_dn_invp, c->d_dn_conv, level, c->L, c->K,
+                                 batch, c->n, s)) != hipSuccess)
+      return e;
+    if ((e = ntt_call(p, false, conv, conv, 0, level, batch, nws, s)) != hipSuccess) return e;
+    if ((e = launch_moddown_final(a, conv, comp ? out1 : out0, p->d_mod, c->d_dn_pinv, level, batch,
+                                  c->n, comp ? acc1_add : acc0_add, s)) != hipSuccess)
+      return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const std::vector<T>& src, std::vector<void*>& owned) {
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1));
+  if (e != hipSuccess) return e;
+  owned.push_back(*dst);
+  return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+static tfhe_status ctx_build(tfhe_ckks_ctx_s* c) {
+  const uint32_t L = c->L, K = c->K, A = c->alpha;
+  const std::vector<uint32_t>& m = c->plan->q;  // q_0..q_{L-1}, p_0..p_{K-1}
+  std::vector<uint2> up_inv((size_t)L * kMaxAlpha, make_uint2(0, 0));
+  std::vector<uint2> up_conv((size_t)L * (L + K) * kMaxAlpha, make_uint2(0, 0));
+  for (uint32_t e = 1; e <= L; ++e) {
+    const uint32_t d0 = A * ((e - 1) / A), nd = e - d0;
+    for (uint32_t r = 0; r < nd; ++r) {
+      const uint32_t i = d0 + r;
+      uint32_t prod = 1;  // Q_D / q_i mod q_i
+      for (uint32_t i2 = d0; i2 < e; ++i2)
+        if (i2 != i) prod = mulm(prod, m[i2] % m[i], m[i]);
+      up_inv[(size_t)(e - 1) * kMaxAlpha + r] = with_companion(inv_mod(prod, m[i]), m[i]);
+      for (uint32_t t = 0; t < L + K; ++t) {
+        uint32_t pt = 1;  // Q_D / q_i mod m_t
+        for (uint32_t i2 = d0; i2 < e; ++i2)
+          if (i2 != i) pt = mulm(pt, m[i2] % m[t], m[t]);
+        up_conv[((size_t)(e - 1) * (L + K) + t) * kMaxAlpha + r] = with_companion(pt, m[t]);
+      }
+    }
+  }
+  std::vector<uint2> invp(kMaxK, make_uint2(0, 0)), dconv((size_t)L * kMaxK, make_uint2(0, 0)), pinv(L);
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t pk = m[L + k];
+    uint32_t prod = 1;
+    for (uint32_t k2 = 0; k2 < K; ++k2)
+      if (k2 != k) prod = mulm(prod, m[L + k2] % pk, pk);
+    invp[k] = with_companion(inv_mod(prod, pk), pk);
+  }
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint32_t qi = m[i];
+    uint32_t P = 1;
+    for (uint32_t k = 0; k < K; ++k) P = mulm(P, m[L + k] % qi, qi);
+    pinv[i] = with_companion(inv_mod(P, qi), qi);
+    for (uint32_t k = 0; k < K; ++k) {
+      uint32_t prod = 1;
+      for (uint32_t k2 = 0; k2 < K; ++k2)
+        if (k2 != k) prod = mulm(prod, m[L + k2] % qi, qi);
+      dconv[(size_t)i * kMaxK + k] = with_companion(prod, qi);
+    }
+  }
+  hipError_t e;
+  if ((e = upload(&c->d_up_inv, up_inv, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_up_conv, up_conv, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_dn_invp, invp, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_dn_conv, dconv, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_dn_pinv, pinv, c->owned)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? fail(TFHE_ENOMEM, "ckks constants: out of device memory")
+                                    : hip_check(e, "ckks constants");
+  return TFHE_OK;
+}
+
+static void ctx_free(tfhe_ckks_ctx_s* c) {
+  for (void* p : c->owned) (void)hipFree(p);
+  c->owned.clear();
+  if (c->plan) tfhe_ntt_plan_destroy(c->plan);
+  c->plan = nullptr;
+}
+
+static tfhe_status check_ct_call(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t batch, void* ws,
+                                 size_t ws_bytes) {
+  if (!c) return fail(TFHE_EINVAL, "null context");
+  if (level < 1 || level > c->L) return fail(TFHE_EINVAL, "level must be in [1, L]");
+  if ((uint64_t)batch * c->n * (c->L + c->K) > (1ull << 38)) return fail(TFHE_EINVAL, "batch too large");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->plan->device)
+    return fail(TFHE_EINVAL, "the context's device is not the current device");
+  if (batch == 0) return TFHE_OK;
+  const size_t need = ks_layout(c, level, batch).total;
+  if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "workspace missing or too small");
+  if ((uintptr_t)ws % 256) return fail(TFHE_EINVAL, "workspace not 256-byte aligned");
+  return TFHE_OK;
+}
+
+static bool al16(const void* p) { return p && ((uintptr_t)p % 16) == 0; }
+
+}  // namespace tfhe
+
+using namespace tfhe;
+
+extern "C" {
+
+tfhe_status tfhe_ckks_ctx_create(tfhe_ckks_ctx* out, uint32_t log_n, uint32_t L, uint32_t K,
+                                 uint32_t dnum, const uint32_t* moduli, const uint32_t* psi,
+                                 tfhe_ntt_algo algo) {
+  if (!out) return fail(TFHE_EINVAL, "ckks_ctx_create: null out");
+  *out = nullptr;
+  if (L == 0 || K == 0 || dnum == 0 || L % dnum != 0)
+    return fail(TFHE_EINVAL, "ckks_ctx_create: need L, K, dnum > 0 and dnum | L");
+  if (L / dnum > (uint32_t)kMaxAlpha || K > (uint32_t)kMaxK)
+    return fail(TFHE_EUNSUPPORTED, "ckks_ctx_create: alpha = L/dnum and K must be <= 8");
+  std::vector<uint32_t> mods(L + K);
+  if (moduli) {
+    memcpy(mods.data(), moduli, sizeof(uint32_t) * (L + K));
+  } else {
+    std::vector<uint32_t> pr(L + K);
+    tfhe_status st = tfhe_find_primes(31, 1ull << 17, L + K, pr.data());
+    if (st != TFHE_OK) return st;
+    for (uint32_t i = 0; i < L; ++i) mods[i] = pr[K + i];
+    for (uint32_t k = 0; k < K; ++k) mods[L + k] = pr[k];
+  }
+  if (std::set<uint32_t>(mods.begin(), mods.end()).size() != mods.size())
+    return fail(TFHE_ENOTNTT, "ckks_ctx_create: moduli must be distinct");
+  tfhe_ckks_ctx_s* c = new (std::nothrow) tfhe_ckks_ctx_s();
+  if (!c) return fail(TFHE_ENOMEM, "ckks_ctx_create: host allocation");
+  c->log_n = log_n;
+  c->n = 1u << log_n;
+  c->L = L;
+  c->K = K;
+  c->dnum = dnum;
+  c->alpha = L / dnum;
+  tfhe_ntt_plan plan = nullptr;
+  tfhe_status st = tfhe_ntt_plan_create(&plan, log_n, L + K, mods.data(), psi, algo);
+  if (st != TFHE_OK) {
+    delete c;
+    return st;
+  }
+  c->plan = plan;
+  if ((st = ctx_build(c)) != TFHE_OK) {
+    ctx_free(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ckks_ctx_destroy(tfhe_ckks_ctx ctx) {
+  if (!ctx) return TFHE_OK;
+  ctx_free(ctx);
+  delete ctx;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ckks_ctx_plan(tfhe_ckks_ctx ctx, tfhe_ntt_plan* plan) {
+  if (!ctx || !plan) return fail(TFHE_EINVAL, "ckks_ctx_plan: null argument");
+  *plan = ctx->plan;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_hmult_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch,
+                                      size_t* bytes) {
+  if (!ctx || !bytes) return fail(TFHE_EINVAL, "hmult_workspace_size: null argument");
+  if (level < 1 || level > ctx->L) return fail(TFHE_EINVAL, "level must be in [1, L]");
+  *bytes = ks_layout(ctx, level, batch).total;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
+                       uint32_t* ct_out, const uint32_t* evk, uint32_t level, uint32_t batch,
+                       void* ws, size_t ws_bytes, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, ws, ws_bytes);
+  if (st != TFHE_OK || batch == 0) return st;
+  if (!al16(ct_a) || !al16(ct_b) || !al16(ct_out) || !al16(evk))
+    return fail(TFHE_EINVAL, "hmult: null or unaligned pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t plane = (uint64_t)level * batch * ctx->n;
+  unsigned char* w = (unsigned char*)ws;
+  uint32_t* d2 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
+  hipError_t e = launch_tensor(ct_a, ct_b, ct_out, d2, ctx->plan->d_mod, level, batch, ctx->n, s);
+  if (e == hipSuccess)
+    e = key_switch(ctx, d2, evk, ct_out, ct_out + plane, true, true, level, batch, w, s);
+  return hip_check(e, "hmult");
+}
+
+tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,
+                        const uint32_t* rotkey, uint32_t galois_elt, uint32_t level, uint32_t batch,
+                        void* ws, size_t ws_bytes, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, ws, ws_bytes);
+  if (st != TFHE_OK || batch == 0) return st;
+  if (!al16(ct_in) || !al16(ct_out) || !al16(rotkey))
+    return fail(TFHE_EINVAL, "rotate: null or unaligned pointer");
+  if ((galois_elt & 1) == 0 || galois_elt >= 2 * ctx->n)
+    return fail(TFHE_EINVAL, "rotate: galois element must be odd and < 2N");
+  const uint64_t plane = (uint64_t)level * batch * ctx->n;
+  if (ct_in < ct_out + 2 * plane && ct_out < ct_in + 2 * plane)
+    return fail(TFHE_EINVAL, "rotate: ct_out must not alias ct_in");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* w = (unsigned char*)ws;
+  uint32_t* r1 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
+  hipError_t e = frobenius_launch(ct_in, ct_out, galois_elt, level * batch, ctx->log_n, s);
+  if (e == hipSuccess) e = frobenius_launch(ct_in + plane, r1, galois_elt, level * batch, ctx->log_n, s);
+  if (e == hipSuccess)
+    e = key_switch(ctx, r1, rotkey, ct_out, ct_out + plane, true, false, level, batch, w, s);
+  return hip_check(e, "rotate");
+}
+
+}  // extern "C"

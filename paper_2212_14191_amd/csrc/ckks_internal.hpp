@@ -1,0 +1,42 @@
+// RNS-CKKS context state and the launchers of ckks_kernels.hip.
+#pragma once
+#include "internal.hpp"
+
+namespace tfhe {
+
+constexpr int kMaxAlpha = 8;  // limbs per key-switching digit
+constexpr int kMaxK = 8;      // special primes
+
+struct CkksCtxImpl {
+  uint32_t log_n = 0, n = 0, L = 0, K = 0, dnum = 0, alpha = 0;
+  tfhe_ntt_plan_s* plan = nullptr;  // over q_0..q_{L-1}, p_0..p_{K-1}
+  // ModUp constants of digit D = [alpha*j, e), indexed by e-1 in [0, L):
+  uint2* d_up_inv = nullptr;   // [L][kMaxAlpha]        [(Q_D/q_i)^{-1}]_{q_i}
+  uint2* d_up_conv = nullptr;  // [L][L+K][kMaxAlpha]   [Q_D/q_i]_{t}
+  // ModDown constants:
+  uint2* d_dn_invp = nullptr;  // [kMaxK]               [(P/p_k)^{-1}]_{p_k}
+  uint2* d_dn_conv = nullptr;  // [L][kMaxK]            [P/p_k]_{q_i}
+  uint2* d_dn_pinv = nullptr;  // [L]                   [P^{-1}]_{q_i}
+  std::vector<void*> owned;
+};
+
+hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
+                         const ModConst* mods, uint32_t level, uint32_t batch, uint32_t n,
+                         hipStream_t s);
+hipError_t launch_modup(const uint32_t* x, uint32_t* up, const ModConst* mods, const uint2* inv,
+                        const uint2* conv, uint32_t d0, uint32_t nd, uint32_t level, uint32_t L,
+                        uint32_t K, uint32_t batch, uint32_t n, hipStream_t s);
+hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const uint32_t* key,
+                                uint32_t* acc0, uint32_t* acc1, const ModConst* mods,
+                                uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,
+                                uint32_t K, uint32_t batch, uint32_t log_n, hipStream_t s);
+hipError_t launch_moddown_conv(const uint32_t* a, uint32_t* conv, const ModConst* mods,
+                               const uint2* invp, const uint2* cp, uint32_t level, uint32_t L,
+                               uint32_t K, uint32_t batch, uint32_t n, hipStream_t s);
+hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint32_t* out,
+                                const ModConst* mods, const uint2* pinv, uint32_t level,
+                                uint32_t batch, uint32_t n, bool accumulate, hipStream_t s);
+
+}  // namespace tfhe
+
+struct tfhe_ckks_ctx_s : tfhe::CkksCtxImpl {};

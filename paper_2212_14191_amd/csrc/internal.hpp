@@ -1,0 +1,92 @@
+// Internal types of the library: plan and context state, error plumbing,
+// kernel launchers.  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tfhe.h"
+#include "modarith.hpp"
+
+namespace tfhe {
+
+void set_error(const std::string& msg);
+tfhe_status fail(tfhe_status s, const std::string& msg);
+tfhe_status hip_check(hipError_t e, const char* what);
+
+// Tables of the four-step algorithm for one pass of a 256-point transform
+// decomposed as 16 x 16 (per limb, per direction).  All arrays are laid out
+// exactly as the kernels load them into MFMA operand registers.
+//   opA[j][lane][4]   level-A twiddle operand, digit plane j (4 dwords/lane)
+//   opB[j][lane][4]   level-B twiddle operand
+//   twist[lane][r]    inter-level twist: uint4 {w, w', 2^16 w, (2^16 w)'}
+struct PassTables {
+  uint32_t opA[4][64][4];
+  uint32_t opB[4][64][4];
+  uint4 twist[64][4];
+};
+
+// Device-side description of one limb for the four-step kernels.
+struct FourStepLimb {
+  const PassTables* pass1;  // column pass
+  const PassTables* pass2;  // row pass
+  const uint4* post1;       // [256 columns][64 lanes][4]: post-twist of pass 1
+  uint32_t q;
+  uint32_t c16, c16p;       // 2^16 mod q and its Shoup companion
+  uint32_t pad;
+};
+
+struct tfhe_plan_impl {
+  uint32_t log_n = 0, n = 0, n_limbs = 0;
+  tfhe_ntt_algo algo = TFHE_NTT_BUTTERFLY;  // what AUTO resolves to
+  bool has_mfma = false;
+  int device = 0;
+  std::vector<uint32_t> q, psi;
+  // device arrays
+  ModConst* d_mod = nullptr;      // [n_limbs]
+  uint2* d_bf_fwd = nullptr;      // [n_limbs][N] {psi^{brv(i)}, companion}
+  uint2* d_bf_inv = nullptr;      // [n_limbs][N] {psi^{-brv(i)}, companion}
+  uint2* d_ninv = nullptr;        // [n_limbs] {N^{-1}, companion}
+  FourStepLimb* d_fs_fwd = nullptr;  // [n_limbs]
+  FourStepLimb* d_fs_inv = nullptr;  // [n_limbs]
+  void* d_fs_blob = nullptr;          // owns all four-step tables
+  std::vector<void*> owned;
+};
+
+}  // namespace tfhe
+
+struct tfhe_ntt_plan_s : tfhe::tfhe_plan_impl {};
+
+namespace tfhe {
+
+// ---- butterfly launchers (ntt_butterfly.hip)
+size_t bf_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_t batch);
+hipError_t bf_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
+                      uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s);
+hipError_t bf_inverse(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
+                      uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s);
+
+// ---- four-step MFMA launchers (ntt_fourstep.hip)
+bool fs_supported(uint32_t log_n);
+size_t fs_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_t batch);
+hipError_t fs_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
+                      uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s);
+hipError_t fs_inverse(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
+                      uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s);
+
+// ---- element-wise launchers (elementwise.hip)
+enum EwOp { EW_MUL = 0, EW_ADD = 1, EW_SUB = 2, EW_MUL_BCAST = 3 };
+hipError_t ew_launch(EwOp op, const ModConst* mods, const uint32_t* a, const uint32_t* b,
+                     uint32_t* c, uint32_t limb_count, uint32_t batch, uint32_t n, hipStream_t s);
+hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, uint32_t rows,
+                            uint32_t log_n, hipStream_t s);
+
+// ---- host-side number theory (plan.cpp)
+bool is_prime_u32(uint32_t q);
+uint32_t pow_mod(uint32_t b, uint64_t e, uint32_t q);
+uint32_t inv_mod(uint32_t x, uint32_t q);
+uint32_t default_psi(uint32_t q, uint32_t log_n);  // 0 if none
+
+}  // namespace tfhe

@@ -1,0 +1,282 @@
+// NTT plan construction: modulus and root validation, and the twiddle tables
+// of both transform algorithms, built once per (N, prime set) on the host and
+// copied to the device (Sec. III-B: the twiddle matrices are fixed by N and q,
+// pre-computed at initialisation and reused by every NTT).
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tfhe {
+
+uint32_t pow_mod(uint32_t b, uint64_t e, uint32_t q) {
+  uint64_t r = 1 % q, x = b % q;
+  while (e) {
+    if (e & 1) r = r * x % q;
+    x = x * x % q;
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+uint32_t inv_mod(uint32_t x, uint32_t q) { return pow_mod(x, q - 2, q); }
+
+static uint32_t mulm(uint32_t a, uint32_t b, uint32_t q) { return (uint32_t)((uint64_t)a * b % q); }
+
+// Deterministic Miller-Rabin for 32-bit integers (bases 2, 7, 61).
+bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t p : {2u, 3u, 5u, 7u, 11u, 13u, 17u, 19u, 23u, 29u, 31u, 37u, 61u})
+    if (n % p == 0) return n == p;
+  uint32_t d = n - 1;
+  int r = 0;
+  while ((d & 1) == 0) { d >>= 1; ++r; }
+  for (uint32_t a : {2u, 7u, 61u}) {
+    uint32_t x = pow_mod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r; ++i) {
+      x = mulm(x, x, n);
+      if (x == n - 1) { comp = false; break; }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+// psi = g^{(q-1)/2N}, g the smallest primitive root of q; 0 if q unsuitable.
+uint32_t default_psi(uint32_t q, uint32_t log_n) {
+  uint64_t two_n = 2ull << log_n;
+  if (!is_prime_u32(q) || (q - 1) % two_n != 0) return 0;
+  std::vector<uint32_t> fac;
+  uint32_t m = q - 1;
+  for (uint32_t d = 2; (uint64_t)d * d <= m; ++d)
+    if (m % d == 0) {
+      fac.push_back(d);
+      while (m % d == 0) m /= d;
+    }
+  if (m > 1) fac.push_back(m);
+  for (uint32_t g = 2; g < q; ++g) {
+    bool ok = true;
+    for (uint32_t f : fac)
+      if (pow_mod(g, (q - 1) / f, q) == 1) { ok = false; break; }
+    if (ok) return pow_mod(g, (q - 1) / two_n, q);
+  }
+  return 0;
+}
+
+static uint32_t bit_reverse(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; ++i) { r = (r << 1) | (x & 1); x >>= 1; }
+  return r;
+}
+
+ModConst make_modconst(uint32_t q) {
+  ModConst c;
+  c.q = q;
+  uint32_t inv = 1;  // q^{-1} mod 2^32 by Newton iteration
+  for (int i = 0; i < 5; ++i) inv *= 2u - q * inv;
+  c.qneg = 0u - inv;
+  c.r = (uint32_t)((1ull << 32) % q);
+  c.rp = shoup_companion(c.r, q);
+  return c;
+}
+
+// ---------------------------------------------------------------- four-step
+// Byte j of the balanced digit expansion of the window representative of w.
+static int8_t digit(uint32_t w, uint32_t q, int j) {
+  uint32_t packed = balanced_digits(to_window(w, q));
+  return (int8_t)(packed >> (8 * j));
+}
+
+typedef uint32_t Mat16[16][16];
+
+// Lay out one 16 x 16 pass (WA[u][s], T[s][v], WB[t][v]) as MFMA operands.
+// Level A contracts over u with the data as MFMA A operand: lane (v, g) holds
+// u = 4g + c, byte 4c + d pairs data digit d with digit j of 2^{8d} WA[u][s].
+// Level B contracts over v with the twiddle as MFMA A operand: lane (t, g)
+// holds v = 4g + c.  After level A, lane (s, g) holds v = 4g + r.
+static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Mat16& WB, uint32_t q) {
+  uint32_t p2[4];
+  for (int d = 0; d < 4; ++d) p2[d] = pow_mod(2, 8 * d, q);
+  for (int j = 0; j < 4; ++j)
+    for (int lane = 0; lane < 64; ++lane) {
+      int col = lane % 16, g = lane / 16;
+      for (int c = 0; c < 4; ++c) {
+        uint32_t a = 0, b = 0;
+        for (int d = 0; d < 4; ++d) {
+          a |= (uint32_t)(uint8_t)digit(mulm(p2[d], WA[4 * g + c][col], q), q, j) << (8 * d);
+          b |= (uint32_t)(uint8_t)digit(mulm(p2[d], WB[col][4 * g + c], q), q, j) << (8 * d);
+        }
+        pt.opA[j][lane][c] = a;
+        pt.opB[j][lane][c] = b;
+      }
+    }
+  uint32_t c16 = pow_mod(2, 16, q);
+  for (int lane = 0; lane < 64; ++lane)
+    for (int r = 0; r < 4; ++r) {
+      uint32_t w = T[lane % 16][4 * (lane / 16) + r];
+      uint32_t w16 = mulm(w, c16, q);
+      pt.twist[lane][r] = make_uint4(w, shoup_companion(w, q), w16, shoup_companion(w16, q));
+    }
+}
+
+// post[col][lane][r] = P(col, k) with k = s + 16 (4g + r) the output index
+// lane (s, g) holds in register r after level B.
+template <typename F>
+static void build_post(uint4* post, uint32_t q, F P) {
+  uint32_t c16 = pow_mod(2, 16, q);
+  for (int col = 0; col < 256; ++col)
+    for (int lane = 0; lane < 64; ++lane)
+      for (int r = 0; r < 4; ++r) {
+        int k = lane % 16 + 16 * (4 * (lane / 16) + r);
+        uint32_t w = P(col, k);
+        uint32_t w16 = mulm(w, c16, q);
+        post[(col * 64 + lane) * 4 + r] =
+            make_uint4(w, shoup_companion(w, q), w16, shoup_companion(w16, q));
+      }
+}
+
+struct FsHostLimb {
+  PassTables p1, p2;
+  std::vector<uint4> post;
+};
+
+// Four-step tables for N = 2^16 = 256 x 256, n = 256 n1 + n2, k = k1 + 256 k2:
+//   A_k = sum_{n2} w^{k2 n2} psi^{(2k1+1) n2} sum_{n1} phi^{(2k1+1) n1} a[n1][n2]
+// with phi = psi^256 (primitive 512th root) and w = psi^512 (primitive 256th
+// root); each 256-point stage is itself split 16 x 16 (n = 16u + v,
+// k = s + 16t).  Returns the forward (dir = 0) or inverse (dir = 1) tables.
+static void build_fourstep_limb(FsHostLimb& L, uint32_t q, uint32_t psi, int dir) {
+  const uint32_t N = 1u << 16;
+  uint32_t phi = pow_mod(psi, 256, q), om = pow_mod(psi, 512, q);
+  uint32_t phii = inv_mod(phi, q), omi = inv_mod(om, q), psii = inv_mod(psi, q);
+  uint32_t ninv = inv_mod(N % q, q);
+  Mat16 WA, T, WB;
+  if (dir == 0) {
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b) {
+        WA[a][b] = pow_mod(phi, 16ull * (2 * b + 1) * a, q);  // [u][s]
+        T[a][b] = pow_mod(phi, (uint64_t)(2 * a + 1) * b, q);   // [s][v]
+        WB[a][b] = pow_mod(phi, 32ull * a * b, q);              // [t][v]
+      }
+    build_pass(L.p1, WA, T, WB, q);
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b) {
+        WA[a][b] = pow_mod(om, 16ull * a * b, q);
+        T[a][b] = pow_mod(om, (uint64_t)a * b, q);
+        WB[a][b] = pow_mod(om, 16ull * a * b, q);
+      }
+    build_pass(L.p2, WA, T, WB, q);
+    L.post.resize(256 * 64 * 4);
+    // column n2, output k1: psi^{(2 k1 + 1) n2}
+    build_post(L.post.data(), q, [&](int n2, int k1) {
+      return pow_mod(psi, (uint64_t)(2 * k1 + 1) * n2 % (2 * N), q);
+    });
+  } else {
+    // inverse pass 1: for each k1, cyclic over k2 with root w^{-1}
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b) {
+        WA[a][b] = pow_mod(omi, 16ull * a * b, q);
+        T[a][b] = pow_mod(omi, (uint64_t)a * b, q);
+        WB[a][b] = pow_mod(omi, 16ull * a * b, q);
+      }
+    build_pass(L.p1, WA, T, WB, q);
+    // inverse pass 2: for each n2, out n1 = s + 16t from in k1 = 16u + v:
+    // N^{-1} phi^{-2 k1 n1 - n1}
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b) {
+        WA[a][b] = pow_mod(phii, 32ull * a * b, q);                    // [u][s]
+        T[a][b] = pow_mod(phii, (uint64_t)(2 * b + 1) * a, q);         // [s][v]
+        WB[a][b] = mulm(pow_mod(phii, (uint64_t)(32 * b + 16) * a, q), ninv, q);  // [t][v]
+      }
+    build_pass(L.p2, WA, T, WB, q);
+    L.post.resize(256 * 64 * 4);
+    // column k1, output n2: psi^{-(2 k1 + 1) n2}
+    build_post(L.post.data(), q, [&](int k1, int n2) {
+      return pow_mod(psii, (uint64_t)(2 * k1 + 1) * n2 % (2 * N), q);
+    });
+  }
+}
+
+template <typename T>
+static hipError_t upload(T** dst, const T* src, size_t count, std::vector<void*>& owned) {
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(count, 1));
+  if (e != hipSuccess) return e;
+  owned.push_back(*dst);
+  return hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice);
+}
+
+tfhe_status plan_build(tfhe_ntt_plan_s* p) {
+  const uint32_t N = p->n, L = p->n_limbs;
+  std::vector<ModConst> mods(L);
+  std::vector<uint2> fwd((size_t)L * N), inv((size_t)L * N), ninv(L);
+  for (uint32_t l = 0; l < L; ++l) {
+    uint32_t q = p->q[l], psi = p->psi[l], psii = inv_mod(psi, q);
+    mods[l] = make_modconst(q);
+    for (uint32_t i = 0; i < N; ++i) {
+      uint32_t b = bit_reverse(i, p->log_n);
+      uint32_t w = pow_mod(psi, b, q), wi = pow_mod(psii, b, q);
+      fwd[(size_t)l * N + i] = make_uint2(w, shoup_companion(w, q));
+      inv[(size_t)l * N + i] = make_uint2(wi, shoup_companion(wi, q));
+    }
+    uint32_t ni = inv_mod(N % q, q);
+    ninv[l] = make_uint2(ni, shoup_companion(ni, q));
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) return fail(TFHE_EHIP, "hipGetDevice failed");
+  hipError_t e;
+  if ((e = upload(&p->d_mod, mods.data(), L, p->owned)) != hipSuccess ||
+      (e = upload(&p->d_bf_fwd, fwd.data(), fwd.size(), p->owned)) != hipSuccess ||
+      (e = upload(&p->d_bf_inv, inv.data(), inv.size(), p->owned)) != hipSuccess ||
+      (e = upload(&p->d_ninv, ninv.data(), L, p->owned)) != hipSuccess)
+    return e == hipErrorOutOfMemory ? fail(TFHE_ENOMEM, "plan tables: out of device memory")
+                                    : hip_check(e, "plan tables");
+
+  p->has_mfma = fs_supported(p->log_n);
+  for (uint32_t l = 0; l < L && p->has_mfma; ++l)
+    if (p->q[l] < (1u << 29)) p->has_mfma = false;  // digit bounds need q > 2^29
+  if (p->has_mfma) {
+    // blob: per limb and direction {PassTables p1, p2, post[256*64*4]}
+    const size_t post_elems = 256 * 64 * 4;
+    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint4);
+    const size_t total = per * 2 * L;
+    std::vector<unsigned char> blob(total);
+    std::vector<FourStepLimb> hf(L), hi(L);
+    e = hipMalloc(&p->d_fs_blob, total);
+    if (e != hipSuccess) return fail(TFHE_ENOMEM, "four-step tables: out of device memory");
+    p->owned.push_back(p->d_fs_blob);
+    unsigned char* dbase = (unsigned char*)p->d_fs_blob;
+    for (uint32_t l = 0; l < L; ++l)
+      for (int dir = 0; dir < 2; ++dir) {
+        FsHostLimb H;
+        build_fourstep_limb(H, p->q[l], p->psi[l], dir);
+        size_t off = per * (2 * l + dir);
+        memcpy(&blob[off], &H.p1, sizeof(PassTables));
+        memcpy(&blob[off + sizeof(PassTables)], &H.p2, sizeof(PassTables));
+        memcpy(&blob[off + 2 * sizeof(PassTables)], H.post.data(), post_elems * sizeof(uint4));
+        FourStepLimb& f = dir == 0 ? hf[l] : hi[l];
+        f.pass1 = (const PassTables*)(dbase + off);
+        f.pass2 = (const PassTables*)(dbase + off + sizeof(PassTables));
+        f.post1 = (const uint4*)(dbase + off + 2 * sizeof(PassTables));
+        f.q = p->q[l];
+        f.c16 = pow_mod(2, 16, p->q[l]);
+        f.c16p = shoup_companion(f.c16, p->q[l]);
+        f.pad = 0;
+      }
+    if ((e = hipMemcpy(p->d_fs_blob, blob.data(), total, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = upload(&p->d_fs_fwd, hf.data(), L, p->owned)) != hipSuccess ||
+        (e = upload(&p->d_fs_inv, hi.data(), L, p->owned)) != hipSuccess)
+      return hip_check(e, "four-step tables");
+  }
+  return TFHE_OK;
+}
+
+void plan_free(tfhe_ntt_plan_s* p) {
+  for (void* ptr : p->owned) (void)hipFree(ptr);
+  p->owned.clear();
+}
+
+}  // namespace tfhe

@@ -1,0 +1,293 @@
+"""Thin ctypes binding of libtfhe.so (include/tfhe.h).
+
+Every compute step runs in the library's HIP kernels; this module only
+marshals arguments.  Device memory and streams come from PyTorch: residue
+arrays are torch tensors of dtype int32 (bit-identical to the uint32 the ABI
+takes) on the current HIP device, in the (limb, batch, N) layout.
+
+The functions named like the C entry points (tfhe_ntt_fwd, ...) take raw
+pointers; the classes NttPlan and CkksContext wrap them for tensors.  Loading
+fails loudly when the library has not been built: there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtfhe.so")
+
+TFHE_OK, TFHE_EINVAL, TFHE_ENOTNTT, TFHE_ENOMEM, TFHE_EHIP, TFHE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+AUTO, BUTTERFLY, FOURSTEP_MFMA = 0, 1, 2
+ALGOS = {"auto": AUTO, "butterfly": BUTTERFLY, "mfma": FOURSTEP_MFMA}
+
+_lib = None
+
+
+class TfheError(RuntimeError):
+    def __init__(self, status, func, detail):
+        self.status = status
+        super().__init__(f"{func} -> {status_name(status)}: {detail}")
+
+
+def load():
+    """Load libtfhe.so and declare its signatures (raises if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2212_14191_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    u32, u64, i32, vp, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+    pu32 = ctypes.POINTER(u32)
+    sig = {
+        "tfhe_status_string": ([i32], ctypes.c_char_p),
+        "tfhe_last_error": ([], ctypes.c_char_p),
+        "tfhe_find_primes": ([u32, u64, u32, pu32], i32),
+        "tfhe_default_psi": ([u32, u32, pu32], i32),
+        "tfhe_ntt_plan_create": ([ctypes.POINTER(vp), u32, u32, pu32, pu32, i32], i32),
+        "tfhe_ntt_plan_destroy": ([vp], i32),
+        "tfhe_ntt_plan_info": ([vp, pu32, pu32, ctypes.POINTER(i32)], i32),
+        "tfhe_ntt_plan_modulus": ([vp, u32, pu32, pu32], i32),
+        "tfhe_ntt_workspace_size": ([vp, i32, u32, u32, ctypes.POINTER(sz)], i32),
+        "tfhe_ntt_fwd": ([vp, i32, vp, vp, u32, u32, u32, vp, sz, vp], i32),
+        "tfhe_ntt_inv": ([vp, i32, vp, vp, u32, u32, u32, vp, sz, vp], i32),
+        "tfhe_pointwise_mul": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_pointwise_add": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_pointwise_sub": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_pointwise_mul_bcast": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_frobenius_map": ([vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_ckks_ctx_create": ([ctypes.POINTER(vp), u32, u32, u32, u32, pu32, pu32, i32], i32),
+        "tfhe_ckks_ctx_destroy": ([vp], i32),
+        "tfhe_ckks_ctx_plan": ([vp, ctypes.POINTER(vp)], i32),
+        "tfhe_hmult_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
+        "tfhe_hmult": ([vp, vp, vp, vp, vp, u32, u32, vp, sz, vp], i32),
+        "tfhe_rotate": ([vp, vp, vp, vp, u32, u32, u32, vp, sz, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def status_name(s):
+    return load().tfhe_status_string(int(s)).decode()
+
+
+def check(status, func):
+    if status != TFHE_OK:
+        detail = load().tfhe_last_error().decode()
+        raise TfheError(status, func, detail)
+
+
+def _call(name, *args):
+    st = getattr(load(), name)(*args)
+    check(st, name)
+    return st
+
+
+def _u32_array(values):
+    if values is None:
+        return None
+    vals = [int(v) for v in values]
+    return (ctypes.c_uint32 * len(vals))(*vals)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------ raw entry points
+def tfhe_find_primes(bits, two_n, count):
+    out = (ctypes.c_uint32 * count)()
+    _call("tfhe_find_primes", bits, two_n, count, out)
+    return list(out)
+
+
+def tfhe_default_psi(q, log_n):
+    r = ctypes.c_uint32()
+    _call("tfhe_default_psi", q, log_n, ctypes.byref(r))
+    return r.value
+
+
+def _check_residues(t, name, shape=None):
+    import torch
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous int32 CUDA/HIP tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+
+
+class NttPlan:
+    """Owns a tfhe_ntt_plan: N = 2^log_n over the given primes."""
+
+    def __init__(self, log_n, q, psi=None, algo="auto", handle=None):
+        self.log_n = int(log_n)
+        self.n = 1 << self.log_n
+        self._owned = handle is None
+        if handle is None:
+            h = ctypes.c_void_p()
+            _call("tfhe_ntt_plan_create", ctypes.byref(h), self.log_n, len(q), _u32_array(q),
+                  _u32_array(psi), ALGOS.get(algo, algo))
+            self.handle = h
+        else:
+            self.handle = handle
+        ln, nl, al = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int()
+        _call("tfhe_ntt_plan_info", self.handle, ctypes.byref(ln), ctypes.byref(nl), ctypes.byref(al))
+        self.n_limbs, self.algo = nl.value, al.value
+        self.q, self.psi = [], []
+        for l in range(self.n_limbs):
+            a, b = ctypes.c_uint32(), ctypes.c_uint32()
+            _call("tfhe_ntt_plan_modulus", self.handle, l, ctypes.byref(a), ctypes.byref(b))
+            self.q.append(a.value)
+            self.psi.append(b.value)
+
+    def close(self):
+        if self._owned and self.handle:
+            load().tfhe_ntt_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, limb_count, batch, algo="auto"):
+        b = ctypes.c_size_t()
+        _call("tfhe_ntt_workspace_size", self.handle, ALGOS.get(algo, algo), limb_count, batch,
+              ctypes.byref(b))
+        return b.value
+
+    def workspace(self, limb_count, batch, algo="auto"):
+        import torch
+        nbytes = self.workspace_bytes(limb_count, batch, algo)
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda") if nbytes else None
+
+    def _transform(self, name, x, out, algo, limb_begin, ws, stream):
+        limbs, batch, n = x.shape
+        if n != self.n:
+            raise ValueError(f"last dimension {n} != N = {self.n}")
+        _check_residues(x, "x")
+        if out is None:
+            out = torch_empty_like(x)
+        _check_residues(out, "out", x.shape)
+        if ws is None:
+            ws = self.workspace(limbs, batch, algo)
+        _call(name, self.handle, ALGOS.get(algo, algo), _ptr(x), _ptr(out), limb_begin, limbs, batch,
+              _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream))
+        return out
+
+    def fwd(self, x, out=None, algo="auto", limb_begin=0, ws=None, stream=None):
+        """Forward NTT (Eq. 4) of x: int32 [limbs][batch][N]."""
+        return self._transform("tfhe_ntt_fwd", x, out, algo, limb_begin, ws, stream)
+
+    def inv(self, x, out=None, algo="auto", limb_begin=0, ws=None, stream=None):
+        """Inverse NTT of x: int32 [limbs][batch][N]."""
+        return self._transform("tfhe_ntt_inv", x, out, algo, limb_begin, ws, stream)
+
+    def _ew(self, name, a, b, out, limb_begin, stream):
+        limbs, batch, n = a.shape
+        _check_residues(a, "a")
+        _check_residues(b, "b")
+        if out is None:
+            out = torch_empty_like(a)
+        _call(name, self.handle, _ptr(a), _ptr(b), _ptr(out), limb_begin, limbs, batch, _stream(stream))
+        return out
+
+    def mul(self, a, b, out=None, limb_begin=0, stream=None):
+        return self._ew("tfhe_pointwise_mul", a, b, out, limb_begin, stream)
+
+    def add(self, a, b, out=None, limb_begin=0, stream=None):
+        return self._ew("tfhe_pointwise_add", a, b, out, limb_begin, stream)
+
+    def sub(self, a, b, out=None, limb_begin=0, stream=None):
+        return self._ew("tfhe_pointwise_sub", a, b, out, limb_begin, stream)
+
+    def mul_bcast(self, a, b, out=None, limb_begin=0, stream=None):
+        """a [limbs][batch][N] times b [limbs][N] broadcast over the batch."""
+        return self._ew("tfhe_pointwise_mul_bcast", a, b, out, limb_begin, stream)
+
+    def frobenius(self, x, galois, out=None, stream=None):
+        limbs, batch, n = x.shape
+        _check_residues(x, "x")
+        if out is None:
+            out = torch_empty_like(x)
+        _call("tfhe_frobenius_map", self.handle, _ptr(x), _ptr(out), galois, limbs, batch, _stream(stream))
+        return out
+
+
+def torch_empty_like(x):
+    import torch
+    return torch.empty_like(x, memory_format=torch.contiguous_format)
+
+
+class CkksContext:
+    """Owns a tfhe_ckks_ctx (RNS-CKKS with hybrid key switching)."""
+
+    def __init__(self, log_n, L, K, dnum, moduli=None, psi=None, algo="auto"):
+        h = ctypes.c_void_p()
+        _call("tfhe_ckks_ctx_create", ctypes.byref(h), log_n, L, K, dnum, _u32_array(moduli),
+              _u32_array(psi), ALGOS.get(algo, algo))
+        self.handle = h
+        self.log_n, self.n, self.L, self.K, self.dnum = log_n, 1 << log_n, L, K, dnum
+        ph = ctypes.c_void_p()
+        _call("tfhe_ckks_ctx_plan", self.handle, ctypes.byref(ph))
+        self.plan = NttPlan(log_n, None, handle=ph)
+        self.moduli = self.plan.q
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.plan.handle = None
+            load().tfhe_ckks_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, level, batch):
+        b = ctypes.c_size_t()
+        _call("tfhe_hmult_workspace_size", self.handle, level, batch, ctypes.byref(b))
+        return b.value
+
+    def workspace(self, level, batch):
+        import torch
+        return torch.empty(max(self.workspace_bytes(level, batch), 256), dtype=torch.uint8, device="cuda")
+
+    def hmult(self, ct_a, ct_b, evk, level, out=None, ws=None, stream=None):
+        """HMULT of ct_a, ct_b: int32 [2][level][batch][N] (NTT domain)."""
+        _, lv, batch, n = ct_a.shape
+        if lv != level:
+            raise ValueError("ciphertext level mismatch")
+        for t, nm in ((ct_a, "ct_a"), (ct_b, "ct_b")):
+            _check_residues(t, nm, (2, level, batch, self.n))
+        _check_residues(evk, "evk", (self.dnum, 2, self.L + self.K, self.n))
+        if out is None:
+            out = torch_empty_like(ct_a)
+        if ws is None:
+            ws = self.workspace(level, batch)
+        _call("tfhe_hmult", self.handle, _ptr(ct_a), _ptr(ct_b), _ptr(out), _ptr(evk), level, batch,
+              _ptr(ws), ws.numel(), _stream(stream))
+        return out
+
+    def rotate(self, ct, rotkey, galois, level, out=None, ws=None, stream=None):
+        _, lv, batch, n = ct.shape
+        _check_residues(ct, "ct", (2, level, batch, self.n))
+        _check_residues(rotkey, "rotkey", (self.dnum, 2, self.L + self.K, self.n))
+        if out is None:
+            out = torch_empty_like(ct)
+        if ws is None:
+            ws = self.workspace(level, batch)
+        _call("tfhe_rotate", self.handle, _ptr(ct), _ptr(out), _ptr(rotkey), galois, level, batch,
+              _ptr(ws), ws.numel(), _stream(stream))
+        return out

@@ -1,0 +1,107 @@
+"""GPU parity of HMULT and HROTATE against the oracle's fixed algorithm
+(bit-exact), plus decryption of the GPU results, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ckks
+from paper_2212_14191_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_14191_amd import tfhe
+    tfhe.load()
+    return tfhe
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).cuda()
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def setup(n, L, K, dnum, h=None):
+    pr = ckks.Params(n, L=L, K=K, dnum=dnum)
+    s = inputs.ternary_secret(1, n, h or min(192, n // 2))
+    a = inputs.uniform_residues(1, pr.moduli, (dnum, n), stream=1).transpose(1, 0, 2)
+    e = inputs.gaussian_error(2, (dnum, n), stream=1)
+    evk = ckks.relin_key(pr, s, a, e)
+    return pr, s, evk, (a, e)
+
+
+def encrypt(pr, s, m, level, seed):
+    b = m.shape[0]
+    c1 = inputs.uniform_residues(seed, pr.mods(range(level)), (b, pr.n), stream=5)
+    e = inputs.gaussian_error(2, (b, pr.n), stream=seed + 10)
+    return ckks.encrypt(pr, s, m, c1, e, level)
+
+
+@pytest.mark.parametrize("log_n,L,K,dnum,level", [
+    (10, 6, 2, 3, 6), (10, 6, 2, 3, 5), (10, 6, 2, 3, 1), (12, 8, 4, 2, 8), (12, 8, 4, 2, 3)])
+def test_hmult_matches_oracle(tf, log_n, L, K, dnum, level):
+    n = 1 << log_n
+    pr, s, evk, _ = setup(n, L, K, dnum)
+    ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
+    assert ctx.moduli == pr.moduli and ctx.plan.psi == pr.psi
+    m1 = inputs.small_messages(0, (3, n))
+    m2 = inputs.small_messages(0, (3, n), stream=1)
+    ca, cb = encrypt(pr, s, m1, level, 1), encrypt(pr, s, m2, level, 2)
+    want = ckks.hmult(pr, ca, cb, evk, level)
+    got = to_host(ctx.hmult(to_dev(ca), to_dev(cb), to_dev(evk), level))
+    assert np.array_equal(got, want)
+
+
+def test_hmult_output_aliases_input(tf):
+    n = 1 << 10
+    pr, s, evk, _ = setup(n, 6, 2, 3)
+    ctx = tf.CkksContext(10, 6, 2, 3, moduli=pr.moduli)
+    m = inputs.small_messages(0, (2, n))
+    ca, cb = encrypt(pr, s, m, 6, 1), encrypt(pr, s, m, 6, 2)
+    want = ckks.hmult(pr, ca, cb, evk, 6)
+    A = to_dev(ca)
+    ctx.hmult(A, to_dev(cb), to_dev(evk), 6, out=A)
+    assert np.array_equal(to_host(A), want)
+
+
+@pytest.mark.parametrize("r", [1, 7])
+def test_rotate_matches_oracle(tf, r):
+    n = 1 << 10
+    L, K, dnum, level = 6, 2, 3, 5
+    pr, s, _, (a, e) = setup(n, L, K, dnum)
+    k = ckks.galois_element(r, n)
+    rk = ckks.rotation_key(pr, s, k, a, e)
+    ctx = tf.CkksContext(10, L, K, dnum, moduli=pr.moduli)
+    m = inputs.small_messages(0, (2, n))
+    ct = encrypt(pr, s, m, level, 1)
+    want = ckks.rotate(pr, ct, rk, k, level)
+    got = to_host(ctx.rotate(to_dev(ct), to_dev(rk), k, level))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.slow
+def test_hmult_config4_full_size_sampled(tf):
+    """N=2^16, L=24, K=8, dnum=3, h=192, 64 pairs on the GPU (MFMA NTT);
+    two sampled pairs equal the oracle bit for bit and decrypt to m1*m2."""
+    n, L, K, dnum, level, B = 1 << 16, 24, 8, 3, 24, 64
+    pr, s, evk, _ = setup(n, L, K, dnum)
+    ctx = tf.CkksContext(16, L, K, dnum, moduli=pr.moduli)
+    m1 = inputs.small_messages(0, (B, n))
+    m2 = inputs.small_messages(0, (B, n), stream=1)
+    ca, cb = encrypt(pr, s, m1, level, 1), encrypt(pr, s, m2, level, 2)
+    got = to_host(ctx.hmult(to_dev(ca), to_dev(cb), to_dev(evk), level))
+    for b in (0, 37):
+        want = ckks.hmult(pr, ca[:, :, b:b + 1], cb[:, :, b:b + 1], evk, level)
+        assert np.array_equal(got[:, :, b:b + 1], want), b
+        dec = ckks.decrypt(pr, s, got[:, :, b:b + 1], level)[0]
+        prod = ckks.negacyclic_int(m1[b], m2[b])
+        d2 = 1 << 60
+        assert np.array_equal(np.array([(int(v) + d2 // 2) // d2 for v in dec]), prod)

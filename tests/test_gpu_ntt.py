@@ -1,0 +1,190 @@
+"""GPU parity of the NTT / INTT / element-wise kernels against the oracle,
+bit-exact (integer work), called through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_14191_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def tf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_14191_amd import tfhe
+    tfhe.load()
+    return tfhe
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).cuda()
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+PRIMES31 = oracle.ntt_primes(6, 31, 1 << 17)
+
+
+@pytest.mark.parametrize("log_n", [4, 5, 8, 11, 12, 13, 14, 15, 16])
+def test_butterfly_matches_oracle(tf, log_n):
+    n = 1 << log_n
+    qs = PRIMES31[:3]
+    plan = tf.NttPlan(log_n, qs, algo="butterfly")
+    psis = plan.psi
+    assert psis == [oracle.psi(q, n) for q in qs]
+    x = inputs.uniform_residues(log_n, qs, (3, n))
+    X = plan.fwd(to_dev(x))
+    ref = oracle.ntt_fwd(x, qs, psis)
+    assert np.array_equal(to_host(X), ref)
+    back = plan.inv(to_dev(ref))
+    assert np.array_equal(to_host(back), x)
+
+
+@pytest.mark.parametrize("batch", [1, 3])
+def test_mfma_matches_oracle(tf, batch):
+    n = 1 << 16
+    qs = PRIMES31[:3]
+    plan = tf.NttPlan(16, qs, algo="mfma")
+    assert plan.algo == tf.FOURSTEP_MFMA
+    x = inputs.uniform_residues(100 + batch, qs, (batch, n))
+    ref = oracle.ntt_fwd(x, qs, plan.psi)
+    X = plan.fwd(to_dev(x), algo="mfma")
+    assert np.array_equal(to_host(X), ref)
+    back = plan.inv(to_dev(ref), algo="mfma")
+    assert np.array_equal(to_host(back), x)
+
+
+def test_mfma_edge_values(tf):
+    """All-zero, all q-1, single spikes and values near 0x7F7F7F7F."""
+    n = 1 << 16
+    qs = [PRIMES31[0], oracle.ntt_primes(1, 30, 1 << 17)[0]]
+    plan = tf.NttPlan(16, qs)
+    x = np.zeros((2, 4, n), np.uint32)
+    for l, q in enumerate(qs):
+        x[l, 1] = q - 1
+        x[l, 2, 0] = q - 1
+        x[l, 2, n - 1] = 1
+        x[l, 3] = np.minimum(np.uint32(0x7F7F7F7F) + np.arange(n, dtype=np.uint32) % 64, q - 1)
+    ref = oracle.ntt_fwd(x, qs, plan.psi)
+    for algo in ("mfma", "butterfly"):
+        got = to_host(plan.fwd(to_dev(x), algo=algo))
+        assert np.array_equal(got, ref), algo
+        assert np.array_equal(to_host(plan.inv(to_dev(ref), algo=algo)), x), algo
+
+
+def test_in_place_and_limb_offset(tf):
+    n = 1 << 16
+    qs = PRIMES31[:5]
+    plan = tf.NttPlan(16, qs)
+    x = inputs.uniform_residues(9, qs[2:4], (2, n))
+    ref = oracle.ntt_fwd(x, qs[2:4], plan.psi[2:4])
+    for algo in ("mfma", "butterfly"):
+        t = to_dev(x)
+        plan.fwd(t, out=t, algo=algo, limb_begin=2)
+        assert np.array_equal(to_host(t), ref), algo
+        plan.inv(t, out=t, algo=algo, limb_begin=2)
+        assert np.array_equal(to_host(t), x), algo
+
+
+def test_config1_negacyclic_product(tf):
+    """N=2^12, 4 limbs of 30-bit primes, 8 pairs: INTT(NTT(a) o NTT(b)) equals
+    the schoolbook negacyclic product, bit for bit."""
+    n = 1 << 12
+    qs = oracle.ntt_primes(4, 30, 2 * n)
+    plan = tf.NttPlan(12, qs)
+    a = inputs.uniform_residues(0, qs, (8, n))
+    b = inputs.uniform_residues(0, qs, (8, n), stream=1)
+    A = plan.fwd(to_dev(a))
+    B = plan.fwd(to_dev(b))
+    c = plan.inv(plan.mul(A, B))
+    ref, _ = oracle.negacyclic_mul(a, b, qs)
+    assert np.array_equal(to_host(c), ref)
+
+
+def test_elementwise_ops(tf):
+    n = 1 << 12
+    qs = PRIMES31[:3]
+    plan = tf.NttPlan(12, qs)
+    a = inputs.uniform_residues(1, qs, (5, n))
+    b = inputs.uniform_residues(2, qs, (5, n))
+    bb = inputs.uniform_residues(3, qs, n)
+    A, B = to_dev(a), to_dev(b)
+    assert np.array_equal(to_host(plan.mul(A, B)), oracle.mul(a, b, qs))
+    assert np.array_equal(to_host(plan.add(A, B)), oracle.add(a, b, qs))
+    assert np.array_equal(to_host(plan.sub(A, B)), oracle.sub(a, b, qs))
+    want = oracle.mul(a, np.broadcast_to(bb[:, None, :], a.shape), qs)
+    assert np.array_equal(to_host(plan.mul_bcast(A, to_dev(bb))), want)
+    # extremes: (q-1)^2 and 0
+    e = np.stack([np.full((2, n), q - 1, np.uint32) for q in qs])
+    E = to_dev(e)
+    assert np.array_equal(to_host(plan.mul(E, E)), oracle.mul(e, e, qs))
+
+
+def test_frobenius_map(tf):
+    from oracle import ckks
+    n = 1 << 12
+    qs = PRIMES31[:2]
+    plan = tf.NttPlan(12, qs)
+    x = inputs.uniform_residues(4, qs, (2, n))
+    for r in (1, 3, 100):
+        k = ckks.galois_element(r, n)
+        want = oracle.ntt_fwd(ckks.automorphism_coeff(oracle.ntt_inv(x, qs, plan.psi), k, qs), qs, plan.psi)
+        assert np.array_equal(to_host(plan.frobenius(to_dev(x), k)), want)
+
+
+def test_empty_batch_and_errors(tf):
+    n = 1 << 16
+    qs = PRIMES31[:2]
+    plan = tf.NttPlan(16, qs)
+    empty = torch.empty((2, 0, n), dtype=torch.int32, device="cuda")
+    plan.fwd(empty, out=torch.empty_like(empty))
+    x = to_dev(inputs.uniform_residues(5, qs, (1, n)))
+    small_ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(tf.TfheError) as ei:
+        plan.fwd(x, ws=small_ws)
+    assert ei.value.status == tf.TFHE_EINVAL
+    with pytest.raises(tf.TfheError) as ei:
+        plan.fwd(x, limb_begin=1)       # limbs [1, 3) exceed the plan
+    assert ei.value.status == tf.TFHE_EINVAL
+
+
+def test_deterministic(tf):
+    n = 1 << 16
+    qs = PRIMES31[:2]
+    plan = tf.NttPlan(16, qs)
+    x = to_dev(inputs.uniform_residues(6, qs, (4, n)))
+    for algo in ("mfma", "butterfly"):
+        a = plan.fwd(x, algo=algo)
+        b = plan.fwd(x, algo=algo)
+        assert torch.equal(a, b)
+
+
+@pytest.mark.slow
+def test_full_size_44x128_sampled(tf):
+    """Config 2/3 shape (N=2^16, 44 limbs, 128 polynomials) in the launch
+    configuration the benchmark times: MFMA == butterfly everywhere, round
+    trip everywhere, and sampled (limb, poly) units equal the oracle."""
+    n = 1 << 16
+    qs = oracle.ntt_primes(44, 31, 1 << 17)
+    plan = tf.NttPlan(16, qs)
+    x_host = inputs.uniform_residues(0, qs, (128, n))
+    x = to_dev(x_host)
+    ws = plan.workspace(44, 128, "mfma")
+    f_m = plan.fwd(x, algo="mfma", ws=ws)
+    f_b = plan.fwd(x, algo="butterfly", ws=ws)
+    assert torch.equal(f_m, f_b)
+    del f_b
+    back = plan.inv(f_m, algo="mfma", ws=ws)
+    assert torch.equal(back, x)
+    rng = np.random.default_rng(1)
+    got = to_host(f_m)
+    for _ in range(12):
+        l, b = int(rng.integers(44)), int(rng.integers(128))
+        ref = oracle.ntt_fwd(x_host[l, b], [qs[l]], [plan.psi[l]])
+        assert np.array_equal(got[l, b], ref), (l, b)
