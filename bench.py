@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Benchmark of the NTT / HMULT hot path on one MI355X.
+
+One step = forward NTT then inverse NTT of a batch of N = 2^16 polynomials:
+44 limbs (31-bit primes, q = 1 mod 2^17) x 128 polynomials, uniform residues,
+computed with the four-step INT8-MFMA transform.  `value` is that transform's
+throughput in KOPS (10^3 limb-transforms per second; one limb-transform is
+one N-point NTT or INTT over one prime).  Measured beside it on the same data:
+the radix-2 butterfly transform, the batched HMULT (N=2^16, L=24, K=8,
+dnum=3, 64 ciphertext pairs), and the plain CPU oracle on a bounded sample.
+
+Prints one JSON line.  Inputs are resident in HBM before timing starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+LOG_N, LIMBS, BATCH = 16, 44, 128
+HM_L, HM_K, HM_DNUM, HM_BATCH = 24, 8, 3, 64
+METRIC = "NTT KOPS & HMULT ops/s at N=2^16, MFMA vs butterfly; p99 request latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(qs, psis, budget_s=12.0):
+    """The oracle's radix-2 NTT+INTT on a bounded sample of the same
+    workload (whole limb-polynomials of N = 2^16), all host cores."""
+    import oracle
+    from paper_2212_14191_amd import inputs
+    n = 1 << LOG_N
+    probe_units = 8
+    x = inputs.uniform_residues(0, qs[:probe_units], (1, n))
+    t0 = time.perf_counter()
+    X, used = oracle.ntt(x, qs[:probe_units], psis[:probe_units])
+    oracle.ntt(X, qs[:probe_units], psis[:probe_units], inverse=True)
+    dt = time.perf_counter() - t0
+    per_unit = dt / probe_units
+    units = int(max(probe_units, min(LIMBS * BATCH, budget_s / max(per_unit, 1e-6))))
+    limbs = min(LIMBS, units)
+    batch = max(1, units // limbs)
+    x = inputs.uniform_residues(0, qs[:limbs], (batch, n))
+    t0 = time.perf_counter()
+    X, used = oracle.ntt(x, qs[:limbs], psis[:limbs])
+    back, _ = oracle.ntt(X, qs[:limbs], psis[:limbs], inverse=True)
+    dt = time.perf_counter() - t0
+    assert np.array_equal(back, x)
+    transforms = 2 * limbs * batch
+    return {"value": transforms / dt / 1e3, "unit": "KOPS (10^3 limb-transforms/s)", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"{limbs} limbs x {batch} polys of N=2^16, forward+inverse radix-2 "
+                      f"({transforms} limb-transforms, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--hmult-steps", type=int, default=5)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-hmult", action="store_true")
+    ap.add_argument("--only", choices=["mfma", "butterfly"], default=None,
+                    help="time one transform only (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the NTT/HMULT "
+              "path shards by ciphertext with no collective, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2212_14191_amd import inputs, tfhe
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sync = torch.cuda.synchronize
+    n = 1 << LOG_N
+
+    qs = tfhe.tfhe_find_primes(31, 1 << 17, LIMBS)
+    plan = tfhe.NttPlan(LOG_N, qs)
+    log(f"generating {LIMBS}x{BATCH}x{n} uniform residues")
+    x_host = inputs.uniform_residues(0, qs, (BATCH, n))
+    x = torch.from_numpy(x_host.view(np.int32)).cuda()
+    del x_host
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    ws = plan.workspace(LIMBS, BATCH, "mfma")
+    units = LIMBS * BATCH
+
+    results = {}
+    for algo in (["mfma", "butterfly"] if args.only is None else [args.only]):
+        def step(algo=algo):
+            plan.fwd(x, out=y, algo=algo, ws=ws)
+            plan.inv(y, out=z, algo=algo, ws=ws)
+        for _ in range(args.warmup):
+            step()
+        sync()
+        assert torch.equal(z, x), f"{algo}: INTT(NTT(x)) != x"
+        steps = args.steps if algo == "mfma" else max(3, args.steps // 2)
+        tfhe.tfhe_timing_enable(True)
+        dt = timed(step, steps, sync)
+        kern = {}
+        for name in (("ntt_mfma_pass1", "ntt_mfma_pass2") if algo == "mfma" else ("ntt_bf_cols", "ntt_bf_rows")):
+            cnt, ms = tfhe.tfhe_timing_read(name)
+            kern[name] = {"launches": cnt, "avg_ms": ms / max(cnt, 1)}
+        tfhe.tfhe_timing_enable(False)
+        # untimed check of forward output: both algorithms must agree bit for bit
+        results[algo] = {"kops": 2 * units * steps / dt / 1e3, "ms_per_step": 1e3 * dt / steps,
+                         "steps": steps, "kernels": kern}
+        log(algo, json.dumps(results[algo]))
+    if args.only is None:
+        ym = torch.empty_like(x)
+        plan.fwd(x, out=ym, algo="mfma", ws=ws)
+        plan.fwd(x, out=y, algo="butterfly", ws=ws)
+        sync()
+        assert torch.equal(ym, y), "MFMA and butterfly forward outputs differ"
+        del ym
+    del y, z, ws
+
+    hmult = None
+    if not args.skip_hmult and args.only is None:
+        from paper_2212_14191_amd.scheme import Scheme
+        ctx = tfhe.CkksContext(LOG_N, HM_L, HM_K, HM_DNUM)
+        sch = Scheme(ctx)
+        s = inputs.ternary_secret(1, n, 192)
+        a = inputs.uniform_residues(1, ctx.moduli, (HM_DNUM, n), stream=1).transpose(1, 0, 2)
+        e = inputs.gaussian_error(2, (HM_DNUM, n), stream=1)
+        evk = sch.relin_key(s, a, e)
+        level = HM_L
+        qsl = ctx.moduli[:level]
+        cts = []
+        for k in range(2):
+            m = inputs.small_messages(0, (HM_BATCH, n), stream=k)
+            c1 = inputs.uniform_residues(10 + k, qsl, (HM_BATCH, n), stream=5)
+            ee = inputs.gaussian_error(2, (HM_BATCH, n), stream=20 + k)
+            cts.append(sch.encrypt(s, m, c1, ee, level))
+        out = torch.empty_like(cts[0])
+        hws = ctx.workspace(level, HM_BATCH)
+        hstep = lambda: ctx.hmult(cts[0], cts[1], evk, level, out=out, ws=hws)
+        for _ in range(2):
+            hstep()
+        tfhe.tfhe_timing_enable(True)
+        dt = timed(hstep, args.hmult_steps, sync)
+        kern = {}
+        for name in ("ntt_mfma_pass1", "ntt_mfma_pass2", "ckks_tensor", "ckks_modup", "ckks_inner",
+                     "ckks_moddown_conv", "ckks_moddown_final"):
+            cnt, ms = tfhe.tfhe_timing_read(name)
+            kern[name] = {"launches": cnt, "total_ms": ms}
+        tfhe.tfhe_timing_enable(False)
+        hmult = {"ops_per_s": HM_BATCH * args.hmult_steps / dt, "ms_per_batch": 1e3 * dt / args.hmult_steps,
+                 "batch": HM_BATCH, "level": level, "kernels": kern}
+        log("hmult", json.dumps(hmult))
+        del cts, out, hws, evk, ctx
+
+    cpu = None
+    if not args.skip_cpu and args.only is None:
+        cpu = cpu_baseline(qs, plan.psi)
+        log("cpu", json.dumps(cpu))
+
+    head = results.get("mfma") or results.get("butterfly")
+    kname, kstat = max(head["kernels"].items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
+    bytes_per_launch = 2 * units * n * 4  # one read and one write of every residue
+    achieved = bytes_per_launch / (kstat["avg_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(head["kops"], 1),
+        "unit": "KOPS (10^3 limb-NTT/INTT per s, N=2^16)",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "negacyclic NTT+INTT, N=2^16, 44 limbs x 128 polys, four-step INT8 MFMA"
+                   if "mfma" in results else "negacyclic NTT+INTT, N=2^16, 44 limbs x 128 polys, butterfly",
+                   "log_n": LOG_N, "limbs": LIMBS, "batch": BATCH, "primes": "31-bit, q = 1 mod 2^17"},
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": round(kstat["avg_ms"], 4)},
+        "cpu_baseline": cpu,
+    }
+    if "butterfly" in results and "mfma" in results:
+        line["butterfly_kops"] = round(results["butterfly"]["kops"], 1)
+        line["mfma_over_butterfly"] = round(results["mfma"]["kops"] / results["butterfly"]["kops"], 3)
+    line["kernels"] = {k: v for r in results.values() for k, v in r["kernels"].items()}
+    if hmult:
+        line["hmult_ops_per_s"] = round(hmult["ops_per_s"], 1)
+        line["hmult"] = hmult
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

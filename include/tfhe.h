@@ -135,6 +135,14 @@ tfhe_status tfhe_pointwise_mul_bcast(tfhe_ntt_plan plan, const uint32_t* a, cons
                                      uint32_t* c, uint32_t limb_begin, uint32_t limb_count,
                                      uint32_t batch, tfhe_stream_t stream);
 
+/* Residues of small signed integers: out[l][b][i] = in[b][i] mod q_{limb_begin+l}
+ * for every plan limb in the range (how secrets, errors and scaled messages
+ * enter the RNS representation, Sec. II-B).  in: device int32 [batch][N];
+ * out: device [limb_count][batch][N]. */
+tfhe_status tfhe_load_small(tfhe_ntt_plan plan, const int32_t* in, uint32_t* out,
+                            uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                            tfhe_stream_t stream);
+
 /* ------------------------------------------------------------ CKKS context */
 
 /* RNS-CKKS context (Sec. II-B) with hybrid key switching: L q-limbs, K
@@ -187,6 +195,20 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
 tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t* out,
                                uint32_t galois_elt, uint32_t limb_count, uint32_t batch,
                                tfhe_stream_t stream);
+
+/* ------------------------------------------------------------ measurement */
+
+/* Per-kernel timing.  While enabled, the library brackets every kernel it
+ * launches with a pair of HIP events recorded on that kernel's stream.
+ * tfhe_timing_enable(0 or 1) also discards earlier records. */
+tfhe_status tfhe_timing_enable(int enable);
+
+/* Launch count and summed event-measured duration (ms) of the kernel named
+ * `kernel` since timing was enabled; waits for the recorded events.  Names:
+ * ntt_mfma_pass1, ntt_mfma_pass2, ntt_bf_single, ntt_bf_cols, ntt_bf_rows,
+ * elementwise, ckks_tensor, ckks_modup, ckks_inner, ckks_moddown_conv,
+ * ckks_moddown_final, frobenius.  Unknown name: TFHE_EINVAL. */
+tfhe_status tfhe_timing_read(const char* kernel, uint64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libtfhe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["plan.cpp", "capi.cpp", "ckks.cpp", "ntt_butterfly.hip", "ntt_fourstep.hip",
-           "elementwise.hip", "ckks_kernels.hip"]
+           "elementwise.hip", "ckks_kernels.hip", "timing.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -257,6 +257,18 @@ tfhe_status tfhe_pointwise_mul_bcast(tfhe_ntt_plan plan, const uint32_t* a, cons
   return ew_dispatch(EW_MUL_BCAST, plan, a, b, c, limb_begin, limb_count, batch, stream);
 }
 
+tfhe_status tfhe_load_small(tfhe_ntt_plan plan, const int32_t* in, uint32_t* out,
+                            uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                            tfhe_stream_t stream) {
+  tfhe_status st = check_range(plan, limb_begin, limb_count, batch);
+  if (st != TFHE_OK) return st;
+  if (limb_count == 0 || batch == 0) return TFHE_OK;
+  if ((st = check_ptr(in, "in")) != TFHE_OK || (st = check_ptr(out, "out")) != TFHE_OK) return st;
+  return hip_check(load_small_launch(plan->d_mod + limb_begin, in, out, limb_count, batch, plan->n,
+                                     (hipStream_t)stream),
+                   "load_small launch");
+}
+
 tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t* out,
                                uint32_t galois_elt, uint32_t limb_count, uint32_t batch,
                                tfhe_stream_t stream) {

@@ -144,8 +144,8 @@ hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, ui
                          const ModConst* mods, uint32_t level, uint32_t batch, uint32_t n,
                          hipStream_t s) {
   const uint64_t per_limb = (uint64_t)batch * n, plane = per_limb * level;
-  hipLaunchKernelGGL(tensor_kernel, dim3(grid_for(plane)), dim3(kThreads), 0, s, a, b, out, d2,
-                     mods, plane, per_limb);
+  TFHE_TIMED(K_TENSOR, s, hipLaunchKernelGGL(tensor_kernel, dim3(grid_for(plane)), dim3(kThreads), 0, s, a, b, out, d2,
+                     mods, plane, per_limb));
   return hipGetLastError();
 }
 
@@ -153,8 +153,8 @@ hipError_t launch_modup(const uint32_t* x, uint32_t* up, const ModConst* mods, c
                         const uint2* conv, uint32_t d0, uint32_t nd, uint32_t level, uint32_t L,
                         uint32_t K, uint32_t batch, uint32_t n, hipStream_t s) {
   const uint64_t bn = (uint64_t)batch * n;
-  hipLaunchKernelGGL(modup_kernel, dim3(grid_for(bn)), dim3(kThreads), 0, s, x, up, mods, inv, conv,
-                     d0, nd, level, L, K, bn);
+  TFHE_TIMED(K_MODUP, s, hipLaunchKernelGGL(modup_kernel, dim3(grid_for(bn)), dim3(kThreads), 0, s, x, up, mods, inv, conv,
+                     d0, nd, level, L, K, bn));
   return hipGetLastError();
 }
 
@@ -163,8 +163,8 @@ hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const ui
                                 uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,
                                 uint32_t K, uint32_t batch, uint32_t log_n, hipStream_t s) {
   const uint64_t total = (uint64_t)(level + K) * batch << log_n;
-  hipLaunchKernelGGL(inner_product_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, d2, up, key,
-                     acc0, acc1, mods, alpha, ndigits, level, L, K, batch, log_n);
+  TFHE_TIMED(K_INNER, s, hipLaunchKernelGGL(inner_product_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, d2, up, key,
+                     acc0, acc1, mods, alpha, ndigits, level, L, K, batch, log_n));
   return hipGetLastError();
 }
 
@@ -172,8 +172,8 @@ hipError_t launch_moddown_conv(const uint32_t* a, uint32_t* conv, const ModConst
                                const uint2* invp, const uint2* cp, uint32_t level, uint32_t L,
                                uint32_t K, uint32_t batch, uint32_t n, hipStream_t s) {
   const uint64_t bn = (uint64_t)batch * n;
-  hipLaunchKernelGGL(moddown_conv_kernel, dim3(grid_for(bn)), dim3(kThreads), 0, s, a, conv, mods,
-                     invp, cp, level, L, K, bn);
+  TFHE_TIMED(K_MD_CONV, s, hipLaunchKernelGGL(moddown_conv_kernel, dim3(grid_for(bn)), dim3(kThreads), 0, s, a, conv, mods,
+                     invp, cp, level, L, K, bn));
   return hipGetLastError();
 }
 
@@ -182,11 +182,11 @@ hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint3
                                 uint32_t batch, uint32_t n, bool accumulate, hipStream_t s) {
   const uint64_t bn = (uint64_t)batch * n, total = bn * level;
   if (accumulate)
-    hipLaunchKernelGGL(moddown_final_kernel<true>, dim3(grid_for(total)), dim3(kThreads), 0, s, acc,
-                       conv, out, mods, pinv, total, bn);
+    TFHE_TIMED(K_MD_FINAL, s, hipLaunchKernelGGL(moddown_final_kernel<true>, dim3(grid_for(total)), dim3(kThreads), 0, s, acc,
+                       conv, out, mods, pinv, total, bn));
   else
-    hipLaunchKernelGGL(moddown_final_kernel<false>, dim3(grid_for(total)), dim3(kThreads), 0, s,
-                       acc, conv, out, mods, pinv, total, bn);
+    TFHE_TIMED(K_MD_FINAL, s, hipLaunchKernelGGL(moddown_final_kernel<false>, dim3(grid_for(total)), dim3(kThreads), 0, s,
+                       acc, conv, out, mods, pinv, total, bn));
   return hipGetLastError();
 }
 

@@ -46,6 +46,20 @@ frobenius_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, ui
   }
 }
 
+// out[l][b][i] = in[b][i] mod q_l for small signed integers in (-2^31, 2^31).
+__global__ void __launch_bounds__(kThreads)
+load_small_kernel(const ModConst* __restrict__ mods, const int32_t* __restrict__ in,
+                  uint32_t* __restrict__ out, uint64_t total, uint64_t per_limb) {
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t l = (uint32_t)(i / per_limb);
+    const uint32_t q = mods[l].q;
+    const int32_t x = in[i % per_limb];
+    uint32_t r = (uint32_t)(x < 0 ? -(int64_t)x : x) % q;
+    out[i] = (x < 0 && r) ? q - r : r;
+  }
+}
+
 uint32_t grid_for(uint64_t items) {
   uint64_t blocks = (items + kThreads - 1) / kThreads;
   return (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
@@ -63,26 +77,34 @@ hipError_t ew_launch(EwOp op, const ModConst* mods, const uint32_t* a, const uin
   uint4* C = (uint4*)c;
   switch (op) {
     case EW_MUL:
-      hipLaunchKernelGGL(ew_kernel<EW_MUL>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4);
+      TFHE_TIMED(K_EW, s, hipLaunchKernelGGL(ew_kernel<EW_MUL>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4));
       break;
     case EW_ADD:
-      hipLaunchKernelGGL(ew_kernel<EW_ADD>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4);
+      TFHE_TIMED(K_EW, s, hipLaunchKernelGGL(ew_kernel<EW_ADD>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4));
       break;
     case EW_SUB:
-      hipLaunchKernelGGL(ew_kernel<EW_SUB>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4);
+      TFHE_TIMED(K_EW, s, hipLaunchKernelGGL(ew_kernel<EW_SUB>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4));
       break;
     case EW_MUL_BCAST:
-      hipLaunchKernelGGL(ew_kernel<EW_MUL_BCAST>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4);
+      TFHE_TIMED(K_EW, s, hipLaunchKernelGGL(ew_kernel<EW_MUL_BCAST>, dim3(grid), dim3(kThreads), 0, s, mods, A, B, C, total4, per_limb4, n4));
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t load_small_launch(const ModConst* mods, const int32_t* in, uint32_t* out,
+                             uint32_t limb_count, uint32_t batch, uint32_t n, hipStream_t s) {
+  const uint64_t per_limb = (uint64_t)batch * n, total = per_limb * limb_count;
+  TFHE_TIMED(K_EW, s, hipLaunchKernelGGL(load_small_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s,
+                                         mods, in, out, total, per_limb));
   return hipGetLastError();
 }
 
 hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, uint32_t rows,
                             uint32_t log_n, hipStream_t s) {
   const uint64_t total = (uint64_t)rows << log_n;
-  hipLaunchKernelGGL(frobenius_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, in, out,
-                     galois, total, log_n);
+  TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, in, out,
+                     galois, total, log_n));
   return hipGetLastError();
 }
 

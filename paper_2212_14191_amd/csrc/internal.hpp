@@ -83,6 +83,25 @@ hipError_t ew_launch(EwOp op, const ModConst* mods, const uint32_t* a, const uin
 hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, uint32_t rows,
                             uint32_t log_n, hipStream_t s);
 
+// ---- per-kernel event timing (timing.cpp)
+enum KernelId {
+  K_FS_PASS1 = 0, K_FS_PASS2, K_BF_SINGLE, K_BF_COLS, K_BF_ROWS, K_EW, K_TENSOR, K_MODUP,
+  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB
+};
+bool timing_on();
+void* timing_begin(int id, hipStream_t s);
+void timing_end(void* token, hipStream_t s);
+// Launch with optional event bracketing.
+#define TFHE_TIMED(id, stream, ...)                  \
+  do {                                               \
+    void* tfhe_tok_ = ::tfhe::timing_begin(id, stream); \
+    __VA_ARGS__;                                     \
+    ::tfhe::timing_end(tfhe_tok_, stream);           \
+  } while (0)
+
+hipError_t load_small_launch(const ModConst* mods, const int32_t* in, uint32_t* out,
+                             uint32_t limb_count, uint32_t batch, uint32_t n, hipStream_t s);
+
 // ---- host-side number theory (plan.cpp)
 bool is_prime_u32(uint32_t q);
 uint32_t pow_mod(uint32_t b, uint64_t e, uint32_t q);

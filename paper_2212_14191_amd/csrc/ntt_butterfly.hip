@@ -218,15 +218,15 @@ hipError_t bf_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* ou
   const uint2* tw = p->d_bf_fwd + (size_t)limb_begin * p->n;
   const ModConst* mods = p->d_mod + limb_begin;
   if (p->log_n <= 12) {
-    hipLaunchKernelGGL(bf_single_fwd, dim3(polys), dim3(kThreads), p->n * sizeof(uint32_t), s, in,
-                       out, tw, mods, p->log_n, batch);
+    TFHE_TIMED(K_BF_SINGLE, s, hipLaunchKernelGGL(bf_single_fwd, dim3(polys), dim3(kThreads), p->n * sizeof(uint32_t), s, in,
+                       out, tw, mods, p->log_n, batch));
   } else {
     uint32_t* mid = (uint32_t*)ws;
     const uint32_t R = p->n / kRow;
-    hipLaunchKernelGGL(bf_cols<false>, poly_grid(kRow / kBlk, polys), dim3(kThreads), 0, s, in,
-                       mid, tw, p->d_ninv + limb_begin, mods, p->log_n, batch);
-    hipLaunchKernelGGL(bf_rows<false>, poly_grid(R / kBlk, polys), dim3(kThreads), 0, s, mid, out,
-                       tw, mods, p->log_n, batch);
+    TFHE_TIMED(K_BF_COLS, s, hipLaunchKernelGGL(bf_cols<false>, poly_grid(kRow / kBlk, polys), dim3(kThreads), 0, s, in,
+                       mid, tw, p->d_ninv + limb_begin, mods, p->log_n, batch));
+    TFHE_TIMED(K_BF_ROWS, s, hipLaunchKernelGGL(bf_rows<false>, poly_grid(R / kBlk, polys), dim3(kThreads), 0, s, mid, out,
+                       tw, mods, p->log_n, batch));
   }
   return hipGetLastError();
 }
@@ -237,15 +237,15 @@ hipError_t bf_inverse(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* ou
   const uint2* tw = p->d_bf_inv + (size_t)limb_begin * p->n;
   const ModConst* mods = p->d_mod + limb_begin;
   if (p->log_n <= 12) {
-    hipLaunchKernelGGL(bf_single_inv, dim3(polys), dim3(kThreads), p->n * sizeof(uint32_t), s, in,
-                       out, tw, p->d_ninv + limb_begin, mods, p->log_n, batch);
+    TFHE_TIMED(K_BF_SINGLE, s, hipLaunchKernelGGL(bf_single_inv, dim3(polys), dim3(kThreads), p->n * sizeof(uint32_t), s, in,
+                       out, tw, p->d_ninv + limb_begin, mods, p->log_n, batch));
   } else {
     uint32_t* mid = (uint32_t*)ws;
     const uint32_t R = p->n / kRow;
-    hipLaunchKernelGGL(bf_rows<true>, poly_grid(R / kBlk, polys), dim3(kThreads), 0, s, in, mid,
-                       tw, mods, p->log_n, batch);
-    hipLaunchKernelGGL(bf_cols<true>, poly_grid(kRow / kBlk, polys), dim3(kThreads), 0, s, mid,
-                       out, tw, p->d_ninv + limb_begin, mods, p->log_n, batch);
+    TFHE_TIMED(K_BF_ROWS, s, hipLaunchKernelGGL(bf_rows<true>, poly_grid(R / kBlk, polys), dim3(kThreads), 0, s, in, mid,
+                       tw, mods, p->log_n, batch));
+    TFHE_TIMED(K_BF_COLS, s, hipLaunchKernelGGL(bf_cols<true>, poly_grid(kRow / kBlk, polys), dim3(kThreads), 0, s, mid,
+                       out, tw, p->d_ninv + limb_begin, mods, p->log_n, batch));
   }
   return hipGetLastError();
 }

@@ -175,9 +175,12 @@ static hipError_t fs_run(const FourStepLimb* limbs, const uint32_t* in, uint32_t
                          uint32_t limb_count, uint32_t batch, hipStream_t s) {
   const uint32_t polys = limb_count * batch;
   dim3 grid(polys * (256 / kCols));
-  hipLaunchKernelGGL(fs_pass<true>, grid, dim3(kThreads), 0, s, in, (uint32_t*)ws, limbs, batch);
-  hipLaunchKernelGGL(fs_pass<false>, grid, dim3(kThreads), 0, s, (const uint32_t*)ws, out, limbs,
-                     batch);
+  TFHE_TIMED(K_FS_PASS1, s,
+             hipLaunchKernelGGL(fs_pass<true>, grid, dim3(kThreads), 0, s, in, (uint32_t*)ws, limbs,
+                                batch));
+  TFHE_TIMED(K_FS_PASS2, s,
+             hipLaunchKernelGGL(fs_pass<false>, grid, dim3(kThreads), 0, s, (const uint32_t*)ws, out,
+                                limbs, batch));
   return hipGetLastError();
 }
 

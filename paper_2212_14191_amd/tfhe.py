@@ -56,6 +56,9 @@ def load():
         "tfhe_pointwise_sub": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
         "tfhe_pointwise_mul_bcast": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
         "tfhe_frobenius_map": ([vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_load_small": ([vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_timing_enable": ([i32], i32),
+        "tfhe_timing_read": ([ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], i32),
         "tfhe_ckks_ctx_create": ([ctypes.POINTER(vp), u32, u32, u32, u32, pu32, pu32, i32], i32),
         "tfhe_ckks_ctx_destroy": ([vp], i32),
         "tfhe_ckks_ctx_plan": ([vp, ctypes.POINTER(vp)], i32),
@@ -215,6 +218,21 @@ class NttPlan:
         """a [limbs][batch][N] times b [limbs][N] broadcast over the batch."""
         return self._ew("tfhe_pointwise_mul_bcast", a, b, out, limb_begin, stream)
 
+    def load_small(self, x, limb_begin=0, limb_count=None, out=None, stream=None):
+        """Residues of small signed ints x (int32 [batch][N]) on limbs
+        [limb_begin, limb_begin + limb_count): int32 [limb_count][batch][N]."""
+        import torch
+        if x.dtype != torch.int32 or not x.is_cuda or x.dim() != 2 or x.shape[1] != self.n:
+            raise ValueError("x: expected an int32 CUDA tensor [batch][N]")
+        x = x.contiguous()
+        if limb_count is None:
+            limb_count = self.n_limbs - limb_begin
+        if out is None:
+            out = torch.empty((limb_count, x.shape[0], self.n), dtype=torch.int32, device=x.device)
+        _call("tfhe_load_small", self.handle, _ptr(x), _ptr(out), limb_begin, limb_count, x.shape[0],
+              _stream(stream))
+        return out
+
     def frobenius(self, x, galois, out=None, stream=None):
         limbs, batch, n = x.shape
         _check_residues(x, "x")
@@ -222,6 +240,17 @@ class NttPlan:
             out = torch_empty_like(x)
         _call("tfhe_frobenius_map", self.handle, _ptr(x), _ptr(out), galois, limbs, batch, _stream(stream))
         return out
+
+
+def tfhe_timing_enable(enable=True):
+    _call("tfhe_timing_enable", 1 if enable else 0)
+
+
+def tfhe_timing_read(kernel):
+    """(launches, total_ms) of a kernel since timing was enabled."""
+    n, ms = ctypes.c_uint64(), ctypes.c_double()
+    _call("tfhe_timing_read", kernel.encode(), ctypes.byref(n), ctypes.byref(ms))
+    return n.value, ms.value
 
 
 def torch_empty_like(x):

@@ -105,3 +105,21 @@ def test_hmult_config4_full_size_sampled(tf):
         prod = ckks.negacyclic_int(m1[b], m2[b])
         d2 = 1 << 60
         assert np.array_equal(np.array([(int(v) + d2 // 2) // d2 for v in dec]), prod)
+
+
+def test_device_keygen_and_encryption_match_oracle(tf):
+    """The library-side key generation / encryption (paper_2212_14191_amd.scheme)
+    produce the oracle's keys and ciphertexts from the same random draws."""
+    from paper_2212_14191_amd.scheme import Scheme
+    n = 1 << 10
+    pr, s, evk, (a, e) = setup(n, 6, 2, 3)
+    ctx = tf.CkksContext(10, 6, 2, 3, moduli=pr.moduli)
+    sch = Scheme(ctx)
+    assert np.array_equal(to_host(sch.relin_key(s, a, e)), evk)
+    k = ckks.galois_element(3, n)
+    assert np.array_equal(to_host(sch.rotation_key(s, k, a, e)), ckks.rotation_key(pr, s, k, a, e))
+    m = inputs.small_messages(0, (3, n))
+    c1 = inputs.uniform_residues(4, pr.mods(range(5)), (3, n), stream=5)
+    ee = inputs.gaussian_error(2, (3, n), stream=9)
+    got = to_host(sch.encrypt(s, m, c1, ee, 5))
+    assert np.array_equal(got, ckks.encrypt(pr, s, m, c1, ee, 5))
