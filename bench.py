@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--skip-hmult", action="store_true")
     ap.add_argument("--only", choices=["mfma", "butterfly"], default=None,
                     help="time one transform only (for profiling runs)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one plain device copy of the input batch (a known-size "
+                         "kernel for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the NTT/HMULT "
@@ -105,6 +108,9 @@ def main():
     ws = plan.workspace(LIMBS, BATCH, "mfma")
     units = LIMBS * BATCH
 
+    if args.copy_calib:
+        y.copy_(x)
+        sync()
     results = {}
     for algo in (["mfma", "butterfly"] if args.only is None else [args.only]):
         def step(algo=algo):

@@ -118,6 +118,33 @@ tfhe_status tfhe_ntt_inv(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t*
                          uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
                          size_t ws_bytes, tfhe_stream_t stream);
 
+/* Operation-level batching (Sec. III-D): one fused launch per kernel pass
+ * covers every descriptor, whatever its N, modulus set, limb range, batch
+ * and direction.  Descriptors are host structs; they are copied into the
+ * launch, so the array may be reused after the call returns. */
+typedef struct {
+  tfhe_ntt_plan plan;
+  const uint32_t* in;   /* device [limb_count][batch][N] of the plan's N */
+  uint32_t* out;        /* device, same shape; == in allowed */
+  uint32_t limb_begin;  /* first plan limb */
+  uint32_t limb_count;
+  uint32_t batch;
+  int32_t inverse;      /* 0 forward (Eq. 4), 1 inverse */
+} tfhe_ntt_desc;
+
+/* Workspace bytes tfhe_ntt_batch needs for these descriptors and algorithm
+ * (AUTO: the four-step MFMA transform where every plan supports it, else
+ * the butterfly). */
+tfhe_status tfhe_ntt_batch_workspace_size(const tfhe_ntt_desc* descs, uint32_t count,
+                                          tfhe_ntt_algo algo, size_t* bytes);
+
+/* Run every descriptor's transform.  Descriptors must not overlap each other
+ * except in == out within one descriptor.  ws: >= the size above, 256-byte
+ * aligned.  Errors as for tfhe_ntt_fwd; TFHE_EUNSUPPORTED if algo is MFMA
+ * and some plan lacks it. */
+tfhe_status tfhe_ntt_batch(const tfhe_ntt_desc* descs, uint32_t count, tfhe_ntt_algo algo,
+                           void* ws, size_t ws_bytes, tfhe_stream_t stream);
+
 /* Element-wise kernels of Sec. III-A over the same layout (a, b, c device,
  * [limb_count][batch][N]; c may alias a or b):
  *   Hada-Mult c = a o b mod q;  Ele-Add c = a + b mod q;  Ele-Sub c = a - b mod q. */

@@ -5,6 +5,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -217,6 +218,66 @@ tfhe_status tfhe_ntt_inv(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t*
                          uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
                          size_t ws_bytes, tfhe_stream_t stream) {
   return ntt_dispatch(true, plan, algo, in, out, limb_begin, limb_count, batch, ws, ws_bytes, stream);
+}
+
+// Resolve a batch's algorithm: MFMA only if every plan has it.
+static tfhe_status batch_algo(const tfhe_ntt_desc* d, uint32_t count, tfhe_ntt_algo algo, bool* mfma) {
+  bool all = true;
+  for (uint32_t k = 0; k < count; ++k) {
+    if (!d[k].plan) return fail(TFHE_EINVAL, "ntt_batch: null plan in a descriptor");
+    all = all && d[k].plan->has_mfma;
+  }
+  if (algo == TFHE_NTT_FOURSTEP_MFMA && !all)
+    return fail(TFHE_EUNSUPPORTED, "ntt_batch: a plan lacks the MFMA four-step transform");
+  if (algo != TFHE_NTT_AUTO && algo != TFHE_NTT_BUTTERFLY && algo != TFHE_NTT_FOURSTEP_MFMA)
+    return fail(TFHE_EINVAL, "ntt_batch: unknown algorithm");
+  *mfma = algo == TFHE_NTT_FOURSTEP_MFMA || (algo == TFHE_NTT_AUTO && all && count > 0 &&
+                                             d[0].plan->algo == TFHE_NTT_FOURSTEP_MFMA);
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_batch_workspace_size(const tfhe_ntt_desc* descs, uint32_t count,
+                                          tfhe_ntt_algo algo, size_t* bytes) {
+  if (!bytes || (count && !descs)) return fail(TFHE_EINVAL, "ntt_batch_workspace_size: null argument");
+  bool mfma = false;
+  tfhe_status st = batch_algo(descs, count, algo, &mfma);
+  if (st != TFHE_OK) return st;
+  size_t total = 0;
+  for (uint32_t k = 0; k < count; ++k) {
+    NttUnit u{descs[k].plan, descs[k].inverse != 0, descs[k].in, descs[k].out, descs[k].limb_begin,
+              descs[k].limb_count, descs[k].batch};
+    total += (unit_ws_bytes(u, mfma) + 255) & ~(size_t)255;
+  }
+  *bytes = total;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_ntt_batch(const tfhe_ntt_desc* descs, uint32_t count, tfhe_ntt_algo algo, void* ws,
+                           size_t ws_bytes, tfhe_stream_t stream) {
+  if (count == 0) return TFHE_OK;
+  if (!descs) return fail(TFHE_EINVAL, "ntt_batch: null descriptors");
+  bool mfma = false;
+  tfhe_status st = batch_algo(descs, count, algo, &mfma);
+  if (st != TFHE_OK) return st;
+  std::vector<NttUnit> units;
+  size_t need = 0;
+  for (uint32_t k = 0; k < count; ++k) {
+    const tfhe_ntt_desc& d = descs[k];
+    if ((st = check_range(d.plan, d.limb_begin, d.limb_count, d.batch)) != TFHE_OK) return st;
+    if (d.limb_count == 0 || d.batch == 0) continue;
+    if ((st = check_ptr(d.in, "in")) != TFHE_OK || (st = check_ptr(d.out, "out")) != TFHE_OK) return st;
+    units.push_back(NttUnit{d.plan, d.inverse != 0, d.in, d.out, d.limb_begin, d.limb_count, d.batch});
+    need += (unit_ws_bytes(units.back(), mfma) + 255) & ~(size_t)255;
+  }
+  if (need) {
+    if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "ntt_batch: workspace missing or too small");
+    if (!aligned(ws, 256)) return fail(TFHE_EINVAL, "ntt_batch: workspace not 256-byte aligned");
+  }
+  if (units.empty()) return TFHE_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = mfma ? fs_run_units(units.data(), (uint32_t)units.size(), ws, s)
+                      : bf_run_units(units.data(), (uint32_t)units.size(), ws, s);
+  return hip_check(e, "ntt_batch launch");
 }
 
 static tfhe_status ew_dispatch(EwOp op, tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,

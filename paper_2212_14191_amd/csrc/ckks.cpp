@@ -10,6 +10,7 @@
 
 #include <new>
 #include <set>
+#include <vector>
 
 #include "ckks_internal.hpp"
 
@@ -22,37 +23,39 @@ static uint32_t mulm(uint32_t a, uint32_t b, uint32_t q) { return (uint32_t)((ui
 
 static uint2 with_companion(uint32_t w, uint32_t q) { return make_uint2(w, shoup_companion(w, q)); }
 
-// Forward/inverse NTT of `count` plan limbs starting at limb_begin, with the
-// plan's algorithm.
-static hipError_t ntt_call(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* in, uint32_t* out,
-                           uint32_t limb_begin, uint32_t count, uint32_t batch, void* ws,
-                           hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  if (p->algo == TFHE_NTT_FOURSTEP_MFMA)
-    return inverse ? fs_inverse(p, in, out, ws, limb_begin, count, batch, s)
-                   : fs_forward(p, in, out, ws, limb_begin, count, batch, s);
-  return inverse ? bf_inverse(p, in, out, ws, limb_begin, count, batch, s)
-                 : bf_forward(p, in, out, ws, limb_begin, count, batch, s);
-}
-
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Workspace regions, in limb-planes of batch*N words.
+// Fused NTT launches over several units with the plan's algorithm.
+static hipError_t ntt_units(const tfhe_ntt_plan_s* p, const std::vector<NttUnit>& u, void* ws,
+                            hipStream_t s) {
+  if (u.empty()) return hipSuccess;
+  return p->algo == TFHE_NTT_FOURSTEP_MFMA ? fs_run_units(u.data(), (uint32_t)u.size(), ws, s)
+                                           : bf_run_units(u.data(), (uint32_t)u.size(), ws, s);
+}
+
+// Workspace regions (byte offsets).
 struct KsLayout {
-  size_t d2, x, up, acc, ntt, total;
+  size_t d2, x, up, acc, tp, conv, ntt, total;
 };
 
 static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t batch) {
   const size_t plane = (size_t)batch * c->n * sizeof(uint32_t);
   const uint32_t digits = (level + c->alpha - 1) / c->alpha;
   const uint32_t ext = level + c->K;
+  // the largest fused NTT: every digit's converted limbs
+  const size_t ntt_planes = std::max<size_t>(std::max<size_t>(level, 2 * c->K),
+                                             (size_t)digits * ext - level);
+  // per-unit 256-byte rounding of the workspace slices
+  const size_t ntt_bytes = plane * ntt_planes + 256 * (3 * digits + 2);
   KsLayout l;
   size_t off = 0;
   l.d2 = off; off += align256(plane * level);
   l.x = off; off += align256(plane * level);
   l.up = off; off += align256(plane * (size_t)digits * ext);
   l.acc = off; off += align256(plane * 2 * ext);
-  l.ntt = off; off += align256(plane * std::max(level, c->K));
+  l.tp = off; off += align256(plane * 2 * c->K);
+  l.conv = off; off += align256(plane * 2 * level);
+  l.ntt = off; off += align256(ntt_bytes);
   l.total = off;
   return l;
 }
@@ -70,10 +73,15 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   uint32_t* x = (uint32_t*)(ws + lay.x);
   uint32_t* up = (uint32_t*)(ws + lay.up);
   uint32_t* acc = (uint32_t*)(ws + lay.acc);
+  uint32_t* tp = (uint32_t*)(ws + lay.tp);
+  uint32_t* conv = (uint32_t*)(ws + lay.conv);
   void* nws = ws + lay.ntt;
   hipError_t e;
-  // INTT of the input, then Dcomp + ModUp + NTT per digit
-  if ((e = ntt_call(p, true, d, x, 0, level, batch, nws, s)) != hipSuccess) return e;
+  // INTT of the input (coefficient domain for the basis conversion)
+  if ((e = ntt_units(p, {NttUnit{p, true, d, x, 0, level, batch}}, nws, s)) != hipSuccess) return e;
+  // Dcomp + ModUp of every digit, then one fused NTT of all converted limbs:
+  // the q-limbs before and after the digit, and the p-limbs
+  std::vector<NttUnit> fwd;
   for (uint32_t j = 0; j < digits; ++j) {
     const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
     const uint32_t key_idx = d0 + nd - 1;
@@ -82,34 +90,38 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
                           c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
                           c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
-    // NTT the converted limbs: q-limbs before and after the digit, then the p-limbs
-    if ((e = ntt_call(p, false, upj, upj, 0, d0, batch, nws, s)) != hipSuccess) return e;
     uint32_t* after = upj + (uint64_t)(d0 + nd) * plane;
-    if ((e = ntt_call(p, false, after, after, d0 + nd, level - d0 - nd, batch, nws, s)) != hipSuccess)
-      return e;
     uint32_t* pl = upj + (uint64_t)level * plane;
-    if ((e = ntt_call(p, false, pl, pl, c->L, c->K, batch, nws, s)) != hipSuccess) return e;
+    if (d0) fwd.push_back(NttUnit{p, false, upj, upj, 0, d0, batch});
+    if (level > d0 + nd) fwd.push_back(NttUnit{p, false, after, after, d0 + nd, level - d0 - nd, batch});
+    fwd.push_back(NttUnit{p, false, pl, pl, c->L, c->K, batch});
   }
+  if ((e = ntt_units(p, fwd, nws, s)) != hipSuccess) return e;
   uint32_t* a0 = acc;
   uint32_t* a1 = acc + (uint64_t)ext * plane;
   if ((e = launch_inner_product(d, up, key, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
                                 batch, c->log_n, s)) != hipSuccess)
     return e;
-  // ModDown of both accumulators (the ModUp region is free again)
-  uint32_t* tp = up;
-  uint32_t* conv = x;
-  for (int comp = 0; comp < 2; ++comp) {
-    uint32_t* a = comp ? a1 : a0;
-    if ((e = ntt_call(p, true, a + (uint64_t)level * plane, tp, c->L, c->K, batch, nws, s)) != hipSuccess)
+  // ModDown of both accumulators, their transforms fused
+  uint32_t* tp1 = tp + (uint64_t)c->K * plane;
+  uint32_t* conv1 = conv + (uint64_t)level * plane;
+  if ((e = ntt_units(p, {NttUnit{p, true, a0 + (uint64_t)level * plane, tp, c->L, c->K, batch},
+                         NttUnit{p, true, a1 + (uint64_t)level * plane, tp1, c->L, c->K, batch}},
+                     nws, s)) != hipSuccess)
+    return e;
+  for (int comp = 0; comp < 2; ++comp)
+    if ((e = launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
+                                 c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
-    if ((e = launch_moddown_conv(tp, conv, p->d_mod, c->d_dn_invp, c->d_dn_conv, level, c->L, c->K,
-                                 batch, c->n, s)) != hipSuccess)
+  if ((e = ntt_units(p, {NttUnit{p, false, conv, conv, 0, level, batch},
+                         NttUnit{p, false, conv1, conv1, 0, level, batch}},
+                     nws, s)) != hipSuccess)
+    return e;
+  for (int comp = 0; comp < 2; ++comp)
+    if ((e = launch_moddown_final(comp ? a1 : a0, comp ? conv1 : conv, comp ? out1 : out0, p->d_mod,
+                                  c->d_dn_pinv, level, batch, c->n, comp ? acc1_add : acc0_add, s)) !=
+        hipSuccess)
       return e;
-    if ((e = ntt_call(p, false, conv, conv, 0, level, batch, nws, s)) != hipSuccess) return e;
-    if ((e = launch_moddown_final(a, conv, comp ? out1 : out0, p->d_mod, c->d_dn_pinv, level, batch,
-                                  c->n, comp ? acc1_add : acc0_add, s)) != hipSuccess)
-      return e;
-  }
   return hipSuccess;
 }
 

@@ -21,21 +21,19 @@ tfhe_status hip_check(hipError_t e, const char* what);
 // exactly as the kernels load them into MFMA operand registers.
 //   opA[j][lane][4]   level-A twiddle operand, digit plane j (4 dwords/lane)
 //   opB[j][lane][4]   level-B twiddle operand
-//   twist[lane][r]    inter-level twist: uint4 {w, w', 2^16 w, (2^16 w)'}
+//   twist[lane][r]    inter-level twist T, stored as {T 2^32 mod q, companion}
 struct PassTables {
   uint32_t opA[4][64][4];
   uint32_t opB[4][64][4];
-  uint4 twist[64][4];
+  uint2 twist[64][4];
 };
 
 // Device-side description of one limb for the four-step kernels.
 struct FourStepLimb {
   const PassTables* pass1;  // column pass
   const PassTables* pass2;  // row pass
-  const uint4* post1;       // [256 columns][64 lanes][4]: post-twist of pass 1
-  uint32_t q;
-  uint32_t c16, c16p;       // 2^16 mod q and its Shoup companion
-  uint32_t pad;
+  const uint2* post1;       // [256 columns][64 lanes][4]: post-twist of pass 1 (x 2^32)
+  uint32_t q, qneg;         // modulus and -q^{-1} mod 2^32
 };
 
 struct tfhe_plan_impl {
@@ -43,6 +41,8 @@ struct tfhe_plan_impl {
   tfhe_ntt_algo algo = TFHE_NTT_BUTTERFLY;  // what AUTO resolves to
   bool has_mfma = false;
   int device = 0;
+  uint32_t num_cus = 256;         // compute units of the device
+  uint32_t fs_wg_per_cu = 0;      // persistent four-step workgroups per CU (0: occupancy)
   std::vector<uint32_t> q, psi;
   // device arrays
   ModConst* d_mod = nullptr;      // [n_limbs]
@@ -60,6 +60,23 @@ struct tfhe_plan_impl {
 struct tfhe_ntt_plan_s : tfhe::tfhe_plan_impl {};
 
 namespace tfhe {
+
+// ---- operation-level batching: one fused launch over many transforms
+// A transform unit: `batch` polynomials of limbs [limb_begin, +limb_count) of
+// a plan, forward or inverse, in -> out (in == out allowed), with its own
+// slice of the workspace.
+struct NttUnit {
+  const tfhe_ntt_plan_s* plan;
+  bool inverse;
+  const uint32_t* in;
+  uint32_t* out;
+  uint32_t limb_begin, limb_count, batch;
+};
+// Runs every unit with the four-step algorithm (all units need has_mfma) or
+// the butterfly; ws must hold the sum of the units' workspaces.
+hipError_t fs_run_units(const NttUnit* u, uint32_t count, void* ws, hipStream_t s);
+hipError_t bf_run_units(const NttUnit* u, uint32_t count, void* ws, hipStream_t s);
+size_t unit_ws_bytes(const NttUnit& u, bool mfma);
 
 // ---- butterfly launchers (ntt_butterfly.hip)
 size_t bf_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_t batch);

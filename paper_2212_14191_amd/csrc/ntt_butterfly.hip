@@ -13,6 +13,11 @@
 // N  > 2^12: two passes over an R x 256 view (R = N/256): the stages with
 // butterfly stride >= 256 act within columns (pass A), the rest within rows
 // of 256 (pass B); the intermediate goes through the caller's workspace.
+//
+// Every kernel walks a descriptor table, so one launch can cover transforms
+// of different N, moduli and direction (operation-level batching, Sec. III-D).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace tfhe {
@@ -21,6 +26,26 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kRow = 256;   // row length of the two-pass view
 constexpr int kBlk = 16;    // columns (pass A) or rows (pass B) per workgroup
+constexpr int kMaxUnits = 32;
+
+struct BfUnit {
+  const uint32_t* in;
+  uint32_t* out;
+  const uint2* tw;       // twiddles of the unit's first limb, [limb][N]
+  const uint2* ninv;     // [limb]
+  const ModConst* mods;  // [limb]
+  uint32_t log_n, batch, inverse, item_begin;
+};
+struct BfTable {
+  uint32_t count, total;
+  BfUnit u[kMaxUnits];
+};
+
+__device__ __forceinline__ uint32_t find_unit(const BfTable& t, uint32_t i) {
+  uint32_t k = 0;
+  while (k + 1 < t.count && i >= t.u[k + 1].item_begin) ++k;
+  return k;
+}
 
 __device__ __forceinline__ uint32_t brev(uint32_t x, uint32_t bits) {
   return __builtin_bitreverse32(x) >> (32 - bits);
@@ -41,75 +66,68 @@ __device__ __forceinline__ void gs_bfly(uint32_t* lds, uint32_t j, uint32_t t, u
 }
 
 // ---------------------------------------------------------- single pass
-__global__ void __launch_bounds__(kThreads)
-bf_single_fwd(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2* __restrict__ tw,
-              const ModConst* __restrict__ mods, uint32_t log_n, uint32_t batch) {
+// item = polynomial of the unit
+__global__ void __launch_bounds__(kThreads) bf_single(const BfTable tab) {
   extern __shared__ uint32_t lds[];
-  const uint32_t n = 1u << log_n;
-  const uint32_t poly = blockIdx.x, limb = poly / batch;
-  const uint32_t q = mods[limb].q;
-  const uint2* w = tw + (size_t)limb * n;
-  const uint32_t* src = in + (size_t)poly * n;
-  for (uint32_t i = threadIdx.x; i < n; i += kThreads) lds[i] = src[i];
-  __syncthreads();
-  for (uint32_t m = 1, t = n >> 1; m < n; m <<= 1, t >>= 1) {
-    for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) {
-      uint32_t i = b / t, j = 2 * i * t + (b % t);
-      ct_bfly(lds, j, t, w[m + i], q);
-    }
+  const uint32_t k = find_unit(tab, blockIdx.x);
+  const BfUnit U = tab.u[k];
+  const uint32_t poly = blockIdx.x - U.item_begin, limb = poly / U.batch;
+  const uint32_t log_n = U.log_n, n = 1u << log_n;
+  const uint32_t q = U.mods[limb].q;
+  const uint2* w = U.tw + (size_t)limb * n;
+  const uint32_t* src = U.in + (size_t)poly * n;
+  uint32_t* dst = U.out + (size_t)poly * n;
+  if (!U.inverse) {
+    for (uint32_t i = threadIdx.x; i < n; i += kThreads) lds[i] = src[i];
     __syncthreads();
-  }
-  uint32_t* dst = out + (size_t)poly * n;
-  for (uint32_t k = threadIdx.x; k < n; k += kThreads) dst[k] = lds[brev(k, log_n)];
-}
-
-__global__ void __launch_bounds__(kThreads)
-bf_single_inv(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2* __restrict__ tw,
-              const uint2* __restrict__ ninv, const ModConst* __restrict__ mods, uint32_t log_n,
-              uint32_t batch) {
-  extern __shared__ uint32_t lds[];
-  const uint32_t n = 1u << log_n;
-  const uint32_t poly = blockIdx.x, limb = poly / batch;
-  const uint32_t q = mods[limb].q;
-  const uint2* w = tw + (size_t)limb * n;
-  const uint32_t* src = in + (size_t)poly * n;
-  for (uint32_t k = threadIdx.x; k < n; k += kThreads) lds[brev(k, log_n)] = src[k];
-  __syncthreads();
-  for (uint32_t h = n >> 1, t = 1; h >= 1; h >>= 1, t <<= 1) {
-    for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) {
-      uint32_t i = b / t, j = 2 * i * t + (b % t);
-      gs_bfly(lds, j, t, w[h + i], q);
+    for (uint32_t m = 1, t = n >> 1; m < n; m <<= 1, t >>= 1) {
+      for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) {
+        uint32_t i = b / t, j = 2 * i * t + (b % t);
+        ct_bfly(lds, j, t, w[m + i], q);
+      }
+      __syncthreads();
     }
+    for (uint32_t kk = threadIdx.x; kk < n; kk += kThreads) dst[kk] = lds[brev(kk, log_n)];
+  } else {
+    for (uint32_t kk = threadIdx.x; kk < n; kk += kThreads) lds[brev(kk, log_n)] = src[kk];
     __syncthreads();
+    for (uint32_t h = n >> 1, t = 1; h >= 1; h >>= 1, t <<= 1) {
+      for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) {
+        uint32_t i = b / t, j = 2 * i * t + (b % t);
+        gs_bfly(lds, j, t, w[h + i], q);
+      }
+      __syncthreads();
+    }
+    const uint2 ni = U.ninv[limb];
+    for (uint32_t kk = threadIdx.x; kk < n; kk += kThreads) dst[kk] = mul_shoup(lds[kk], ni.x, ni.y, q);
   }
-  const uint2 ni = ninv[limb];
-  uint32_t* dst = out + (size_t)poly * n;
-  for (uint32_t k = threadIdx.x; k < n; k += kThreads) dst[k] = mul_shoup(lds[k], ni.x, ni.y, q);
 }
 
 // ------------------------------------------------------------ two passes
-// Column pass: a workgroup owns kBlk consecutive columns of one polynomial,
-// tile lds[r][c] (R x kBlk).  Forward runs stages m = 1 .. R/2; inverse runs
+// Column pass: item = (polynomial, block of kBlk consecutive columns), tile
+// lds[r][c] (R x kBlk).  Forward runs stages m = 1 .. R/2; inverse runs
 // h = R/2 .. 1 then scales by N^{-1}.
-template <bool kInverse>
-__global__ void __launch_bounds__(kThreads)
-bf_cols(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2* __restrict__ tw,
-        const uint2* __restrict__ ninv, const ModConst* __restrict__ mods, uint32_t log_n,
-        uint32_t batch) {
+__global__ void __launch_bounds__(kThreads) bf_cols(const BfTable tab) {
   __shared__ uint32_t lds[kRow * kBlk];
-  const uint32_t n = 1u << log_n, R = n / kRow;
-  const uint32_t cb = blockIdx.x % (kRow / kBlk), poly = blockIdx.x / (kRow / kBlk);
-  const uint32_t limb = poly / batch;
-  const uint32_t q = mods[limb].q;
-  const uint2* w = tw + (size_t)limb * n;
-  const uint32_t* src = in + (size_t)poly * n + cb * kBlk;
+  const uint32_t k = find_unit(tab, blockIdx.x);
+  const BfUnit U = tab.u[k];
+  const uint32_t local = blockIdx.x - U.item_begin;
+  const uint32_t n = 1u << U.log_n, R = n / kRow;
+  // column blocks 2b and 2b+1 share 128-byte lines: place them 8 items
+  // apart so both land on the same XCD (workgroups go round-robin over 8)
+  const uint32_t c = local % (kRow / kBlk), poly = local / (kRow / kBlk);
+  const uint32_t cb = 2 * (c % 8) + c / 8;
+  const uint32_t limb = poly / U.batch;
+  const uint32_t q = U.mods[limb].q;
+  const uint2* w = U.tw + (size_t)limb * n;
+  const uint32_t* src = U.in + (size_t)poly * n + cb * kBlk;
   for (uint32_t e = threadIdx.x; e < R * kBlk; e += kThreads) {
     uint32_t r = e / kBlk, c = e % kBlk;
     lds[e] = src[r * kRow + c];
   }
   __syncthreads();
   const uint32_t nb = (R / 2) * kBlk;  // butterflies per stage
-  if (!kInverse) {
+  if (!U.inverse) {
     for (uint32_t m = 1, tr = R / 2; m < R; m <<= 1, tr >>= 1) {
       for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
         uint32_t c = b % kBlk, rb = b / kBlk;
@@ -128,37 +146,38 @@ bf_cols(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2
       __syncthreads();
     }
   }
-  uint32_t* dst = out + (size_t)poly * n + cb * kBlk;
-  const uint2 ni = ninv[limb];
+  uint32_t* dst = U.out + (size_t)poly * n + cb * kBlk;
+  const uint2 ni = U.ninv[limb];
   for (uint32_t e = threadIdx.x; e < R * kBlk; e += kThreads) {
     uint32_t r = e / kBlk, c = e % kBlk;
     uint32_t v = lds[e];
-    if (kInverse) v = mul_shoup(v, ni.x, ni.y, q);
+    if (U.inverse) v = mul_shoup(v, ni.x, ni.y, q);
     dst[r * kRow + c] = v;
   }
 }
 
-// Row pass: a workgroup owns the kBlk rows whose bit-reversed indices are
-// consecutive, {row = bitrev(kBlk*rb + i)}, tile lds[i][col].  Position
-// row*256 + col of the bit-reversed order holds the natural-order index
-// bitrev8(col)*R + kBlk*rb + i, so the natural-order side is accessed in
-// runs of kBlk consecutive words.
+// Row pass: item = (polynomial, block of the kBlk rows whose bit-reversed
+// indices are consecutive, {row = bitrev(kBlk*rb + i)}), tile lds[i][col].
+// Position row*256 + col of the bit-reversed order holds the natural-order
+// index bitrev8(col)*R + kBlk*rb + i, so the natural-order side is accessed
+// in runs of kBlk consecutive words.
 // Forward: input = pass-A result (natural rows), stages m = R .. N/2, store
 // gathered to natural order.  Inverse: load gathered from the natural-order
 // input, stages h = N/2 .. R, store natural rows.
-template <bool kInverse>
-__global__ void __launch_bounds__(kThreads)
-bf_rows(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2* __restrict__ tw,
-        const ModConst* __restrict__ mods, uint32_t log_n, uint32_t batch) {
+__global__ void __launch_bounds__(kThreads) bf_rows(const BfTable tab) {
   __shared__ uint32_t lds[kBlk * kRow];
-  const uint32_t n = 1u << log_n, R = n / kRow, log_r = log_n - 8;
-  const uint32_t rb = blockIdx.x % (R / kBlk), poly = blockIdx.x / (R / kBlk);
-  const uint32_t limb = poly / batch;
-  const uint32_t q = mods[limb].q;
-  const uint2* w = tw + (size_t)limb * n;
-  const uint32_t* src = in + (size_t)poly * n;
+  const uint32_t k = find_unit(tab, blockIdx.x);
+  const BfUnit U = tab.u[k];
+  const uint32_t local = blockIdx.x - U.item_begin;
+  const uint32_t n = 1u << U.log_n, R = n / kRow, log_r = U.log_n - 8;
+  const uint32_t rb = local % (R / kBlk), poly = local / (R / kBlk);
+  const uint32_t limb = poly / U.batch;
+  const uint32_t q = U.mods[limb].q;
+  const uint2* w = U.tw + (size_t)limb * n;
+  const uint32_t* src = U.in + (size_t)poly * n;
+  const bool inv = U.inverse != 0;
   for (uint32_t e = threadIdx.x; e < kBlk * kRow; e += kThreads) {
-    if (!kInverse) {
+    if (!inv) {
       uint32_t i = e / kRow, col = e % kRow;
       lds[e] = src[brev(kBlk * rb + i, log_r) * kRow + col];
     } else {
@@ -168,7 +187,7 @@ bf_rows(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2
   }
   __syncthreads();
   const uint32_t nb = kBlk * kRow / 2;
-  if (!kInverse) {
+  if (!inv) {
     for (uint32_t m = R, t = kRow / 2; m < n; m <<= 1, t >>= 1) {
       for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
         uint32_t i = b / (kRow / 2), bb = b % (kRow / 2);
@@ -191,9 +210,9 @@ bf_rows(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2
       __syncthreads();
     }
   }
-  uint32_t* dst = out + (size_t)poly * n;
+  uint32_t* dst = U.out + (size_t)poly * n;
   for (uint32_t e = threadIdx.x; e < kBlk * kRow; e += kThreads) {
-    if (!kInverse) {
+    if (!inv) {
       uint32_t i = e % kBlk, cn = e / kBlk;
       dst[cn * R + kBlk * rb + i] = lds[i * kRow + brev(cn, 8)];
     } else {
@@ -203,7 +222,27 @@ bf_rows(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const uint2
   }
 }
 
-dim3 poly_grid(uint32_t x, uint32_t polys) { return dim3(x * polys); }
+BfUnit make_unit(const NttUnit& u, const uint32_t* in, uint32_t* out) {
+  const tfhe_ntt_plan_s* p = u.plan;
+  BfUnit b;
+  b.in = in;
+  b.out = out;
+  b.tw = (u.inverse ? p->d_bf_inv : p->d_bf_fwd) + (size_t)u.limb_begin * p->n;
+  b.ninv = p->d_ninv + u.limb_begin;
+  b.mods = p->d_mod + u.limb_begin;
+  b.log_n = p->log_n;
+  b.batch = u.batch;
+  b.inverse = u.inverse ? 1 : 0;
+  b.item_begin = 0;
+  return b;
+}
+
+// Append a unit of `items` work items to a table.
+void push(BfTable& t, BfUnit b, uint32_t items) {
+  b.item_begin = t.total;
+  t.u[t.count++] = b;
+  t.total += items;
+}
 
 }  // namespace
 
@@ -212,42 +251,61 @@ size_t bf_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_
   return (size_t)limb_count * batch * p->n * sizeof(uint32_t);
 }
 
-hipError_t bf_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
-                      uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s) {
-  const uint32_t polys = limb_count * batch;
-  const uint2* tw = p->d_bf_fwd + (size_t)limb_begin * p->n;
-  const ModConst* mods = p->d_mod + limb_begin;
-  if (p->log_n <= 12) {
-    TFHE_TIMED(K_BF_SINGLE, s, hipLaunchKernelGGL(bf_single_fwd, dim3(polys), dim3(kThreads), p->n * sizeof(uint32_t), s, in,
-                       out, tw, mods, p->log_n, batch));
-  } else {
-    uint32_t* mid = (uint32_t*)ws;
-    const uint32_t R = p->n / kRow;
-    TFHE_TIMED(K_BF_COLS, s, hipLaunchKernelGGL(bf_cols<false>, poly_grid(kRow / kBlk, polys), dim3(kThreads), 0, s, in,
-                       mid, tw, p->d_ninv + limb_begin, mods, p->log_n, batch));
-    TFHE_TIMED(K_BF_ROWS, s, hipLaunchKernelGGL(bf_rows<false>, poly_grid(R / kBlk, polys), dim3(kThreads), 0, s, mid, out,
-                       tw, mods, p->log_n, batch));
+// Fused launches: every single-pass unit in one launch; every two-pass unit
+// in one column-pass launch and one row-pass launch (ordered so each unit's
+// first pass writes its workspace slice and its second pass reads it:
+// forward = columns then rows, inverse = rows then columns).
+hipError_t bf_run_units(const NttUnit* units, uint32_t count, void* ws, hipStream_t s) {
+  unsigned char* w = (unsigned char*)ws;
+  for (uint32_t first = 0; first < count; first += kMaxUnits) {
+    const uint32_t n = std::min<uint32_t>(kMaxUnits, count - first);
+    BfTable single{}, cols1{}, rows1{}, rows2{}, cols2{};
+    uint32_t max_n = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+      const NttUnit& u = units[first + k];
+      const uint32_t polys = u.limb_count * u.batch;
+      if (polys == 0) continue;
+      const uint32_t N = u.plan->n, R = N / kRow;
+      if (u.plan->log_n <= 12) {
+        push(single, make_unit(u, u.in, u.out), polys);
+        max_n = std::max(max_n, N);
+        continue;
+      }
+      uint32_t* mid = (uint32_t*)w;
+      w += (bf_workspace_bytes(u.plan, u.limb_count, u.batch) + 255) & ~(size_t)255;
+      if (!u.inverse) {
+        push(cols1, make_unit(u, u.in, mid), polys * (kRow / kBlk));
+        push(rows2, make_unit(u, mid, u.out), polys * (R / kBlk));
+      } else {
+        push(rows1, make_unit(u, u.in, mid), polys * (R / kBlk));
+        push(cols2, make_unit(u, mid, u.out), polys * (kRow / kBlk));
+      }
+    }
+    if (single.total)
+      TFHE_TIMED(K_BF_SINGLE, s, hipLaunchKernelGGL(bf_single, dim3(single.total), dim3(kThreads),
+                                                    max_n * sizeof(uint32_t), s, single));
+    if (cols1.total)
+      TFHE_TIMED(K_BF_COLS, s, hipLaunchKernelGGL(bf_cols, dim3(cols1.total), dim3(kThreads), 0, s, cols1));
+    if (rows1.total)
+      TFHE_TIMED(K_BF_ROWS, s, hipLaunchKernelGGL(bf_rows, dim3(rows1.total), dim3(kThreads), 0, s, rows1));
+    if (rows2.total)
+      TFHE_TIMED(K_BF_ROWS, s, hipLaunchKernelGGL(bf_rows, dim3(rows2.total), dim3(kThreads), 0, s, rows2));
+    if (cols2.total)
+      TFHE_TIMED(K_BF_COLS, s, hipLaunchKernelGGL(bf_cols, dim3(cols2.total), dim3(kThreads), 0, s, cols2));
   }
   return hipGetLastError();
 }
 
+hipError_t bf_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
+                      uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s) {
+  NttUnit u{p, false, in, out, limb_begin, limb_count, batch};
+  return bf_run_units(&u, 1, ws, s);
+}
+
 hipError_t bf_inverse(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
                       uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s) {
-  const uint32_t polys = limb_count * batch;
-  const uint2* tw = p->d_bf_inv + (size_t)limb_begin * p->n;
-  const ModConst* mods = p->d_mod + limb_begin;
-  if (p->log_n <= 12) {
-    TFHE_TIMED(K_BF_SINGLE, s, hipLaunchKernelGGL(bf_single_inv, dim3(polys), dim3(kThreads), p->n * sizeof(uint32_t), s, in,
-                       out, tw, p->d_ninv + limb_begin, mods, p->log_n, batch));
-  } else {
-    uint32_t* mid = (uint32_t*)ws;
-    const uint32_t R = p->n / kRow;
-    TFHE_TIMED(K_BF_ROWS, s, hipLaunchKernelGGL(bf_rows<true>, poly_grid(R / kBlk, polys), dim3(kThreads), 0, s, in, mid,
-                       tw, mods, p->log_n, batch));
-    TFHE_TIMED(K_BF_COLS, s, hipLaunchKernelGGL(bf_cols<true>, poly_grid(kRow / kBlk, polys), dim3(kThreads), 0, s, mid,
-                       out, tw, p->d_ninv + limb_begin, mods, p->log_n, batch));
-  }
-  return hipGetLastError();
+  NttUnit u{p, true, in, out, limb_begin, limb_count, batch};
+  return bf_run_units(&u, 1, ws, s);
 }
 
 }  // namespace tfhe

@@ -16,20 +16,27 @@
 // the four data digits of a coefficient packed into four consecutive K
 // bytes, one v_mfma_i32_16x16x64_i8 per twiddle digit plane j yields
 //   C_j = sum_u sum_d x_d[u] * digit_j(W^(d)[u])   (|C_j| <= 2^20, exact)
-// and sum_j 2^{8j} C_j = sum_u x[u] w[u] (mod q).  The "fusion" step recombines
-// L = C_0 + 2^8 C_1, H = C_2 + 2^8 C_3 (32-bit exact; C_0 and C_2 start at q so
-// both are positive) and reduces z = L*t + H*(2^16 t) mod q with two Shoup
-// products, t being the twist of that position; z is then re-sliced into
-// digits for the next contraction (two VALU operations).
+// and V = sum_j 2^{8j} C_j = sum_u x[u] w[u] (mod q).  The "fusion" step
+// forms V = (C_0 + 2^8 C_1) + 2^16 (C_2 + 2^8 C_3) (C_0 and C_2 start at q
+// so both halves are positive), reduces it by one Montgomery step to
+// V 2^{-32} mod q, and multiplies by the next twist (stored as t 2^32, Shoup
+// form), or, after the last level, whose twiddles carry the 2^32, leaves the
+// canonical residue.  Twisted results are re-sliced into digits for the next
+// contraction with two VALU operations.
 //
-// Data movement: a workgroup takes 16 vectors (columns of a 256 x 256 row-
-// major matrix) of one polynomial through LDS; each wave transforms four of
-// them, one vector per 16 x 16 tile with four coefficients per lane.  Both
-// passes load column blocks; pass 1 writes its digit-form result row-wise to
-// the workspace (the transpose), pass 2 writes canonical residues back as a
-// column block through LDS.  The inverse runs the same two kernels with the
-// inverse tables (w^{-1}, phi^{-2}, psi^{-(2k1+1) n2}, N^{-1} folded into the
-// last level).
+// Data movement: persistent workgroups stride over the work items (16
+// vectors = 16 columns of the 256 x 256 matrix of one polynomial) with a
+// stride that is a multiple of 16, so a workgroup keeps the same columns and
+// reloads the limb's tables and the pass-1 post-twist only when the limb
+// changes.  Each item is staged through LDS; the global loads of the next item
+// are issued before the current one is computed.  Each wave transforms four vectors, one per
+// 16 x 16 tile with four coefficients per lane.  Pass 1 writes its digit-form
+// result row-wise to the workspace (the transpose), pass 2 writes canonical
+// residues back as a column block through LDS.  The inverse runs the same
+// kernels with the inverse tables (w^{-1}, phi^{-2}, psi^{-(2k1+1) n2}, N^{-1}
+// folded into the last level).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace tfhe {
@@ -43,35 +50,49 @@ constexpr int kStride = 324;  // LDS words per vector: 256 + 64 pad, = 4 (mod 64
 
 __device__ __forceinline__ int lds_pos(int col, int n) { return col * kStride + n + 16 * (n >> 6); }
 
+// Descriptor table of a fused launch (passed by value as a kernel argument):
+// unit k covers work items [item_begin[k], item_begin[k+1]).
+constexpr int kMaxUnits = 40;
+struct FsUnit {
+  const uint32_t* in;
+  uint32_t* out;
+  const FourStepLimb* limbs;  // tables of the unit's first limb
+  uint32_t batch;
+  uint32_t item_begin;
+};
+struct FsTable {
+  uint32_t count, total;
+  FsUnit u[kMaxUnits];
+};
+
 __device__ __forceinline__ v4i mfma(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
 
-// Fusion + twist + re-slice of one coefficient (see the file comment).
-__device__ __forceinline__ uint32_t fuse_twist_digits(int c0, int c1, int c2, int c3, uint4 t,
-                                                      uint32_t q) {
-  uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
-  uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
-  uint32_t r1 = reduce_once(mul_shoup_lazy(lo, t.x, t.y, q), q);
-  uint32_t r2 = reduce_once(mul_shoup_lazy(hi, t.z, t.w, q), q);
-  int32_t z = (int32_t)(r1 + r2 - q);          // in [-q, q)
-  z = z > 0x7F7F7F7F ? z - (int32_t)q : z;     // only when q > 0x7F7F7F7F
-  return balanced_digits(z);
+// Fusion and one Montgomery step: V 2^{-32} mod q, in [0, q + 2^17).
+__device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, uint32_t q,
+                                              uint32_t qneg) {
+  const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
+  const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
+  const uint64_t V = ((uint64_t)hi << 16) + lo;
+  const uint32_t vlo = (uint32_t)V, vhi = (uint32_t)(V >> 32);
+  const uint32_t m = vlo * qneg;
+  return vhi + __umulhi(m, q) + (vlo != 0u);
 }
 
-// Fusion + canonical reduction (no twist): (L + 2^16 H) mod q in [0, q).
-__device__ __forceinline__ uint32_t fuse_final(int c0, int c1, int c2, int c3, uint32_t c16,
-                                               uint32_t c16p, uint32_t q) {
-  uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
-  uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
-  return add_mod(reduce_once(lo, q), mul_shoup(hi, c16, c16p, q), q);
+// Twist (Shoup, t = {w 2^32, companion}) and re-slice into digits.
+__device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q) {
+  const uint32_t z = mul_shoup_lazy(r, t.x, t.y, q);  // [0, 2q)
+  int32_t zz = (int32_t)(z - q);                      // [-q, q)
+  zz = zz > 0x7F7F7F7F ? zz - (int32_t)q : zz;        // only when q > 0x7F7F7F7F
+  return balanced_digits(zz);
 }
 
 // One 256-point stage of one vector: level A, twist, level B.  x holds the
 // lane's four input words as digits (lane (v, g), word c: element 64g+16c+v);
 // on return acc[j][r] is plane j of output s + 16 (4g + r) for lane (s, g).
-__device__ __forceinline__ void stage256(v4i x, const v4i* opA, const v4i* opB, const uint4* tw,
-                                         uint32_t q, v4i* acc) {
+__device__ __forceinline__ void stage256(v4i x, const v4i* opA, const v4i* opB, const uint2* tw,
+                                         uint32_t q, uint32_t qneg, v4i* acc) {
   const v4i bias = {(int)q, (int)q, (int)q, (int)q};
   const v4i zero = {0, 0, 0, 0};
   v4i c0 = mfma(x, opA[0], bias);
@@ -80,118 +101,226 @@ __device__ __forceinline__ void stage256(v4i x, const v4i* opA, const v4i* opB, 
   v4i c3 = mfma(x, opA[3], zero);
   v4i z;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) z[r] = (int)fuse_twist_digits(c0[r], c1[r], c2[r], c3[r], tw[r], q);
+  for (int r = 0; r < 4; ++r)
+    z[r] = (int)twist_digits(fuse_redc(c0[r], c1[r], c2[r], c3[r], q, qneg), tw[r], q);
   acc[0] = mfma(opB[0], z, bias);
   acc[1] = mfma(opB[1], z, zero);
   acc[2] = mfma(opB[2], z, bias);
   acc[3] = mfma(opB[3], z, zero);
 }
 
+// Work item i -> (unit, limb, polynomial, column block).  Workgroups are
+// dispatched round-robin over the 8 XCDs, each with its own L2, and the grid
+// stride is a multiple of 16, so item i runs on XCD i % 8.  The two 64-byte
+// halves of a 128-byte line belong to column blocks 2b and 2b+1; mapping
+// them to items i and i + 8 of a group of 16 puts both on one XCD at the same
+// time, so the line is fetched from memory once.  `k` is the caller's running
+// unit index (items only increase along a workgroup's walk).
+struct Item {
+  uint32_t unit, limb, blk;
+  size_t poly_base;  // word offset of the polynomial within the unit's arrays
+};
+__device__ __forceinline__ Item decode_item(const FsTable& t, uint32_t i, uint32_t& k) {
+  while (k + 1 < t.count && i >= t.u[k + 1].item_begin) ++k;
+  const uint32_t local = i - t.u[k].item_begin;
+  const uint32_t c = local % (256 / kCols);
+  Item it;
+  it.unit = k;
+  it.blk = 2 * (c % 8) + c / 8;
+  const uint32_t poly = local / (256 / kCols);
+  it.limb = poly / t.u[k].batch;
+  it.poly_base = (size_t)poly << 16;
+  return it;
+}
+
 template <bool kFirst>
 __global__ void __launch_bounds__(kThreads)
-fs_pass(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-        const FourStepLimb* __restrict__ limbs, uint32_t batch) {
+fs_pass(const FsTable tab) {
   __shared__ uint32_t lds[kCols * kStride];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t blk = blockIdx.x % (256 / kCols), poly = blockIdx.x / (256 / kCols);
-  const FourStepLimb L = limbs[poly / batch];
-  const uint32_t q = L.q;
-  const PassTables* P = kFirst ? L.pass1 : L.pass2;
-  const size_t base = (size_t)poly << 16;
-
-  // column block -> LDS (each thread: four 16-byte row segments)
-  const uint32_t* src = in + base + blk * kCols;
-#pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    int row = it * 64 + (tid >> 2), c0 = 4 * (tid & 3);
-    uint4 v = *(const uint4*)(src + row * 256 + c0);
-    lds[lds_pos(c0 + 0, row)] = v.x;
-    lds[lds_pos(c0 + 1, row)] = v.y;
-    lds[lds_pos(c0 + 2, row)] = v.z;
-    lds[lds_pos(c0 + 3, row)] = v.w;
-  }
-
-  v4i opA[4], opB[4];
-  uint4 tw[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    opA[j] = *(const v4i*)&P->opA[j][lane][0];
-    opB[j] = *(const v4i*)&P->opB[j][lane][0];
-    tw[j] = P->twist[lane][j];
-  }
-  __syncthreads();
-
   const int v = lane & 15, g = lane >> 4;
-#pragma unroll 2
-  for (int cc = 0; cc < 4; ++cc) {
-    const int col = 4 * wave + cc;
-    v4i x;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      uint32_t w = lds[lds_pos(col, 64 * g + 16 * c + v)];
-      x[c] = kFirst ? (int)balanced_digits(to_window(w, q)) : (int)w;
-    }
-    v4i acc[4];
-    stage256(x, opA, opB, tw, q, acc);
-    if (kFirst) {
-      // post twist and row store: output k = s + 64g + 16r of vector col
-      const uint32_t gcol = blk * kCols + col;
-      const uint4* pt = L.post1 + ((size_t)gcol * 64 + lane) * 4;
-      uint32_t* dst = out + base + gcol * 256 + v + 64 * g;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        dst[16 * r] = fuse_twist_digits(acc[0][r], acc[1][r], acc[2][r], acc[3][r], pt[r], q);
-    } else {
-      // the wave owns this vector's LDS column: overwrite it with the output
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        lds[lds_pos(col, v + 64 * g + 16 * r)] =
-            fuse_final(acc[0][r], acc[1][r], acc[2][r], acc[3][r], L.c16, L.c16p, q);
-    }
-  }
+  const uint32_t begin = blockIdx.x, stride = gridDim.x, total = tab.total;
+  if (begin >= total) return;
 
-  if (!kFirst) {
-    __syncthreads();
-    uint32_t* dst = out + base + blk * kCols;
+  // this thread's four 16-byte row segments of a column block
+  uint4 pre[4];
+  uint32_t kf = 0, kc = 0;  // running unit indices of the fetch and compute walks
+  auto fetch = [&](uint32_t i) {
+    const Item it = decode_item(tab, i, kf);
+    const uint32_t* src = tab.u[it.unit].in + it.poly_base + it.blk * kCols;
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      int row = it * 64 + (tid >> 2), c0 = 4 * (tid & 3);
-      uint4 v4 = make_uint4(lds[lds_pos(c0, row)], lds[lds_pos(c0 + 1, row)],
-                            lds[lds_pos(c0 + 2, row)], lds[lds_pos(c0 + 3, row)]);
-      *(uint4*)(dst + row * 256 + c0) = v4;
+    for (int r4 = 0; r4 < 4; ++r4)
+      pre[r4] = *(const uint4*)(src + (r4 * 64 + (tid >> 2)) * 256 + 4 * (tid & 3));
+  };
+  fetch(begin);
+
+  const FourStepLimb* cur_limb = nullptr;
+  uint32_t cur_blk = 0xFFFFFFFFu;
+  uint32_t q = 0, qneg = 0;
+  const uint2* post = nullptr;
+  v4i opA[4], opB[4];
+  uint2 tw[4];
+  uint2 pt[4][4];
+  for (uint32_t i = begin; i < total; i += stride) {
+    const Item it = decode_item(tab, i, kc);
+    const FourStepLimb* limb = tab.u[it.unit].limbs + it.limb;
+    const uint32_t blk = it.blk;
+    __syncthreads();  // the previous item is done with the LDS tile
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      const int row = r4 * 64 + (tid >> 2), c0 = 4 * (tid & 3);
+      lds[lds_pos(c0 + 0, row)] = pre[r4].x;
+      lds[lds_pos(c0 + 1, row)] = pre[r4].y;
+      lds[lds_pos(c0 + 2, row)] = pre[r4].z;
+      lds[lds_pos(c0 + 3, row)] = pre[r4].w;
+    }
+    __syncthreads();
+    if (i + stride < total) fetch(i + stride);  // in flight while this item is computed
+
+    if (limb != cur_limb) {
+      const FourStepLimb L = *limb;
+      const PassTables* P = kFirst ? L.pass1 : L.pass2;
+      q = L.q;
+      qneg = L.qneg;
+      post = L.post1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        opA[j] = *(const v4i*)&P->opA[j][lane][0];
+        opB[j] = *(const v4i*)&P->opB[j][lane][0];
+        tw[j] = P->twist[lane][j];
+      }
+      cur_limb = limb;
+      cur_blk = 0xFFFFFFFFu;
+    }
+    if (kFirst && blk != cur_blk) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const uint2* p = post + ((size_t)(blk * kCols + 4 * wave + cc) * 64 + lane) * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pt[cc][r] = p[r];
+      }
+      cur_blk = blk;
+    }
+
+    const size_t base = it.poly_base;
+    uint32_t* const out = tab.u[it.unit].out;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const int col = 4 * wave + cc;
+      v4i x;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint32_t w = lds[lds_pos(col, 64 * g + 16 * c + v)];
+        x[c] = kFirst ? (int)balanced_digits(to_window(w, q)) : (int)w;
+      }
+      v4i acc[4];
+      stage256(x, opA, opB, tw, q, qneg, acc);
+      if (kFirst) {
+        // post twist and row store: output k = s + 64g + 16r of vector col
+        uint32_t* dst = out + base + (blk * kCols + col) * 256 + v + 64 * g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dst[16 * r] = twist_digits(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg),
+                                     pt[cc][r], q);
+      } else {
+        // the wave owns this vector's LDS column: overwrite it with the output
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          lds[lds_pos(col, v + 64 * g + 16 * r)] =
+              reduce_once(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg), q);
+      }
+    }
+
+    if (!kFirst) {
+      __syncthreads();
+      uint32_t* dst = out + base + blk * kCols;
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int row = r4 * 64 + (tid >> 2), c0 = 4 * (tid & 3);
+        *(uint4*)(dst + row * 256 + c0) =
+            make_uint4(lds[lds_pos(c0, row)], lds[lds_pos(c0 + 1, row)], lds[lds_pos(c0 + 2, row)],
+                       lds[lds_pos(c0 + 3, row)]);
+      }
     }
   }
+}
+
+// Resident workgroups per CU of each pass kernel (queried once per process).
+static uint32_t occupancy(bool first) {
+  static int occ[2] = {0, 0};
+  int& o = occ[first ? 1 : 0];
+  if (o == 0) {
+    int n = 0;
+    hipError_t e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<true>, kThreads, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<false>, kThreads, 0);
+    o = (e == hipSuccess && n > 0) ? n : 2;
+  }
+  return (uint32_t)o;
+}
+
+// Persistent grid: resident workgroups of the whole device, rounded down to a
+// multiple of the 16 column blocks of a polynomial.
+static uint32_t grid_size(const tfhe_ntt_plan_s* p, bool first, uint32_t total) {
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy(first);
+  uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
+  return std::min(g, total);
 }
 
 }  // namespace
 
 bool fs_supported(uint32_t log_n) { return log_n == 16; }
 
+size_t unit_ws_bytes(const NttUnit& u, bool mfma) {
+  if (mfma) return (size_t)u.limb_count * u.batch * u.plan->n * sizeof(uint32_t);
+  return bf_workspace_bytes(u.plan, u.limb_count, u.batch);
+}
+
 size_t fs_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_t batch) {
   return (size_t)limb_count * batch * p->n * sizeof(uint32_t);
 }
 
-static hipError_t fs_run(const FourStepLimb* limbs, const uint32_t* in, uint32_t* out, void* ws,
-                         uint32_t limb_count, uint32_t batch, hipStream_t s) {
-  const uint32_t polys = limb_count * batch;
-  dim3 grid(polys * (256 / kCols));
-  TFHE_TIMED(K_FS_PASS1, s,
-             hipLaunchKernelGGL(fs_pass<true>, grid, dim3(kThreads), 0, s, in, (uint32_t*)ws, limbs,
-                                batch));
-  TFHE_TIMED(K_FS_PASS2, s,
-             hipLaunchKernelGGL(fs_pass<false>, grid, dim3(kThreads), 0, s, (const uint32_t*)ws, out,
-                                limbs, batch));
+// Fused launch: pass 1 of every unit (in -> unit workspace), then pass 2 of
+// every unit (workspace -> out), kMaxUnits units per launch pair.
+hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStream_t s) {
+  unsigned char* w = (unsigned char*)ws;
+  for (uint32_t first = 0; first < count; first += kMaxUnits) {
+    const uint32_t n = std::min<uint32_t>(kMaxUnits, count - first);
+    FsTable t1, t2;
+    t1.count = t2.count = 0;
+    uint32_t total = 0;
+    const tfhe_ntt_plan_s* p0 = nullptr;
+    for (uint32_t k = 0; k < n; ++k) {
+      const NttUnit& u = units[first + k];
+      const uint32_t items = u.limb_count * u.batch * (256 / kCols);
+      if (items == 0) continue;
+      p0 = u.plan;
+      const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;
+      uint32_t* mid = (uint32_t*)w;
+      w += (unit_ws_bytes(u, true) + 255) & ~(size_t)255;
+      t1.u[t1.count++] = FsUnit{u.in, mid, tabs, u.batch, total};
+      t2.u[t2.count++] = FsUnit{mid, u.out, tabs, u.batch, total};
+      total += items;
+    }
+    if (total == 0) continue;
+    t1.total = t2.total = total;
+    TFHE_TIMED(K_FS_PASS1, s,
+               hipLaunchKernelGGL(fs_pass<true>, dim3(grid_size(p0, true, total)), dim3(kThreads), 0, s, t1));
+    TFHE_TIMED(K_FS_PASS2, s,
+               hipLaunchKernelGGL(fs_pass<false>, dim3(grid_size(p0, false, total)), dim3(kThreads), 0, s, t2));
+  }
   return hipGetLastError();
 }
 
 hipError_t fs_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
                       uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s) {
-  return fs_run(p->d_fs_fwd + limb_begin, in, out, ws, limb_count, batch, s);
+  NttUnit u{p, false, in, out, limb_begin, limb_count, batch};
+  return fs_run_units(&u, 1, ws, s);
 }
 
 hipError_t fs_inverse(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
                       uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s) {
-  return fs_run(p->d_fs_inv + limb_begin, in, out, ws, limb_count, batch, s);
+  NttUnit u{p, true, in, out, limb_begin, limb_count, batch};
+  return fs_run_units(&u, 1, ws, s);
 }
 
 }  // namespace tfhe

@@ -98,8 +98,11 @@ typedef uint32_t Mat16[16][16];
 // Level A contracts over u with the data as MFMA A operand: lane (v, g) holds
 // u = 4g + c, byte 4c + d pairs data digit d with digit j of 2^{8d} WA[u][s].
 // Level B contracts over v with the twiddle as MFMA A operand: lane (t, g)
-// holds v = 4g + c.  After level A, lane (s, g) holds v = 4g + r.
-static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Mat16& WB, uint32_t q) {
+// holds v = 4g + c.  After level A, lane (s, g) holds v = 4g + r.  The twist
+// carries the factor 2^32 that cancels the Montgomery reduction of the level-A
+// fusion; wb_scale multiplies WB (2^32 when level B is the transform's last).
+static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Mat16& WB, uint32_t q,
+                       uint32_t wb_scale) {
   uint32_t p2[4];
   for (int d = 0; d < 4; ++d) p2[d] = pow_mod(2, 8 * d, q);
   for (int j = 0; j < 4; ++j)
@@ -108,41 +111,39 @@ static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Ma
       for (int c = 0; c < 4; ++c) {
         uint32_t a = 0, b = 0;
         for (int d = 0; d < 4; ++d) {
+          uint32_t wb = mulm(WB[col][4 * g + c], wb_scale, q);
           a |= (uint32_t)(uint8_t)digit(mulm(p2[d], WA[4 * g + c][col], q), q, j) << (8 * d);
-          b |= (uint32_t)(uint8_t)digit(mulm(p2[d], WB[col][4 * g + c], q), q, j) << (8 * d);
+          b |= (uint32_t)(uint8_t)digit(mulm(p2[d], wb, q), q, j) << (8 * d);
         }
         pt.opA[j][lane][c] = a;
         pt.opB[j][lane][c] = b;
       }
     }
-  uint32_t c16 = pow_mod(2, 16, q);
+  uint32_t r32 = (uint32_t)((1ull << 32) % q);
   for (int lane = 0; lane < 64; ++lane)
     for (int r = 0; r < 4; ++r) {
-      uint32_t w = T[lane % 16][4 * (lane / 16) + r];
-      uint32_t w16 = mulm(w, c16, q);
-      pt.twist[lane][r] = make_uint4(w, shoup_companion(w, q), w16, shoup_companion(w16, q));
+      uint32_t w = mulm(T[lane % 16][4 * (lane / 16) + r], r32, q);
+      pt.twist[lane][r] = make_uint2(w, shoup_companion(w, q));
     }
 }
 
-// post[col][lane][r] = P(col, k) with k = s + 16 (4g + r) the output index
-// lane (s, g) holds in register r after level B.
+// post[col][lane][r] = P(col, k) 2^32 with k = s + 16 (4g + r) the output
+// index lane (s, g) holds in register r after level B.
 template <typename F>
-static void build_post(uint4* post, uint32_t q, F P) {
-  uint32_t c16 = pow_mod(2, 16, q);
+static void build_post(uint2* post, uint32_t q, F P) {
+  uint32_t r32 = (uint32_t)((1ull << 32) % q);
   for (int col = 0; col < 256; ++col)
     for (int lane = 0; lane < 64; ++lane)
       for (int r = 0; r < 4; ++r) {
         int k = lane % 16 + 16 * (4 * (lane / 16) + r);
-        uint32_t w = P(col, k);
-        uint32_t w16 = mulm(w, c16, q);
-        post[(col * 64 + lane) * 4 + r] =
-            make_uint4(w, shoup_companion(w, q), w16, shoup_companion(w16, q));
+        uint32_t w = mulm(P(col, k), r32, q);
+        post[(col * 64 + lane) * 4 + r] = make_uint2(w, shoup_companion(w, q));
       }
 }
 
 struct FsHostLimb {
   PassTables p1, p2;
-  std::vector<uint4> post;
+  std::vector<uint2> post;
 };
 
 // Four-step tables for N = 2^16 = 256 x 256, n = 256 n1 + n2, k = k1 + 256 k2:
@@ -163,14 +164,14 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t q, uint32_t psi, int dir
         T[a][b] = pow_mod(phi, (uint64_t)(2 * a + 1) * b, q);   // [s][v]
         WB[a][b] = pow_mod(phi, 32ull * a * b, q);              // [t][v]
       }
-    build_pass(L.p1, WA, T, WB, q);
+    build_pass(L.p1, WA, T, WB, q, 1);
     for (int a = 0; a < 16; ++a)
       for (int b = 0; b < 16; ++b) {
         WA[a][b] = pow_mod(om, 16ull * a * b, q);
         T[a][b] = pow_mod(om, (uint64_t)a * b, q);
         WB[a][b] = pow_mod(om, 16ull * a * b, q);
       }
-    build_pass(L.p2, WA, T, WB, q);
+    build_pass(L.p2, WA, T, WB, q, (uint32_t)((1ull << 32) % q));
     L.post.resize(256 * 64 * 4);
     // column n2, output k1: psi^{(2 k1 + 1) n2}
     build_post(L.post.data(), q, [&](int n2, int k1) {
@@ -184,7 +185,7 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t q, uint32_t psi, int dir
         T[a][b] = pow_mod(omi, (uint64_t)a * b, q);
         WB[a][b] = pow_mod(omi, 16ull * a * b, q);
       }
-    build_pass(L.p1, WA, T, WB, q);
+    build_pass(L.p1, WA, T, WB, q, 1);
     // inverse pass 2: for each n2, out n1 = s + 16t from in k1 = 16u + v:
     // N^{-1} phi^{-2 k1 n1 - n1}
     for (int a = 0; a < 16; ++a)
@@ -193,7 +194,7 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t q, uint32_t psi, int dir
         T[a][b] = pow_mod(phii, (uint64_t)(2 * b + 1) * a, q);         // [s][v]
         WB[a][b] = mulm(pow_mod(phii, (uint64_t)(32 * b + 16) * a, q), ninv, q);  // [t][v]
       }
-    build_pass(L.p2, WA, T, WB, q);
+    build_pass(L.p2, WA, T, WB, q, (uint32_t)((1ull << 32) % q));
     L.post.resize(256 * 64 * 4);
     // column k1, output n2: psi^{-(2 k1 + 1) n2}
     build_post(L.post.data(), q, [&](int k1, int n2) {
@@ -227,6 +228,9 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
     ninv[l] = make_uint2(ni, shoup_companion(ni, q));
   }
   if (hipGetDevice(&p->device) != hipSuccess) return fail(TFHE_EHIP, "hipGetDevice failed");
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+    p->num_cus = (uint32_t)cus;
   hipError_t e;
   if ((e = upload(&p->d_mod, mods.data(), L, p->owned)) != hipSuccess ||
       (e = upload(&p->d_bf_fwd, fwd.data(), fwd.size(), p->owned)) != hipSuccess ||
@@ -241,7 +245,7 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
   if (p->has_mfma) {
     // blob: per limb and direction {PassTables p1, p2, post[256*64*4]}
     const size_t post_elems = 256 * 64 * 4;
-    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint4);
+    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint2);
     const size_t total = per * 2 * L;
     std::vector<unsigned char> blob(total);
     std::vector<FourStepLimb> hf(L), hi(L);
@@ -256,15 +260,13 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
         size_t off = per * (2 * l + dir);
         memcpy(&blob[off], &H.p1, sizeof(PassTables));
         memcpy(&blob[off + sizeof(PassTables)], &H.p2, sizeof(PassTables));
-        memcpy(&blob[off + 2 * sizeof(PassTables)], H.post.data(), post_elems * sizeof(uint4));
+        memcpy(&blob[off + 2 * sizeof(PassTables)], H.post.data(), post_elems * sizeof(uint2));
         FourStepLimb& f = dir == 0 ? hf[l] : hi[l];
         f.pass1 = (const PassTables*)(dbase + off);
         f.pass2 = (const PassTables*)(dbase + off + sizeof(PassTables));
-        f.post1 = (const uint4*)(dbase + off + 2 * sizeof(PassTables));
+        f.post1 = (const uint2*)(dbase + off + 2 * sizeof(PassTables));
         f.q = p->q[l];
-        f.c16 = pow_mod(2, 16, p->q[l]);
-        f.c16p = shoup_companion(f.c16, p->q[l]);
-        f.pad = 0;
+        f.qneg = mods[l].qneg;
       }
     if ((e = hipMemcpy(p->d_fs_blob, blob.data(), total, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = upload(&p->d_fs_fwd, hf.data(), L, p->owned)) != hipSuccess ||

@@ -1,0 +1,245 @@
+"""Continuous-batching request loop for HMULT / HROTATE (the API layer of
+Sec. III-E: requests are collected, decomposed into batched kernel workflows
+and dispatched; keys and ciphertexts stay resident in HBM).
+
+A scheduler thread keeps up to `slots` batches in flight, each on its own
+HIP stream.  Pending requests are grouped by (op, N, level, galois element);
+whenever a slot is free, the oldest pending request and up to max_batch - 1
+compatible ones form a batch, provided its device memory (staged inputs,
+outputs, workspace) fits the remaining budget; otherwise admission waits
+(back-pressure).  Requests that arrive while other batches run are admitted
+as soon as a slot and memory free up, so their work overlaps on the device.
+Each result depends only on its own inputs: batching never changes bits.
+
+The backend does the device work (GpuBackend below); tests drive the same
+scheduler with a CPU backend.
+"""
+import collections
+import concurrent.futures
+import threading
+import time
+
+import numpy as np
+
+HMULT, ROTATE = 0, 1
+
+
+class Request:
+    __slots__ = ("op", "log_n", "level", "galois", "ct_a", "ct_b", "future", "t_submit", "t_done",
+                 "deadline")
+
+    def __init__(self, op, log_n, level, galois, ct_a, ct_b, timeout_s):
+        self.op, self.log_n, self.level, self.galois = op, log_n, level, galois
+        self.ct_a, self.ct_b = ct_a, ct_b
+        self.future = concurrent.futures.Future()
+        self.t_submit = time.perf_counter()
+        self.t_done = None
+        self.deadline = None if timeout_s is None else self.t_submit + timeout_s
+
+    @property
+    def key(self):
+        return (self.op, self.log_n, self.level, self.galois if self.op == ROTATE else 0)
+
+
+class Server:
+    def __init__(self, backend, mem_budget_bytes, slots=4, max_batch=16, poll_s=0.0002):
+        self.backend = backend
+        self.budget = int(mem_budget_bytes)
+        self.slots = int(slots)
+        self.max_batch = int(max_batch)
+        self.poll_s = poll_s
+        self._pending = collections.OrderedDict()  # id -> Request (FIFO)
+        self._inflight = []                         # (handle, requests, nbytes, slot)
+        self._free_slots = list(range(self.slots))
+        self._used = 0
+        self._peak_used = 0
+        self._lock = threading.Condition()
+        self._done = []
+        self._stop = False
+        self._next_id = 0
+        self._t0 = None
+        self._thread = threading.Thread(target=self._run, name="tfhe-serving", daemon=True)
+        self._thread.start()
+
+    # ------------------------------------------------------------------ API
+    def submit(self, op, log_n, level, ct_a, ct_b=None, galois=None, timeout_s=None):
+        """Queue an HMULT (ct_a * ct_b) or a rotation of ct_a by the Galois
+        element `galois`.  Returns a Future resolving to the output."""
+        if op == HMULT and ct_b is None:
+            raise ValueError("HMULT needs two ciphertexts")
+        if op == ROTATE and galois is None:
+            raise ValueError("rotation needs a Galois element")
+        req = Request(op, log_n, level, galois, ct_a, ct_b, timeout_s)
+        need = self.backend.nbytes(op, log_n, level, 1)
+        if need > self.budget:
+            req.future.set_exception(MemoryError(f"request needs {need} B > budget {self.budget} B"))
+            return req.future
+        with self._lock:
+            if self._t0 is None:
+                self._t0 = req.t_submit
+            self._pending[self._next_id] = req
+            self._next_id += 1
+            self._lock.notify()
+        return req.future
+
+    def stats(self):
+        with self._lock:
+            lat = np.array([r.t_done - r.t_submit for r in self._done if r.t_done is not None])
+            n = len(lat)
+            span = (max(r.t_done for r in self._done) - self._t0) if n else 0.0
+            return {
+                "completed": n,
+                "throughput_per_s": n / span if span > 0 else 0.0,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3) if n else None,
+                "p99_ms": float(np.percentile(lat, 99) * 1e3) if n else None,
+                "mean_batch": (n / self._batches) if getattr(self, "_batches", 0) else None,
+                "peak_mem_bytes": self._peak_used,
+            }
+
+    def reset_stats(self):
+        with self._lock:
+            self._done = []
+            self._t0 = None
+            self._batches = 0
+            self._peak_used = self._used
+
+    def drain(self, timeout_s=None):
+        t_end = None if timeout_s is None else time.perf_counter() + timeout_s
+        while True:
+            with self._lock:
+                if not self._pending and not self._inflight:
+                    return True
+            if t_end is not None and time.perf_counter() > t_end:
+                return False
+            time.sleep(self.poll_s)
+
+    def close(self):
+        with self._lock:
+            self._stop = True
+            self._lock.notify()
+        self._thread.join()
+
+    # ------------------------------------------------------------ scheduler
+    def _form_batch(self):
+        """Oldest pending request plus compatible ones, within the budget."""
+        now = time.perf_counter()
+        for rid in [rid for rid, r in self._pending.items() if r.future.cancelled() or
+                    (r.deadline is not None and now > r.deadline)]:
+            r = self._pending.pop(rid)
+            if not r.future.cancelled():
+                r.future.set_exception(TimeoutError("request timed out in the queue"))
+        if not self._pending:
+            return None
+        head = next(iter(self._pending.values()))
+        ids = [rid for rid, r in self._pending.items() if r.key == head.key][: self.max_batch]
+        while ids:
+            need = self.backend.nbytes(head.op, head.log_n, head.level, len(ids))
+            if self._used + need <= self.budget:
+                return ids, need
+            if len(ids) == 1:
+                return None  # wait for memory
+            ids = ids[: len(ids) // 2]
+        return None
+
+    def _run(self):
+        self._batches = 0
+        while True:
+            with self._lock:
+                if self._stop:
+                    return
+                # completions
+                still = []
+                for h, reqs, nbytes, slot in self._inflight:
+                    if self.backend.done(h):
+                        outs = self.backend.results(h)
+                        t = time.perf_counter()
+                        for r, o in zip(reqs, outs):
+                            r.t_done = t
+                            if not r.future.cancelled():
+                                r.future.set_result(o)
+                            self._done.append(r)
+                        self._used -= nbytes
+                        self._free_slots.append(slot)
+                    else:
+                        still.append((h, reqs, nbytes, slot))
+                self._inflight = still
+                # admissions
+                while self._free_slots:
+                    fb = self._form_batch()
+                    if fb is None:
+                        break
+                    ids, nbytes = fb
+                    reqs = [self._pending.pop(rid) for rid in ids]
+                    for r in reqs:
+                        r.future.set_running_or_notify_cancel()
+                    slot = self._free_slots.pop()
+                    self._used += nbytes
+                    self._peak_used = max(self._peak_used, self._used)
+                    try:
+                        h = self.backend.launch(slot, reqs)
+                    except Exception as e:  # surface to the callers, free the slot
+                        for r in reqs:
+                            r.future.set_exception(e)
+                        self._used -= nbytes
+                        self._free_slots.append(slot)
+                        continue
+                    self._batches += 1
+                    self._inflight.append((h, reqs, nbytes, slot))
+                idle = not self._pending and not self._inflight
+                if idle:
+                    self._lock.wait(timeout=0.05)
+            if not idle:
+                time.sleep(self.poll_s)
+
+
+class GpuBackend:
+    """Device backend: one CkksContext per N, resident keys, one HIP stream
+    per slot.  Inputs of a batch are staged into one [2][level][B][N] tensor
+    on the slot's stream; HMULT / HROTATE run batched; the outputs are
+    per-request views of the batch output."""
+
+    def __init__(self, contexts, relin_keys, rot_keys, slots=4):
+        import torch
+        self.torch = torch
+        self.ctx = contexts          # log_n -> CkksContext
+        self.evk = relin_keys        # log_n -> tensor
+        self.rk = rot_keys           # (log_n, galois) -> tensor
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+
+    def nbytes(self, op, log_n, level, batch):
+        n = 1 << log_n
+        ct = 2 * level * batch * n * 4
+        inputs = 2 * ct if op == HMULT else ct
+        return inputs + ct + self.ctx[log_n].workspace_bytes(level, batch)
+
+    def launch(self, slot, reqs):
+        torch = self.torch
+        r0 = reqs[0]
+        ctx = self.ctx[r0.log_n]
+        B, level, n = len(reqs), r0.level, 1 << r0.log_n
+        s = self.streams[slot]
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            a = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
+            for b, r in enumerate(reqs):
+                a[:, :, b].copy_(r.ct_a.reshape(2, level, n), non_blocking=True)
+            out = torch.empty_like(a)
+            ws = ctx.workspace(level, B)
+            if r0.op == HMULT:
+                bb = torch.empty_like(a)
+                for b, r in enumerate(reqs):
+                    bb[:, :, b].copy_(r.ct_b.reshape(2, level, n), non_blocking=True)
+                ctx.hmult(a, bb, self.evk[r0.log_n], level, out=out, ws=ws, stream=s)
+            else:
+                bb = None
+                ctx.rotate(a, self.rk[(r0.log_n, r0.galois)], r0.galois, level, out=out, ws=ws, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"event": ev, "out": out, "keep": (a, bb, ws), "B": B}
+
+    def done(self, h):
+        return h["event"].query()
+
+    def results(self, h):
+        out = h["out"]
+        return [out[:, :, b:b + 1] for b in range(h["B"])]

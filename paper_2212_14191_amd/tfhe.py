@@ -22,6 +22,13 @@ ALGOS = {"auto": AUTO, "butterfly": BUTTERFLY, "mfma": FOURSTEP_MFMA}
 _lib = None
 
 
+class NttDesc(ctypes.Structure):
+    """tfhe_ntt_desc: one transform of a fused batch."""
+    _fields_ = [("plan", ctypes.c_void_p), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("limb_begin", ctypes.c_uint32), ("limb_count", ctypes.c_uint32),
+                ("batch", ctypes.c_uint32), ("inverse", ctypes.c_int32)]
+
+
 class TfheError(RuntimeError):
     def __init__(self, status, func, detail):
         self.status = status
@@ -57,6 +64,8 @@ def load():
         "tfhe_pointwise_mul_bcast": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
         "tfhe_frobenius_map": ([vp, vp, vp, u32, u32, u32, vp], i32),
         "tfhe_load_small": ([vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_ntt_batch_workspace_size": ([ctypes.POINTER(NttDesc), u32, i32, ctypes.POINTER(sz)], i32),
+        "tfhe_ntt_batch": ([ctypes.POINTER(NttDesc), u32, i32, vp, sz, vp], i32),
         "tfhe_timing_enable": ([i32], i32),
         "tfhe_timing_read": ([ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], i32),
         "tfhe_ckks_ctx_create": ([ctypes.POINTER(vp), u32, u32, u32, u32, pu32, pu32, i32], i32),
@@ -251,6 +260,30 @@ def tfhe_timing_read(kernel):
     n, ms = ctypes.c_uint64(), ctypes.c_double()
     _call("tfhe_timing_read", kernel.encode(), ctypes.byref(n), ctypes.byref(ms))
     return n.value, ms.value
+
+
+def ntt_batch(items, algo="auto", ws=None, stream=None):
+    """Fused transforms (operation-level batching).  items: list of
+    (plan, x, out, inverse, limb_begin); x/out int32 [limbs][batch][N]."""
+    import torch
+    descs = (NttDesc * len(items))()
+    keep = []
+    for d, (plan, x, out, inverse, limb_begin) in zip(descs, items):
+        _check_residues(x, "x")
+        _check_residues(out, "out", x.shape)
+        limbs, batch, n = x.shape
+        if n != plan.n:
+            raise ValueError("last dimension != plan N")
+        d.plan, d.in_, d.out = plan.handle.value, x.data_ptr(), out.data_ptr()
+        d.limb_begin, d.limb_count, d.batch, d.inverse = limb_begin, limbs, batch, 1 if inverse else 0
+        keep.append((x, out))
+    a = ALGOS.get(algo, algo)
+    if ws is None:
+        nb = ctypes.c_size_t()
+        _call("tfhe_ntt_batch_workspace_size", descs, len(items), a, ctypes.byref(nb))
+        ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+    _call("tfhe_ntt_batch", descs, len(items), a, _ptr(ws), ws.numel(), _stream(stream))
+    return [o for _, o in keep]
 
 
 def torch_empty_like(x):

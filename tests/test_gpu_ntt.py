@@ -188,3 +188,28 @@ def test_full_size_44x128_sampled(tf):
         l, b = int(rng.integers(44)), int(rng.integers(128))
         ref = oracle.ntt_fwd(x_host[l, b], [qs[l]], [plan.psi[l]])
         assert np.array_equal(got[l, b], ref), (l, b)
+
+
+def test_fused_batch_mixed_sizes_and_directions(tf):
+    """Operation-level batching: one fused launch per pass covers transforms
+    of different N, limb ranges and directions (butterfly), and of different
+    directions and batches (MFMA, N = 2^16)."""
+    plans = {ln: tf.NttPlan(ln, PRIMES31[:3]) for ln in (10, 13, 16)}
+    specs = [(10, False, 3), (13, True, 2), (16, False, 1), (16, True, 2), (13, False, 1), (10, True, 4)]
+    items, refs = [], []
+    for ln, inv, b in specs:
+        n = 1 << ln
+        plan = plans[ln]
+        x = inputs.uniform_residues(ln * 10 + b, plan.q[1:3], (b, n))
+        X = to_dev(x)
+        items.append((plan, X, torch.empty_like(X), inv, 1))
+        refs.append(oracle.ntt(x, plan.q[1:3], plan.psi[1:3], inverse=inv)[0])
+    for o, r in zip(tf.ntt_batch(items, algo="butterfly"), refs):
+        assert np.array_equal(to_host(o), r)
+    mf = [(i, r) for (i, r), (ln, _, _) in zip(zip(items, refs), specs) if ln == 16]
+    outs = tf.ntt_batch([i for i, _ in mf], algo="mfma")
+    for o, (_, r) in zip(outs, mf):
+        assert np.array_equal(to_host(o), r)
+    X = mf[0][0][1].clone()
+    tf.ntt_batch([(plans[16], X, X, False, 1)], algo="mfma")   # in place
+    assert np.array_equal(to_host(X), mf[0][1])

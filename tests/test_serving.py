@@ -1,0 +1,169 @@
+"""Scheduler of the serving loop, driven on the CPU by a backend that runs
+the oracle: admission by memory, back-pressure, continuous batching,
+alone-vs-mix equality, time-outs and cancellation."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import ckks
+from paper_2212_14191_amd import inputs
+from paper_2212_14191_amd.serving import HMULT, ROTATE, Server
+
+
+class OracleBackend:
+    """Same interface as GpuBackend; work runs on a worker thread."""
+
+    def __init__(self, pr, evk, rks, delay_s=0.0):
+        self.pr, self.evk, self.rks, self.delay = pr, evk, rks, delay_s
+        self.lock = threading.Lock()
+        self.inflight_bytes = 0
+        self.peak = 0
+        self.launch_log = []   # (t_start, t_end, batch size, key)
+
+    def nbytes(self, op, log_n, level, batch):
+        return (3 if op == HMULT else 2) * 2 * level * batch * (1 << log_n) * 4 + 1000 * batch
+
+    def launch(self, slot, reqs):
+        r0 = reqs[0]
+        nb = self.nbytes(r0.op, r0.log_n, r0.level, len(reqs))
+        with self.lock:
+            self.inflight_bytes += nb
+            self.peak = max(self.peak, self.inflight_bytes)
+        h = {"done": False, "out": None}
+
+        def work():
+            t0 = time.perf_counter()
+            time.sleep(self.delay)
+            a = np.concatenate([r.ct_a for r in reqs], axis=2)
+            if r0.op == HMULT:
+                b = np.concatenate([r.ct_b for r in reqs], axis=2)
+                out = ckks.hmult(self.pr, a, b, self.evk, r0.level)
+            else:
+                out = ckks.rotate(self.pr, a, self.rks[r0.galois], r0.galois, r0.level)
+            h["out"] = [out[:, :, i:i + 1] for i in range(len(reqs))]
+            with self.lock:
+                self.inflight_bytes -= nb
+                self.launch_log.append((t0, time.perf_counter(), len(reqs), r0.key))
+            h["done"] = True
+
+        threading.Thread(target=work, daemon=True).start()
+        return h
+
+    def done(self, h):
+        return h["done"]
+
+    def results(self, h):
+        return h["out"]
+
+
+@pytest.fixture(scope="module")
+def world():
+    n = 64
+    pr = ckks.Params(n, L=6, K=2, dnum=3)
+    s = inputs.ternary_secret(1, n, 16)
+    a = inputs.uniform_residues(1, pr.moduli, (3, n), stream=1).transpose(1, 0, 2)
+    e = inputs.gaussian_error(2, (3, n), stream=1)
+    evk = ckks.relin_key(pr, s, a, e)
+    gal = [ckks.galois_element(r, n) for r in (1, 2)]
+    rks = {k: ckks.rotation_key(pr, s, k, a, e) for k in gal}
+    cts = {}
+    for level in (2, 4, 6):
+        for i in range(3):
+            m = inputs.small_messages(i, (1, n))
+            c1 = inputs.uniform_residues(10 + i, pr.mods(range(level)), (1, n), stream=5)
+            cts[(level, i)] = ckks.encrypt(pr, s, m, c1, inputs.gaussian_error(2, (1, n), stream=i), level)
+    return pr, evk, rks, gal, cts
+
+
+def mix(world, count=24, seed=0):
+    pr, evk, rks, gal, cts = world
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        level = int(rng.choice([2, 4, 6]))
+        i, j = int(rng.integers(3)), int(rng.integers(3))
+        if rng.random() < 0.5:
+            out.append((HMULT, level, cts[(level, i)], cts[(level, j)], None))
+        else:
+            out.append((ROTATE, level, cts[(level, i)], None, gal[int(rng.integers(2))]))
+    return out
+
+
+def run(server, reqs):
+    futs = [server.submit(op, 6, lv, a, b, g) for op, lv, a, b, g in reqs]
+    return [f.result(timeout=60) for f in futs]
+
+
+def test_alone_equals_mix(world):
+    pr, evk, rks, _, _ = world
+    reqs = mix(world)
+    alone = []
+    for r in reqs:
+        srv = Server(OracleBackend(pr, evk, rks), mem_budget_bytes=1 << 30, slots=1, max_batch=1)
+        alone.append(run(srv, [r])[0])
+        srv.close()
+    be = OracleBackend(pr, evk, rks, delay_s=0.01)
+    srv = Server(be, mem_budget_bytes=1 << 30, slots=3, max_batch=8)
+    mixed = run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    for x, y in zip(alone, mixed):
+        assert np.array_equal(x, y)
+    assert st["completed"] == len(reqs)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    assert max(b for _, _, b, _ in be.launch_log) > 1   # some batching happened
+
+
+def test_budget_is_never_exceeded(world):
+    pr, evk, rks, _, _ = world
+    be = OracleBackend(pr, evk, rks, delay_s=0.005)
+    budget = be.nbytes(HMULT, 6, 6, 2) + 10   # room for about two small requests
+    srv = Server(be, mem_budget_bytes=budget, slots=4, max_batch=8)
+    out = run(srv, mix(world, 30, seed=1))
+    srv.close()
+    assert len(out) == 30
+    assert be.peak <= budget
+
+
+def test_request_larger_than_budget_fails(world):
+    pr, evk, rks, _, cts = world
+    srv = Server(OracleBackend(pr, evk, rks), mem_budget_bytes=100, slots=1)
+    f = srv.submit(HMULT, 6, 6, cts[(6, 0)], cts[(6, 1)])
+    with pytest.raises(MemoryError):
+        f.result(timeout=5)
+    srv.close()
+
+
+def test_continuous_batching_overlaps(world):
+    """A request arriving while a batch runs is dispatched before that
+    batch finishes (another slot), not after."""
+    pr, evk, rks, _, cts = world
+    be = OracleBackend(pr, evk, rks, delay_s=0.3)
+    srv = Server(be, mem_budget_bytes=1 << 30, slots=2, max_batch=4)
+    f1 = srv.submit(HMULT, 6, 6, cts[(6, 0)], cts[(6, 1)])
+    time.sleep(0.05)
+    f2 = srv.submit(HMULT, 6, 4, cts[(4, 0)], cts[(4, 1)])
+    f1.result(timeout=10)
+    f2.result(timeout=10)
+    srv.close()
+    (s1, e1, _, _), (s2, e2, _, _) = sorted(be.launch_log)
+    assert s2 < e1   # overlapped
+
+
+def test_timeout_and_cancel(world):
+    pr, evk, rks, _, cts = world
+    be = OracleBackend(pr, evk, rks, delay_s=0.3)
+    srv = Server(be, mem_budget_bytes=1 << 30, slots=1, max_batch=1)
+    f1 = srv.submit(HMULT, 6, 6, cts[(6, 0)], cts[(6, 1)])
+    time.sleep(0.05)
+    f2 = srv.submit(HMULT, 6, 4, cts[(4, 0)], cts[(4, 1)], timeout_s=0.01)
+    f3 = srv.submit(HMULT, 6, 2, cts[(2, 0)], cts[(2, 1)])
+    assert f3.cancel()
+    f1.result(timeout=10)
+    with pytest.raises(TimeoutError):
+        f2.result(timeout=10)
+    srv.drain(5)
+    srv.close()
+    assert len(be.launch_log) == 1
