@@ -71,6 +71,71 @@ def cpu_baseline(qs, psis, budget_s=12.0):
                       f"({transforms} limb-transforms, {dt:.1f} s)"}
 
 
+def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs):
+    """Config 5: Poisson HMULT / rotate requests, N in {2^13..2^16}, levels
+    uniform in 1..24, 8 rotation keys per N, keys and ciphertexts resident,
+    memory-gated continuous batching.  Returns throughput and p50/p99."""
+    from paper_2212_14191_amd.scheme import Scheme
+    from paper_2212_14191_amd.serving import GpuBackend, Server
+    L, K, dnum = HM_L, HM_K, HM_DNUM
+    log_ns, rots = (13, 14, 15, 16), (1, 2, 4, 8, 16, 32, 64, 128)
+    ctxs, evks, rks, pool = {}, {}, {}, {}
+    for ln in log_ns:
+        n = 1 << ln
+        ctx = tfhe.CkksContext(ln, L, K, dnum)
+        sch = Scheme(ctx)
+        s = inputs.ternary_secret(1, n, 192)
+        a = inputs.uniform_residues(1, ctx.moduli, (dnum, n), stream=1).transpose(1, 0, 2)
+        e = inputs.gaussian_error(2, (dnum, n), stream=1)
+        ctxs[ln], evks[ln] = ctx, sch.relin_key(s, a, e)
+        for r in rots:
+            g = pow(5, r, 2 * n)
+            rks[(ln, g)] = sch.rotation_key(s, g, a, e)
+        full = []
+        for i in range(2):
+            m = inputs.small_messages(i, (1, n))
+            c1 = inputs.uniform_residues(30 + i, ctx.moduli[:L], (1, n), stream=5)
+            full.append(sch.encrypt(s, m, c1, inputs.gaussian_error(2, (1, n), stream=40 + i), L))
+        for level in range(1, L + 1):  # dropping top limbs keeps a valid ciphertext
+            pool[(ln, level)] = [c[:, :level].contiguous() for c in full]
+    torch.cuda.synchronize()
+    slots, budget = 4, 48 << 30
+
+    def run(count, seed, rate):
+        mix = inputs.request_mix(seed, count, log_ns=log_ns, max_level=L, rotations=rots)
+        arrivals = inputs.poisson_arrivals(seed, rate, count) if rate else np.zeros(count)
+        srv = Server(GpuBackend(ctxs, evks, rks, slots=slots), budget, slots=slots, max_batch=16)
+        futs = []
+        t0 = time.perf_counter()
+        for i in range(count):
+            wait = arrivals[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            ln, lv = int(mix["log_n"][i]), int(mix["level"][i])
+            c = pool[(ln, lv)]
+            if mix["op"][i] == 0:
+                futs.append(srv.submit(0, ln, lv, c[0], c[1]))
+            else:
+                futs.append(srv.submit(1, ln, lv, c[0], galois=pow(5, int(mix["rot"][i]), 2 << ln)))
+        for f in futs:
+            f.result(timeout=300)
+        st = srv.stats()
+        srv.close()
+        return st
+
+    run(min(64, n_sat), 99, 0)  # warm-up
+    sat = run(n_sat, 98, 0)
+    out = {"saturated_ops_per_s": round(sat["throughput_per_s"], 1), "requests": n_req, "slots": slots,
+           "max_batch": 16, "runs": []}
+    for frac in fracs:
+        rate = frac * sat["throughput_per_s"]
+        st = run(n_req, 3, rate)
+        out["runs"].append({"load": frac, "rate_per_s": round(rate, 1),
+                            "throughput_per_s": round(st["throughput_per_s"], 1),
+                            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +144,8 @@ def main():
     ap.add_argument("--hmult-steps", type=int, default=5)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-hmult", action="store_true")
+    ap.add_argument("--skip-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=400)
     ap.add_argument("--only", choices=["mfma", "butterfly"], default=None,
                     help="time one transform only (for profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -176,6 +243,11 @@ def main():
         log("hmult", json.dumps(hmult))
         del cts, out, hws, evk, ctx
 
+    serving = None
+    if not args.skip_serving and args.only is None:
+        serving = serving_leg(args.serving_requests, args.serving_requests, (0.5, 0.9), torch, tfhe, inputs)
+        log("serving", json.dumps(serving))
+
     cpu = None
     if not args.skip_cpu and args.only is None:
         cpu = cpu_baseline(qs, plan.psi)
@@ -214,6 +286,9 @@ def main():
     if hmult:
         line["hmult_ops_per_s"] = round(hmult["ops_per_s"], 1)
         line["hmult"] = hmult
+    if serving:
+        line["p99_ms"] = serving["runs"][0]["p99_ms"]
+        line["serving"] = serving
     print(json.dumps(line), flush=True)
 
 

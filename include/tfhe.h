@@ -96,6 +96,16 @@ tfhe_status tfhe_ntt_plan_info(tfhe_ntt_plan plan, uint32_t* log_n, uint32_t* n_
                                tfhe_ntt_algo* algo);
 tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q, uint32_t* psi);
 
+/* Tuning knobs of a plan (written by an autotuner; the defaults are sound):
+ *   TFHE_PARAM_FS_WG_PER_CU  persistent four-step workgroups per compute
+ *                            unit (0 = as many as fit, the default)
+ *   TFHE_PARAM_AUTO_ALGO     what TFHE_NTT_AUTO resolves to (a tfhe_ntt_algo;
+ *                            MFMA only where the plan supports it)
+ * Not thread-safe against concurrent compute calls on the same plan. */
+typedef enum { TFHE_PARAM_FS_WG_PER_CU = 1, TFHE_PARAM_AUTO_ALGO = 2 } tfhe_plan_param;
+tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t value);
+tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t* value);
+
 /* Bytes of device workspace tfhe_ntt_fwd/inv need for `batch` polynomials
  * of `limb_count` limbs (the transposed intermediate between the two
  * passes).  0 is possible; the value never exceeds limb_count*batch*N*4. */

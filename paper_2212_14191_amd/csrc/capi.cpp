@@ -167,6 +167,36 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
   return TFHE_OK;
 }
 
+tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t value) {
+  if (!plan) return fail(TFHE_EINVAL, "null plan");
+  switch (param) {
+    case TFHE_PARAM_FS_WG_PER_CU:
+      if (value < 0 || value > 32) return fail(TFHE_EINVAL, "fs_wg_per_cu must be in [0, 32]");
+      plan->fs_wg_per_cu = (uint32_t)value;
+      return TFHE_OK;
+    case TFHE_PARAM_AUTO_ALGO:
+      if (value == TFHE_NTT_BUTTERFLY || (value == TFHE_NTT_FOURSTEP_MFMA && plan->has_mfma)) {
+        plan->algo = (tfhe_ntt_algo)value;
+        return TFHE_OK;
+      }
+      if (value == TFHE_NTT_AUTO) {
+        plan->algo = plan->has_mfma ? TFHE_NTT_FOURSTEP_MFMA : TFHE_NTT_BUTTERFLY;
+        return TFHE_OK;
+      }
+      return fail(TFHE_EINVAL, "auto_algo: not an algorithm this plan supports");
+  }
+  return fail(TFHE_EINVAL, "unknown plan parameter");
+}
+
+tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t* value) {
+  if (!plan || !value) return fail(TFHE_EINVAL, "null argument");
+  switch (param) {
+    case TFHE_PARAM_FS_WG_PER_CU: *value = plan->fs_wg_per_cu; return TFHE_OK;
+    case TFHE_PARAM_AUTO_ALGO: *value = plan->algo; return TFHE_OK;
+  }
+  return fail(TFHE_EINVAL, "unknown plan parameter");
+}
+
 tfhe_status tfhe_ntt_workspace_size(tfhe_ntt_plan plan, tfhe_ntt_algo algo, uint32_t limb_count,
                                     uint32_t batch, size_t* bytes) {
   if (!plan || !bytes) return fail(TFHE_EINVAL, "workspace_size: null argument");

@@ -115,8 +115,8 @@ __global__ void __launch_bounds__(kThreads) bf_cols(const BfTable tab) {
   const uint32_t n = 1u << U.log_n, R = n / kRow;
   // column blocks 2b and 2b+1 share 128-byte lines: place them 8 items
   // apart so both land on the same XCD (workgroups go round-robin over 8)
-  const uint32_t c = local % (kRow / kBlk), poly = local / (kRow / kBlk);
-  const uint32_t cb = 2 * (c % 8) + c / 8;
+  const uint32_t slot = local % (kRow / kBlk), poly = local / (kRow / kBlk);
+  const uint32_t cb = 2 * (slot % 8) + slot / 8;
   const uint32_t limb = poly / U.batch;
   const uint32_t q = U.mods[limb].q;
   const uint2* w = U.tw + (size_t)limb * n;

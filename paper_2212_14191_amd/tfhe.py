@@ -64,6 +64,8 @@ def load():
         "tfhe_pointwise_mul_bcast": ([vp, vp, vp, vp, u32, u32, u32, vp], i32),
         "tfhe_frobenius_map": ([vp, vp, vp, u32, u32, u32, vp], i32),
         "tfhe_load_small": ([vp, vp, vp, u32, u32, u32, vp], i32),
+        "tfhe_ntt_plan_set_param": ([vp, i32, ctypes.c_int64], i32),
+        "tfhe_ntt_plan_get_param": ([vp, i32, ctypes.POINTER(ctypes.c_int64)], i32),
         "tfhe_ntt_batch_workspace_size": ([ctypes.POINTER(NttDesc), u32, i32, ctypes.POINTER(sz)], i32),
         "tfhe_ntt_batch": ([ctypes.POINTER(NttDesc), u32, i32, vp, sz, vp], i32),
         "tfhe_timing_enable": ([i32], i32),
@@ -160,6 +162,18 @@ class NttPlan:
             _call("tfhe_ntt_plan_modulus", self.handle, l, ctypes.byref(a), ctypes.byref(b))
             self.q.append(a.value)
             self.psi.append(b.value)
+
+    PARAMS = {"fs_wg_per_cu": 1, "auto_algo": 2}
+
+    def set_param(self, name, value):
+        _call("tfhe_ntt_plan_set_param", self.handle, self.PARAMS[name], int(value))
+        if name == "auto_algo":
+            self.algo = self.get_param("auto_algo")
+
+    def get_param(self, name):
+        v = ctypes.c_int64()
+        _call("tfhe_ntt_plan_get_param", self.handle, self.PARAMS[name], ctypes.byref(v))
+        return v.value
 
     def close(self):
         if self._owned and self.handle:
