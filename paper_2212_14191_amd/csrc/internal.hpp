@@ -16,23 +16,28 @@ void set_error(const std::string& msg);
 tfhe_status fail(tfhe_status s, const std::string& msg);
 tfhe_status hip_check(hipError_t e, const char* what);
 
-// Tables of the four-step algorithm for one pass of a 256-point transform
-// decomposed as 16 x 16 (per limb, per direction).  All arrays are laid out
-// exactly as the kernels load them into MFMA operand registers.
+// Tables of one pass of the four-step algorithm (per limb and direction).
+// A pass transforms vectors of P = 16 r points (r in {1, 2, 4, 8, 16}),
+// decomposed as 16 x r: a radix-16 level on the matrix cores (level A), a
+// twist, and a radix-r level (level B: matrix cores when r = 16, VALU
+// butterflies otherwise).  Laid out exactly as the kernels load them.
 //   opA[j][lane][4]   level-A twiddle operand, digit plane j (4 dwords/lane)
-//   opB[j][lane][4]   level-B twiddle operand
-//   twist[lane][r]    inter-level twist T, stored as {T 2^32 mod q, companion}
+//   opB[j][lane][4]   level-B twiddle operand (r = 16 only)
+//   twist[lane][j]    twist after level A, {T 2^32 mod q, companion}
+//   lb[16]            level-B constants (r < 16): lb[0..3] = rho^0..rho^3 of
+//                     the radix-r root rho; lb[8 + t] = factor of output t
 struct PassTables {
   uint32_t opA[4][64][4];
   uint32_t opB[4][64][4];
   uint2 twist[64][4];
+  uint2 lb[16];
 };
 
 // Device-side description of one limb for the four-step kernels.
 struct FourStepLimb {
-  const PassTables* pass1;  // column pass
-  const PassTables* pass2;  // row pass
-  const uint2* post1;       // [256 columns][64 lanes][4]: post-twist of pass 1 (x 2^32)
+  const PassTables* pass1;  // first pass (its post-twist: post1)
+  const PassTables* pass2;  // second pass
+  const uint2* post1;       // [256 column bases][64 lanes][4]: post-twist of pass 1
   uint32_t q, qneg;         // modulus and -q^{-1} mod 2^32
 };
 

@@ -109,137 +109,207 @@ __device__ __forceinline__ void stage256(v4i x, const v4i* opA, const v4i* opB, 
   acc[3] = mfma(opB[3], z, zero);
 }
 
-// Work item i -> (unit, limb, polynomial, column block).  Workgroups are
-// dispatched round-robin over the 8 XCDs, each with its own L2, and the grid
-// stride is a multiple of 16, so item i runs on XCD i % 8.  The two 64-byte
-// halves of a 128-byte line belong to column blocks 2b and 2b+1; mapping
-// them to items i and i + 8 of a group of 16 puts both on one XCD at the same
-// time, so the line is fetched from memory once.  `k` is the caller's running
-// unit index (items only increase along a workgroup's walk).
+// Work distribution.  The grid is a multiple of 16; workgroup w belongs to
+// group w / 16 and owns column block blk(w % 16) of every polynomial in its
+// group's contiguous range, so it changes limb (and reloads the limb's
+// tables and its post-twist slice) at most a few times.  Workgroups are
+// dispatched round-robin over the 8 XCDs, each with its own L2: the two
+// 64-byte halves of a 128-byte line are column blocks 2b and 2b+1, owned by
+// workgroups c and c + 8 of a group, i.e. on the same XCD at the same time,
+// so each line is fetched from memory once.
+struct Walk {
+  uint32_t blk, p, p_end;  // column block; current and end polynomial (global index)
+};
+__device__ __forceinline__ Walk make_walk(uint32_t total_polys) {
+  const uint32_t groups = gridDim.x / 16, a = blockIdx.x / 16, c = blockIdx.x % 16;
+  Walk w;
+  w.blk = 2 * (c % 8) + c / 8;
+  w.p = (uint32_t)((uint64_t)a * total_polys / groups);
+  w.p_end = (uint32_t)((uint64_t)(a + 1) * total_polys / groups);
+  return w;
+}
+
 struct Item {
-  uint32_t unit, limb, blk;
+  uint32_t unit, limb;
   size_t poly_base;  // word offset of the polynomial within the unit's arrays
 };
-__device__ __forceinline__ Item decode_item(const FsTable& t, uint32_t i, uint32_t& k) {
-  while (k + 1 < t.count && i >= t.u[k + 1].item_begin) ++k;
-  const uint32_t local = i - t.u[k].item_begin;
-  const uint32_t c = local % (256 / kCols);
+// Global polynomial p -> (unit, limb, offset); `k` is a running unit index
+// (p only increases along a walk).
+__device__ __forceinline__ Item locate(const FsTable& t, uint32_t p, uint32_t& k) {
+  while (k + 1 < t.count && p >= t.u[k + 1].item_begin) ++k;
+  const uint32_t local = p - t.u[k].item_begin;
   Item it;
   it.unit = k;
-  it.blk = 2 * (c % 8) + c / 8;
-  const uint32_t poly = local / (256 / kCols);
-  it.limb = poly / t.u[k].batch;
-  it.poly_base = (size_t)poly << 16;
+  it.limb = local / t.u[k].batch;
+  it.poly_base = (size_t)local << 16;
   return it;
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Item tile in LDS, as the direct-to-LDS loads deposit it: region k (1 KiB)
+// holds rows 16k .. 16k+15 of the item's 16 columns; its 16-byte slot L holds
+// row 16k + L % 16, columns 4 (L / 16) .. 4 (L / 16) + 3.
+constexpr int kTile = 256 * kCols;  // words
+constexpr int kStages = 3;           // input ring depth (items in LDS)
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Each wave loads regions 4 wave .. 4 wave + 3 of an item: one 16-byte
+// direct-to-LDS load per lane per region (a 64-byte segment of 16 rows);
+// lane L's bytes land at the region base + 16 L.  Issued as inline assembly so
+// that the compiler does not serialise later LDS reads on these loads: the
+// pipeline waits for them explicitly (wait_item) before a barrier.
+__device__ __forceinline__ void issue_tile(const uint32_t* src, uint32_t* stage, int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = 4 * wave + j;
+    const uint32_t* g = src + (16 * k + (lane & 15)) * 256 + 4 * (lane >> 4);
+    const uint32_t lds_addr = (uint32_t)(uintptr_t)(lds_void_t*)(stage + k * 256);
+    asm volatile(
+        "s_mov_b32 m0, %0\n\t"
+        "global_load_lds_dwordx4 %1, off"
+        :
+        : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
+        : "memory", "m0");
+  }
+}
+
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every outstanding load): LDS writes of this wave are completed
+// first; the direct-to-LDS loads are covered by wait_item.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+}
+
+// Wait until this wave's loads of the current item have landed.  Vector
+// memory operations of a wave complete in issue order, so it suffices that at
+// most as many operations remain outstanding as were issued after those
+// loads: in steady state the stores of the two previous items (16 each in
+// pass 1, 4 in pass 2) and the loads of the next item (4); fewer near the
+// start; without a next item everything is awaited.  Table loads issued in
+// between only make the wait stricter.
+template <bool kFirst>
+__device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
+  constexpr int st = kFirst ? 16 : 4;
+  if (!has_next) wait_vmcnt<0>();
+  else if (n == 0) wait_vmcnt<4>();
+  else if (n == 1) wait_vmcnt<4 + st>();
+  else wait_vmcnt<4 + 2 * st>();
 }
 
 template <bool kFirst>
 __global__ void __launch_bounds__(kThreads)
 fs_pass(const FsTable tab) {
-  __shared__ uint32_t lds[kCols * kStride];
+  __shared__ __attribute__((aligned(16))) uint32_t ring[(kStages + (kFirst ? 0 : 1)) * kTile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int v = lane & 15, g = lane >> 4;
-  const uint32_t begin = blockIdx.x, stride = gridDim.x, total = tab.total;
-  if (begin >= total) return;
+  const Walk walk = make_walk(tab.total);
+  const uint32_t blk = walk.blk, p_begin = walk.p, p_end = walk.p_end;
+  if (p_begin >= p_end) return;
 
-  // this thread's four 16-byte row segments of a column block
-  uint4 pre[4];
-  uint32_t kf = 0, kc = 0;  // running unit indices of the fetch and compute walks
-  auto fetch = [&](uint32_t i) {
-    const Item it = decode_item(tab, i, kf);
-    const uint32_t* src = tab.u[it.unit].in + it.poly_base + it.blk * kCols;
-#pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4)
-      pre[r4] = *(const uint4*)(src + (r4 * 64 + (tid >> 2)) * 256 + 4 * (tid & 3));
+  uint32_t kf = 0, kc = 0;  // running unit indices of the load and compute walks
+  auto issue = [&](uint32_t p, int st) {
+    const Item it = locate(tab, p, kf);
+    issue_tile(tab.u[it.unit].in + it.poly_base + blk * kCols, ring + st * kTile, wave, lane);
   };
-  fetch(begin);
+#pragma unroll
+  for (int j = 0; j < kStages - 1; ++j)
+    if (p_begin + j < p_end) issue(p_begin + j, j);
 
   const FourStepLimb* cur_limb = nullptr;
-  uint32_t cur_blk = 0xFFFFFFFFu;
   uint32_t q = 0, qneg = 0;
-  const uint2* post = nullptr;
   v4i opA[4], opB[4];
   uint2 tw[4];
   uint2 pt[4][4];
-  for (uint32_t i = begin; i < total; i += stride) {
-    const Item it = decode_item(tab, i, kc);
+  int st = 0;
+  for (uint32_t p = p_begin; p < p_end; ++p, st = (st + 1 == kStages) ? 0 : st + 1) {
+    const uint32_t n = p - p_begin;
+    const Item it = locate(tab, p, kc);
     const FourStepLimb* limb = tab.u[it.unit].limbs + it.limb;
-    const uint32_t blk = it.blk;
-    __syncthreads();  // the previous item is done with the LDS tile
-#pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4) {
-      const int row = r4 * 64 + (tid >> 2), c0 = 4 * (tid & 3);
-      lds[lds_pos(c0 + 0, row)] = pre[r4].x;
-      lds[lds_pos(c0 + 1, row)] = pre[r4].y;
-      lds[lds_pos(c0 + 2, row)] = pre[r4].z;
-      lds[lds_pos(c0 + 3, row)] = pre[r4].w;
-    }
-    __syncthreads();
-    if (i + stride < total) fetch(i + stride);  // in flight while this item is computed
-
     if (limb != cur_limb) {
+      // rare (a few times per workgroup): completed here, so that the
+      // steady-state path carries no wait on these loads
       const FourStepLimb L = *limb;
       const PassTables* P = kFirst ? L.pass1 : L.pass2;
       q = L.q;
       qneg = L.qneg;
-      post = L.post1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         opA[j] = *(const v4i*)&P->opA[j][lane][0];
         opB[j] = *(const v4i*)&P->opB[j][lane][0];
         tw[j] = P->twist[lane][j];
       }
-      cur_limb = limb;
-      cur_blk = 0xFFFFFFFFu;
-    }
-    if (kFirst && blk != cur_blk) {
+      if (kFirst) {
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        const uint2* p = post + ((size_t)(blk * kCols + 4 * wave + cc) * 64 + lane) * 4;
+        for (int cc = 0; cc < 4; ++cc) {
+          const uint2* pp = L.post1 + ((size_t)(blk * kCols + 4 * wave + cc) * 64 + lane) * 4;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pt[cc][r] = p[r];
+          for (int r = 0; r < 4; ++r) pt[cc][r] = pp[r];
+        }
       }
-      cur_blk = blk;
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      cur_limb = limb;
     }
+    wait_item<kFirst>(n, p + 1 < p_end);
+    lds_barrier();  // the item's tile is complete; the oldest stage is free
+    if (p + kStages - 1 < p_end) issue(p + kStages - 1, (st + kStages - 1) % kStages);
+
+    // lane (v, g): rows 64g + 16c + v of the wave's four columns 4 wave .. +3
+    const uint32_t* tile = ring + st * kTile;
+    uint4 rows[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rows[c] = *(const uint4*)(tile + (4 * g + c) * 256 + (v + 16 * wave) * 4);
 
     const size_t base = it.poly_base;
     uint32_t* const out = tab.u[it.unit].out;
+    uint4 res[4];  // pass 2: res[r] = the four columns' outputs for row s + 64g + 16r
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
-      const int col = 4 * wave + cc;
       v4i x;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const uint32_t w = lds[lds_pos(col, 64 * g + 16 * c + v)];
+        const uint32_t w = cc == 0 ? rows[c].x : cc == 1 ? rows[c].y : cc == 2 ? rows[c].z : rows[c].w;
         x[c] = kFirst ? (int)balanced_digits(to_window(w, q)) : (int)w;
       }
       v4i acc[4];
       stage256(x, opA, opB, tw, q, qneg, acc);
       if (kFirst) {
         // post twist and row store: output k = s + 64g + 16r of vector col
+        const int col = 4 * wave + cc;
         uint32_t* dst = out + base + (blk * kCols + col) * 256 + v + 64 * g;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           dst[16 * r] = twist_digits(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg),
                                      pt[cc][r], q);
       } else {
-        // the wave owns this vector's LDS column: overwrite it with the output
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          lds[lds_pos(col, v + 64 * g + 16 * r)] =
-              reduce_once(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg), q);
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t y = reduce_once(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg), q);
+          if (cc == 0) res[r].x = y;
+          else if (cc == 1) res[r].y = y;
+          else if (cc == 2) res[r].z = y;
+          else res[r].w = y;
+        }
       }
     }
 
     if (!kFirst) {
-      __syncthreads();
+      // output tile in the input layout, then 16-byte row-segment stores
+      uint32_t* otile = ring + kStages * kTile;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *(uint4*)(otile + (4 * g + r) * 256 + (v + 16 * wave) * 4) = res[r];
+      lds_barrier();
       uint32_t* dst = out + base + blk * kCols;
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const int row = r4 * 64 + (tid >> 2), c0 = 4 * (tid & 3);
-        *(uint4*)(dst + row * 256 + c0) =
-            make_uint4(lds[lds_pos(c0, row)], lds[lds_pos(c0 + 1, row)], lds[lds_pos(c0 + 2, row)],
-                       lds[lds_pos(c0 + 3, row)]);
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * wave + j;
+        *(uint4*)(dst + (16 * k + (lane & 15)) * 256 + 4 * (lane >> 4)) =
+            *(const uint4*)(otile + k * 256 + lane * 4);
       }
     }
   }
@@ -259,11 +329,12 @@ static uint32_t occupancy(bool first) {
 }
 
 // Persistent grid: resident workgroups of the whole device, rounded down to a
-// multiple of the 16 column blocks of a polynomial.
-static uint32_t grid_size(const tfhe_ntt_plan_s* p, bool first, uint32_t total) {
+// multiple of 16 (one workgroup per column block in each group), and at most
+// 16 per polynomial.
+static uint32_t grid_size(const tfhe_ntt_plan_s* p, bool first, uint32_t polys) {
   const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy(first);
   uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
-  return std::min(g, total);
+  return std::min(g, 16 * polys);
 }
 
 }  // namespace
@@ -291,7 +362,7 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     const tfhe_ntt_plan_s* p0 = nullptr;
     for (uint32_t k = 0; k < n; ++k) {
       const NttUnit& u = units[first + k];
-      const uint32_t items = u.limb_count * u.batch * (256 / kCols);
+      const uint32_t items = u.limb_count * u.batch;  // polynomials
       if (items == 0) continue;
       p0 = u.plan;
       const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;

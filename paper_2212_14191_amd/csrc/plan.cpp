@@ -94,15 +94,36 @@ static int8_t digit(uint32_t w, uint32_t q, int j) {
 
 typedef uint32_t Mat16[16][16];
 
-// Lay out one 16 x 16 pass (WA[u][s], T[s][v], WB[t][v]) as MFMA operands.
-// Level A contracts over u with the data as MFMA A operand: lane (v, g) holds
-// u = 4g + c, byte 4c + d pairs data digit d with digit j of 2^{8d} WA[u][s].
-// Level B contracts over v with the twiddle as MFMA A operand: lane (t, g)
-// holds v = 4g + c.  After level A, lane (s, g) holds v = 4g + r.  The twist
-// carries the factor 2^32 that cancels the Montgomery reduction of the level-A
-// fusion; wb_scale multiplies WB (2^32 when level B is the transform's last).
-static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Mat16& WB, uint32_t q,
-                       uint32_t wb_scale) {
+// Level-A data row of MFMA row i is (column m, element v) with i = m r + v;
+// after level A lane (s, g) register j holds row i = 4g + j.  After level B
+// register j holds output t of column m:
+//   r = 16: m = 0, t = 4g + j      r = 8: m = g / 2, t = 2j + g % 2
+//   r = 4:  m = g, t = j           r = 2: m = 2g + j / 2, t = j % 2
+//   r = 1:  m = 4g + j, t = 0
+static void lane_output(int r, int lane, int j, int* m, int* t) {
+  const int g = lane / 16;
+  switch (r) {
+    case 16: *m = 0; *t = 4 * g + j; break;
+    case 8: *m = g / 2; *t = 2 * j + g % 2; break;
+    case 4: *m = g; *t = j; break;
+    case 2: *m = 2 * g + j / 2; *t = j % 2; break;
+    default: *m = 4 * g + j; *t = 0; break;
+  }
+}
+
+// Columns a wave handles per tile (of its four): 16 / r, at most 4.
+static int cols_per_tile(int r) { return r >= 16 ? 1 : std::min(4, 16 / r); }
+
+// Lay out one pass (WA[u][s], T[s][v], WB[t][v] (r = 16), lb) as MFMA
+// operands.  Level A contracts over u with the data as MFMA A operand: lane
+// (i, g) holds u = 4g + c, byte 4c + d pairs data digit d with digit j of
+// 2^{8d} WA[u][s].  Level B (r = 16) contracts over v with the twiddle as MFMA
+// A operand: lane (t, g) holds v = 4g + c.  The twist carries the factor 2^32
+// that cancels the Montgomery reduction of the level-A fusion; wb_scale
+// multiplies WB (2^32 when level B is the transform's last).
+static void build_pass(PassTables& pt, int r, const Mat16& WA, const Mat16& T, const Mat16& WB,
+                       uint32_t q, uint32_t wb_scale, const uint32_t* lb) {
+  memset(&pt, 0, sizeof(pt));
   uint32_t p2[4];
   for (int d = 0; d < 4; ++d) p2[d] = pow_mod(2, 8 * d, q);
   for (int j = 0; j < 4; ++j)
@@ -111,9 +132,11 @@ static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Ma
       for (int c = 0; c < 4; ++c) {
         uint32_t a = 0, b = 0;
         for (int d = 0; d < 4; ++d) {
-          uint32_t wb = mulm(WB[col][4 * g + c], wb_scale, q);
           a |= (uint32_t)(uint8_t)digit(mulm(p2[d], WA[4 * g + c][col], q), q, j) << (8 * d);
-          b |= (uint32_t)(uint8_t)digit(mulm(p2[d], wb, q), q, j) << (8 * d);
+          if (r == 16) {
+            uint32_t wb = mulm(WB[col][4 * g + c], wb_scale, q);
+            b |= (uint32_t)(uint8_t)digit(mulm(p2[d], wb, q), q, j) << (8 * d);
+          }
         }
         pt.opA[j][lane][c] = a;
         pt.opB[j][lane][c] = b;
@@ -121,23 +144,32 @@ static void build_pass(PassTables& pt, const Mat16& WA, const Mat16& T, const Ma
     }
   uint32_t r32 = (uint32_t)((1ull << 32) % q);
   for (int lane = 0; lane < 64; ++lane)
-    for (int r = 0; r < 4; ++r) {
-      uint32_t w = mulm(T[lane % 16][4 * (lane / 16) + r], r32, q);
-      pt.twist[lane][r] = make_uint2(w, shoup_companion(w, q));
+    for (int j = 0; j < 4; ++j) {
+      const int v = (4 * (lane / 16) + j) % r;
+      uint32_t w = mulm(T[lane % 16][v], r32, q);
+      pt.twist[lane][j] = make_uint2(w, shoup_companion(w, q));
     }
+  for (int i = 0; i < 16; ++i) {
+    uint32_t w = lb ? lb[i] % q : 0;
+    pt.lb[i] = make_uint2(w, shoup_companion(w, q));
+  }
 }
 
-// post[col][lane][r] = P(col, k) 2^32 with k = s + 16 (4g + r) the output
-// index lane (s, g) holds in register r after level B.
+// post[col0][lane][j]: the post-twist P(column, output) of the value lane
+// `lane` holds in register j after level B, for the tile whose first column
+// is col0 (column = col0 + m, output = s + 16 t).  `scale` is 2^32 when the
+// value still carries the Montgomery factor (r = 16), else 1.
 template <typename F>
-static void build_post(uint2* post, uint32_t q, F P) {
-  uint32_t r32 = (uint32_t)((1ull << 32) % q);
-  for (int col = 0; col < 256; ++col)
+static void build_post(uint2* post, int r, int ncols, uint32_t q, uint32_t scale, F P) {
+  const int cpt = cols_per_tile(r);
+  for (int col0 = 0; col0 < 256; ++col0)
     for (int lane = 0; lane < 64; ++lane)
-      for (int r = 0; r < 4; ++r) {
-        int k = lane % 16 + 16 * (4 * (lane / 16) + r);
-        uint32_t w = mulm(P(col, k), r32, q);
-        post[(col * 64 + lane) * 4 + r] = make_uint2(w, shoup_companion(w, q));
+      for (int j = 0; j < 4; ++j) {
+        int m, t;
+        lane_output(r, lane, j, &m, &t);
+        const int col = col0 + m, k = lane % 16 + 16 * t;
+        uint32_t w = (m < cpt && col < ncols) ? mulm(P(col, k), scale, q) : 0;
+        post[(col0 * 64 + lane) * 4 + j] = make_uint2(w, shoup_companion(w, q));
       }
 }
 
@@ -146,59 +178,74 @@ struct FsHostLimb {
   std::vector<uint2> post;
 };
 
-// Four-step tables for N = 2^16 = 256 x 256, n = 256 n1 + n2, k = k1 + 256 k2:
+// Four-step tables for N = N1 x 256 (N1 = 16 r), n = 256 n1 + n2,
+// k = k1 + N1 k2:
 //   A_k = sum_{n2} w^{k2 n2} psi^{(2k1+1) n2} sum_{n1} phi^{(2k1+1) n1} a[n1][n2]
-// with phi = psi^256 (primitive 512th root) and w = psi^512 (primitive 256th
-// root); each 256-point stage is itself split 16 x 16 (n = 16u + v,
-// k = s + 16t).  Returns the forward (dir = 0) or inverse (dir = 1) tables.
-static void build_fourstep_limb(FsHostLimb& L, uint32_t q, uint32_t psi, int dir) {
-  const uint32_t N = 1u << 16;
-  uint32_t phi = pow_mod(psi, 256, q), om = pow_mod(psi, 512, q);
-  uint32_t phii = inv_mod(phi, q), omi = inv_mod(om, q), psii = inv_mod(psi, q);
-  uint32_t ninv = inv_mod(N % q, q);
+// with phi = psi^256 (order 2 N1) and w = psi^{2 N1} (order 256).  The
+// N1-point stage splits as n1 = r u + v, k1 = s + 16 t; the 256-point stage
+// as n2 = 16 u + v, k2 = s + 16 t.  Forward: pass 1 = N1-point over columns
+// (+ psi^{(2k1+1) n2}), pass 2 = 256-point.  Inverse: pass 1 = 256-point with
+// w^{-1} (+ psi^{-(2k1+1) n2}), pass 2 = N1-point
+//   a[s + 16t] = N^{-1} phi^{-s} phi^{-16t} sum_v phi^{-32vt} phi^{-2vs}
+//                sum_u phi^{-2rus} Y[ru + v].
+static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint32_t psi, int dir) {
+  const uint32_t N = 1u << log_n, N1 = N / 256;
+  const int r = (int)(N1 / 16);
+  const uint64_t twoN = 2ull * N;
+  const uint32_t phi = pow_mod(psi, 256, q), om = pow_mod(psi, 2 * N1, q);
+  const uint32_t phii = inv_mod(phi, q), omi = inv_mod(om, q), psii = inv_mod(psi, q);
+  const uint32_t ninv = inv_mod(N % q, q), r32 = (uint32_t)((1ull << 32) % q);
   Mat16 WA, T, WB;
+  uint32_t lb[16];
+  auto cyc256 = [&](PassTables& pt, uint32_t root, uint32_t scale) {
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b) {
+        WA[a][b] = pow_mod(root, 16ull * a * b, q);
+        T[a][b] = pow_mod(root, (uint64_t)a * b, q);
+        WB[a][b] = pow_mod(root, 16ull * a * b, q);
+      }
+    build_pass(pt, 16, WA, T, WB, q, scale, nullptr);
+  };
+  L.post.resize(256 * 64 * 4);
   if (dir == 0) {
     for (int a = 0; a < 16; ++a)
       for (int b = 0; b < 16; ++b) {
-        WA[a][b] = pow_mod(phi, 16ull * (2 * b + 1) * a, q);  // [u][s]
-        T[a][b] = pow_mod(phi, (uint64_t)(2 * a + 1) * b, q);   // [s][v]
-        WB[a][b] = pow_mod(phi, 32ull * a * b, q);              // [t][v]
+        WA[a][b] = pow_mod(phi, (uint64_t)r * (2 * b + 1) * a, q);  // [u][s]
+        T[a][b] = pow_mod(phi, (uint64_t)(2 * a + 1) * b, q);       // [s][v]
+        WB[a][b] = pow_mod(phi, 32ull * a * b, q);                  // [t][v]
       }
-    build_pass(L.p1, WA, T, WB, q, 1);
-    for (int a = 0; a < 16; ++a)
-      for (int b = 0; b < 16; ++b) {
-        WA[a][b] = pow_mod(om, 16ull * a * b, q);
-        T[a][b] = pow_mod(om, (uint64_t)a * b, q);
-        WB[a][b] = pow_mod(om, 16ull * a * b, q);
-      }
-    build_pass(L.p2, WA, T, WB, q, (uint32_t)((1ull << 32) % q));
-    L.post.resize(256 * 64 * 4);
+    const uint32_t rho = pow_mod(phi, 32, q);
+    for (int i = 0; i < 16; ++i) lb[i] = i < 8 ? pow_mod(rho, i, q) : 1;
+    build_pass(L.p1, r, WA, T, WB, q, 1, lb);
+    cyc256(L.p2, om, r32);
     // column n2, output k1: psi^{(2 k1 + 1) n2}
-    build_post(L.post.data(), q, [&](int n2, int k1) {
-      return pow_mod(psi, (uint64_t)(2 * k1 + 1) * n2 % (2 * N), q);
+    build_post(L.post.data(), r, 256, q, r == 16 ? r32 : 1, [&](int n2, int k1) {
+      return pow_mod(psi, (uint64_t)(2 * k1 + 1) * n2 % twoN, q);
     });
   } else {
-    // inverse pass 1: for each k1, cyclic over k2 with root w^{-1}
-    for (int a = 0; a < 16; ++a)
-      for (int b = 0; b < 16; ++b) {
-        WA[a][b] = pow_mod(omi, 16ull * a * b, q);
-        T[a][b] = pow_mod(omi, (uint64_t)a * b, q);
-        WB[a][b] = pow_mod(omi, 16ull * a * b, q);
-      }
-    build_pass(L.p1, WA, T, WB, q, 1);
-    // inverse pass 2: for each n2, out n1 = s + 16t from in k1 = 16u + v:
-    // N^{-1} phi^{-2 k1 n1 - n1}
-    for (int a = 0; a < 16; ++a)
-      for (int b = 0; b < 16; ++b) {
-        WA[a][b] = pow_mod(phii, 32ull * a * b, q);                    // [u][s]
-        T[a][b] = pow_mod(phii, (uint64_t)(2 * b + 1) * a, q);         // [s][v]
-        WB[a][b] = mulm(pow_mod(phii, (uint64_t)(32 * b + 16) * a, q), ninv, q);  // [t][v]
-      }
-    build_pass(L.p2, WA, T, WB, q, (uint32_t)((1ull << 32) % q));
-    L.post.resize(256 * 64 * 4);
+    cyc256(L.p1, omi, 1);
+    if (r == 16) {
+      for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) {
+          WA[a][b] = pow_mod(phii, 32ull * a * b, q);                               // [u][s]
+          T[a][b] = pow_mod(phii, (uint64_t)(2 * b + 1) * a, q);                    // [s][v]
+          WB[a][b] = mulm(pow_mod(phii, (uint64_t)(32 * b + 16) * a, q), ninv, q);  // [t][v]
+        }
+      build_pass(L.p2, 16, WA, T, WB, q, r32, nullptr);
+    } else {
+      for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) {
+          WA[a][b] = pow_mod(phii, 2ull * r * a * b, q);                             // [u][s]
+          T[a][b] = mulm(pow_mod(phii, (uint64_t)(2 * b + 1) * a, q), ninv, q);     // [s][v]
+          WB[a][b] = 0;
+        }
+      const uint32_t rho = pow_mod(phii, 32, q);
+      for (int i = 0; i < 16; ++i) lb[i] = i < 8 ? pow_mod(rho, i, q) : pow_mod(phii, 16ull * (i - 8), q);
+      build_pass(L.p2, r, WA, T, WB, q, 1, lb);
+    }
     // column k1, output n2: psi^{-(2 k1 + 1) n2}
-    build_post(L.post.data(), q, [&](int k1, int n2) {
-      return pow_mod(psii, (uint64_t)(2 * k1 + 1) * n2 % (2 * N), q);
+    build_post(L.post.data(), 16, (int)N1, q, r32, [&](int k1, int n2) {
+      return pow_mod(psii, (uint64_t)(2 * k1 + 1) * n2 % twoN, q);
     });
   }
 }
@@ -256,7 +303,7 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
     for (uint32_t l = 0; l < L; ++l)
       for (int dir = 0; dir < 2; ++dir) {
         FsHostLimb H;
-        build_fourstep_limb(H, p->q[l], p->psi[l], dir);
+        build_fourstep_limb(H, p->log_n, p->q[l], p->psi[l], dir);
         size_t off = per * (2 * l + dir);
         memcpy(&blob[off], &H.p1, sizeof(PassTables));
         memcpy(&blob[off + sizeof(PassTables)], &H.p2, sizeof(PassTables));

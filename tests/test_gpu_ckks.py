@@ -123,3 +123,34 @@ def test_device_keygen_and_encryption_match_oracle(tf):
     ee = inputs.gaussian_error(2, (3, n), stream=9)
     got = to_host(sch.encrypt(s, m, c1, ee, 5))
     assert np.array_equal(got, ckks.encrypt(pr, s, m, c1, ee, 5))
+
+
+def test_graph_replay_matches_eager(tf):
+    """HMULT and HROTATE captured once as a HIP graph and replayed with new
+    inputs, with eager work and synchronisation between replays: every replay
+    equals the eager result bit for bit."""
+    from paper_2212_14191_amd.graphs import CapturedOp
+    n = 1 << 12
+    L, K, dnum, level, B = 6, 2, 3, 5, 3
+    pr, s, evk, (a, e) = setup(n, L, K, dnum)
+    ctx = tf.CkksContext(12, L, K, dnum, moduli=pr.moduli)
+    k = ckks.galois_element(3, n)
+    rk = to_dev(ckks.rotation_key(pr, s, k, a, e))
+    evk_d = to_dev(evk)
+    g_mul = CapturedOp(ctx, evk_d, level, B, op=0)
+    g_rot = CapturedOp(ctx, rk, level, B, op=1, galois=k)
+    for rep in range(3):
+        m1 = inputs.small_messages(rep, (B, n))
+        m2 = inputs.small_messages(rep + 10, (B, n))
+        ca, cb = to_dev(encrypt(pr, s, m1, level, 1 + rep)), to_dev(encrypt(pr, s, m2, level, 5 + rep))
+        eager_mul = ctx.hmult(ca, cb, evk_d, level)
+        eager_rot = ctx.rotate(ca, rk, k, level)
+        torch.cuda.synchronize()
+        got_mul = g_mul.run(ca, cb).clone()
+        got_rot = g_rot.run(ca).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(got_mul, eager_mul), rep
+        assert torch.equal(got_rot, eager_rot), rep
+        if rep == 0:
+            want = ckks.hmult(pr, to_host(ca), to_host(cb), evk, level)
+            assert np.array_equal(to_host(got_mul), want)
