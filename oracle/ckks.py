@@ -30,6 +30,12 @@ Dcomp, ModUp, Inner-product, ModDown), with these readings:
   d2 = c1c1' (NTT domain); no rescale.
 * HROTATE(ct, k) = (sigma_k(c0), 0) + KS_k(sigma_k(c1)), the automorphism
   X -> X^k applied here in the coefficient domain.
+* RESCALE (Sec. II-B; Table 2: NTT and Ele-Sub) divides by the top modulus
+  q_t = q_{l-1} and drops its limb: t = INTT(c_t) taken in [0, q_t), then
+  c'_i = (c_i - NTT_i(t mod q_i)) * q_t^{-1} mod q_i for i < l-1, i.e. the
+  exact floor(C / q_t) of the CRT value C in [0, Q_l) (no rounding offset).
+* CMULT(ct, p) = (c0 o p, c1 o p) and HADD(ct, ct') = (c0 + c0', c1 + c1'),
+  element-wise in the NTT domain (Sec. II-B).
 
 Arrays: ciphertexts uint32 [2][level][batch][N] in the NTT domain; keys
 uint32 [dnum][2][L+K][N] in the NTT domain, q-limbs first, then p-limbs.
@@ -300,6 +306,37 @@ def rotate(pr, ct, rk, k, level):
     r1 = _ntt(pr, automorphism_coeff(_intt(pr, ct[1], idx), k, qs), idx)
     o0, o1 = key_switch(pr, r1, rk, level)
     return np.stack([add(r0, o0, qs), o1])
+
+
+def rescale(pr, ct, level):
+    """RESCALE (Sec. II-B, Table 2): ct [2][level][B][N] (NTT domain) at
+    `level` >= 2 -> [2][level-1][B][N], dividing by q_{level-1}."""
+    if level < 2:
+        raise ValueError("rescale needs level >= 2")
+    top = level - 1
+    qt = pr.q[top]
+    idx = list(range(top))
+    qs = pr.mods(idx)
+    out = np.empty((2, top) + ct.shape[2:], dtype=np.uint32)
+    for c in range(2):
+        t = _intt(pr, ct[c][top:top + 1], [top])[0].astype(np.uint64)  # [B][N] in [0, q_t)
+        t_mod = np.stack([(t % np.uint64(qi)).astype(np.uint32) for qi in qs])
+        diff = sub(ct[c][:top], _ntt(pr, t_mod, idx), qs)
+        qinv = np.array([pow(qt % qi, -1, qi) for qi in qs], dtype=np.uint32).reshape(-1, 1, 1)
+        out[c] = mul(diff, np.broadcast_to(qinv, diff.shape), qs)
+    return out
+
+
+def cmult(pr, ct, pt, level):
+    """CMULT (Sec. II-B): (c0 o p, c1 o p); pt [level][B][N], NTT domain."""
+    qs = pr.mods(range(level))
+    return np.stack([mul(ct[0], pt, qs), mul(ct[1], pt, qs)])
+
+
+def hadd(pr, ct_a, ct_b, level):
+    """HADD (Sec. II-B): component-wise addition."""
+    qs = pr.mods(range(level))
+    return np.stack([add(ct_a[0], ct_b[0], qs), add(ct_a[1], ct_b[1], qs)])
 
 
 def negacyclic_int(a, b):

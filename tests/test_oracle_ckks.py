@@ -223,3 +223,82 @@ def test_rotate_decrypts_to_rotated_message():
     for b in range(2):
         got = np.array([(int(v) + delta // 2) // delta for v in dec[b]], dtype=np.int64)
         assert np.array_equal(got, ckks.automorphism_int(m[b], k))
+
+
+# ------------------------------------------------------------------ RESCALE
+@pytest.mark.parametrize("level", [2, 4, 6])
+def test_rescale_is_floor_division_by_top_modulus(level):
+    """Coefficient-wise, RESCALE is floor(C / q_{l-1}) of the CRT value C in
+    [0, Q_l) (Garner CRT in Python integers), reduced mod each q_i, i < l-1."""
+    pr = small_params(32)
+    idx = list(range(level))
+    qs, ps = pr.mods(idx), pr.psis(idx)
+    ct = np.stack([inputs.uniform_residues(40 + c, qs, (2, pr.n)) for c in range(2)])
+    got = ckks.rescale(pr, ct, level)
+    assert got.shape == (2, level - 1, 2, pr.n)
+    qt = qs[-1]
+    for c in range(2):
+        coef = oracle.ntt_inv(ct[c], qs, ps)
+        got_coef = oracle.ntt_inv(got[c], qs[:-1], ps[:-1])
+        for b in range(2):
+            for k in range(pr.n):
+                C = tiny.crt([int(coef[i, b, k]) for i in range(level)], qs)
+                want = C // qt
+                assert [int(got_coef[i, b, k]) for i in range(level - 1)] == [want % q for q in qs[:-1]]
+
+
+@pytest.mark.parametrize("level", [6, 3])
+def test_rescale_decrypts_to_scaled_message(level):
+    """Dec(RESCALE(ct)) = Dec(ct) / q_{l-1} up to |r0 + r1 s| / q_{l-1} <= 1 + h
+    (r0, r1 in [0, q_{l-1}) are the dropped residues, h the secret's weight)."""
+    pr = small_params(256)
+    s, _, _ = make_keys(pr)
+    h = int(np.count_nonzero(s))
+    m = inputs.small_messages(0, (2, pr.n))
+    ct = enc(pr, s, m, level, 3)
+    dec = ckks.decrypt(pr, s, ct, level)
+    dec2 = ckks.decrypt(pr, s, ckks.rescale(pr, ct, level), level - 1)
+    qt = pr.q[level - 1]
+    err = max(abs(int(d2) * qt - int(d)) for d, d2 in zip(dec.ravel(), dec2.ravel()))
+    assert err <= (1 + h) * qt
+    assert err > 0  # the division is not exact for these inputs
+
+
+def test_rescale_after_hmult_recovers_product():
+    """HMULT then RESCALE: Delta^2 m1 m2 / q_{l-1} rounds back to m1*m2 at the
+    new scale Delta^2 / q_{l-1}."""
+    pr = small_params(256)
+    s, a, e = make_keys(pr)
+    evk = ckks.relin_key(pr, s, a, e)
+    level = 6
+    m1 = inputs.small_messages(0, (1, pr.n))
+    m2 = inputs.small_messages(0, (1, pr.n), stream=1)
+    out = ckks.hmult(pr, enc(pr, s, m1, level, 1), enc(pr, s, m2, level, 2), evk, level)
+    dec = ckks.decrypt(pr, s, ckks.rescale(pr, out, level), level - 1)
+    scale = (1 << 60) / pr.q[level - 1]
+    want = ckks.negacyclic_int(m1[0], m2[0])
+    got = np.array([round(int(v) / scale) for v in dec[0]], dtype=np.int64)
+    assert np.array_equal(got, want)
+
+
+def test_cmult_and_hadd_decrypt_exactly():
+    """CMULT by a plaintext p (NTT of a small integer polynomial) decrypts to
+    p * (Delta m + e) exactly; HADD to the sum of the two decryptions."""
+    pr = small_params(64)
+    s, _, _ = make_keys(pr)
+    level = 4
+    idx = list(range(level))
+    qs, ps = pr.mods(idx), pr.psis(idx)
+    m1 = inputs.small_messages(0, (2, pr.n))
+    m2 = inputs.small_messages(0, (2, pr.n), stream=1)
+    c1, c2 = enc(pr, s, m1, level, 1), enc(pr, s, m2, level, 2)
+    d1, d2 = ckks.decrypt(pr, s, c1, level), ckks.decrypt(pr, s, c2, level)
+    dsum = ckks.decrypt(pr, s, ckks.hadd(pr, c1, c2, level), level)
+    assert np.array_equal(dsum.astype(np.int64), d1.astype(np.int64) + d2.astype(np.int64))
+    p = inputs.small_messages(7, (2, pr.n))
+    pt = oracle.ntt_fwd(oracle.to_residues(p, qs), qs, ps)
+    dprod = ckks.decrypt(pr, s, ckks.cmult(pr, c1, pt, level), level)
+    for b in range(2):
+        want = [sum(int(d1[b, i]) * int(p[b, (k - i) % pr.n]) * (1 if i <= k else -1) for i in range(pr.n))
+                for k in range(pr.n)]
+        assert [int(v) for v in dprod[b]] == want
