@@ -12,8 +12,10 @@ dnum=3, 64 ciphertext pairs), and the plain CPU oracle on a bounded sample.
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +29,36 @@ LOG_N, LIMBS, BATCH = 16, 44, 128
 HM_L, HM_K, HM_DNUM, HM_BATCH = 24, 8, 3, 64
 METRIC = "NTT KOPS & HMULT ops/s at N=2^16, MFMA vs butterfly; p99 request latency"
 HBM_PEAK_GBS = 8000.0
+
+
+# Sources that determine the four-step kernels' memory traffic; the profile
+# summary records their hash next to the hardware byte counts.
+TRAFFIC_SOURCES = ("csrc/ntt_fourstep.hip", "csrc/internal.hpp", "csrc/modarith.hpp", "csrc/plan.cpp")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ntt_mfma_n16_44x128.md")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2212_14191_amd", rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when the summary is missing or was taken from
+    different kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            m = re.search(r"^traffic: (\{.*\})$", f.read(), re.M)
+        d = json.loads(m.group(1)) if m else None
+    except (OSError, ValueError):
+        return None
+    if not d or d.get("source_sha256") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(kernel)
 
 
 def log(*a):
@@ -241,7 +273,22 @@ def main():
         hmult = {"ops_per_s": HM_BATCH * args.hmult_steps / dt, "ms_per_batch": 1e3 * dt / args.hmult_steps,
                  "batch": HM_BATCH, "level": level, "kernels": kern}
         log("hmult", json.dumps(hmult))
-        del cts, out, hws, evk, ctx
+        # RESCALE of the HMULT results (level 24 -> 23), same batch
+        rs_out = torch.empty((2, level - 1, HM_BATCH, n), dtype=torch.int32, device="cuda")
+        rws = ctx.rescale_workspace(level, HM_BATCH)
+        rstep = lambda: ctx.rescale(out, level, out=rs_out, ws=rws)
+        rstep()
+        tfhe.tfhe_timing_enable(True)
+        dt = timed(rstep, args.hmult_steps, sync)
+        rk = {}
+        for name in ("ntt_mfma_pass1", "ntt_mfma_pass2", "ckks_rescale_bcast", "ckks_rescale_final"):
+            cnt, ms = tfhe.tfhe_timing_read(name)
+            rk[name] = {"launches": cnt, "total_ms": ms}
+        tfhe.tfhe_timing_enable(False)
+        hmult["rescale"] = {"ops_per_s": HM_BATCH * args.hmult_steps / dt,
+                            "ms_per_batch": 1e3 * dt / args.hmult_steps, "kernels": rk}
+        log("rescale", json.dumps(hmult["rescale"]))
+        del cts, out, hws, evk, ctx, rs_out, rws
 
     serving = None
     if not args.skip_serving and args.only is None:
@@ -274,7 +321,8 @@ def main():
                    if "mfma" in results else "negacyclic NTT+INTT, N=2^16, 44 limbs x 128 polys, butterfly",
                    "log_n": LOG_N, "limbs": LIMBS, "batch": BATCH, "primes": "31-bit, q = 1 mod 2^17"},
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(kname) if "mfma" in results else None,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(kstat["avg_ms"], 4)},
         "cpu_baseline": cpu,
@@ -285,6 +333,7 @@ def main():
     line["kernels"] = {k: v for r in results.values() for k, v in r["kernels"].items()}
     if hmult:
         line["hmult_ops_per_s"] = round(hmult["ops_per_s"], 1)
+        line["rescale_ops_per_s"] = round(hmult["rescale"]["ops_per_s"], 1)
         line["hmult"] = hmult
     if serving:
         line["p99_ms"] = serving["runs"][0]["p99_ms"]

@@ -84,7 +84,7 @@ tfhe_status tfhe_default_psi(uint32_t q, uint32_t log_n, uint32_t* psi);
  *   algo: transform used by tfhe_ntt_fwd/inv; AUTO picks per N.
  * Builds the twiddle tables of both algorithms on the device (Sec. III-B:
  * "pre-computed in the initialization and reused").  Synchronous.
- * log_n in [4, 16]; the MFMA algorithm covers log_n in {8, 12, 16}.
+ * log_n in [4, 16]; the MFMA algorithm covers log_n in [12, 16] (N = N1 x 256).
  * Errors: TFHE_ENOTNTT for a bad modulus/root, TFHE_EINVAL, TFHE_ENOMEM. */
 tfhe_status tfhe_ntt_plan_create(tfhe_ntt_plan* out, uint32_t log_n, uint32_t n_limbs,
                                  const uint32_t* q, const uint32_t* psi, tfhe_ntt_algo algo);
@@ -227,6 +227,34 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
                         const uint32_t* rotkey, uint32_t galois_elt, uint32_t level,
                         uint32_t batch, void* ws, size_t ws_bytes, tfhe_stream_t stream);
 
+/* Device workspace (bytes) tfhe_rescale needs at this level (>= 2) and
+ * batch. */
+tfhe_status tfhe_rescale_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch,
+                                        size_t* bytes);
+
+/* RESCALE (Sec. II-B; kernels of Table 2: NTT and Ele-Sub): divides every
+ * ciphertext by the top modulus q_t = q_{level-1} and drops that limb.  Per
+ * component: t = INTT(c_t) in [0, q_t); c'_i = (c_i - NTT(t mod q_i)) *
+ * q_t^{-1} mod q_i for i < level-1, i.e. floor(C / q_t) of the CRT value C
+ * in [0, Q_level) (no rounding offset).
+ *   ct_in: device [2][level][batch][N], NTT domain, level in [2, L].
+ *   ct_out: device [2][level-1][batch][N]; must not overlap ct_in.
+ *   ws: >= tfhe_rescale_workspace_size bytes, 256-byte aligned. */
+tfhe_status tfhe_rescale(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out, uint32_t level,
+                         uint32_t batch, void* ws, size_t ws_bytes, tfhe_stream_t stream);
+
+/* CMULT (Sec. II-B; Hada-Mult): ct_out = (c0 o p, c1 o p) for each of
+ * `batch` ciphertexts with its own plaintext.
+ *   ct, ct_out: device [2][level][batch][N]; pt: device [level][batch][N];
+ *   all NTT domain; ct_out may alias ct (element-wise). */
+tfhe_status tfhe_cmult(tfhe_ckks_ctx ctx, const uint32_t* ct, const uint32_t* pt, uint32_t* ct_out,
+                       uint32_t level, uint32_t batch, tfhe_stream_t stream);
+
+/* HADD (Sec. II-B; Ele-Add): ct_out = ct_a + ct_b component-wise.
+ *   device [2][level][batch][N] each; ct_out may alias either input. */
+tfhe_status tfhe_hadd(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b, uint32_t* ct_out,
+                      uint32_t level, uint32_t batch, tfhe_stream_t stream);
+
 /* FrobeniusMap alone (Sec. III-A): out_j = in_{pi(j)} on every polynomial of
  * a [limb_count][batch][N] array (NTT domain).  out must not alias in. */
 tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t* out,
@@ -244,7 +272,8 @@ tfhe_status tfhe_timing_enable(int enable);
  * `kernel` since timing was enabled; waits for the recorded events.  Names:
  * ntt_mfma_pass1, ntt_mfma_pass2, ntt_bf_single, ntt_bf_cols, ntt_bf_rows,
  * elementwise, ckks_tensor, ckks_modup, ckks_inner, ckks_moddown_conv,
- * ckks_moddown_final, frobenius.  Unknown name: TFHE_EINVAL. */
+ * ckks_moddown_final, frobenius, ckks_rescale_bcast, ckks_rescale_final.
+ * Unknown name: TFHE_EINVAL. */
 tfhe_status tfhe_timing_read(const char* kernel, uint64_t* launches, double* total_ms);
 
 #ifdef __cplusplus

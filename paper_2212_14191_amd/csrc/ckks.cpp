@@ -125,6 +125,61 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   return hipSuccess;
 }
 
+// RESCALE workspace: the top limbs in the coefficient domain [2][B][N], their
+// broadcast to the remaining limbs [2][top][B][N], the transforms' workspace.
+struct RsLayout {
+  size_t t, u, ntt, total;
+};
+
+static RsLayout rs_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t batch) {
+  const size_t plane = (size_t)batch * c->n * sizeof(uint32_t);
+  const uint32_t top = level - 1;
+  const tfhe_ntt_plan_s* p = c->plan;
+  const bool mfma = p->algo == TFHE_NTT_FOURSTEP_MFMA;
+  // the larger of the two fused transforms (2 x one limb, 2 x top limbs)
+  const size_t a = 2 * align256(unit_ws_bytes(NttUnit{p, true, nullptr, nullptr, top, 1, batch}, mfma));
+  const size_t b = 2 * align256(unit_ws_bytes(NttUnit{p, false, nullptr, nullptr, 0, top, batch}, mfma));
+  RsLayout l;
+  size_t off = 0;
+  l.t = off; off += align256(2 * plane);
+  l.u = off; off += align256(2 * plane * top);
+  l.ntt = off; off += std::max(a, b);
+  l.total = off;
+  return l;
+}
+
+// RESCALE of ct [2][level][B][N] (NTT domain) into out [2][level-1][B][N].
+static hipError_t rescale(const tfhe_ckks_ctx_s* c, const uint32_t* ct, uint32_t* out, uint32_t level,
+                          uint32_t batch, unsigned char* ws, hipStream_t s) {
+  const tfhe_ntt_plan_s* p = c->plan;
+  const RsLayout lay = rs_layout(c, level, batch);
+  const uint64_t plane = (uint64_t)batch * c->n;
+  const uint32_t top = level - 1;
+  uint32_t* t = (uint32_t*)(ws + lay.t);
+  uint32_t* u = (uint32_t*)(ws + lay.u);
+  void* nws = ws + lay.ntt;
+  hipError_t e;
+  // INTT of both components' top limb
+  if ((e = ntt_units(p, {NttUnit{p, true, ct + (uint64_t)top * plane, t, top, 1, batch},
+                         NttUnit{p, true, ct + (uint64_t)(level + top) * plane, t + plane, top, 1, batch}},
+                     nws, s)) != hipSuccess)
+    return e;
+  // reduce into every remaining limb, back to the NTT domain
+  if ((e = launch_rescale_bcast(t, u, p->d_mod, top, batch, c->n, s)) != hipSuccess) return e;
+  if ((e = ntt_units(p, {NttUnit{p, false, u, u, 0, top, batch},
+                         NttUnit{p, false, u + (uint64_t)top * plane, u + (uint64_t)top * plane, 0, top, batch}},
+                     nws, s)) != hipSuccess)
+    return e;
+  // (c_i - u_i) q_top^{-1}
+  for (int comp = 0; comp < 2; ++comp)
+    if ((e = launch_moddown_final(ct + (uint64_t)comp * level * plane, u + (uint64_t)comp * top * plane,
+                                  out + (uint64_t)comp * top * plane, p->d_mod,
+                                  c->d_rs_qinv + (size_t)top * c->L, top, batch, c->n, false, s,
+                                  K_RS_FINAL)) != hipSuccess)
+      return e;
+  return hipSuccess;
+}
+
 template <typename T>
 static hipError_t upload(T** dst, const std::vector<T>& src, std::vector<void*>& owned) {
   hipError_t e = hipMalloc((void**)dst, sizeof(T) * std::max<size_t>(src.size(), 1));
@@ -174,8 +229,13 @@ static tfhe_status ctx_build(tfhe_ckks_ctx_s* c) {
       dconv[(size_t)i * kMaxK + k] = with_companion(prod, qi);
     }
   }
+  std::vector<uint2> rsq((size_t)L * L, make_uint2(0, 0));
+  for (uint32_t t = 1; t < L; ++t)
+    for (uint32_t i = 0; i < t; ++i)
+      rsq[(size_t)t * L + i] = with_companion(inv_mod(m[t] % m[i], m[i]), m[i]);
   hipError_t e;
-  if ((e = upload(&c->d_up_inv, up_inv, c->owned)) != hipSuccess ||
+  if ((e = upload(&c->d_rs_qinv, rsq, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_up_inv, up_inv, c->owned)) != hipSuccess ||
       (e = upload(&c->d_up_conv, up_conv, c->owned)) != hipSuccess ||
       (e = upload(&c->d_dn_invp, invp, c->owned)) != hipSuccess ||
       (e = upload(&c->d_dn_conv, dconv, c->owned)) != hipSuccess ||
@@ -193,14 +253,14 @@ static void ctx_free(tfhe_ckks_ctx_s* c) {
 }
 
 static tfhe_status check_ct_call(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t batch, void* ws,
-                                 size_t ws_bytes) {
+                                 size_t ws_bytes, bool ks_ws = true) {
   if (!c) return fail(TFHE_EINVAL, "null context");
   if (level < 1 || level > c->L) return fail(TFHE_EINVAL, "level must be in [1, L]");
   if ((uint64_t)batch * c->n * (c->L + c->K) > (1ull << 38)) return fail(TFHE_EINVAL, "batch too large");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != c->plan->device)
     return fail(TFHE_EINVAL, "the context's device is not the current device");
-  if (batch == 0) return TFHE_OK;
+  if (batch == 0 || !ks_ws) return TFHE_OK;
   const size_t need = ks_layout(c, level, batch).total;
   if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "workspace missing or too small");
   if ((uintptr_t)ws % 256) return fail(TFHE_EINVAL, "workspace not 256-byte aligned");
@@ -318,6 +378,56 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
   if (e == hipSuccess)
     e = key_switch(ctx, r1, rotkey, ct_out, ct_out + plane, true, false, level, batch, w, s);
   return hip_check(e, "rotate");
+}
+
+tfhe_status tfhe_rescale_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch,
+                                        size_t* bytes) {
+  if (!ctx || !bytes) return fail(TFHE_EINVAL, "rescale_workspace_size: null argument");
+  if (level < 2 || level > ctx->L) return fail(TFHE_EINVAL, "rescale: level must be in [2, L]");
+  *bytes = rs_layout(ctx, level, batch).total;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_rescale(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out, uint32_t level,
+                         uint32_t batch, void* ws, size_t ws_bytes, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, nullptr, 0, false);
+  if (st != TFHE_OK) return st;
+  if (level < 2) return fail(TFHE_EINVAL, "rescale: level must be in [2, L]");
+  if (batch == 0) return TFHE_OK;
+  if (!al16(ct_in) || !al16(ct_out)) return fail(TFHE_EINVAL, "rescale: null or unaligned pointer");
+  const uint64_t plane = (uint64_t)batch * ctx->n;
+  if (ct_in < ct_out + 2 * (level - 1) * plane && ct_out < ct_in + 2 * level * plane)
+    return fail(TFHE_EINVAL, "rescale: ct_out must not alias ct_in");
+  const size_t need = rs_layout(ctx, level, batch).total;
+  if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "rescale: workspace missing or too small");
+  if ((uintptr_t)ws % 256) return fail(TFHE_EINVAL, "rescale: workspace not 256-byte aligned");
+  return hip_check(rescale(ctx, ct_in, ct_out, level, batch, (unsigned char*)ws, (hipStream_t)stream),
+                   "rescale");
+}
+
+tfhe_status tfhe_cmult(tfhe_ckks_ctx ctx, const uint32_t* ct, const uint32_t* pt, uint32_t* ct_out,
+                       uint32_t level, uint32_t batch, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, nullptr, 0, false);
+  if (st != TFHE_OK || batch == 0) return st;
+  if (!al16(ct) || !al16(pt) || !al16(ct_out)) return fail(TFHE_EINVAL, "cmult: null or unaligned pointer");
+  const uint64_t plane = (uint64_t)level * batch * ctx->n;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ew_launch(EW_MUL, ctx->plan->d_mod, ct, pt, ct_out, level, batch, ctx->n, s);
+  if (e == hipSuccess) e = ew_launch(EW_MUL, ctx->plan->d_mod, ct + plane, pt, ct_out + plane, level, batch, ctx->n, s);
+  return hip_check(e, "cmult");
+}
+
+tfhe_status tfhe_hadd(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b, uint32_t* ct_out,
+                      uint32_t level, uint32_t batch, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, nullptr, 0, false);
+  if (st != TFHE_OK || batch == 0) return st;
+  if (!al16(ct_a) || !al16(ct_b) || !al16(ct_out)) return fail(TFHE_EINVAL, "hadd: null or unaligned pointer");
+  const uint64_t plane = (uint64_t)level * batch * ctx->n;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ew_launch(EW_ADD, ctx->plan->d_mod, ct_a, ct_b, ct_out, level, batch, ctx->n, s);
+  if (e == hipSuccess)
+    e = ew_launch(EW_ADD, ctx->plan->d_mod, ct_a + plane, ct_b + plane, ct_out + plane, level, batch, ctx->n, s);
+  return hip_check(e, "hadd");
 }
 
 }  // extern "C"

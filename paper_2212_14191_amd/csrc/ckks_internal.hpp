@@ -17,6 +17,8 @@ struct CkksCtxImpl {
   uint2* d_dn_invp = nullptr;  // [kMaxK]               [(P/p_k)^{-1}]_{p_k}
   uint2* d_dn_conv = nullptr;  // [L][kMaxK]            [P/p_k]_{q_i}
   uint2* d_dn_pinv = nullptr;  // [L]                   [P^{-1}]_{q_i}
+  // RESCALE constants:
+  uint2* d_rs_qinv = nullptr;  // [L][L]                [q_t^{-1}]_{q_i} at row t
   std::vector<void*> owned;
 };
 
@@ -35,7 +37,10 @@ hipError_t launch_moddown_conv(const uint32_t* a, uint32_t* conv, const ModConst
                                uint32_t K, uint32_t batch, uint32_t n, hipStream_t s);
 hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint32_t* out,
                                 const ModConst* mods, const uint2* pinv, uint32_t level,
-                                uint32_t batch, uint32_t n, bool accumulate, hipStream_t s);
+                                uint32_t batch, uint32_t n, bool accumulate, hipStream_t s,
+                                KernelId id = K_MD_FINAL);
+hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
+                                uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 
 }  // namespace tfhe
 

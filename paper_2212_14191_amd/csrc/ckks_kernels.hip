@@ -1,4 +1,4 @@
-// Kernels of HMULT / HROTATE other than the NTT (Sec. III-A, Table 2):
+// Kernels of HMULT / HROTATE / RESCALE other than the NTT (Sec. III-A, Table 2):
 // the tensor product (Hada-Mult, Ele-Add), the fast basis conversion (Conv)
 // of ModUp and ModDown, the key-switching inner product (Hada-Mult, Ele-Add)
 // and the ModDown finalisation (Ele-Sub, Hada-Mult).  All run over the
@@ -171,7 +171,37 @@ moddown_final_kernel(const uint4* __restrict__ acc, const uint4* __restrict__ co
   }
 }
 
+// RESCALE broadcast: t holds the two components' top limbs in the
+// coefficient domain, [2][B][N] in [0, q_top); u[c][i] = t[c] mod q_i for
+// i < top.  Every modulus exceeds 2^29 and t < 2^31 < 4 q_i, so two
+// conditional subtractions reduce exactly.
+__global__ void __launch_bounds__(kThreads)
+rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
+                     const ModConst* __restrict__ mods, uint32_t top, uint64_t bn4) {
+  for (uint64_t pos = blockIdx.x * (uint64_t)kThreads + threadIdx.x; pos < 2 * bn4;
+       pos += (uint64_t)gridDim.x * kThreads) {
+    const uint64_t c = pos / bn4, r = pos - c * bn4;
+    const uint4 x = t[pos];
+    uint4* dst = u + c * top * bn4 + r;
+    for (uint32_t i = 0; i < top; ++i) {
+      const uint32_t q = mods[i].q, q2 = 2 * q;
+      dst[(uint64_t)i * bn4] = map4(x, [&](uint32_t v, int) {
+        v = v >= q2 ? v - q2 : v;
+        return v >= q ? v - q : v;
+      });
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
+                                uint32_t top, uint32_t batch, uint32_t n, hipStream_t s) {
+  const uint64_t bn4 = (uint64_t)batch * n / 4;
+  TFHE_TIMED(K_RS_BCAST, s, hipLaunchKernelGGL(rescale_bcast_kernel, dim3(grid_for(2 * bn4)), dim3(kThreads),
+                                               0, s, (const uint4*)t, (uint4*)u, mods, top, bn4));
+  return hipGetLastError();
+}
 
 hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
                          const ModConst* mods, uint32_t level, uint32_t batch, uint32_t n,
@@ -217,15 +247,16 @@ hipError_t launch_moddown_conv(const uint32_t* a, uint32_t* conv, const ModConst
 
 hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint32_t* out,
                                 const ModConst* mods, const uint2* pinv, uint32_t level,
-                                uint32_t batch, uint32_t n, bool accumulate, hipStream_t s) {
+                                uint32_t batch, uint32_t n, bool accumulate, hipStream_t s,
+                                KernelId id) {
   const uint64_t bn4 = (uint64_t)batch * n / 4, total4 = bn4 * level;
   const uint4 *A = (const uint4*)acc, *C = (const uint4*)conv;
   uint4* O = (uint4*)out;
   if (accumulate)
-    TFHE_TIMED(K_MD_FINAL, s, hipLaunchKernelGGL(moddown_final_kernel<true>, dim3(grid_for(total4)),
+    TFHE_TIMED(id, s, hipLaunchKernelGGL(moddown_final_kernel<true>, dim3(grid_for(total4)),
                                                  dim3(kThreads), 0, s, A, C, O, mods, pinv, total4, bn4));
   else
-    TFHE_TIMED(K_MD_FINAL, s, hipLaunchKernelGGL(moddown_final_kernel<false>, dim3(grid_for(total4)),
+    TFHE_TIMED(id, s, hipLaunchKernelGGL(moddown_final_kernel<false>, dim3(grid_for(total4)),
                                                  dim3(kThreads), 0, s, A, C, O, mods, pinv, total4, bn4));
   return hipGetLastError();
 }

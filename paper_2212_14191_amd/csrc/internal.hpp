@@ -108,7 +108,7 @@ hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, 
 // ---- per-kernel event timing (timing.cpp)
 enum KernelId {
   K_FS_PASS1 = 0, K_FS_PASS2, K_BF_SINGLE, K_BF_COLS, K_BF_ROWS, K_EW, K_TENSOR, K_MODUP,
-  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB
+  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL
 };
 bool timing_on();
 void* timing_begin(int id, hipStream_t s);

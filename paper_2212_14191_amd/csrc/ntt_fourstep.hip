@@ -1,13 +1,19 @@
 // Four-step NTT on INT8 matrix cores (Sec. III-B/III-C, Eq. 8 and Eq. 9),
-// re-designed for gfx950.
+// re-designed for gfx950, for N = N1 x 256 with N1 = 16 r, r in {1,..,16}.
 //
-// N = 2^16 is viewed as a 256 x 256 matrix (n = 256 n1 + n2, k = k1 + 256 k2):
-//   pass 1, per column n2:  Y[k1] = sum_{n1} phi^{(2k1+1) n1} a[n1][n2],
-//                           Z[k1][n2] = Y[k1] * psi^{(2k1+1) n2}   (the W2 twist)
-//   pass 2, per row k1:     A[k1 + 256 k2] = sum_{n2} w^{k2 n2} Z[k1][n2]
-// (phi = psi^256, w = psi^512).  Each 256-point stage runs as two radix-16
-// levels (n = 16u + v, k = s + 16t): a dense 16 x 16 contraction on the
-// matrix cores, an element-wise twist, a second 16 x 16 contraction.
+// With n = 256 n1 + n2 and k = k1 + N1 k2 (phi = psi^256 of order 2 N1,
+// w = psi^{2 N1} of order 256):
+//   A_k = sum_{n2} w^{k2 n2} psi^{(2k1+1) n2} sum_{n1} phi^{(2k1+1) n1} a[n1][n2].
+// Forward: pass 1 transforms the 256 columns (N1 points each, negacyclic) and
+// applies the twist psi^{(2k1+1) n2}; pass 2 transforms the N1 rows of the
+// result (256 points, cyclic).  The inverse runs the mirror image: pass 1 the
+// 256-point inverse over k2 with the twist psi^{-(2k1+1) n2}, pass 2 the
+// N1-point inverse over k1 with N^{-1} folded in.
+//
+// A P-point stage (P = 16 r) splits as n = r u + v, k = s + 16 t: level A is
+// a 16-point contraction over u on the matrix cores, then a twist by
+// T[s][v], then level B, an r-point transform over v: on the matrix cores
+// when r = 16, as VALU butterflies when r < 16.
 //
 // Exactness (the segment-fusion idea of Sec. III-C, Fig. 4): every operand
 // enters the matrix core as four balanced signed byte digits.  A data word x
@@ -20,21 +26,19 @@
 // forms V = (C_0 + 2^8 C_1) + 2^16 (C_2 + 2^8 C_3) (C_0 and C_2 start at q
 // so both halves are positive), reduces it by one Montgomery step to
 // V 2^{-32} mod q, and multiplies by the next twist (stored as t 2^32, Shoup
-// form), or, after the last level, whose twiddles carry the 2^32, leaves the
-// canonical residue.  Twisted results are re-sliced into digits for the next
-// contraction with two VALU operations.
+// form), or, after a last matrix-core level whose twiddles carry the 2^32,
+// leaves the canonical residue.  Twisted results are re-sliced into digits
+// for the next contraction with two VALU operations.
 //
-// Data movement: persistent workgroups stride over the work items (16
-// vectors = 16 columns of the 256 x 256 matrix of one polynomial) with a
-// stride that is a multiple of 16, so a workgroup keeps the same columns and
-// reloads the limb's tables and the pass-1 post-twist only when the limb
-// changes.  Each item is staged through LDS; the global loads of the next item
-// are issued before the current one is computed.  Each wave transforms four vectors, one per
-// 16 x 16 tile with four coefficients per lane.  Pass 1 writes its digit-form
-// result row-wise to the workspace (the transpose), pass 2 writes canonical
-// residues back as a column block through LDS.  The inverse runs the same
-// kernels with the inverse tables (w^{-1}, phi^{-2}, psi^{-(2k1+1) n2}, N^{-1}
-// folded into the last level).
+// Data movement.  A work item is 4096 words: P rows x W = 4096 / P columns
+// (vectors) of one polynomial.  Items are staged through a three-deep LDS
+// ring by direct-to-LDS loads issued two items ahead.  Each wave transforms
+// four sets of vectors; a set fills the 16 rows of one MFMA tile with 16 / r
+// vectors.  The intermediate array between the passes is tiled: block kb of
+// 16 consecutive pass-1 outputs holds, for every pass-1 column c, the 16
+// words (kb, c) contiguously, so pass 1 writes 1 KiB runs and pass 2 reads
+// its items as contiguous 16 KiB tiles.  Pass 2 writes its canonical results
+// back in natural order through the LDS stage it has just consumed.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -45,13 +49,26 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kCols = 16;     // vectors per workgroup
-constexpr int kStride = 324;  // LDS words per vector: 256 + 64 pad, = 4 (mod 64)
+constexpr int kItem = 4096;  // words per work item
+constexpr int kStages = 3;   // LDS ring depth (items)
 
-__device__ __forceinline__ int lds_pos(int col, int n) { return col * kStride + n + 16 * (n >> 6); }
+// Geometry of a pass with P = 16 kR points.  The LDS tile of an item is 16
+// slabs of 64 16-byte slots: slab k holds rows kR k .. kR k + kR - 1, slot L
+// holds row kR k + L % kR, columns 4 (L / kR) .. + 3 (a "quad").  Slabs are
+// padded where the stores of the second pass would otherwise hit the same
+// LDS banks from several slabs at once.
+template <bool kFirst, int kR>
+struct Geo {
+  static constexpr int P = 16 * kR;
+  static constexpr int W = kItem / P;    // vectors per item
+  static constexpr int Mt = 16 / kR;     // vectors per MFMA tile (quads per wave)
+  static constexpr int pitch = (kFirst || kR == 16) ? 256 : 256 + 4 * kR;  // words per slab
+  static constexpr int tile = 16 * pitch;
+};
 
 // Descriptor table of a fused launch (passed by value as a kernel argument):
-// unit k covers work items [item_begin[k], item_begin[k+1]).
+// unit k covers global polynomials [item_begin[k], item_begin[k+1]).  Every
+// unit of a launch has the same N and direction.
 constexpr int kMaxUnits = 40;
 struct FsUnit {
   const uint32_t* in;
@@ -61,7 +78,10 @@ struct FsUnit {
   uint32_t item_begin;
 };
 struct FsTable {
-  uint32_t count, total;
+  uint32_t count, total;  // units, polynomials
+  uint32_t log_n;
+  uint32_t cols;          // S = N / P: columns of this pass (row stride in natural order)
+  uint32_t ipp_log;       // log2 of the items per polynomial (N / 4096)
   FsUnit u[kMaxUnits];
 };
 
@@ -80,7 +100,7 @@ __device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, ui
   return vhi + __umulhi(m, q) + (vlo != 0u);
 }
 
-// Twist (Shoup, t = {w 2^32, companion}) and re-slice into digits.
+// Twist (Shoup, t = {w, companion}) and re-slice into digits; r < 2^32.
 __device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q) {
   const uint32_t z = mul_shoup_lazy(r, t.x, t.y, q);  // [0, 2q)
   int32_t zz = (int32_t)(z - q);                      // [-q, q)
@@ -88,43 +108,78 @@ __device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q
   return balanced_digits(zz);
 }
 
-// One 256-point stage of one vector: level A, twist, level B.  x holds the
-// lane's four input words as digits (lane (v, g), word c: element 64g+16c+v);
-// on return acc[j][r] is plane j of output s + 16 (4g + r) for lane (s, g).
-__device__ __forceinline__ void stage256(v4i x, const v4i* opA, const v4i* opB, const uint2* tw,
-                                         uint32_t q, uint32_t qneg, v4i* acc) {
-  const v4i bias = {(int)q, (int)q, (int)q, (int)q};
-  const v4i zero = {0, 0, 0, 0};
-  v4i c0 = mfma(x, opA[0], bias);
-  v4i c1 = mfma(x, opA[1], zero);
-  v4i c2 = mfma(x, opA[2], bias);
-  v4i c3 = mfma(x, opA[3], zero);
-  v4i z;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    z[r] = (int)twist_digits(fuse_redc(c0[r], c1[r], c2[r], c3[r], q, qneg), tw[r], q);
-  acc[0] = mfma(opB[0], z, bias);
-  acc[1] = mfma(opB[1], z, zero);
-  acc[2] = mfma(opB[2], z, bias);
-  acc[3] = mfma(opB[3], z, zero);
+// After level A, lane (s, g) register j holds MFMA row i = 4g + j, i.e.
+// vector m = i / kR, element v = i % kR.  After level B register j holds
+// output t of vector m (the output index is s + 16 t).
+template <int kR>
+__device__ __forceinline__ void lane_out(int g, int j, int& m, int& t) {
+  if (kR == 16) { m = 0; t = 4 * g + j; }
+  else if (kR == 8) { m = g >> 1; t = 2 * j + (g & 1); }
+  else if (kR == 4) { m = g; t = j; }
+  else if (kR == 2) { m = 2 * g + (j >> 1); t = j & 1; }
+  else { m = 4 * g + j; t = 0; }
 }
 
-// Work distribution.  The grid is a multiple of 16; workgroup w belongs to
-// group w / 16 and owns column block blk(w % 16) of every polynomial in its
-// group's contiguous range, so it changes limb (and reloads the limb's
-// tables and its post-twist slice) at most a few times.  Workgroups are
-// dispatched round-robin over the 8 XCDs, each with its own L2: the two
-// 64-byte halves of a 128-byte line are column blocks 2b and 2b+1, owned by
-// workgroups c and c + 8 of a group, i.e. on the same XCD at the same time,
-// so each line is fetched from memory once.
+// Radix-4 DFT y_t = sum_v x_v w4^{vt} (w4 of order 4) on residues in [0, q).
+__device__ __forceinline__ void dft4(uint32_t* x, uint2 w4, uint32_t q) {
+  const uint32_t a0 = add_mod(x[0], x[2], q), a1 = sub_mod(x[0], x[2], q);
+  const uint32_t b0 = add_mod(x[1], x[3], q);
+  const uint32_t b1 = mul_shoup(sub_mod(x[1], x[3], q), w4.x, w4.y, q);
+  x[0] = add_mod(a0, b0, q);
+  x[1] = add_mod(a1, b1, q);
+  x[2] = sub_mod(a0, b0, q);
+  x[3] = sub_mod(a1, b1, q);
+}
+
+// Level B for kR < 16: the kR-point cyclic DFT over v of y (residues in
+// [0, q)), with lb[x] = rho^x for the root rho of order kR.  For kR = 8 the
+// eight inputs of a vector sit in lanes g and g ^ 1 (four each): lane
+// parity h computes the outputs t = 2 j + h from e_j = z_j + z_{j+4} (h = 0)
+// or o_j = (z_j - z_{j+4}) rho^j (h = 1) with a radix-4 DFT by rho^2.
+template <int kR>
+__device__ __forceinline__ void level_b(uint32_t* y, const uint2* lb, const uint2* rj, int g,
+                                        uint32_t q) {
+  if (kR == 2) {
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+      const uint32_t a = y[j], b = y[j + 1];
+      y[j] = add_mod(a, b, q);
+      y[j + 1] = sub_mod(a, b, q);
+    }
+  } else if (kR == 4) {
+    dft4(y, lb[1], q);
+  } else if (kR == 8) {
+    const bool h = g & 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t other = (uint32_t)__shfl_xor((int)y[j], 16);
+      const uint32_t lo = h ? other : y[j], hi = h ? y[j] : other;  // z_j, z_{j+4}
+      const uint32_t d = h ? sub_mod(lo, hi, q) : add_mod(lo, hi, q);
+      y[j] = mul_shoup(d, rj[j].x, rj[j].y, q);
+    }
+    dft4(y, lb[2], q);
+  }
+}
+
+// Work distribution.  The grid is a multiple of 16.  Workgroup w belongs to
+// group w / 16, which owns a contiguous range of polynomials; within the
+// group, slot j = 2 (c % 8) + c / 8 of workgroup c = w % 16 selects its item
+// column block (j mod items-per-polynomial) and its offset into the range
+// (the group walks 16 / items-per-polynomial polynomials side by side).  A
+// workgroup keeps its column block, so it reloads the limb's tables only when
+// the limb changes.  Workgroups are dispatched round-robin over the 8 XCDs,
+// each with its own L2: c and c + 8 own column blocks 2b and 2b + 1, which
+// share the 128-byte lines of 64-byte row segments, on the same XCD.
 struct Walk {
-  uint32_t blk, p, p_end;  // column block; current and end polynomial (global index)
+  uint32_t blk, p, step, p_end;
 };
-__device__ __forceinline__ Walk make_walk(uint32_t total_polys) {
+__device__ __forceinline__ Walk make_walk(uint32_t total_polys, uint32_t ipp_log) {
   const uint32_t groups = gridDim.x / 16, a = blockIdx.x / 16, c = blockIdx.x % 16;
+  const uint32_t j = 2 * (c % 8) + c / 8;
   Walk w;
-  w.blk = 2 * (c % 8) + c / 8;
-  w.p = (uint32_t)((uint64_t)a * total_polys / groups);
+  w.blk = j & ((1u << ipp_log) - 1);
+  w.step = 16u >> ipp_log;
+  w.p = (uint32_t)((uint64_t)a * total_polys / groups) + (j >> ipp_log);
   w.p_end = (uint32_t)((uint64_t)(a + 1) * total_polys / groups);
   return w;
 }
@@ -141,34 +196,29 @@ __device__ __forceinline__ Item locate(const FsTable& t, uint32_t p, uint32_t& k
   Item it;
   it.unit = k;
   it.limb = local / t.u[k].batch;
-  it.poly_base = (size_t)local << 16;
+  it.poly_base = (size_t)local << t.log_n;
   return it;
 }
 
 typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Item tile in LDS, as the direct-to-LDS loads deposit it: region k (1 KiB)
-// holds rows 16k .. 16k+15 of the item's 16 columns; its 16-byte slot L holds
-// row 16k + L % 16, columns 4 (L / 16) .. 4 (L / 16) + 3.
-constexpr int kTile = 256 * kCols;  // words
-constexpr int kStages = 3;           // input ring depth (items in LDS)
 
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-// Each wave loads regions 4 wave .. 4 wave + 3 of an item: one 16-byte
-// direct-to-LDS load per lane per region (a 64-byte segment of 16 rows);
-// lane L's bytes land at the region base + 16 L.  Issued as inline assembly so
-// that the compiler does not serialise later LDS reads on these loads: the
-// pipeline waits for them explicitly (wait_item) before a barrier.
-__device__ __forceinline__ void issue_tile(const uint32_t* src, uint32_t* stage, int wave, int lane) {
+// Each wave loads slabs 4 wave .. 4 wave + 3 of an item: one 16-byte
+// direct-to-LDS load per lane per slab; lane L's bytes land at the slab base
+// + 16 L.  Issued as inline assembly so that the compiler does not serialise
+// later LDS reads on these loads: the pipeline waits for them explicitly
+// (wait_item) before a barrier.
+template <int kPitch>
+__device__ __forceinline__ void issue_tile(const uint32_t* src, const uint32_t* off, uint32_t* stage,
+                                           int wave) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int k = 4 * wave + j;
-    const uint32_t* g = src + (16 * k + (lane & 15)) * 256 + 4 * (lane >> 4);
-    const uint32_t lds_addr = (uint32_t)(uintptr_t)(lds_void_t*)(stage + k * 256);
+    const uint32_t* g = src + off[j];
+    const uint32_t lds_addr = (uint32_t)(uintptr_t)(lds_void_t*)(stage + (4 * wave + j) * kPitch);
     asm volatile(
         "s_mov_b32 m0, %0\n\t"
         "global_load_lds_dwordx4 %1, off"
@@ -179,7 +229,7 @@ __device__ __forceinline__ void issue_tile(const uint32_t* src, uint32_t* stage,
 }
 
 // Workgroup barrier without the memory fence of __syncthreads (which would
-// wait for every outstanding load): LDS writes of this wave are completed
+// wait for every outstanding load): LDS accesses of this wave are completed
 // first; the direct-to-LDS loads are covered by wait_item.
 __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -202,33 +252,56 @@ __device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
   else wait_vmcnt<4 + 2 * st>();
 }
 
-template <bool kFirst>
+template <bool kFirst, int kR>
 __global__ void __launch_bounds__(kThreads)
 fs_pass(const FsTable tab) {
-  __shared__ __attribute__((aligned(16))) uint32_t ring[(kStages + (kFirst ? 0 : 1)) * kTile];
+  using G = Geo<kFirst, kR>;
+  __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int v = lane & 15, g = lane >> 4;
-  const Walk walk = make_walk(tab.total);
-  const uint32_t blk = walk.blk, p_begin = walk.p, p_end = walk.p_end;
-  if (p_begin >= p_end) return;
+  const int i16 = lane & 15, g = lane >> 4;
+  const Walk walk = make_walk(tab.total, tab.ipp_log);
+  if (walk.p >= walk.p_end) return;
+  const uint32_t S = tab.cols, c0 = walk.blk * G::W;
+
+  // Per-lane word offsets within a polynomial.  Slab k = 4 wave + j, slot
+  // L = lane: row kR k + L % kR, item column 4 (L / kR).
+  uint32_t ld_off[4], st_off[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t row = kR * (4 * wave + j) + lane % kR, col = 4 * (lane / kR);
+    const uint32_t natural = row * S + c0 + col;
+    const uint32_t tiled = ((c0 + col) >> 4) * (16 * G::P) + 16 * row + (col & 15);
+    ld_off[j] = kFirst ? natural : tiled;
+    if (kFirst) {
+      // tiled store of output s + 16 t of column c0 + 4 (wave Mt + m) (+ set)
+      int m, t;
+      lane_out<kR>(g, j, m, t);
+      st_off[j] = t * 16 * S + (c0 + 4 * (wave * G::Mt + m)) * 16 + i16;
+    } else {
+      st_off[j] = natural;
+    }
+  }
 
   uint32_t kf = 0, kc = 0;  // running unit indices of the load and compute walks
-  auto issue = [&](uint32_t p, int st) {
+  auto issue = [&](uint32_t p, int stage) {
     const Item it = locate(tab, p, kf);
-    issue_tile(tab.u[it.unit].in + it.poly_base + blk * kCols, ring + st * kTile, wave, lane);
+    issue_tile<G::pitch>(tab.u[it.unit].in + it.poly_base, ld_off, ring + stage * G::tile, wave);
   };
 #pragma unroll
   for (int j = 0; j < kStages - 1; ++j)
-    if (p_begin + j < p_end) issue(p_begin + j, j);
+    if (walk.p + j * walk.step < walk.p_end) issue(walk.p + j * walk.step, j);
 
   const FourStepLimb* cur_limb = nullptr;
   uint32_t q = 0, qneg = 0;
   v4i opA[4], opB[4];
   uint2 tw[4];
-  uint2 pt[4][4];
+  uint2 pt[4][4];  // pass 1: post-twist per set and register
+  uint2 lb[4];     // kR < 16: rho^0..rho^3
+  uint2 rj[4];     // kR = 8: multiplier of register j (rho^j or 1)
+  uint2 pf[4];     // kR < 16, pass 2: per-output factor
   int st = 0;
-  for (uint32_t p = p_begin; p < p_end; ++p, st = (st + 1 == kStages) ? 0 : st + 1) {
-    const uint32_t n = p - p_begin;
+  uint32_t n = 0;
+  for (uint32_t p = walk.p; p < walk.p_end; p += walk.step, ++n, st = (st + 1 == kStages) ? 0 : st + 1) {
     const Item it = locate(tab, p, kc);
     const FourStepLimb* limb = tab.u[it.unit].limbs + it.limb;
     if (limb != cur_limb) {
@@ -241,105 +314,154 @@ fs_pass(const FsTable tab) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         opA[j] = *(const v4i*)&P->opA[j][lane][0];
-        opB[j] = *(const v4i*)&P->opB[j][lane][0];
+        if (kR == 16) opB[j] = *(const v4i*)&P->opB[j][lane][0];
         tw[j] = P->twist[lane][j];
+        if (kR < 16) {
+          lb[j] = P->lb[j];
+          int m, t;
+          lane_out<kR>(g, j, m, t);
+          pf[j] = P->lb[8 + t];
+        }
+      }
+      if (kR == 8) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rj[j] = (g & 1) ? lb[j] : lb[0];
       }
       if (kFirst) {
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-          const uint2* pp = L.post1 + ((size_t)(blk * kCols + 4 * wave + cc) * 64 + lane) * 4;
+        for (int sg = 0; sg < 4; ++sg) {
+          const uint2* pp = L.post1 + ((size_t)(c0 + 4 * wave * G::Mt + sg) * 64 + lane) * 4;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) pt[cc][r] = pp[r];
+          for (int j = 0; j < 4; ++j) pt[sg][j] = pp[j];
         }
       }
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       cur_limb = limb;
     }
-    wait_item<kFirst>(n, p + 1 < p_end);
+    const bool has_next = p + walk.step < walk.p_end;
+    wait_item<kFirst>(n, has_next);
     lds_barrier();  // the item's tile is complete; the oldest stage is free
-    if (p + kStages - 1 < p_end) issue(p + kStages - 1, (st + kStages - 1) % kStages);
+    {
+      const uint32_t pn = p + (kStages - 1) * walk.step;
+      if (pn < walk.p_end) issue(pn, (st + kStages - 1) % kStages);
+    }
 
-    // lane (v, g): rows 64g + 16c + v of the wave's four columns 4 wave .. +3
-    const uint32_t* tile = ring + st * kTile;
+    // lane (i, g) of wave w reads slab 4g + c, slot 16 w + i: row
+    // kR (4g + c) + i % kR of the quad w Mt + i / kR (four vectors, one per set)
+    uint32_t* const tile = ring + st * G::tile;
     uint4 rows[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) rows[c] = *(const uint4*)(tile + (4 * g + c) * 256 + (v + 16 * wave) * 4);
+    for (int c = 0; c < 4; ++c) rows[c] = *(const uint4*)(tile + (4 * g + c) * G::pitch + (16 * wave + i16) * 4);
 
-    const size_t base = it.poly_base;
-    uint32_t* const out = tab.u[it.unit].out;
-    uint4 res[4];  // pass 2: res[r] = the four columns' outputs for row s + 64g + 16r
+    uint32_t* const out = tab.u[it.unit].out + it.poly_base;
+    uint4 res[4];  // pass 2: res[j] = the four sets' outputs of register j
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
+    for (int sg = 0; sg < 4; ++sg) {
       v4i x;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const uint32_t w = cc == 0 ? rows[c].x : cc == 1 ? rows[c].y : cc == 2 ? rows[c].z : rows[c].w;
+        const uint32_t w = sg == 0 ? rows[c].x : sg == 1 ? rows[c].y : sg == 2 ? rows[c].z : rows[c].w;
         x[c] = kFirst ? (int)balanced_digits(to_window(w, q)) : (int)w;
       }
-      v4i acc[4];
-      stage256(x, opA, opB, tw, q, qneg, acc);
-      if (kFirst) {
-        // post twist and row store: output k = s + 64g + 16r of vector col
-        const int col = 4 * wave + cc;
-        uint32_t* dst = out + base + (blk * kCols + col) * 256 + v + 64 * g;
+      const v4i bias = {(int)q, (int)q, (int)q, (int)q};
+      const v4i zero = {0, 0, 0, 0};
+      const v4i a0 = mfma(x, opA[0], bias);
+      const v4i a1 = mfma(x, opA[1], zero);
+      const v4i a2 = mfma(x, opA[2], bias);
+      const v4i a3 = mfma(x, opA[3], zero);
+      uint32_t y[4];
+      if (kR == 16) {
+        v4i z;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          dst[16 * r] = twist_digits(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg),
-                                     pt[cc][r], q);
+        for (int j = 0; j < 4; ++j) z[j] = (int)twist_digits(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j], q);
+        const v4i b0 = mfma(opB[0], z, bias);
+        const v4i b1 = mfma(opB[1], z, zero);
+        const v4i b2 = mfma(opB[2], z, bias);
+        const v4i b3 = mfma(opB[3], z, zero);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j] = fuse_redc(b0[j], b1[j], b2[j], b3[j], q, qneg);
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint32_t y = reduce_once(fuse_redc(acc[0][r], acc[1][r], acc[2][r], acc[3][r], q, qneg), q);
-          if (cc == 0) res[r].x = y;
-          else if (cc == 1) res[r].y = y;
-          else if (cc == 2) res[r].z = y;
-          else res[r].w = y;
+        for (int j = 0; j < 4; ++j)
+          y[j] = reduce_once(mul_shoup_lazy(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j].x, tw[j].y, q), q);
+        level_b<kR>(y, lb, rj, g, q);
+      }
+      if (kFirst) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[st_off[j] + 16 * sg] = twist_digits(y[j], pt[sg][j], q);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t r = kR == 16 ? reduce_once(y[j], q) : mul_shoup(y[j], pf[j].x, pf[j].y, q);
+          if (sg == 0) res[j].x = r;
+          else if (sg == 1) res[j].y = r;
+          else if (sg == 2) res[j].z = r;
+          else res[j].w = r;
         }
       }
     }
 
     if (!kFirst) {
-      // output tile in the input layout, then 16-byte row-segment stores
-      uint32_t* otile = ring + kStages * kTile;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) *(uint4*)(otile + (4 * g + r) * 256 + (v + 16 * wave) * 4) = res[r];
-      lds_barrier();
-      uint32_t* dst = out + base + blk * kCols;
+      // results into the consumed stage in the slab layout, then 16-byte
+      // stores with the load's lane mapping
+      lds_barrier();  // every wave has read the stage
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int k = 4 * wave + j;
-        *(uint4*)(dst + (16 * k + (lane & 15)) * 256 + 4 * (lane >> 4)) =
-            *(const uint4*)(otile + k * 256 + lane * 4);
+        int m, t;
+        lane_out<kR>(g, j, m, t);
+        const int row = i16 + 16 * t;
+        *(uint4*)(tile + (row / kR) * G::pitch + ((wave * G::Mt + m) * kR + row % kR) * 4) = res[j];
       }
+      lds_barrier();
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        *(uint4*)(out + st_off[j]) = *(const uint4*)(tile + (4 * wave + j) * G::pitch + lane * 4);
     }
   }
 }
 
-// Resident workgroups per CU of each pass kernel (queried once per process).
-static uint32_t occupancy(bool first) {
-  static int occ[2] = {0, 0};
-  int& o = occ[first ? 1 : 0];
-  if (o == 0) {
+// Resident workgroups per CU of a pass kernel (queried once per process).
+template <bool kFirst, int kR>
+uint32_t occupancy() {
+  static int occ = 0;
+  if (occ == 0) {
     int n = 0;
-    hipError_t e = first ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<true>, kThreads, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<false>, kThreads, 0);
-    o = (e == hipSuccess && n > 0) ? n : 2;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<kFirst, kR>, kThreads, 0);
+    occ = (e == hipSuccess && n > 0) ? n : 2;
   }
-  return (uint32_t)o;
+  return (uint32_t)occ;
 }
 
 // Persistent grid: resident workgroups of the whole device, rounded down to a
-// multiple of 16 (one workgroup per column block in each group), and at most
-// 16 per polynomial.
-static uint32_t grid_size(const tfhe_ntt_plan_s* p, bool first, uint32_t polys) {
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy(first);
-  uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
-  return std::min(g, 16 * polys);
+// multiple of 16, and no more than the items need.
+template <bool kFirst, int kR>
+uint32_t grid_size(const tfhe_ntt_plan_s* p, uint32_t items) {
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR>();
+  const uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
+  return std::min(g, (items + 15) / 16 * 16);
+}
+
+template <bool kFirst, int kR>
+void launch_pass(const tfhe_ntt_plan_s* p, const FsTable& t, hipStream_t s) {
+  const uint32_t grid = grid_size<kFirst, kR>(p, t.total << t.ipp_log);
+  TFHE_TIMED(kFirst ? K_FS_PASS1 : K_FS_PASS2, s,
+             hipLaunchKernelGGL((fs_pass<kFirst, kR>), dim3(grid), dim3(kThreads), 0, s, t));
+}
+
+template <bool kFirst>
+void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipStream_t s) {
+  switch (r) {
+    case 1: launch_pass<kFirst, 1>(p, t, s); break;
+    case 2: launch_pass<kFirst, 2>(p, t, s); break;
+    case 4: launch_pass<kFirst, 4>(p, t, s); break;
+    case 8: launch_pass<kFirst, 8>(p, t, s); break;
+    default: launch_pass<kFirst, 16>(p, t, s); break;
+  }
 }
 
 }  // namespace
 
-bool fs_supported(uint32_t log_n) { return log_n == 16; }
+bool fs_supported(uint32_t log_n) { return log_n >= 12 && log_n <= 16; }
 
 size_t unit_ws_bytes(const NttUnit& u, bool mfma) {
   if (mfma) return (size_t)u.limb_count * u.batch * u.plan->n * sizeof(uint32_t);
@@ -350,34 +472,58 @@ size_t fs_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_
   return (size_t)limb_count * batch * p->n * sizeof(uint32_t);
 }
 
-// Fused launch: pass 1 of every unit (in -> unit workspace), then pass 2 of
-// every unit (workspace -> out), kMaxUnits units per launch pair.
+// Fused launches: units are grouped by (N, direction), in order of first
+// appearance; per group, pass 1 of every unit (in -> unit workspace), then
+// pass 2 of every unit (workspace -> out), kMaxUnits units per launch pair.
+// Units are independent, so the grouping does not change any result.
 hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStream_t s) {
-  unsigned char* w = (unsigned char*)ws;
-  for (uint32_t first = 0; first < count; first += kMaxUnits) {
-    const uint32_t n = std::min<uint32_t>(kMaxUnits, count - first);
-    FsTable t1, t2;
-    t1.count = t2.count = 0;
-    uint32_t total = 0;
-    const tfhe_ntt_plan_s* p0 = nullptr;
-    for (uint32_t k = 0; k < n; ++k) {
-      const NttUnit& u = units[first + k];
-      const uint32_t items = u.limb_count * u.batch;  // polynomials
-      if (items == 0) continue;
-      p0 = u.plan;
-      const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;
-      uint32_t* mid = (uint32_t*)w;
-      w += (unit_ws_bytes(u, true) + 255) & ~(size_t)255;
-      t1.u[t1.count++] = FsUnit{u.in, mid, tabs, u.batch, total};
-      t2.u[t2.count++] = FsUnit{mid, u.out, tabs, u.batch, total};
-      total += items;
+  // workspace slices in unit order
+  std::vector<uint32_t*> mids(count);
+  {
+    unsigned char* w = (unsigned char*)ws;
+    for (uint32_t k = 0; k < count; ++k) {
+      mids[k] = (uint32_t*)w;
+      w += (unit_ws_bytes(units[k], true) + 255) & ~(size_t)255;
     }
-    if (total == 0) continue;
-    t1.total = t2.total = total;
-    TFHE_TIMED(K_FS_PASS1, s,
-               hipLaunchKernelGGL(fs_pass<true>, dim3(grid_size(p0, true, total)), dim3(kThreads), 0, s, t1));
-    TFHE_TIMED(K_FS_PASS2, s,
-               hipLaunchKernelGGL(fs_pass<false>, dim3(grid_size(p0, false, total)), dim3(kThreads), 0, s, t2));
+  }
+  std::vector<bool> done(count, false);
+  for (uint32_t lead = 0; lead < count; ++lead) {
+    if (done[lead]) continue;
+    const uint32_t log_n = units[lead].plan->log_n;
+    const bool inverse = units[lead].inverse;
+    const tfhe_ntt_plan_s* p0 = units[lead].plan;
+    const uint32_t N = 1u << log_n, N1 = N >> 8, r = N1 / 16;
+    FsTable t1, t2;
+    t1.log_n = t2.log_n = log_n;
+    t1.ipp_log = t2.ipp_log = log_n - 12;
+    t1.cols = inverse ? N1 : 256;  // N / P of pass 1
+    t2.cols = inverse ? 256 : N1;
+    const uint32_t r1 = inverse ? 16 : r, r2 = inverse ? r : 16;
+    auto flush = [&]() {
+      if (t1.total == 0) return;
+      launch_pass_r<true>(p0, r1, t1, s);
+      launch_pass_r<false>(p0, r2, t2, s);
+    };
+    t1.count = t2.count = 0;
+    t1.total = t2.total = 0;
+    for (uint32_t k = lead; k < count; ++k) {
+      const NttUnit& u = units[k];
+      if (done[k] || u.plan->log_n != log_n || u.inverse != inverse) continue;
+      done[k] = true;
+      const uint32_t polys = u.limb_count * u.batch;
+      if (polys == 0) continue;
+      if (t1.count == kMaxUnits) {
+        flush();
+        t1.count = t2.count = 0;
+        t1.total = t2.total = 0;
+      }
+      const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;
+      t1.u[t1.count++] = FsUnit{u.in, mids[k], tabs, u.batch, t1.total};
+      t2.u[t2.count++] = FsUnit{mids[k], u.out, tabs, u.batch, t2.total};
+      t1.total += polys;
+      t2.total += polys;
+    }
+    flush();
   }
   return hipGetLastError();
 }

@@ -111,9 +111,6 @@ static void lane_output(int r, int lane, int j, int* m, int* t) {
   }
 }
 
-// Columns a wave handles per tile (of its four): 16 / r, at most 4.
-static int cols_per_tile(int r) { return r >= 16 ? 1 : std::min(4, 16 / r); }
-
 // Lay out one pass (WA[u][s], T[s][v], WB[t][v] (r = 16), lb) as MFMA
 // operands.  Level A contracts over u with the data as MFMA A operand: lane
 // (i, g) holds u = 4g + c, byte 4c + d pairs data digit d with digit j of
@@ -155,21 +152,20 @@ static void build_pass(PassTables& pt, int r, const Mat16& WA, const Mat16& T, c
   }
 }
 
-// post[col0][lane][j]: the post-twist P(column, output) of the value lane
-// `lane` holds in register j after level B, for the tile whose first column
-// is col0 (column = col0 + m, output = s + 16 t).  `scale` is 2^32 when the
-// value still carries the Montgomery factor (r = 16), else 1.
+// post[b][lane][j]: the post-twist P(column, output) of the value lane `lane`
+// holds in register j after level B, for the set of columns b + 4 m (m as in
+// lane_output; output = s + 16 t).  `scale` is 2^32 when the value still
+// carries the Montgomery factor (r = 16), else 1.
 template <typename F>
 static void build_post(uint2* post, int r, int ncols, uint32_t q, uint32_t scale, F P) {
-  const int cpt = cols_per_tile(r);
-  for (int col0 = 0; col0 < 256; ++col0)
+  for (int b = 0; b < 256; ++b)
     for (int lane = 0; lane < 64; ++lane)
       for (int j = 0; j < 4; ++j) {
         int m, t;
         lane_output(r, lane, j, &m, &t);
-        const int col = col0 + m, k = lane % 16 + 16 * t;
-        uint32_t w = (m < cpt && col < ncols) ? mulm(P(col, k), scale, q) : 0;
-        post[(col0 * 64 + lane) * 4 + j] = make_uint2(w, shoup_companion(w, q));
+        const int col = b + 4 * m, k = lane % 16 + 16 * t;
+        uint32_t w = col < ncols ? mulm(P(col, k), scale, q) : 0;
+        post[(b * 64 + lane) * 4 + j] = make_uint2(w, shoup_companion(w, q));
       }
 }
 

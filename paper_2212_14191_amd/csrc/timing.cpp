@@ -32,7 +32,8 @@ hipEvent_t take() {
 
 const char* kNames[] = {"ntt_mfma_pass1", "ntt_mfma_pass2", "ntt_bf_single", "ntt_bf_cols",
                         "ntt_bf_rows",    "elementwise",    "ckks_tensor",   "ckks_modup",
-                        "ckks_inner",     "ckks_moddown_conv", "ckks_moddown_final", "frobenius"};
+                        "ckks_inner",     "ckks_moddown_conv", "ckks_moddown_final", "frobenius",
+                        "ckks_rescale_bcast", "ckks_rescale_final"};
 constexpr int kNumNames = sizeof(kNames) / sizeof(kNames[0]);
 }  // namespace
 

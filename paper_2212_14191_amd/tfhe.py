@@ -76,6 +76,10 @@ def load():
         "tfhe_hmult_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
         "tfhe_hmult": ([vp, vp, vp, vp, vp, u32, u32, vp, sz, vp], i32),
         "tfhe_rotate": ([vp, vp, vp, vp, u32, u32, u32, vp, sz, vp], i32),
+        "tfhe_rescale_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
+        "tfhe_rescale": ([vp, vp, vp, u32, u32, vp, sz, vp], i32),
+        "tfhe_cmult": ([vp, vp, vp, vp, u32, u32, vp], i32),
+        "tfhe_hadd": ([vp, vp, vp, vp, u32, u32, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -366,4 +370,44 @@ class CkksContext:
             ws = self.workspace(level, batch)
         _call("tfhe_rotate", self.handle, _ptr(ct), _ptr(out), _ptr(rotkey), galois, level, batch,
               _ptr(ws), ws.numel(), _stream(stream))
+        return out
+
+    def rescale_workspace(self, level, batch):
+        import torch
+        b = ctypes.c_size_t()
+        _call("tfhe_rescale_workspace_size", self.handle, level, batch, ctypes.byref(b))
+        return torch.empty(max(b.value, 256), dtype=torch.uint8, device="cuda")
+
+    def rescale(self, ct, level, out=None, ws=None, stream=None):
+        """RESCALE of ct: int32 [2][level][batch][N] -> [2][level-1][batch][N]."""
+        _, lv, batch, n = ct.shape
+        _check_residues(ct, "ct", (2, level, batch, self.n))
+        if out is None:
+            import torch
+            out = torch.empty((2, level - 1, batch, self.n), dtype=torch.int32, device=ct.device)
+        _check_residues(out, "out", (2, level - 1, batch, self.n))
+        if ws is None:
+            ws = self.rescale_workspace(level, batch)
+        _call("tfhe_rescale", self.handle, _ptr(ct), _ptr(out), level, batch, _ptr(ws), ws.numel(),
+              _stream(stream))
+        return out
+
+    def cmult(self, ct, pt, level, out=None, stream=None):
+        """CMULT: ct [2][level][batch][N] times plaintext pt [level][batch][N]."""
+        _, lv, batch, n = ct.shape
+        _check_residues(ct, "ct", (2, level, batch, self.n))
+        _check_residues(pt, "pt", (level, batch, self.n))
+        if out is None:
+            out = torch_empty_like(ct)
+        _call("tfhe_cmult", self.handle, _ptr(ct), _ptr(pt), _ptr(out), level, batch, _stream(stream))
+        return out
+
+    def hadd(self, ct_a, ct_b, level, out=None, stream=None):
+        """HADD of two ciphertexts [2][level][batch][N]."""
+        _, lv, batch, n = ct_a.shape
+        for t, nm in ((ct_a, "ct_a"), (ct_b, "ct_b")):
+            _check_residues(t, nm, (2, level, batch, self.n))
+        if out is None:
+            out = torch_empty_like(ct_a)
+        _call("tfhe_hadd", self.handle, _ptr(ct_a), _ptr(ct_b), _ptr(out), level, batch, _stream(stream))
         return out

@@ -1,4 +1,4 @@
-"""GPU parity of HMULT and HROTATE against the oracle's fixed algorithm
+"""GPU parity of HMULT, HROTATE, RESCALE, CMULT and HADD against the oracle
 (bit-exact), plus decryption of the GPU results, through the C ABI."""
 import numpy as np
 import pytest
@@ -72,14 +72,16 @@ def test_hmult_output_aliases_input(tf):
     assert np.array_equal(to_host(A), want)
 
 
-@pytest.mark.parametrize("r", [1, 7])
-def test_rotate_matches_oracle(tf, r):
-    n = 1 << 10
+@pytest.mark.parametrize("log_n,r", [(10, 1), (10, 7), (10, "conj"), (13, 5)])
+def test_rotate_matches_oracle(tf, log_n, r):
+    """HROTATE by 5^r, and conjugation (galois element 2N - 1 with its own
+    key), bit-exact vs the oracle; N = 2^13 runs the MFMA transform."""
+    n = 1 << log_n
     L, K, dnum, level = 6, 2, 3, 5
     pr, s, _, (a, e) = setup(n, L, K, dnum)
-    k = ckks.galois_element(r, n)
+    k = 2 * n - 1 if r == "conj" else ckks.galois_element(r, n)
     rk = ckks.rotation_key(pr, s, k, a, e)
-    ctx = tf.CkksContext(10, L, K, dnum, moduli=pr.moduli)
+    ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
     m = inputs.small_messages(0, (2, n))
     ct = encrypt(pr, s, m, level, 1)
     want = ckks.rotate(pr, ct, rk, k, level)
@@ -154,3 +156,64 @@ def test_graph_replay_matches_eager(tf):
         if rep == 0:
             want = ckks.hmult(pr, to_host(ca), to_host(cb), evk, level)
             assert np.array_equal(to_host(got_mul), want)
+
+
+@pytest.mark.parametrize("log_n,L,K,dnum,level", [
+    (10, 6, 2, 3, 6), (10, 6, 2, 3, 2), (12, 8, 4, 2, 5), (13, 24, 8, 3, 24), (14, 6, 2, 3, 3)])
+def test_rescale_matches_oracle(tf, log_n, L, K, dnum, level):
+    """RESCALE on the GPU (butterfly below N = 2^12, MFMA from 2^12) equals
+    the oracle bit for bit and decrypts to Dec(ct) / q_{level-1} within 1 + h."""
+    n = 1 << log_n
+    pr, s, _, _ = setup(n, L, K, dnum)
+    ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
+    m = inputs.small_messages(3, (3, n))
+    ct = encrypt(pr, s, m, level, 7)
+    got = to_host(ctx.rescale(to_dev(ct), level))
+    want = ckks.rescale(pr, ct, level)
+    assert np.array_equal(got, want)
+    h = int(np.count_nonzero(s))
+    qt = pr.q[level - 1]
+    dec = ckks.decrypt(pr, s, ct[:, :, :1], level)
+    dec2 = ckks.decrypt(pr, s, got[:, :, :1], level - 1)
+    assert max(abs(int(b) * qt - int(a)) for a, b in zip(dec.ravel(), dec2.ravel())) <= (1 + h) * qt
+
+
+def test_rescale_errors(tf):
+    n = 1 << 10
+    ctx = tf.CkksContext(10, 6, 2, 3)
+    ct = torch.zeros((2, 1, 2, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(tf.TfheError):
+        ctx.rescale(ct, 1)
+    ct = torch.zeros((2, 3, 2, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(tf.TfheError):   # output overlapping the input
+        ctx.rescale(ct, 3, out=ct.view(-1)[: 8 * n].view(2, 2, 2, n))
+
+
+@pytest.mark.slow
+def test_rescale_config4_full_size_sampled(tf):
+    """N = 2^16, L = 24, 64 ciphertexts at level 24 (the HMULT benchmark
+    shape): two sampled ciphertexts equal the oracle bit for bit."""
+    n, L, K, dnum, level, B = 1 << 16, 24, 8, 3, 24, 64
+    pr = ckks.Params(n, L=L, K=K, dnum=dnum)
+    ctx = tf.CkksContext(16, L, K, dnum, moduli=pr.moduli)
+    qs = pr.mods(range(level))
+    ct = np.stack([inputs.uniform_residues(60 + c, qs, (B, n)) for c in range(2)])
+    got = to_host(ctx.rescale(to_dev(ct), level))
+    for b in (0, 41):
+        assert np.array_equal(got[:, :, b:b + 1], ckks.rescale(pr, ct[:, :, b:b + 1], level)), b
+
+
+def test_cmult_hadd_match_oracle(tf):
+    n = 1 << 12
+    pr, s, _, _ = setup(n, 8, 4, 2)
+    ctx = tf.CkksContext(12, 8, 4, 2, moduli=pr.moduli)
+    level = 6
+    qs, ps = pr.mods(range(level)), pr.psis(range(level))
+    c1 = encrypt(pr, s, inputs.small_messages(1, (3, n)), level, 1)
+    c2 = encrypt(pr, s, inputs.small_messages(2, (3, n)), level, 2)
+    pt = oracle.ntt_fwd(oracle.to_residues(inputs.small_messages(3, (3, n)), qs), qs, ps)
+    assert np.array_equal(to_host(ctx.cmult(to_dev(c1), to_dev(pt), level)), ckks.cmult(pr, c1, pt, level))
+    assert np.array_equal(to_host(ctx.hadd(to_dev(c1), to_dev(c2), level)), ckks.hadd(pr, c1, c2, level))
+    a = to_dev(c1)
+    ctx.hadd(a, to_dev(c2), level, out=a)   # in place
+    assert np.array_equal(to_host(a), ckks.hadd(pr, c1, c2, level))

@@ -46,18 +46,47 @@ def test_butterfly_matches_oracle(tf, log_n):
     assert np.array_equal(to_host(back), x)
 
 
-@pytest.mark.parametrize("batch", [1, 3])
-def test_mfma_matches_oracle(tf, batch):
-    n = 1 << 16
+@pytest.mark.parametrize("log_n,batch", [(16, 1), (16, 3), (15, 3), (14, 5), (13, 3), (12, 1), (12, 7)])
+def test_mfma_matches_oracle(tf, log_n, batch):
+    """Four-step MFMA transform (N = N1 x 256, N1 = 16 .. 256) against the
+    oracle, forward and inverse, on three limbs."""
+    n = 1 << log_n
     qs = PRIMES31[:3]
-    plan = tf.NttPlan(16, qs, algo="mfma")
+    plan = tf.NttPlan(log_n, qs, algo="mfma")
     assert plan.algo == tf.FOURSTEP_MFMA
-    x = inputs.uniform_residues(100 + batch, qs, (batch, n))
+    x = inputs.uniform_residues(100 + batch + log_n, qs, (batch, n))
     ref = oracle.ntt_fwd(x, qs, plan.psi)
     X = plan.fwd(to_dev(x), algo="mfma")
     assert np.array_equal(to_host(X), ref)
     back = plan.inv(to_dev(ref), algo="mfma")
     assert np.array_equal(to_host(back), x)
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15])
+def test_mfma_equals_butterfly_ragged(tf, log_n):
+    """Batches whose polynomial count is not a multiple of the workgroup
+    grouping (5 limbs x 37 polynomials): MFMA == butterfly bit for bit, and
+    the MFMA round trip is the identity."""
+    n = 1 << log_n
+    qs = PRIMES31[:5]
+    plan = tf.NttPlan(log_n, qs)
+    x = to_dev(inputs.uniform_residues(7 * log_n, qs, (37, n)))
+    f_m = plan.fwd(x, algo="mfma")
+    f_b = plan.fwd(x, algo="butterfly")
+    assert torch.equal(f_m, f_b)
+    assert torch.equal(plan.inv(f_m, algo="mfma"), x)
+
+
+def test_mfma_small_primes_config1(tf):
+    """N = 2^12 with the four largest primes below 2^30 (q = 1 mod 2^13)."""
+    n = 1 << 12
+    qs = oracle.ntt_primes(4, 30, 1 << 13)
+    plan = tf.NttPlan(12, qs, algo="mfma")
+    x = inputs.uniform_residues(12, qs, (8, n))
+    ref = oracle.ntt_fwd(x, qs, plan.psi)
+    X = plan.fwd(to_dev(x), algo="mfma")
+    assert np.array_equal(to_host(X), ref)
+    assert np.array_equal(to_host(plan.inv(X, algo="mfma")), x)
 
 
 def test_mfma_edge_values(tf):
@@ -193,7 +222,7 @@ def test_full_size_44x128_sampled(tf):
 def test_fused_batch_mixed_sizes_and_directions(tf):
     """Operation-level batching: one fused launch per pass covers transforms
     of different N, limb ranges and directions (butterfly), and of different
-    directions and batches (MFMA, N = 2^16)."""
+    directions and batches (MFMA, N = 2^13 and 2^16)."""
     plans = {ln: tf.NttPlan(ln, PRIMES31[:3]) for ln in (10, 13, 16)}
     specs = [(10, False, 3), (13, True, 2), (16, False, 1), (16, True, 2), (13, False, 1), (10, True, 4)]
     items, refs = [], []
@@ -206,10 +235,11 @@ def test_fused_batch_mixed_sizes_and_directions(tf):
         refs.append(oracle.ntt(x, plan.q[1:3], plan.psi[1:3], inverse=inv)[0])
     for o, r in zip(tf.ntt_batch(items, algo="butterfly"), refs):
         assert np.array_equal(to_host(o), r)
-    mf = [(i, r) for (i, r), (ln, _, _) in zip(zip(items, refs), specs) if ln == 16]
+    mf = [(i, r) for (i, r), (ln, _, _) in zip(zip(items, refs), specs) if ln >= 12]
     outs = tf.ntt_batch([i for i, _ in mf], algo="mfma")
     for o, (_, r) in zip(outs, mf):
         assert np.array_equal(to_host(o), r)
-    X = mf[0][0][1].clone()
+    first16 = next(k for k, (ln, inv, _) in enumerate(specs) if ln == 16 and not inv)
+    X = items[first16][1].clone()
     tf.ntt_batch([(plans[16], X, X, False, 1)], algo="mfma")   # in place
-    assert np.array_equal(to_host(X), mf[0][1])
+    assert np.array_equal(to_host(X), refs[first16])

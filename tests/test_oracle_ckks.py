@@ -210,11 +210,14 @@ def test_automorphism_is_ntt_permutation():
     assert list(got) == want
 
 
-def test_rotate_decrypts_to_rotated_message():
+@pytest.mark.parametrize("which", ["rot5", "conj"])
+def test_rotate_decrypts_to_rotated_message(which):
+    """Rotation by 5^5 and conjugation (X -> X^{2N-1}, i.e. X^i -> -X^{N-i})
+    decrypt to the automorphism of the message."""
     pr = small_params(1024)
     level = 4
     s, a, e = make_keys(pr)
-    k = ckks.galois_element(5, pr.n)
+    k = ckks.galois_element(5, pr.n) if which == "rot5" else 2 * pr.n - 1
     rk = ckks.rotation_key(pr, s, k, a, e)
     m = inputs.small_messages(0, (2, pr.n))
     out = ckks.rotate(pr, enc(pr, s, m, level, 1), rk, k, level)
@@ -223,6 +226,9 @@ def test_rotate_decrypts_to_rotated_message():
     for b in range(2):
         got = np.array([(int(v) + delta // 2) // delta for v in dec[b]], dtype=np.int64)
         assert np.array_equal(got, ckks.automorphism_int(m[b], k))
+        if which == "conj":  # closed form of X -> X^{-1} on Z[X]/(X^N + 1)
+            want = np.concatenate([m[b][:1], -m[b][:0:-1]])
+            assert np.array_equal(got, want)
 
 
 # ------------------------------------------------------------------ RESCALE
