@@ -30,14 +30,14 @@
 // leaves the canonical residue.  Twisted results are re-sliced into digits
 // for the next contraction with two VALU operations.
 //
-// Data movement.  A work item is 4096 words: P rows x W = 4096 / P columns
-// (vectors) of one polynomial.  Items are staged through a three-deep LDS
-// ring by direct-to-LDS loads issued two items ahead.  Each wave transforms
-// four sets of vectors; a set fills the 16 rows of one MFMA tile with 16 / r
-// vectors.  The intermediate array between the passes is tiled: block kb of
+// Data movement.  A work item is P rows x W columns (vectors) of one
+// polynomial, 1024 words per wave (4 waves, or 8 for the wide items of the
+// 256-point stage).  Items are staged through a three-deep LDS ring by
+// direct-to-LDS loads issued two items ahead.  Each wave transforms four sets
+// of vectors; a set fills the 16 rows of one MFMA tile with 16 / r vectors.  The intermediate array between the passes is tiled: block kb of
 // 16 consecutive pass-1 outputs holds, for every pass-1 column c, the 16
-// words (kb, c) contiguously, so pass 1 writes 1 KiB runs and pass 2 reads
-// its items as contiguous 16 KiB tiles.  Pass 2 writes its canonical results
+// words (kb, c) contiguously, so pass 1 writes runs of whole lines and pass 2
+// reads its items as contiguous 16 KiB blocks.  Pass 2 writes its canonical results
 // back in natural order through the LDS stage it has just consumed.
 #include <algorithm>
 
@@ -48,22 +48,32 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
-constexpr int kItem = 4096;  // words per work item
 constexpr int kStages = 3;   // LDS ring depth (items)
 
-// Geometry of a pass with P = 16 kR points.  The LDS tile of an item is 16
-// slabs of 64 16-byte slots: slab k holds rows kR k .. kR k + kR - 1, slot L
-// holds row kR k + L % kR, columns 4 (L / kR) .. + 3 (a "quad").  Slabs are
-// padded where the stores of the second pass would otherwise hit the same
-// LDS banks from several slabs at once.
-template <bool kFirst, int kR>
+// Geometry of a pass with P = 16 kR points.  A work item is P rows x W
+// vectors (columns) of one polynomial, 1024 words per wave; each wave
+// transforms four sets of vectors per item.  Its LDS tile is a sequence of
+// 1 KiB slabs; slab k holds rows Rs k .. Rs k + Rs - 1 of every column of the
+// item, slot L (16 bytes) row Rs k + L % Rs, columns 4 (L / Rs) .. + 3 (a
+// "quad"), so one direct-to-LDS load covers Rs rows x W columns.  Narrow
+// items (W = 16 for kR = 16) use 4 waves and Rs = 16: 64-byte row segments.
+// Wide items (kR = 16 with at least 32 columns) use 8 waves and Rs = 8, so
+// every load and store moves whole 128-byte lines.  For kR < 16, Rs = kR and
+// W = 256 / kR >= 32.  Slabs are padded where 16 lanes of an LDS access
+// would otherwise hit the same banks in several slabs.
+template <bool kFirst, int kR, bool kWide>
 struct Geo {
+  static constexpr int waves = kWide ? 8 : 4;
+  static constexpr int threads = 64 * waves;
+  static constexpr int item = 1024 * waves;      // words per work item
+  static constexpr int slabs = item / 256;
   static constexpr int P = 16 * kR;
-  static constexpr int W = kItem / P;    // vectors per item
-  static constexpr int Mt = 16 / kR;     // vectors per MFMA tile (quads per wave)
-  static constexpr int pitch = (kFirst || kR == 16) ? 256 : 256 + 4 * kR;  // words per slab
-  static constexpr int tile = 16 * pitch;
+  static constexpr int W = item / P;             // vectors per item
+  static constexpr int Mt = 16 / kR;             // vectors per MFMA tile (quads per wave)
+  static constexpr int Rs = kWide ? 8 : kR;      // rows per slab
+  static constexpr int pitch = kWide ? 256 + 32 : (kFirst || kR == 16) ? 256 : 256 + 4 * kR;
+  static constexpr int tile = slabs * pitch;
+  static_assert(!kWide || kR == 16, "wide items are for the 256-point stage");
 };
 
 // Descriptor table of a fused launch (passed by value as a kernel argument):
@@ -81,7 +91,7 @@ struct FsTable {
   uint32_t count, total;  // units, polynomials
   uint32_t log_n;
   uint32_t cols;          // S = N / P: columns of this pass (row stride in natural order)
-  uint32_t ipp_log;       // log2 of the items per polynomial (N / 4096)
+  uint32_t ipp_log;       // log2 of the items per polynomial (N / item words)
   FsUnit u[kMaxUnits];
 };
 
@@ -252,10 +262,10 @@ __device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
   else wait_vmcnt<4 + 2 * st>();
 }
 
-template <bool kFirst, int kR>
-__global__ void __launch_bounds__(kThreads)
+template <bool kFirst, int kR, bool kWide>
+__global__ void __launch_bounds__(kWide ? 512 : 256)
 fs_pass(const FsTable tab) {
-  using G = Geo<kFirst, kR>;
+  using G = Geo<kFirst, kR, kWide>;
   __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g = lane >> 4;
@@ -264,11 +274,11 @@ fs_pass(const FsTable tab) {
   const uint32_t S = tab.cols, c0 = walk.blk * G::W;
 
   // Per-lane word offsets within a polynomial.  Slab k = 4 wave + j, slot
-  // L = lane: row kR k + L % kR, item column 4 (L / kR).
+  // L = lane: row Rs k + L % Rs, item column 4 (L / Rs).
   uint32_t ld_off[4], st_off[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const uint32_t row = kR * (4 * wave + j) + lane % kR, col = 4 * (lane / kR);
+    const uint32_t row = G::Rs * (4 * wave + j) + lane % G::Rs, col = 4 * (lane / G::Rs);
     const uint32_t natural = row * S + c0 + col;
     const uint32_t tiled = ((c0 + col) >> 4) * (16 * G::P) + 16 * row + (col & 15);
     ld_off[j] = kFirst ? natural : tiled;
@@ -346,12 +356,16 @@ fs_pass(const FsTable tab) {
       if (pn < walk.p_end) issue(pn, (st + kStages - 1) % kStages);
     }
 
-    // lane (i, g) of wave w reads slab 4g + c, slot 16 w + i: row
-    // kR (4g + c) + i % kR of the quad w Mt + i / kR (four vectors, one per set)
+    // lane (i, g) of wave w reads row kR (4g + c) + i % kR of the quad
+    // w Mt + i / kR (four vectors, one per set): for 16 lanes either 256
+    // contiguous bytes of one slab, or (wide) 128 bytes of two slabs
     uint32_t* const tile = ring + st * G::tile;
     uint4 rows[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) rows[c] = *(const uint4*)(tile + (4 * g + c) * G::pitch + (16 * wave + i16) * 4);
+    for (int c = 0; c < 4; ++c) {
+      const int row = kR * (4 * g + c) + i16 % kR, quad = wave * G::Mt + i16 / kR;
+      rows[c] = *(const uint4*)(tile + (row / G::Rs) * G::pitch + (quad * G::Rs + row % G::Rs) * 4);
+    }
 
     uint32_t* const out = tab.u[it.unit].out + it.poly_base;
     uint4 res[4];  // pass 2: res[j] = the four sets' outputs of register j
@@ -410,7 +424,7 @@ fs_pass(const FsTable tab) {
         int m, t;
         lane_out<kR>(g, j, m, t);
         const int row = i16 + 16 * t;
-        *(uint4*)(tile + (row / kR) * G::pitch + ((wave * G::Mt + m) * kR + row % kR) * 4) = res[j];
+        *(uint4*)(tile + (row / G::Rs) * G::pitch + ((wave * G::Mt + m) * G::Rs + row % G::Rs) * 4) = res[j];
       }
       lds_barrier();
 #pragma unroll
@@ -421,41 +435,50 @@ fs_pass(const FsTable tab) {
 }
 
 // Resident workgroups per CU of a pass kernel (queried once per process).
-template <bool kFirst, int kR>
+template <bool kFirst, int kR, bool kWide>
 uint32_t occupancy() {
   static int occ = 0;
   if (occ == 0) {
     int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<kFirst, kR>, kThreads, 0);
-    occ = (e == hipSuccess && n > 0) ? n : 2;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<kFirst, kR, kWide>,
+                                                                Geo<kFirst, kR, kWide>::threads, 0);
+    occ = (e == hipSuccess && n > 0) ? n : 1;
   }
   return (uint32_t)occ;
 }
 
 // Persistent grid: resident workgroups of the whole device, rounded down to a
 // multiple of 16, and no more than the items need.
-template <bool kFirst, int kR>
+template <bool kFirst, int kR, bool kWide>
 uint32_t grid_size(const tfhe_ntt_plan_s* p, uint32_t items) {
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR>();
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide>();
   const uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
   return std::min(g, (items + 15) / 16 * 16);
 }
 
-template <bool kFirst, int kR>
-void launch_pass(const tfhe_ntt_plan_s* p, const FsTable& t, hipStream_t s) {
-  const uint32_t grid = grid_size<kFirst, kR>(p, t.total << t.ipp_log);
+template <bool kFirst, int kR, bool kWide>
+void launch_pass(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
+  using G = Geo<kFirst, kR, kWide>;
+  t.ipp_log = t.log_n - (kWide ? 13 : 12);  // items per polynomial: N / item words
+  const uint32_t grid = grid_size<kFirst, kR, kWide>(p, t.total << t.ipp_log);
   TFHE_TIMED(kFirst ? K_FS_PASS1 : K_FS_PASS2, s,
-             hipLaunchKernelGGL((fs_pass<kFirst, kR>), dim3(grid), dim3(kThreads), 0, s, t));
+             hipLaunchKernelGGL((fs_pass<kFirst, kR, kWide>), dim3(grid), dim3(G::threads), 0, s, t));
 }
 
+// The 256-point stage uses wide items when the pass has >= 128 columns
+// (N >= 2^15); below that the narrow items leave more work items per
+// polynomial, which measured faster.
 template <bool kFirst>
 void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipStream_t s) {
   switch (r) {
-    case 1: launch_pass<kFirst, 1>(p, t, s); break;
-    case 2: launch_pass<kFirst, 2>(p, t, s); break;
-    case 4: launch_pass<kFirst, 4>(p, t, s); break;
-    case 8: launch_pass<kFirst, 8>(p, t, s); break;
-    default: launch_pass<kFirst, 16>(p, t, s); break;
+    case 1: launch_pass<kFirst, 1, false>(p, t, s); break;
+    case 2: launch_pass<kFirst, 2, false>(p, t, s); break;
+    case 4: launch_pass<kFirst, 4, false>(p, t, s); break;
+    case 8: launch_pass<kFirst, 8, false>(p, t, s); break;
+    default:
+      if (t.cols >= 128) launch_pass<kFirst, 16, true>(p, t, s);
+      else launch_pass<kFirst, 16, false>(p, t, s);
+      break;
   }
 }
 
@@ -495,7 +518,6 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     const uint32_t N = 1u << log_n, N1 = N >> 8, r = N1 / 16;
     FsTable t1, t2;
     t1.log_n = t2.log_n = log_n;
-    t1.ipp_log = t2.ipp_log = log_n - 12;
     t1.cols = inverse ? N1 : 256;  // N / P of pass 1
     t2.cols = inverse ? 256 : N1;
     const uint32_t r1 = inverse ? 16 : r, r2 = inverse ? r : 16;
