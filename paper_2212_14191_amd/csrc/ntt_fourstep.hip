@@ -40,6 +40,7 @@
 // reads its items as contiguous 16 KiB blocks.  Pass 2 writes its canonical results
 // back in natural order through the LDS stage it has just consumed.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -111,10 +112,12 @@ __device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, ui
 }
 
 // Twist (Shoup, t = {w, companion}) and re-slice into digits; r < 2^32.
+// z - q lies in [-q, q), inside the digit window unless q > 0x7F7F7F7F.
+template <bool kBigQ>
 __device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q) {
   const uint32_t z = mul_shoup_lazy(r, t.x, t.y, q);  // [0, 2q)
   int32_t zz = (int32_t)(z - q);                      // [-q, q)
-  zz = zz > 0x7F7F7F7F ? zz - (int32_t)q : zz;        // only when q > 0x7F7F7F7F
+  if (kBigQ) zz = zz > 0x7F7F7F7F ? zz - (int32_t)q : zz;
   return balanced_digits(zz);
 }
 
@@ -263,7 +266,7 @@ __device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
 }
 
 template <bool kFirst, int kR, bool kWide>
-__global__ void __launch_bounds__(kWide ? 512 : 256)
+__global__ void __launch_bounds__(kWide ? 512 : 256, kWide ? 2 : 3)
 fs_pass(const FsTable tab) {
   using G = Geo<kFirst, kR, kWide>;
   __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile];
@@ -369,51 +372,62 @@ fs_pass(const FsTable tab) {
 
     uint32_t* const out = tab.u[it.unit].out + it.poly_base;
     uint4 res[4];  // pass 2: res[j] = the four sets' outputs of register j
+    // The digit window needs a correction only for q > 0x7F7F7F7F; q is
+    // uniform, so the item body is instantiated for both cases.
+    auto body = [&](auto big_q) {
+      constexpr bool kBigQ = decltype(big_q)::value;
 #pragma unroll
-    for (int sg = 0; sg < 4; ++sg) {
-      v4i x;
+      for (int sg = 0; sg < 4; ++sg) {
+        v4i x;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const uint32_t w = sg == 0 ? rows[c].x : sg == 1 ? rows[c].y : sg == 2 ? rows[c].z : rows[c].w;
-        x[c] = kFirst ? (int)balanced_digits(to_window(w, q)) : (int)w;
-      }
-      const v4i bias = {(int)q, (int)q, (int)q, (int)q};
-      const v4i zero = {0, 0, 0, 0};
-      const v4i a0 = mfma(x, opA[0], bias);
-      const v4i a1 = mfma(x, opA[1], zero);
-      const v4i a2 = mfma(x, opA[2], bias);
-      const v4i a3 = mfma(x, opA[3], zero);
-      uint32_t y[4];
-      if (kR == 16) {
-        v4i z;
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t w = sg == 0 ? rows[c].x : sg == 1 ? rows[c].y : sg == 2 ? rows[c].z : rows[c].w;
+          x[c] = kFirst ? (int)balanced_digits(kBigQ ? to_window(w, q) : (int32_t)w) : (int)w;
+        }
+        const v4i bias = {(int)q, (int)q, (int)q, (int)q};
+        const v4i zero = {0, 0, 0, 0};
+        const v4i a0 = mfma(x, opA[0], bias);
+        const v4i a1 = mfma(x, opA[1], zero);
+        const v4i a2 = mfma(x, opA[2], bias);
+        const v4i a3 = mfma(x, opA[3], zero);
+        uint32_t y[4];
+        if (kR == 16) {
+          v4i z;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) z[j] = (int)twist_digits(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j], q);
-        const v4i b0 = mfma(opB[0], z, bias);
-        const v4i b1 = mfma(opB[1], z, zero);
-        const v4i b2 = mfma(opB[2], z, bias);
-        const v4i b3 = mfma(opB[3], z, zero);
+          for (int j = 0; j < 4; ++j)
+            z[j] = (int)twist_digits<kBigQ>(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j], q);
+          const v4i b0 = mfma(opB[0], z, bias);
+          const v4i b1 = mfma(opB[1], z, zero);
+          const v4i b2 = mfma(opB[2], z, bias);
+          const v4i b3 = mfma(opB[3], z, zero);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) y[j] = fuse_redc(b0[j], b1[j], b2[j], b3[j], q, qneg);
-      } else {
+          for (int j = 0; j < 4; ++j) y[j] = fuse_redc(b0[j], b1[j], b2[j], b3[j], q, qneg);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          y[j] = reduce_once(mul_shoup_lazy(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j].x, tw[j].y, q), q);
-        level_b<kR>(y, lb, rj, g, q);
-      }
-      if (kFirst) {
+          for (int j = 0; j < 4; ++j)
+            y[j] = reduce_once(mul_shoup_lazy(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j].x, tw[j].y, q), q);
+          level_b<kR>(y, lb, rj, g, q);
+        }
+        if (kFirst) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) out[st_off[j] + 16 * sg] = twist_digits(y[j], pt[sg][j], q);
-      } else {
+          for (int j = 0; j < 4; ++j) out[st_off[j] + 16 * sg] = twist_digits<kBigQ>(y[j], pt[sg][j], q);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t r = kR == 16 ? reduce_once(y[j], q) : mul_shoup(y[j], pf[j].x, pf[j].y, q);
-          if (sg == 0) res[j].x = r;
-          else if (sg == 1) res[j].y = r;
-          else if (sg == 2) res[j].z = r;
-          else res[j].w = r;
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t r = kR == 16 ? reduce_once(y[j], q) : mul_shoup(y[j], pf[j].x, pf[j].y, q);
+            if (sg == 0) res[j].x = r;
+            else if (sg == 1) res[j].y = r;
+            else if (sg == 2) res[j].z = r;
+            else res[j].w = r;
+          }
         }
       }
-    }
+    };
+    // (the narrow first pass of the 256-point stage keeps one body: two
+    // would not fit its register budget without spilling)
+    constexpr bool kDual = !(kFirst && kR == 16 && !kWide);
+    if (!kDual || q > 0x7F7F7F7Fu) body(std::true_type{});
+    else body(std::false_type{});
 
     if (!kFirst) {
       // results into the consumed stage in the slab layout, then 16-byte
