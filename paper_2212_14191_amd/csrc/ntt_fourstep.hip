@@ -48,6 +48,7 @@ namespace tfhe {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kStages = 3;   // LDS ring depth (items)
 
@@ -221,8 +222,8 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 // Each wave loads slabs 4 wave .. 4 wave + 3 of an item: one 16-byte
-// direct-to-LDS load per lane per slab; lane L's bytes land at the slab base
-// + 16 L.  Issued as inline assembly so that the compiler does not serialise
+// direct-to-LDS load per lane per slab (streaming hint: every byte is read
+// once); lane L's bytes land at the slab base + 16 L.  Issued as inline assembly so that the compiler does not serialise
 // later LDS reads on these loads: the pipeline waits for them explicitly
 // (wait_item) before a barrier.
 template <int kPitch>
@@ -234,7 +235,7 @@ __device__ __forceinline__ void issue_tile(const uint32_t* src, const uint32_t* 
     const uint32_t lds_addr = (uint32_t)(uintptr_t)(lds_void_t*)(stage + (4 * wave + j) * kPitch);
     asm volatile(
         "s_mov_b32 m0, %0\n\t"
-        "global_load_lds_dwordx4 %1, off"
+        "global_load_lds_dwordx4 %1, off nt"
         :
         : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
         : "memory", "m0");
@@ -431,7 +432,8 @@ fs_pass(const FsTable tab) {
 
     if (!kFirst) {
       // results into the consumed stage in the slab layout, then 16-byte
-      // stores with the load's lane mapping
+      // streaming stores with the load's lane mapping (whole lines; the
+      // first pass keeps cached stores, whose 64-byte halves merge in L2)
       lds_barrier();  // every wave has read the stage
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -443,7 +445,7 @@ fs_pass(const FsTable tab) {
       lds_barrier();
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        *(uint4*)(out + st_off[j]) = *(const uint4*)(tile + (4 * wave + j) * G::pitch + lane * 4);
+        __builtin_nontemporal_store(*(const v4u*)(tile + (4 * wave + j) * G::pitch + lane * 4), (v4u*)(out + st_off[j]));
     }
   }
 }
@@ -461,11 +463,13 @@ uint32_t occupancy() {
   return (uint32_t)occ;
 }
 
-// Persistent grid: resident workgroups of the whole device, rounded down to a
-// multiple of 16, and no more than the items need.
+// Persistent grid: a multiple of 16 workgroups, no more than the items need.
 template <bool kFirst, int kR, bool kWide>
 uint32_t grid_size(const tfhe_ntt_plan_s* p, uint32_t items) {
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide>();
+  // default: the resident count; twice that for the wide kernels (one
+  // resident workgroup per CU), whose tail balances better with the second
+  // half of the grid scheduled as the first half drains (measured)
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide>() * (kWide ? 2 : 1);
   const uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
   return std::min(g, (items + 15) / 16 * 16);
 }
