@@ -101,8 +101,12 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *                            unit (0 = as many as fit, the default)
  *   TFHE_PARAM_AUTO_ALGO     what TFHE_NTT_AUTO resolves to (a tfhe_ntt_algo;
  *                            MFMA only where the plan supports it)
+ *   TFHE_PARAM_FS_WIDE       work items of the four-step 256-point stage:
+ *                            0 = library default (wide for N >= 2^15),
+ *                            1 = always 16 vectors (4 waves), 2 = 32 vectors
+ *                            (8 waves) whenever N >= 2^13
  * Not thread-safe against concurrent compute calls on the same plan. */
-typedef enum { TFHE_PARAM_FS_WG_PER_CU = 1, TFHE_PARAM_AUTO_ALGO = 2 } tfhe_plan_param;
+typedef enum { TFHE_PARAM_FS_WG_PER_CU = 1, TFHE_PARAM_AUTO_ALGO = 2, TFHE_PARAM_FS_WIDE = 3 } tfhe_plan_param;
 tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t value);
 tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t* value);
 

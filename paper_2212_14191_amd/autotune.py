@@ -3,8 +3,8 @@ the different involved kernels according to the hardware resources",
 Sec. III-E; the best batch differs per kernel, Sec. VI).
 
 * NTT: for a (log N, limbs, batch) shape, times forward + inverse for each
-  candidate (algorithm x persistent four-step workgroups per CU) with the
-  library's event timing and keeps the fastest.
+  candidate (algorithm x 256-point item width x persistent four-step
+  workgroups per CU) and keeps the fastest.
 * HMULT: sweeps the batch size at a (log N, level) and keeps the smallest
   batch within `slack` of the best throughput (small batches keep latency
   low in the serving loop).
@@ -15,6 +15,7 @@ import os
 import time
 
 NTT_WG_CANDIDATES = (0, 1, 2, 3, 4, 6, 8)
+NTT_WIDE_CANDIDATES = (1, 2)   # narrow / wide 256-point items (0 = library default)
 
 
 def ntt_key(log_n, limbs, batch):
@@ -69,6 +70,7 @@ def apply(plan, table, limbs, batch):
         return False
     plan.set_param("auto_algo", {"butterfly": 1, "mfma": 2}[e["algo"]])
     plan.set_param("fs_wg_per_cu", e.get("fs_wg_per_cu", 0))
+    plan.set_param("fs_wide", e.get("fs_wide", 0))
     return True
 
 
@@ -78,14 +80,15 @@ def tune_ntt(plan, x, reps=5, warmup=1):
     from . import tfhe
     limbs, batch, _ = x.shape
     y, z = torch.empty_like(x), torch.empty_like(x)
-    cands = [("butterfly", 0)]
+    cands = [("butterfly", 0, 0)]
     if plan.get_param("auto_algo") == tfhe.FOURSTEP_MFMA or _has_mfma(plan):
-        cands += [("mfma", w) for w in NTT_WG_CANDIDATES]
+        cands += [("mfma", wide, w) for wide in NTT_WIDE_CANDIDATES for w in NTT_WG_CANDIDATES]
     ws = plan.workspace(limbs, batch, "mfma" if len(cands) > 1 else "butterfly")
     results = []
-    old = plan.get_param("fs_wg_per_cu")
-    for algo, w in cands:
+    old = (plan.get_param("fs_wg_per_cu"), plan.get_param("fs_wide"))
+    for algo, wide, w in cands:
         plan.set_param("fs_wg_per_cu", w)
+        plan.set_param("fs_wide", wide)
         for _ in range(warmup):
             plan.fwd(x, out=y, algo=algo, ws=ws)
             plan.inv(y, out=z, algo=algo, ws=ws)
@@ -97,9 +100,10 @@ def tune_ntt(plan, x, reps=5, warmup=1):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if not torch.equal(z, x):
-            raise RuntimeError(f"autotune: {algo}/{w} failed the round trip")
-        results.append(({"algo": algo, "fs_wg_per_cu": w}, 2 * limbs * batch * reps / dt / 1e3))
-    plan.set_param("fs_wg_per_cu", old)
+            raise RuntimeError(f"autotune: {algo}/{wide}/{w} failed the round trip")
+        results.append(({"algo": algo, "fs_wide": wide, "fs_wg_per_cu": w}, 2 * limbs * batch * reps / dt / 1e3))
+    plan.set_param("fs_wg_per_cu", old[0])
+    plan.set_param("fs_wide", old[1])
     cfg, kops = pick_best(results)
     best = dict(cfg, kops=kops)
     return best, [dict(c, kops=k) for c, k in results]

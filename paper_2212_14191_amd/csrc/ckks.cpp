@@ -60,6 +60,65 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
   return l;
 }
 
+// ModUp conversion of digit [d0, d0 + nd) on the matrix cores: every
+// extended-basis position outside the digit, in launches of <= 32 targets.
+static hipError_t modup_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* x, uint32_t* up, uint32_t key_idx,
+                             uint32_t d0, uint32_t nd, uint32_t level, uint64_t plane, hipStream_t s) {
+  ConvArgs a;
+  a.in = x + (uint64_t)d0 * plane;
+  a.out = up;
+  a.plane = plane;
+  a.nin = nd;
+  for (uint32_t r = 0; r < nd; ++r) {
+    a.in_q[r] = c->h_mod[d0 + r].q;
+    a.in_mult[r] = c->h_up_inv[(size_t)key_idx * kMaxAlpha + r];
+  }
+  a.nout = 0;
+  for (uint32_t pos = 0; pos < level + c->K; ++pos) {
+    if (pos >= d0 && pos < d0 + nd) continue;
+    const uint32_t t = pos < level ? pos : c->L + (pos - level);
+    a.out_plane[a.nout] = pos;
+    a.out_q[a.nout] = c->h_mod[t].q;
+    a.out_qneg[a.nout] = c->h_mod[t].qneg;
+    a.out_k[a.nout] = c->h_up_k[(size_t)key_idx * (c->L + c->K) + t];
+    a.a_tab[a.nout] = c->d_up_mfma + ((size_t)key_idx * (c->L + c->K) + t) * 32;
+    if (++a.nout == kConvMaxOut) {
+      hipError_t e = launch_conv_mfma(a, K_MODUP, s);
+      if (e != hipSuccess) return e;
+      a.nout = 0;
+    }
+  }
+  return a.nout ? launch_conv_mfma(a, K_MODUP, s) : hipSuccess;
+}
+
+// ModDown conversion of the K special limbs to the level q-limbs.
+static hipError_t moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp, uint32_t* conv,
+                                    uint32_t level, uint64_t plane, hipStream_t s) {
+  ConvArgs a;
+  a.in = tp;
+  a.out = conv;
+  a.plane = plane;
+  a.nin = c->K;
+  for (uint32_t k = 0; k < c->K; ++k) {
+    a.in_q[k] = c->h_mod[c->L + k].q;
+    a.in_mult[k] = c->h_dn_invp[k];
+  }
+  a.nout = 0;
+  for (uint32_t i = 0; i < level; ++i) {
+    a.out_plane[a.nout] = i;
+    a.out_q[a.nout] = c->h_mod[i].q;
+    a.out_qneg[a.nout] = c->h_mod[i].qneg;
+    a.out_k[a.nout] = c->h_dn_k[i];
+    a.a_tab[a.nout] = c->d_dn_mfma + (size_t)i * 32;
+    if (++a.nout == kConvMaxOut) {
+      hipError_t e = launch_conv_mfma(a, K_MD_CONV, s);
+      if (e != hipSuccess) return e;
+      a.nout = 0;
+    }
+  }
+  return a.nout ? launch_conv_mfma(a, K_MD_CONV, s) : hipSuccess;
+}
+
 // Key switching of d (NTT domain, [level][B][N]) with key [dnum][2][L+K][N];
 // out0 (+)= ModDown(acc0), out1 (+)= ModDown(acc1).
 static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const uint32_t* key,
@@ -76,6 +135,8 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   uint32_t* tp = (uint32_t*)(ws + lay.tp);
   uint32_t* conv = (uint32_t*)(ws + lay.conv);
   void* nws = ws + lay.ntt;
+  // matrix-core conversion needs planes in whole 64-word chunks
+  const bool mfma_conv = plane % 64 == 0;
   hipError_t e;
   // INTT of the input (coefficient domain for the basis conversion)
   if ((e = ntt_units(p, {NttUnit{p, true, d, x, 0, level, batch}}, nws, s)) != hipSuccess) return e;
@@ -86,9 +147,10 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
     const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
     const uint32_t key_idx = d0 + nd - 1;
     uint32_t* upj = up + (uint64_t)j * ext * plane;
-    if ((e = launch_modup(x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
-                          c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
-                          c->L, c->K, batch, c->n, s)) != hipSuccess)
+    if ((e = mfma_conv ? modup_mfma(c, x, upj, key_idx, d0, nd, level, plane, s)
+                       : launch_modup(x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
+                                      c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd,
+                                      level, c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
     uint32_t* after = upj + (uint64_t)(d0 + nd) * plane;
     uint32_t* pl = upj + (uint64_t)level * plane;
@@ -110,8 +172,9 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
                      nws, s)) != hipSuccess)
     return e;
   for (int comp = 0; comp < 2; ++comp)
-    if ((e = launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
-                                 c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
+    if ((e = mfma_conv ? moddown_conv_mfma(c, comp ? tp1 : tp, comp ? conv1 : conv, level, plane, s)
+                       : launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
+                                             c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
   if ((e = ntt_units(p, {NttUnit{p, false, conv, conv, 0, level, batch},
                          NttUnit{p, false, conv1, conv1, 0, level, batch}},
@@ -229,12 +292,59 @@ static tfhe_status ctx_build(tfhe_ckks_ctx_s* c) {
       dconv[(size_t)i * kMaxK + k] = with_companion(prod, qi);
     }
   }
+  // Matrix-core conversion operands: dword (j, r) of target t packs, for
+  // d = 0..3, digit j of the balanced expansion of 2^{8d} C[t][r] 2^32 mod m_t.
+  auto pack = [&](uint32_t C, uint32_t mt, int j) {
+    const uint32_t c32 = mulm(C, (uint32_t)((1ull << 32) % mt), mt);
+    uint32_t w = 0;
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t v = mulm(c32, (uint32_t)((1ull << (8 * d)) % mt), mt);
+      w |= ((balanced_digits(to_window(v, mt)) >> (8 * j)) & 0xFFu) << (8 * d);
+    }
+    return w;
+  };
+  std::vector<uint32_t> up_mfma((size_t)L * (L + K) * 32, 0), dn_mfma((size_t)L * 32, 0);
+  for (uint32_t e = 1; e <= L; ++e) {
+    const uint32_t d0 = A * ((e - 1) / A), nd = e - d0;
+    for (uint32_t t = 0; t < L + K; ++t)
+      for (int j = 0; j < 4; ++j)
+        for (uint32_t r = 0; r < nd; ++r)
+          up_mfma[((size_t)(e - 1) * (L + K) + t) * 32 + 8 * j + r] =
+              pack(up_conv[((size_t)(e - 1) * (L + K) + t) * kMaxAlpha + r].x, m[t], j);
+  }
+  for (uint32_t i = 0; i < L; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (uint32_t k = 0; k < K; ++k) dn_mfma[(size_t)i * 32 + 8 * j + k] = pack(dconv[(size_t)i * kMaxK + k].x, m[i], j);
+  // offset corrections: 2^30 sum_r C[t][r] mod m_t
+  const auto k30 = [&](uint32_t mt) { return (uint32_t)((1ull << 30) % mt); };
+  c->h_up_k.assign((size_t)L * (L + K), 0);
+  for (uint32_t e = 1; e <= L; ++e) {
+    const uint32_t d0 = A * ((e - 1) / A), nd = e - d0;
+    for (uint32_t t = 0; t < L + K; ++t) {
+      uint32_t sum = 0;
+      for (uint32_t r = 0; r < nd; ++r)
+        sum = (uint32_t)(((uint64_t)sum + up_conv[((size_t)(e - 1) * (L + K) + t) * kMaxAlpha + r].x) % m[t]);
+      c->h_up_k[(size_t)(e - 1) * (L + K) + t] = mulm(sum, k30(m[t]), m[t]);
+    }
+  }
+  c->h_dn_k.assign(L, 0);
+  for (uint32_t i = 0; i < L; ++i) {
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < K; ++k) sum = (uint32_t)(((uint64_t)sum + dconv[(size_t)i * kMaxK + k].x) % m[i]);
+    c->h_dn_k[i] = mulm(sum, k30(m[i]), m[i]);
+  }
+  c->h_up_inv = up_inv;
+  c->h_dn_invp = invp;
+  c->h_mod.resize(L + K);
+  for (uint32_t t = 0; t < L + K; ++t) c->h_mod[t] = make_modconst(m[t]);
   std::vector<uint2> rsq((size_t)L * L, make_uint2(0, 0));
   for (uint32_t t = 1; t < L; ++t)
     for (uint32_t i = 0; i < t; ++i)
       rsq[(size_t)t * L + i] = with_companion(inv_mod(m[t] % m[i], m[i]), m[i]);
   hipError_t e;
   if ((e = upload(&c->d_rs_qinv, rsq, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_up_mfma, up_mfma, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_dn_mfma, dn_mfma, c->owned)) != hipSuccess ||
       (e = upload(&c->d_up_inv, up_inv, c->owned)) != hipSuccess ||
       (e = upload(&c->d_up_conv, up_conv, c->owned)) != hipSuccess ||
       (e = upload(&c->d_dn_invp, invp, c->owned)) != hipSuccess ||

@@ -19,7 +19,31 @@ struct CkksCtxImpl {
   uint2* d_dn_pinv = nullptr;  // [L]                   [P^{-1}]_{q_i}
   // RESCALE constants:
   uint2* d_rs_qinv = nullptr;  // [L][L]                [q_t^{-1}]_{q_i} at row t
+  // Matrix-core basis conversion operands (ConvArgs::a_tab layout):
+  uint32_t* d_up_mfma = nullptr;  // [L (digit end - 1)][L+K (target)][4][8]
+  uint32_t* d_dn_mfma = nullptr;  // [L (target)][4][8]
+  // host copies of the per-input multipliers and per-limb Montgomery constants
+  std::vector<uint2> h_up_inv, h_dn_invp;  // as d_up_inv, d_dn_invp
+  std::vector<uint32_t> h_up_k, h_dn_k;    // [L][L+K], [L]: ConvArgs::out_k
+  std::vector<ModConst> h_mod;             // [L+K]
   std::vector<void*> owned;
+};
+
+// Basis conversion on the matrix cores: out_t = sum_r y_r C[t][r] mod m_t
+// with y_r = in_r * mult_r mod q_r in [0, q_r) (the integer itself matters:
+// q_r != m_t), for up to 8 inputs and 32 targets.
+constexpr int kConvMaxIn = 8, kConvMaxOut = 32;
+struct ConvArgs {
+  const uint32_t* in;   // input plane r at in + r * plane
+  uint32_t* out;        // target t written to out + out_plane[t] * plane
+  uint64_t plane;       // words per plane (batch * N), a multiple of 64
+  uint32_t nin, nout;
+  uint32_t in_q[kConvMaxIn];
+  uint2 in_mult[kConvMaxIn];       // Shoup pair of mult_r
+  uint32_t out_plane[kConvMaxOut];
+  uint32_t out_q[kConvMaxOut], out_qneg[kConvMaxOut];
+  uint32_t out_k[kConvMaxOut];         // 2^30 sum_r C[t][r] mod m_t (offset correction)
+  const uint32_t* a_tab[kConvMaxOut];  // 32 dwords per target: [plane j][8]
 };
 
 hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
@@ -39,6 +63,7 @@ hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint3
                                 const ModConst* mods, const uint2* pinv, uint32_t level,
                                 uint32_t batch, uint32_t n, bool accumulate, hipStream_t s,
                                 KernelId id = K_MD_FINAL);
+hipError_t launch_conv_mfma(const ConvArgs& a, KernelId id, hipStream_t s);
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 

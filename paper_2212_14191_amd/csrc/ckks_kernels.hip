@@ -171,6 +171,97 @@ moddown_final_kernel(const uint4* __restrict__ acc, const uint4* __restrict__ co
   }
 }
 
+// Basis conversion (the Conv kernel of ModUp / ModDown) as a skinny matrix
+// product on the INT8 matrix cores: D[t][pos] = sum_{r,d} A[t][(r,d)] *
+// digit_d(y_r[pos]), K = 4 digits x 8 inputs = 32 with
+// v_mfma_i32_16x16x32_i8, one product per digit plane j of the constants
+// (A_j[t][(r,d)] = digit j of 2^{8d} C[t][r] 2^32 mod m_t), fused as in the
+// four-step NTT: V = (C_0 + 2^8 C_1) + 2^16 (C_2 + 2^8 C_3), one Montgomery
+// step (the 2^32 in the constants cancels it), one conditional subtraction.
+// The inputs enter as y_r - 2^30 in [-2^30, 2^30), inside the digit window
+// for every modulus below 2^31; the offset comes back as the per-target
+// constant 2^30 sum_r C[t][r] mod m_t.  Lane (n, g) loads four consecutive positions 4n..4n+3 of inputs 2g and
+// 2g+1 (16-byte loads) and the product for sub-tile p pairs MFMA column n
+// with position 4n + p; after the four sub-tiles it holds targets 4g..4g+3
+// at positions 4n..4n+3 and stores them as 16-byte runs.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t conv_fuse(int c0, int c1, int c2, int c3, uint32_t q, uint32_t qneg) {
+  const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
+  const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
+  const uint64_t V = ((uint64_t)hi << 16) + lo;
+  const uint32_t vlo = (uint32_t)V, vhi = (uint32_t)(V >> 32);
+  const uint32_t m = vlo * qneg;
+  return reduce_once(vhi + __umulhi(m, q) + (vlo != 0u), q);
+}
+
+__global__ void __launch_bounds__(kThreads)
+conv_mfma_kernel(const ConvArgs a) {
+  const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
+  const uint64_t chunks = a.plane / 64;
+  const uint64_t wave_id = (blockIdx.x * (uint64_t)kThreads + threadIdx.x) / 64;
+  const uint64_t waves = (uint64_t)gridDim.x * (kThreads / 64);
+  const int r0 = 2 * g, r1 = 2 * g + 1;
+  const bool h0 = r0 < (int)a.nin, h1 = r1 < (int)a.nin;
+  const uint32_t q0 = h0 ? a.in_q[r0] : 1, q1 = h1 ? a.in_q[r1] : 1;
+  const uint2 m0 = h0 ? a.in_mult[r0] : make_uint2(0, 0), m1 = h1 ? a.in_mult[r1] : make_uint2(0, 0);
+  // constant operands of the (at most two) 16-target blocks
+  long av[2][4];
+  uint32_t tq[2][4], tn[2][4], tk[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const uint32_t ta = 16 * b + n;  // target of this lane's A row
+#pragma unroll
+    for (int j = 0; j < 4; ++j) av[b][j] = ta < a.nout ? *(const long*)(a.a_tab[ta] + 8 * j + 2 * g) : 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t t = 16 * b + 4 * g + i;
+      tq[b][i] = t < a.nout ? a.out_q[t] : 1;
+      tn[b][i] = t < a.nout ? a.out_qneg[t] : 0;
+      tk[b][i] = t < a.nout ? a.out_k[t] : 0;
+    }
+  }
+  const int blocks = a.nout > 16 ? 2 : 1;
+  const v4i zero = {0, 0, 0, 0};
+  for (uint64_t c = wave_id; c < chunks; c += waves) {
+    const uint64_t pos = c * 64 + 4 * n;
+    uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0;
+    if (h0) x0 = *(const uint4*)(a.in + (uint64_t)r0 * a.plane + pos);
+    if (h1) x1 = *(const uint4*)(a.in + (uint64_t)r1 * a.plane + pos);
+    // y = x * mult mod q in [0, q), then the digits of y - 2^30
+    const uint4 d0 = map4(x0, [&](uint32_t v, int) {
+      return h0 ? balanced_digits((int32_t)(mul_shoup(v, m0.x, m0.y, q0) - (1u << 30))) : 0u;
+    });
+    const uint4 d1 = map4(x1, [&](uint32_t v, int) {
+      return h1 ? balanced_digits((int32_t)(mul_shoup(v, m1.x, m1.y, q1) - (1u << 30))) : 0u;
+    });
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (b >= blocks) break;
+      const v4i bias = {(int)tq[b][0], (int)tq[b][1], (int)tq[b][2], (int)tq[b][3]};
+      uint32_t res[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const long bv = (long)((uint64_t)comp(d0, p) | ((uint64_t)comp(d1, p) << 32));
+        const v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][0], bv, bias, 0, 0, 0);
+        const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][1], bv, zero, 0, 0, 0);
+        const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][2], bv, bias, 0, 0, 0);
+        const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][3], bv, zero, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          res[i][p] = add_mod(conv_fuse(c0[i], c1[i], c2[i], c3[i], tq[b][i], tn[b][i]), tk[b][i], tq[b][i]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t t = 16 * b + 4 * g + i;
+        if (t < a.nout)
+          *(uint4*)(a.out + (uint64_t)a.out_plane[t] * a.plane + pos) =
+              make_uint4(res[i][0], res[i][1], res[i][2], res[i][3]);
+      }
+    }
+  }
+}
+
 // RESCALE broadcast: t holds the two components' top limbs in the
 // coefficient domain, [2][B][N] in [0, q_top); u[c][i] = t[c] mod q_i for
 // i < top.  Every modulus exceeds 2^29 and t < 2^31 < 4 q_i, so two
@@ -194,6 +285,14 @@ rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
 }
 
 }  // namespace
+
+hipError_t launch_conv_mfma(const ConvArgs& a, KernelId id, hipStream_t s) {
+  const uint64_t chunks = a.plane / 64;
+  const uint64_t blocks = (chunks + 3) / 4;  // 4 waves per block, one chunk each per round
+  const uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+  TFHE_TIMED(id, s, hipLaunchKernelGGL(conv_mfma_kernel, dim3(grid), dim3(kThreads), 0, s, a));
+  return hipGetLastError();
+}
 
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s) {

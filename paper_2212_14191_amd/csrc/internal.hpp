@@ -48,6 +48,7 @@ struct tfhe_plan_impl {
   int device = 0;
   uint32_t num_cus = 256;         // compute units of the device
   uint32_t fs_wg_per_cu = 0;      // persistent four-step workgroups per CU (0: occupancy)
+  uint32_t fs_wide = 0;           // 256-point stage items: 0 auto, 1 narrow, 2 wide when possible
   std::vector<uint32_t> q, psi;
   // device arrays
   ModConst* d_mod = nullptr;      // [n_limbs]
@@ -126,6 +127,7 @@ hipError_t load_small_launch(const ModConst* mods, const int32_t* in, uint32_t* 
 
 // ---- host-side number theory (plan.cpp)
 bool is_prime_u32(uint32_t q);
+ModConst make_modconst(uint32_t q);
 uint32_t pow_mod(uint32_t b, uint64_t e, uint32_t q);
 uint32_t inv_mod(uint32_t x, uint32_t q);
 uint32_t default_psi(uint32_t q, uint32_t log_n);  // 0 if none

@@ -483,9 +483,9 @@ void launch_pass(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
              hipLaunchKernelGGL((fs_pass<kFirst, kR, kWide>), dim3(grid), dim3(G::threads), 0, s, t));
 }
 
-// The 256-point stage uses wide items when the pass has >= 128 columns
-// (N >= 2^15); below that the narrow items leave more work items per
-// polynomial, which measured faster.
+// The 256-point stage uses wide items by default when the pass has >= 128
+// columns (N >= 2^15); below that the narrow items leave more work items per
+// polynomial, which measured faster.  The plan's fs_wide overrides this.
 template <bool kFirst>
 void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipStream_t s) {
   switch (r) {
@@ -494,7 +494,8 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
     case 4: launch_pass<kFirst, 4, false>(p, t, s); break;
     case 8: launch_pass<kFirst, 8, false>(p, t, s); break;
     default:
-      if (t.cols >= 128) launch_pass<kFirst, 16, true>(p, t, s);
+      if (p->fs_wide == 1 ? false : t.cols >= (p->fs_wide == 2 ? 32u : 128u))
+        launch_pass<kFirst, 16, true>(p, t, s);
       else launch_pass<kFirst, 16, false>(p, t, s);
       break;
   }

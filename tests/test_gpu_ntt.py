@@ -62,14 +62,18 @@ def test_mfma_matches_oracle(tf, log_n, batch):
     assert np.array_equal(to_host(back), x)
 
 
-@pytest.mark.parametrize("log_n", [12, 13, 14, 15])
-def test_mfma_equals_butterfly_ragged(tf, log_n):
+@pytest.mark.parametrize("log_n,wide", [(12, 0), (13, 0), (14, 0), (15, 0), (13, 2), (14, 2),
+                                         (15, 1), (16, 1), (16, 2)])
+def test_mfma_equals_butterfly_ragged(tf, log_n, wide):
     """Batches whose polynomial count is not a multiple of the workgroup
-    grouping (5 limbs x 37 polynomials): MFMA == butterfly bit for bit, and
-    the MFMA round trip is the identity."""
+    grouping (5 limbs x 37 polynomials), with the default, narrow (1) and
+    wide (2) items of the 256-point stage: MFMA == butterfly bit for bit,
+    and the MFMA round trip is the identity."""
     n = 1 << log_n
     qs = PRIMES31[:5]
     plan = tf.NttPlan(log_n, qs)
+    plan.set_param("fs_wide", wide)
+    assert plan.get_param("fs_wide") == wide
     x = to_dev(inputs.uniform_residues(7 * log_n, qs, (37, n)))
     f_m = plan.fwd(x, algo="mfma")
     f_b = plan.fwd(x, algo="butterfly")
