@@ -223,11 +223,19 @@ conv_mfma_kernel(const ConvArgs a) {
   }
   const int blocks = a.nout > 16 ? 2 : 1;
   const v4i zero = {0, 0, 0, 0};
+  // the next chunk's inputs are loaded while this one is converted
+  uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
+  if (wave_id < chunks) {
+    if (h0) nx0 = *(const uint4*)(a.in + (uint64_t)r0 * a.plane + wave_id * 64 + 4 * n);
+    if (h1) nx1 = *(const uint4*)(a.in + (uint64_t)r1 * a.plane + wave_id * 64 + 4 * n);
+  }
   for (uint64_t c = wave_id; c < chunks; c += waves) {
     const uint64_t pos = c * 64 + 4 * n;
-    uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0;
-    if (h0) x0 = *(const uint4*)(a.in + (uint64_t)r0 * a.plane + pos);
-    if (h1) x1 = *(const uint4*)(a.in + (uint64_t)r1 * a.plane + pos);
+    const uint4 x0 = nx0, x1 = nx1;
+    if (c + waves < chunks) {
+      if (h0) nx0 = *(const uint4*)(a.in + (uint64_t)r0 * a.plane + pos + waves * 64);
+      if (h1) nx1 = *(const uint4*)(a.in + (uint64_t)r1 * a.plane + pos + waves * 64);
+    }
     // y = x * mult mod q in [0, q), then the digits of y - 2^30
     const uint4 d0 = map4(x0, [&](uint32_t v, int) {
       return h0 ? balanced_digits((int32_t)(mul_shoup(v, m0.x, m0.y, q0) - (1u << 30))) : 0u;
@@ -289,7 +297,9 @@ rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
 hipError_t launch_conv_mfma(const ConvArgs& a, KernelId id, hipStream_t s) {
   const uint64_t chunks = a.plane / 64;
   const uint64_t blocks = (chunks + 3) / 4;  // 4 waves per block, one chunk each per round
-  const uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+  // about one resident round: each wave then converts several chunks with
+  // its next inputs in flight
+  const uint32_t grid = (uint32_t)(blocks < 1536 ? (blocks ? blocks : 1) : 1536);
   TFHE_TIMED(id, s, hipLaunchKernelGGL(conv_mfma_kernel, dim3(grid), dim3(kThreads), 0, s, a));
   return hipGetLastError();
 }

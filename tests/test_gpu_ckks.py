@@ -47,11 +47,12 @@ def encrypt(pr, s, m, level, seed):
 
 @pytest.mark.parametrize("log_n,L,K,dnum,level", [
     (10, 6, 2, 3, 6), (10, 6, 2, 3, 5), (10, 6, 2, 3, 1), (12, 8, 4, 2, 8), (12, 8, 4, 2, 3),
-    (13, 24, 8, 3, 24), (13, 24, 8, 3, 17), (5, 6, 2, 3, 6)])
+    (13, 24, 8, 3, 24), (13, 24, 8, 3, 17), (5, 6, 2, 3, 6), (10, 12, 2, 12, 12), (10, 12, 2, 12, 9)])
 def test_hmult_matches_oracle(tf, log_n, L, K, dnum, level):
     """Bit-exact HMULT.  The basis conversions run on the matrix cores,
     except at N = 2^5 (3 x 32-word planes are not whole 64-word chunks),
-    which takes the VALU conversion."""
+    which takes the VALU conversion; dnum = 12 runs the inner product in
+    two digit groups."""
     n = 1 << log_n
     pr, s, evk, _ = setup(n, L, K, dnum)
     ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
