@@ -6,8 +6,10 @@ One step = forward NTT then inverse NTT of a batch of N = 2^16 polynomials:
 computed with the four-step INT8-MFMA transform.  `value` is that transform's
 throughput in KOPS (10^3 limb-transforms per second; one limb-transform is
 one N-point NTT or INTT over one prime).  Measured beside it on the same data:
-the radix-2 butterfly transform, the batched HMULT (N=2^16, L=24, K=8,
-dnum=3, 64 ciphertext pairs), and the plain CPU oracle on a bounded sample.
+the radix-2 butterfly transform, the vector-ALU GEMM variant of the four-step
+transform, the batched HMULT (N=2^16, L=24, K=8, dnum=3, 64 ciphertext
+pairs) and RESCALE, the serving mix, and the plain CPU oracle on a bounded
+sample.
 
 Prints one JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -178,7 +180,7 @@ def main():
     ap.add_argument("--skip-hmult", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=400)
-    ap.add_argument("--only", choices=["mfma", "butterfly", "hmult"], default=None,
+    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult"], default=None,
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of the input batch (a known-size "
@@ -211,7 +213,7 @@ def main():
         y.copy_(x)
         sync()
     results = {}
-    algos = ["mfma", "butterfly"] if args.only is None else [args.only] if args.only != "hmult" else []
+    algos = ["mfma", "butterfly", "co"] if args.only is None else [args.only] if args.only != "hmult" else []
     for algo in algos:
         def step(algo=algo):
             plan.fwd(x, out=y, algo=algo, ws=ws)
@@ -224,7 +226,9 @@ def main():
         tfhe.tfhe_timing_enable(True)
         dt = timed(step, steps, sync)
         kern = {}
-        for name in (("ntt_mfma_pass1", "ntt_mfma_pass2") if algo == "mfma" else ("ntt_bf_cols", "ntt_bf_rows")):
+        names = {"mfma": ("ntt_mfma_pass1", "ntt_mfma_pass2"), "co": ("ntt_co_pass1", "ntt_co_pass2"),
+                 "butterfly": ("ntt_bf_cols", "ntt_bf_rows")}[algo]
+        for name in names:
             cnt, ms = tfhe.tfhe_timing_read(name)
             kern[name] = {"launches": cnt, "avg_ms": ms / max(cnt, 1)}
         tfhe.tfhe_timing_enable(False)
@@ -301,7 +305,7 @@ def main():
         cpu = cpu_baseline(qs, plan.psi)
         log("cpu", json.dumps(cpu))
 
-    head = results.get("mfma") or results.get("butterfly")
+    head = results.get("mfma") or results.get("butterfly") or results.get("co")
     if head is None:  # --only hmult (profiling runs)
         print(json.dumps({"hmult": hmult}), flush=True)
         return
@@ -334,6 +338,8 @@ def main():
     if "butterfly" in results and "mfma" in results:
         line["butterfly_kops"] = round(results["butterfly"]["kops"], 1)
         line["mfma_over_butterfly"] = round(results["mfma"]["kops"] / results["butterfly"]["kops"], 3)
+    if "co" in results:
+        line["valu_gemm_kops"] = round(results["co"]["kops"], 1)
     line["kernels"] = {k: v for r in results.values() for k, v in r["kernels"].items()}
     if hmult:
         line["hmult_ops_per_s"] = round(hmult["ops_per_s"], 1)

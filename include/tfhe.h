@@ -50,9 +50,15 @@ typedef enum {
   TFHE_NTT_BUTTERFLY = 1,     /* radix-2 Cooley-Tukey / Gentleman-Sande
                                  butterflies on the vector ALUs (Sec. II-A,
                                  Fig. 2) */
-  TFHE_NTT_FOURSTEP_MFMA = 2  /* four-step NTT whose DFT stages are exact
+  TFHE_NTT_FOURSTEP_MFMA = 2, /* four-step NTT whose DFT stages are exact
                                  INT8 matrix-core contractions over byte
                                  slices (Sec. III-C, Eq. 8, Eq. 9) */
+  TFHE_NTT_FOURSTEP_VALU = 3  /* the same four-step passes with each 16 x 16
+                                 matrix product on the vector ALUs, 64-bit
+                                 accumulation and one reduction per output
+                                 (Sec. III-B, Eq. 6, Eq. 7); N = 2^16 only,
+                                 tfhe_ntt_fwd / tfhe_ntt_inv only; never
+                                 chosen by AUTO */
 } tfhe_ntt_algo;
 
 typedef struct tfhe_ntt_plan_s* tfhe_ntt_plan;
@@ -274,7 +280,8 @@ tfhe_status tfhe_timing_enable(int enable);
 
 /* Launch count and summed event-measured duration (ms) of the kernel named
  * `kernel` since timing was enabled; waits for the recorded events.  Names:
- * ntt_mfma_pass1, ntt_mfma_pass2, ntt_bf_single, ntt_bf_cols, ntt_bf_rows,
+ * ntt_mfma_pass1, ntt_mfma_pass2, ntt_co_pass1, ntt_co_pass2, ntt_bf_single,
+ * ntt_bf_cols, ntt_bf_rows,
  * elementwise, ckks_tensor, ckks_modup, ckks_inner, ckks_moddown_conv,
  * ckks_moddown_final, frobenius, ckks_rescale_bcast, ckks_rescale_final.
  * Unknown name: TFHE_EINVAL. */

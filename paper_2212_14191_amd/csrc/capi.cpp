@@ -208,8 +208,10 @@ tfhe_status tfhe_ntt_workspace_size(tfhe_ntt_plan plan, tfhe_ntt_algo algo, uint
   tfhe_ntt_algo a = resolve(plan, algo);
   if (a == TFHE_NTT_FOURSTEP_MFMA && !plan->has_mfma)
     return fail(TFHE_EUNSUPPORTED, "MFMA four-step not available for this plan");
-  *bytes = a == TFHE_NTT_FOURSTEP_MFMA ? fs_workspace_bytes(plan, limb_count, batch)
-                                       : bf_workspace_bytes(plan, limb_count, batch);
+  if (a == TFHE_NTT_FOURSTEP_VALU && !plan->has_co)
+    return fail(TFHE_EUNSUPPORTED, "vector-ALU four-step is available for N = 2^16 only");
+  *bytes = a == TFHE_NTT_BUTTERFLY ? bf_workspace_bytes(plan, limb_count, batch)
+                                   : fs_workspace_bytes(plan, limb_count, batch);
   return TFHE_OK;
 }
 
@@ -222,19 +224,23 @@ static tfhe_status ntt_dispatch(bool inverse, tfhe_ntt_plan plan, tfhe_ntt_algo 
   if (limb_count == 0 || batch == 0) return TFHE_OK;
   if ((st = check_ptr(in, "in")) != TFHE_OK || (st = check_ptr(out, "out")) != TFHE_OK) return st;
   const tfhe_ntt_algo a = resolve(plan, algo);
-  if (a != TFHE_NTT_BUTTERFLY && a != TFHE_NTT_FOURSTEP_MFMA)
+  if (a != TFHE_NTT_BUTTERFLY && a != TFHE_NTT_FOURSTEP_MFMA && a != TFHE_NTT_FOURSTEP_VALU)
     return fail(TFHE_EINVAL, "unknown algorithm");
   if (a == TFHE_NTT_FOURSTEP_MFMA && !plan->has_mfma)
     return fail(TFHE_EUNSUPPORTED, "MFMA four-step not available for this plan");
-  const size_t need = a == TFHE_NTT_FOURSTEP_MFMA ? fs_workspace_bytes(plan, limb_count, batch)
-                                                  : bf_workspace_bytes(plan, limb_count, batch);
+  if (a == TFHE_NTT_FOURSTEP_VALU && !plan->has_co)
+    return fail(TFHE_EUNSUPPORTED, "vector-ALU four-step is available for N = 2^16 only");
+  const size_t need = a == TFHE_NTT_BUTTERFLY ? bf_workspace_bytes(plan, limb_count, batch)
+                                              : fs_workspace_bytes(plan, limb_count, batch);
   if (need) {
     if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "workspace missing or too small");
     if (!aligned(ws, 256)) return fail(TFHE_EINVAL, "workspace not 256-byte aligned");
   }
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
-  if (a == TFHE_NTT_FOURSTEP_MFMA)
+  if (a == TFHE_NTT_FOURSTEP_VALU)
+    e = co_transform(plan, inverse, in, out, ws, limb_begin, limb_count, batch, s);
+  else if (a == TFHE_NTT_FOURSTEP_MFMA)
     e = inverse ? fs_inverse(plan, in, out, ws, limb_begin, limb_count, batch, s)
                 : fs_forward(plan, in, out, ws, limb_begin, limb_count, batch, s);
   else

@@ -33,11 +33,21 @@ struct PassTables {
   uint2 lb[16];
 };
 
+// Plain matrices of one 256-point pass (16 x 16 split) for the vector-ALU
+// GEMM variant, as Shoup pairs {w, companion}: level A WA[u][s], twist
+// T[s][v], level B WB[t][v].
+struct CoPass {
+  uint2 WA[16][16], T[16][16], WB[16][16];
+};
+
 // Device-side description of one limb for the four-step kernels.
 struct FourStepLimb {
   const PassTables* pass1;  // first pass (its post-twist: post1)
   const PassTables* pass2;  // second pass
   const uint2* post1;       // [256 column bases][64 lanes][4]: post-twist of pass 1
+  const CoPass* co1;        // vector-ALU variant (N = 2^16 only): pass matrices
+  const CoPass* co2;
+  const uint2* co_post;     // [256 columns][256 outputs]: post-twist of pass 1
   uint32_t q, qneg;         // modulus and -q^{-1} mod 2^32
 };
 
@@ -45,6 +55,7 @@ struct tfhe_plan_impl {
   uint32_t log_n = 0, n = 0, n_limbs = 0;
   tfhe_ntt_algo algo = TFHE_NTT_BUTTERFLY;  // what AUTO resolves to
   bool has_mfma = false;
+  bool has_co = false;            // vector-ALU four-step variant (N = 2^16)
   int device = 0;
   uint32_t num_cus = 256;         // compute units of the device
   uint32_t fs_wg_per_cu = 0;      // persistent four-step workgroups per CU (0: occupancy)
@@ -98,6 +109,10 @@ hipError_t fs_forward(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* ou
                       uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s);
 hipError_t fs_inverse(const tfhe_ntt_plan_s* p, const uint32_t* in, uint32_t* out, void* ws,
                       uint32_t limb_begin, uint32_t limb_count, uint32_t batch, hipStream_t s);
+// Vector-ALU GEMM variant of the same passes (plan->has_co); same workspace.
+hipError_t co_transform(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* in, uint32_t* out,
+                        void* ws, uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                        hipStream_t s);
 
 // ---- element-wise launchers (elementwise.hip)
 enum EwOp { EW_MUL = 0, EW_ADD = 1, EW_SUB = 2, EW_MUL_BCAST = 3 };
@@ -109,7 +124,7 @@ hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, 
 // ---- per-kernel event timing (timing.cpp)
 enum KernelId {
   K_FS_PASS1 = 0, K_FS_PASS2, K_BF_SINGLE, K_BF_COLS, K_BF_ROWS, K_EW, K_TENSOR, K_MODUP,
-  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL
+  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL, K_CO_PASS1, K_CO_PASS2
 };
 bool timing_on();
 void* timing_begin(int id, hipStream_t s);

@@ -501,6 +501,152 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Vector-ALU GEMM variant ("CO", Sec. III-B: the NTT as matrix products on
+// the general-purpose cores, one modular reduction per output), N = 2^16.
+// Same passes, tables, work items and data movement as the matrix-core
+// kernel (narrow items); each 16-point level is a 16 x 16 matrix product in
+// which a thread forms one output from 16 lazy Shoup products (each in
+// [0, 2q)) summed in 64 bits and reduced once ("reduce every 16").
+//   level A: thread (v, col) computes Y[s][v] = T[s][v] sum_u WA[u][s] x[16u+v]
+//   level B: thread (s, col) computes out[s+16t] = sum_v WB[t][v] Y[s][v]
+// Level-A results go through LDS at (col 16 + s) 17 + v, conflict-free for
+// both access patterns.
+__device__ __forceinline__ uint32_t reduce36(uint64_t acc, uint32_t q, uint2 one, uint2 two32) {
+  // acc < 32 q: lo mod q (Shoup by 1) plus hi 2^32 mod q (Shoup by 2^32 mod q)
+  const uint32_t lo = reduce_once(mul_shoup_lazy((uint32_t)acc, one.x, one.y, q), q);
+  const uint32_t hi = mul_shoup((uint32_t)(acc >> 32), two32.x, two32.y, q);
+  return add_mod(lo, hi, q);
+}
+
+template <bool kFirst>
+__global__ void __launch_bounds__(256)
+co_pass(const FsTable tab) {
+  using G = Geo<kFirst, 16, false>;
+  constexpr int kCoStages = 2;  // one item ahead: leaves LDS for three workgroups per CU
+  __shared__ __attribute__((aligned(16))) uint32_t ring[kCoStages * G::tile];
+  __shared__ uint32_t ybuf[16 * 16 * 17];
+  __shared__ uint2 mats[512];  // WA[u][s] then WB[t][v] of the current limb (broadcast reads)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lo16 = tid & 15, col = tid >> 4;  // level A: v = lo16; level B: s = lo16
+  const Walk walk = make_walk(tab.total, tab.ipp_log);
+  if (walk.p >= walk.p_end) return;
+  const uint32_t S = tab.cols, c0 = walk.blk * G::W;
+
+  uint32_t ld_off[4], st_off[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t row = 16 * (4 * wave + j) + lane % 16, c4 = 4 * (lane / 16);
+    const uint32_t natural = row * S + c0 + c4;
+    const uint32_t tiled = ((c0 + c4) >> 4) * (16 * G::P) + 16 * row + (c4 & 15);
+    ld_off[j] = kFirst ? natural : tiled;
+    st_off[j] = natural;
+  }
+  uint32_t kf = 0, kc = 0;
+  auto issue = [&](uint32_t p, int stage) {
+    const Item it = locate(tab, p, kf);
+    issue_tile<G::pitch>(tab.u[it.unit].in + it.poly_base, ld_off, ring + stage * G::tile, wave);
+  };
+  issue(walk.p, 0);
+
+  const FourStepLimb* cur_limb = nullptr;
+  const CoPass* M = nullptr;
+  uint32_t q = 0;
+  uint2 one = make_uint2(0, 0), two32 = one;
+  uint2 tv[16], post[16];  // T[s][v] of this thread's v; post-twist of (col, s + 16 t)
+  int st = 0;
+  uint32_t n = 0;
+  for (uint32_t p = walk.p; p < walk.p_end; p += walk.step, ++n, st ^= 1) {
+    const Item it = locate(tab, p, kc);
+    const FourStepLimb* limb = tab.u[it.unit].limbs + it.limb;
+    if (limb != cur_limb) {
+      const FourStepLimb L = *limb;
+      M = kFirst ? L.co1 : L.co2;
+      q = L.q;
+      lds_barrier();  // every wave is done with the previous limb's matrices
+      mats[tid] = M->WA[tid >> 4][tid & 15];
+      mats[256 + tid] = M->WB[tid >> 4][tid & 15];
+      one = make_uint2(1, shoup_companion(1, q));
+      const uint32_t r32 = (uint32_t)((1ull << 32) % q);
+      two32 = make_uint2(r32, shoup_companion(r32, q));
+#pragma unroll
+      for (int s2 = 0; s2 < 16; ++s2) tv[s2] = M->T[s2][lo16];
+      if (kFirst) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) post[t] = L.co_post[(c0 + col) * 256 + lo16 + 16 * t];
+      }
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      cur_limb = limb;
+    }
+    // this item's loads were followed only by the previous item's stores
+    if (n == 0) wait_vmcnt<0>();
+    else if (kFirst) wait_vmcnt<16>();
+    else wait_vmcnt<4>();
+    lds_barrier();  // also publishes a new limb's matrices; the other stage is free
+    if (p + walk.step < walk.p_end) issue(p + walk.step, st ^ 1);
+    uint32_t* const tile = ring + st * G::tile;
+    // level A
+    uint32_t x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = tile[u * G::pitch + ((col >> 2) * 16 + lo16) * 4 + (col & 3)];
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2) {
+      uint64_t acc = 0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const uint2 w = mats[u * 16 + s2];
+        acc += mul_shoup_lazy(x[u], w.x, w.y, q);
+      }
+      ybuf[(col * 16 + s2) * 17 + lo16] = mul_shoup(reduce36(acc, q, one, two32), tv[s2].x, tv[s2].y, q);
+    }
+    lds_barrier();
+    // level B
+    uint32_t y[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) y[v] = ybuf[(col * 16 + lo16) * 17 + v];
+    uint32_t* const out = tab.u[it.unit].out + it.poly_base;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      uint64_t acc = 0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const uint2 w = mats[256 + t * 16 + v];
+        acc += mul_shoup_lazy(y[v], w.x, w.y, q);
+      }
+      const uint32_t r = reduce36(acc, q, one, two32);
+      if (kFirst) {
+        // post-twist, tiled store: block t, column c0 + col, word s
+        out[t * 16 * S + (c0 + col) * 16 + lo16] = mul_shoup(r, post[t].x, post[t].y, q);
+      } else {
+        // into the consumed stage: row s + 16 t, column col, slab layout
+        tile[t * G::pitch + ((col >> 2) * 16 + lo16) * 4 + (col & 3)] = r;
+      }
+    }
+    if (!kFirst) {
+      lds_barrier();
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        __builtin_nontemporal_store(*(const v4u*)(tile + (4 * wave + j) * G::pitch + lane * 4), (v4u*)(out + st_off[j]));
+    }
+  }
+}
+
+template <bool kFirst>
+void co_launch(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
+  t.ipp_log = t.log_n - 12;
+  static int occ = 0;
+  if (occ == 0) {
+    int k = 0;
+    occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, co_pass<kFirst>, 256, 0) == hipSuccess && k > 0 ? k : 1;
+  }
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : (uint32_t)occ;
+  const uint32_t items = t.total << t.ipp_log;
+  const uint32_t grid = std::min(std::max(16u, (p->num_cus * w) / 16 * 16), (items + 15) / 16 * 16);
+  TFHE_TIMED(kFirst ? K_CO_PASS1 : K_CO_PASS2, s,
+             hipLaunchKernelGGL((co_pass<kFirst>), dim3(grid), dim3(256), 0, s, t));
+}
+
 }  // namespace
 
 bool fs_supported(uint32_t log_n) { return log_n >= 12 && log_n <= 16; }
@@ -566,6 +712,23 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     }
     flush();
   }
+  return hipGetLastError();
+}
+
+hipError_t co_transform(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* in, uint32_t* out,
+                        void* ws, uint32_t limb_begin, uint32_t limb_count, uint32_t batch,
+                        hipStream_t s) {
+  if (!p->has_co) return hipErrorInvalidValue;
+  const FourStepLimb* tabs = (inverse ? p->d_fs_inv : p->d_fs_fwd) + limb_begin;
+  FsTable t1, t2;
+  t1.count = t2.count = 1;
+  t1.total = t2.total = limb_count * batch;
+  t1.log_n = t2.log_n = p->log_n;
+  t1.cols = t2.cols = 256;  // N = 2^16: both passes are 256 x 256
+  t1.u[0] = FsUnit{in, (uint32_t*)ws, tabs, batch, 0};
+  t2.u[0] = FsUnit{(const uint32_t*)ws, out, tabs, batch, 0};
+  co_launch<true>(p, t1, s);
+  co_launch<false>(p, t2, s);
   return hipGetLastError();
 }
 

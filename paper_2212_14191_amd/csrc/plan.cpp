@@ -172,7 +172,18 @@ static void build_post(uint2* post, int r, int ncols, uint32_t q, uint32_t scale
 struct FsHostLimb {
   PassTables p1, p2;
   std::vector<uint2> post;
+  CoPass c1, c2;               // N = 2^16: plain matrices for the vector-ALU variant
+  std::vector<uint2> co_post;  // [column][output]
 };
+
+static void co_pass(CoPass& c, const Mat16& WA, const Mat16& T, const Mat16& WB, uint32_t q) {
+  for (int a = 0; a < 16; ++a)
+    for (int b = 0; b < 16; ++b) {
+      c.WA[a][b] = make_uint2(WA[a][b], shoup_companion(WA[a][b], q));
+      c.T[a][b] = make_uint2(T[a][b], shoup_companion(T[a][b], q));
+      c.WB[a][b] = make_uint2(WB[a][b], shoup_companion(WB[a][b], q));
+    }
+}
 
 // Four-step tables for N = N1 x 256 (N1 = 16 r), n = 256 n1 + n2,
 // k = k1 + N1 k2:
@@ -201,6 +212,16 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint3
         WB[a][b] = pow_mod(root, 16ull * a * b, q);
       }
     build_pass(pt, 16, WA, T, WB, q, scale, nullptr);
+    if (r == 16) co_pass(&pt == &L.p1 ? L.c1 : L.c2, WA, T, WB, q);
+  };
+  // natural-order post-twist table of the vector-ALU variant
+  auto co_post = [&](auto P) {
+    L.co_post.resize(256 * 256);
+    for (int col = 0; col < 256; ++col)
+      for (int k = 0; k < 256; ++k) {
+        const uint32_t w = P(col, k);
+        L.co_post[col * 256 + k] = make_uint2(w, shoup_companion(w, q));
+      }
   };
   L.post.resize(256 * 64 * 4);
   if (dir == 0) {
@@ -213,11 +234,12 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint3
     const uint32_t rho = pow_mod(phi, 32, q);
     for (int i = 0; i < 16; ++i) lb[i] = i < 8 ? pow_mod(rho, i, q) : 1;
     build_pass(L.p1, r, WA, T, WB, q, 1, lb);
+    if (r == 16) co_pass(L.c1, WA, T, WB, q);
     cyc256(L.p2, om, r32);
     // column n2, output k1: psi^{(2 k1 + 1) n2}
-    build_post(L.post.data(), r, 256, q, r == 16 ? r32 : 1, [&](int n2, int k1) {
-      return pow_mod(psi, (uint64_t)(2 * k1 + 1) * n2 % twoN, q);
-    });
+    auto P = [&](int n2, int k1) { return pow_mod(psi, (uint64_t)(2 * k1 + 1) * n2 % twoN, q); };
+    build_post(L.post.data(), r, 256, q, r == 16 ? r32 : 1, P);
+    if (r == 16) co_post(P);
   } else {
     cyc256(L.p1, omi, 1);
     if (r == 16) {
@@ -228,6 +250,7 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint3
           WB[a][b] = mulm(pow_mod(phii, (uint64_t)(32 * b + 16) * a, q), ninv, q);  // [t][v]
         }
       build_pass(L.p2, 16, WA, T, WB, q, r32, nullptr);
+      co_pass(L.c2, WA, T, WB, q);
     } else {
       for (int a = 0; a < 16; ++a)
         for (int b = 0; b < 16; ++b) {
@@ -240,9 +263,9 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint3
       build_pass(L.p2, r, WA, T, WB, q, 1, lb);
     }
     // column k1, output n2: psi^{-(2 k1 + 1) n2}
-    build_post(L.post.data(), 16, (int)N1, q, r32, [&](int k1, int n2) {
-      return pow_mod(psii, (uint64_t)(2 * k1 + 1) * n2 % twoN, q);
-    });
+    auto P = [&](int k1, int n2) { return pow_mod(psii, (uint64_t)(2 * k1 + 1) * n2 % twoN, q); };
+    build_post(L.post.data(), 16, (int)N1, q, r32, P);
+    if (r == 16) co_post(P);
   }
 }
 
@@ -285,10 +308,14 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
   p->has_mfma = fs_supported(p->log_n);
   for (uint32_t l = 0; l < L && p->has_mfma; ++l)
     if (p->q[l] < (1u << 29)) p->has_mfma = false;  // digit bounds need q > 2^29
+  p->has_co = p->has_mfma && p->log_n == 16;
   if (p->has_mfma) {
-    // blob: per limb and direction {PassTables p1, p2, post[256*64*4]}
+    // blob: per limb and direction {PassTables p1, p2, post[256*64*4]} and,
+    // for N = 2^16, {CoPass c1, c2, co_post[256*256]}
     const size_t post_elems = 256 * 64 * 4;
-    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint2);
+    const bool co = p->log_n == 16;
+    const size_t co_bytes = co ? 2 * sizeof(CoPass) + 256 * 256 * sizeof(uint2) : 0;
+    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint2) + co_bytes;
     const size_t total = per * 2 * L;
     std::vector<unsigned char> blob(total);
     std::vector<FourStepLimb> hf(L), hi(L);
@@ -308,6 +335,17 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
         f.pass1 = (const PassTables*)(dbase + off);
         f.pass2 = (const PassTables*)(dbase + off + sizeof(PassTables));
         f.post1 = (const uint2*)(dbase + off + 2 * sizeof(PassTables));
+        f.co1 = f.co2 = nullptr;
+        f.co_post = nullptr;
+        if (co) {
+          const size_t o2 = off + 2 * sizeof(PassTables) + post_elems * sizeof(uint2);
+          memcpy(&blob[o2], &H.c1, sizeof(CoPass));
+          memcpy(&blob[o2 + sizeof(CoPass)], &H.c2, sizeof(CoPass));
+          memcpy(&blob[o2 + 2 * sizeof(CoPass)], H.co_post.data(), 256 * 256 * sizeof(uint2));
+          f.co1 = (const CoPass*)(dbase + o2);
+          f.co2 = (const CoPass*)(dbase + o2 + sizeof(CoPass));
+          f.co_post = (const uint2*)(dbase + o2 + 2 * sizeof(CoPass));
+        }
         f.q = p->q[l];
         f.qneg = mods[l].qneg;
       }

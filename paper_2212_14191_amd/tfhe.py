@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtfhe.so")
 
 TFHE_OK, TFHE_EINVAL, TFHE_ENOTNTT, TFHE_ENOMEM, TFHE_EHIP, TFHE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-AUTO, BUTTERFLY, FOURSTEP_MFMA = 0, 1, 2
-ALGOS = {"auto": AUTO, "butterfly": BUTTERFLY, "mfma": FOURSTEP_MFMA}
+AUTO, BUTTERFLY, FOURSTEP_MFMA, FOURSTEP_VALU = 0, 1, 2, 3
+ALGOS = {"auto": AUTO, "butterfly": BUTTERFLY, "mfma": FOURSTEP_MFMA, "co": FOURSTEP_VALU}
 
 _lib = None
 

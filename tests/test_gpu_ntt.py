@@ -247,3 +247,26 @@ def test_fused_batch_mixed_sizes_and_directions(tf):
     X = items[first16][1].clone()
     tf.ntt_batch([(plans[16], X, X, False, 1)], algo="mfma")   # in place
     assert np.array_equal(to_host(X), refs[first16])
+
+
+def test_valu_gemm_variant_matches_oracle(tf):
+    """The vector-ALU GEMM four-step variant (N = 2^16): forward and inverse
+    equal the oracle; on a ragged 4 x 21 batch it equals the MFMA transform
+    and round-trips; other N and the fused-batch API refuse it."""
+    n = 1 << 16
+    qs = PRIMES31[:4]
+    plan = tf.NttPlan(16, qs)
+    x = inputs.uniform_residues(321, qs[:2], (2, n))
+    ref = oracle.ntt_fwd(x, qs[:2], plan.psi[:2])
+    X = plan.fwd(to_dev(x), algo="co")
+    assert np.array_equal(to_host(X), ref)
+    assert np.array_equal(to_host(plan.inv(to_dev(ref), algo="co")), x)
+    y = to_dev(inputs.uniform_residues(322, qs, (21, n)))
+    f_co = plan.fwd(y, algo="co")
+    assert torch.equal(f_co, plan.fwd(y, algo="mfma"))
+    assert torch.equal(plan.inv(f_co, algo="co"), y)
+    small = tf.NttPlan(15, qs[:1])
+    with pytest.raises(tf.TfheError):
+        small.fwd(to_dev(inputs.uniform_residues(1, qs[:1], (1, 1 << 15))), algo="co")
+    with pytest.raises(tf.TfheError):
+        tf.ntt_batch([(plan, y, torch.empty_like(y), False, 0)], algo="co")
