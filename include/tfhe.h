@@ -52,11 +52,11 @@ typedef enum {
                                  Fig. 2) */
   TFHE_NTT_FOURSTEP_MFMA = 2, /* four-step NTT whose DFT stages are exact
                                  INT8 matrix-core contractions over byte
-                                 slices (Sec. III-C, Eq. 8, Eq. 9) */
+                                 slices (Sec. III-C, Eq. 9, Eq. 10) */
   TFHE_NTT_FOURSTEP_VALU = 3  /* the same four-step passes with each 16 x 16
                                  matrix product on the vector ALUs, 64-bit
                                  accumulation and one reduction per output
-                                 (Sec. III-B, Eq. 6, Eq. 7); N = 2^16 only,
+                                 (Sec. III-B, Eq. 7 to Eq. 9); N = 2^16 only,
                                  tfhe_ntt_fwd / tfhe_ntt_inv only; never
                                  chosen by AUTO */
 } tfhe_ntt_algo;

@@ -1,4 +1,4 @@
-// Four-step NTT on INT8 matrix cores (Sec. III-B/III-C, Eq. 8 and Eq. 9),
+// Four-step NTT on INT8 matrix cores (Sec. III-B/III-C, Eq. 9 and Eq. 10),
 // re-designed for gfx950, for N = N1 x 256 with N1 = 16 r, r in {1,..,16}.
 //
 // With n = 256 n1 + n2 and k = k1 + N1 k2 (phi = psi^256 of order 2 N1,
