@@ -176,6 +176,18 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
                        : launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
                                              c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
+  if (p->algo == TFHE_NTT_FOURSTEP_MFMA) {
+    // the transform's second pass finishes ModDown in its store epilogue:
+    // out (+)= (acc - NTT(conv)) P^{-1}
+    NttUnit u0{p, false, conv, out0, 0, level, batch};
+    NttUnit u1{p, false, conv1, out1, 0, level, batch};
+    u0.acc = a0;
+    u1.acc = a1;
+    u0.epi_mult = u1.epi_mult = c->d_dn_pinv;
+    u0.epi_add = acc0_add;
+    u1.epi_add = acc1_add;
+    return ntt_units(p, {u0, u1}, nws, s);
+  }
   if ((e = ntt_units(p, {NttUnit{p, false, conv, conv, 0, level, batch},
                          NttUnit{p, false, conv1, conv1, 0, level, batch}},
                      nws, s)) != hipSuccess)
@@ -229,6 +241,15 @@ static hipError_t rescale(const tfhe_ckks_ctx_s* c, const uint32_t* ct, uint32_t
     return e;
   // reduce into every remaining limb, back to the NTT domain
   if ((e = launch_rescale_bcast(t, u, p->d_mod, top, batch, c->n, s)) != hipSuccess) return e;
+  if (p->algo == TFHE_NTT_FOURSTEP_MFMA) {
+    // NTT of the broadcast, finished in the store epilogue: (c_i - u_i) q_top^{-1}
+    NttUnit u0{p, false, u, out, 0, top, batch};
+    NttUnit u1{p, false, u + (uint64_t)top * plane, out + (uint64_t)top * plane, 0, top, batch};
+    u0.acc = ct;
+    u1.acc = ct + (uint64_t)level * plane;
+    u0.epi_mult = u1.epi_mult = c->d_rs_qinv + (size_t)top * c->L;
+    return ntt_units(p, {u0, u1}, nws, s);
+  }
   if ((e = ntt_units(p, {NttUnit{p, false, u, u, 0, top, batch},
                          NttUnit{p, false, u + (uint64_t)top * plane, u + (uint64_t)top * plane, 0, top, batch}},
                      nws, s)) != hipSuccess)

@@ -88,6 +88,12 @@ struct NttUnit {
   const uint32_t* in;
   uint32_t* out;
   uint32_t limb_begin, limb_count, batch;
+  // Forward four-step transforms only: instead of the transform y, write
+  // out = (acc - y) mult_l (epi_add: out += ...), mult_l the Shoup pair of
+  // limb limb_begin + l; acc has the layout of out.
+  const uint32_t* acc = nullptr;
+  const uint2* epi_mult = nullptr;
+  bool epi_add = false;
 };
 // Runs every unit with the four-step algorithm (all units need has_mfma) or
 // the butterfly; ws must hold the sum of the units' workspaces.

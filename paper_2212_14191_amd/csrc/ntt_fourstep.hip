@@ -88,6 +88,11 @@ struct FsUnit {
   const FourStepLimb* limbs;  // tables of the unit's first limb
   uint32_t batch;
   uint32_t item_begin;
+  // second-pass epilogue (forward transforms): out = (acc - y) m_l, or
+  // out += (acc - y) m_l, with m_l the Shoup pair of the unit's limb l
+  const uint32_t* acc;
+  const uint2* mult;
+  uint32_t accumulate;
 };
 struct FsTable {
   uint32_t count, total;  // units, polynomials
@@ -266,9 +271,19 @@ __device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
   else wait_vmcnt<4 + 2 * st>();
 }
 
-template <bool kFirst, int kR, bool kWide>
-__global__ void __launch_bounds__(kWide ? 512 : 256, kWide ? 2 : 3)
+// Like wait_item, for the second pass with the epilogue: each item also
+// issues its 8 epilogue loads (before the ring loads of item n + 2).
+__device__ __forceinline__ void wait_item_epi(uint32_t n, bool has_next) {
+  if (!has_next) wait_vmcnt<0>();
+  else if (n == 0) wait_vmcnt<4>();
+  else if (n == 1) wait_vmcnt<4 + 4 + 8>();
+  else wait_vmcnt<4 + 2 * 4 + 8>();
+}
+
+template <bool kFirst, int kR, bool kWide, bool kEpi = false>
+__global__ void __launch_bounds__(kWide ? 512 : 256, (kWide || kEpi) ? 2 : 3)
 fs_pass(const FsTable tab) {
+  static_assert(!kEpi || (!kFirst && kR == 16), "the epilogue belongs to the forward second pass");
   using G = Geo<kFirst, kR, kWide>;
   __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -353,12 +368,20 @@ fs_pass(const FsTable tab) {
       cur_limb = limb;
     }
     const bool has_next = p + walk.step < walk.p_end;
-    wait_item<kFirst>(n, has_next);
+    if (kEpi) wait_item_epi(n, has_next);
+    else wait_item<kFirst>(n, has_next);
     lds_barrier();  // the item's tile is complete; the oldest stage is free
-    {
-      const uint32_t pn = p + (kStages - 1) * walk.step;
-      if (pn < walk.p_end) issue(pn, (st + kStages - 1) % kStages);
+    uint4 e_acc[4], e_out[4];  // epilogue operands at the item's store positions
+    if (kEpi) {
+      const FsUnit& U = tab.u[it.unit];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        e_acc[j] = *(const uint4*)(U.acc + it.poly_base + st_off[j]);
+        e_out[j] = *(const uint4*)(U.out + it.poly_base + st_off[j]);
+      }
     }
+    const bool issued = p + (kStages - 1) * walk.step < walk.p_end;
+    if (issued) issue(p + (kStages - 1) * walk.step, (st + kStages - 1) % kStages);
 
     // lane (i, g) of wave w reads row kR (4g + c) + i % kR of the quad
     // w Mt + i / kR (four vectors, one per set): for 16 lanes either 256
@@ -443,20 +466,45 @@ fs_pass(const FsTable tab) {
         *(uint4*)(tile + (row / G::Rs) * G::pitch + ((wave * G::Mt + m) * G::Rs + row % G::Rs) * 4) = res[j];
       }
       lds_barrier();
+      if (kEpi) {
+        // only the ring loads of item n + 2 were issued after the epilogue loads
+        if (issued) wait_vmcnt<4>();
+        else wait_vmcnt<0>();
+        const FsUnit& U = tab.u[it.unit];
+        const uint2 m = U.mult[it.limb];
+        const bool add = U.accumulate != 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        __builtin_nontemporal_store(*(const v4u*)(tile + (4 * wave + j) * G::pitch + lane * 4), (v4u*)(out + st_off[j]));
+        for (int j = 0; j < 4; ++j) {
+          const uint4 y = *(const uint4*)(tile + (4 * wave + j) * G::pitch + lane * 4);
+          uint4 r;
+          r.x = mul_shoup(sub_mod(e_acc[j].x, y.x, q), m.x, m.y, q);
+          r.y = mul_shoup(sub_mod(e_acc[j].y, y.y, q), m.x, m.y, q);
+          r.z = mul_shoup(sub_mod(e_acc[j].z, y.z, q), m.x, m.y, q);
+          r.w = mul_shoup(sub_mod(e_acc[j].w, y.w, q), m.x, m.y, q);
+          if (add) {
+            r.x = add_mod(r.x, e_out[j].x, q);
+            r.y = add_mod(r.y, e_out[j].y, q);
+            r.z = add_mod(r.z, e_out[j].z, q);
+            r.w = add_mod(r.w, e_out[j].w, q);
+          }
+          __builtin_nontemporal_store(*(const v4u*)&r, (v4u*)(out + st_off[j]));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          __builtin_nontemporal_store(*(const v4u*)(tile + (4 * wave + j) * G::pitch + lane * 4), (v4u*)(out + st_off[j]));
+      }
     }
   }
 }
 
 // Resident workgroups per CU of a pass kernel (queried once per process).
-template <bool kFirst, int kR, bool kWide>
+template <bool kFirst, int kR, bool kWide, bool kEpi>
 uint32_t occupancy() {
   static int occ = 0;
   if (occ == 0) {
     int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<kFirst, kR, kWide>,
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<kFirst, kR, kWide, kEpi>,
                                                                 Geo<kFirst, kR, kWide>::threads, 0);
     occ = (e == hipSuccess && n > 0) ? n : 1;
   }
@@ -464,28 +512,32 @@ uint32_t occupancy() {
 }
 
 // Persistent grid: a multiple of 16 workgroups, no more than the items need.
-template <bool kFirst, int kR, bool kWide>
+template <bool kFirst, int kR, bool kWide, bool kEpi>
 uint32_t grid_size(const tfhe_ntt_plan_s* p, uint32_t items) {
   // default: the resident count; twice that for the wide kernels (one
   // resident workgroup per CU), whose tail balances better with the second
   // half of the grid scheduled as the first half drains (measured)
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide>() * (kWide ? 2 : 1);
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide, kEpi>() * (kWide ? 2 : 1);
   const uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
   return std::min(g, (items + 15) / 16 * 16);
 }
 
-template <bool kFirst, int kR, bool kWide>
+template <bool kFirst, int kR, bool kWide, bool kEpi = false>
 void launch_pass(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
   using G = Geo<kFirst, kR, kWide>;
   t.ipp_log = t.log_n - (kWide ? 13 : 12);  // items per polynomial: N / item words
-  const uint32_t grid = grid_size<kFirst, kR, kWide>(p, t.total << t.ipp_log);
+  const uint32_t grid = grid_size<kFirst, kR, kWide, kEpi>(p, t.total << t.ipp_log);
   TFHE_TIMED(kFirst ? K_FS_PASS1 : K_FS_PASS2, s,
-             hipLaunchKernelGGL((fs_pass<kFirst, kR, kWide>), dim3(grid), dim3(G::threads), 0, s, t));
+             hipLaunchKernelGGL((fs_pass<kFirst, kR, kWide, kEpi>), dim3(grid), dim3(G::threads), 0, s, t));
 }
 
 // The 256-point stage uses wide items by default when the pass has >= 128
 // columns (N >= 2^15); below that the narrow items leave more work items per
 // polynomial, which measured faster.  The plan's fs_wide overrides this.
+static bool use_wide(const tfhe_ntt_plan_s* p, uint32_t cols) {
+  return p->fs_wide == 1 ? false : cols >= (p->fs_wide == 2 ? 32u : 128u);
+}
+
 template <bool kFirst>
 void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipStream_t s) {
   switch (r) {
@@ -494,7 +546,7 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
     case 4: launch_pass<kFirst, 4, false>(p, t, s); break;
     case 8: launch_pass<kFirst, 8, false>(p, t, s); break;
     default:
-      if (p->fs_wide == 1 ? false : t.cols >= (p->fs_wide == 2 ? 32u : 128u))
+      if (use_wide(p, t.cols))
         launch_pass<kFirst, 16, true>(p, t, s);
       else launch_pass<kFirst, 16, false>(p, t, s);
       break;
@@ -679,6 +731,8 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     if (done[lead]) continue;
     const uint32_t log_n = units[lead].plan->log_n;
     const bool inverse = units[lead].inverse;
+    const bool epi = units[lead].acc != nullptr;
+    if (epi && inverse) return hipErrorInvalidValue;
     const tfhe_ntt_plan_s* p0 = units[lead].plan;
     const uint32_t N = 1u << log_n, N1 = N >> 8, r = N1 / 16;
     FsTable t1, t2;
@@ -689,13 +743,15 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     auto flush = [&]() {
       if (t1.total == 0) return;
       launch_pass_r<true>(p0, r1, t1, s);
-      launch_pass_r<false>(p0, r2, t2, s);
+      if (!epi) launch_pass_r<false>(p0, r2, t2, s);
+      else if (use_wide(p0, t2.cols)) launch_pass<false, 16, true, true>(p0, t2, s);
+      else launch_pass<false, 16, false, true>(p0, t2, s);
     };
     t1.count = t2.count = 0;
     t1.total = t2.total = 0;
     for (uint32_t k = lead; k < count; ++k) {
       const NttUnit& u = units[k];
-      if (done[k] || u.plan->log_n != log_n || u.inverse != inverse) continue;
+      if (done[k] || u.plan->log_n != log_n || u.inverse != inverse || (u.acc != nullptr) != epi) continue;
       done[k] = true;
       const uint32_t polys = u.limb_count * u.batch;
       if (polys == 0) continue;
@@ -705,8 +761,8 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
         t1.total = t2.total = 0;
       }
       const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;
-      t1.u[t1.count++] = FsUnit{u.in, mids[k], tabs, u.batch, t1.total};
-      t2.u[t2.count++] = FsUnit{mids[k], u.out, tabs, u.batch, t2.total};
+      t1.u[t1.count++] = FsUnit{u.in, mids[k], tabs, u.batch, t1.total, nullptr, nullptr, 0};
+      t2.u[t2.count++] = FsUnit{mids[k], u.out, tabs, u.batch, t2.total, u.acc, u.epi_mult, u.epi_add ? 1u : 0u};
       t1.total += polys;
       t2.total += polys;
     }
@@ -725,8 +781,8 @@ hipError_t co_transform(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* 
   t1.total = t2.total = limb_count * batch;
   t1.log_n = t2.log_n = p->log_n;
   t1.cols = t2.cols = 256;  // N = 2^16: both passes are 256 x 256
-  t1.u[0] = FsUnit{in, (uint32_t*)ws, tabs, batch, 0};
-  t2.u[0] = FsUnit{(const uint32_t*)ws, out, tabs, batch, 0};
+  t1.u[0] = FsUnit{in, (uint32_t*)ws, tabs, batch, 0, nullptr, nullptr, 0};
+  t2.u[0] = FsUnit{(const uint32_t*)ws, out, tabs, batch, 0, nullptr, nullptr, 0};
   co_launch<true>(p, t1, s);
   co_launch<false>(p, t2, s);
   return hipGetLastError();
