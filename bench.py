@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-hmult", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=1500)
     ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult"], default=None,
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",

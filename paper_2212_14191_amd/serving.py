@@ -195,8 +195,10 @@ class Server:
 class GpuBackend:
     """Device backend: one CkksContext per N, resident keys, one HIP stream
     per slot.  Inputs of a batch are staged into one [2][level][B][N] tensor
-    on the slot's stream; HMULT / HROTATE run batched; the outputs are
-    per-request views of the batch output."""
+    on the slot's stream (a single contiguous request is used in place);
+    HMULT / HROTATE run batched; the outputs are per-request views of the
+    batch output.  Each slot keeps one workspace, grown to the largest batch
+    it has run."""
 
     def __init__(self, contexts, relin_keys, rot_keys, slots=4):
         import torch
@@ -205,6 +207,29 @@ class GpuBackend:
         self.evk = relin_keys        # log_n -> tensor
         self.rk = rot_keys           # (log_n, galois) -> tensor
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        # one workspace per slot, grown to the largest batch it has run (a
+        # slot's next batch starts only after its previous one completed)
+        self.ws = [None] * slots
+
+    def _workspace(self, slot, ctx, level, batch):
+        need = max(ctx.workspace_bytes(level, batch), 256)
+        w = self.ws[slot]
+        if w is None or w.numel() < need:
+            w = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
+            self.ws[slot] = w
+        return w
+
+    def _stage(self, reqs, attr, level, n):
+        """[2][level][B][N] input: a single contiguous request is used as is."""
+        torch = self.torch
+        if len(reqs) == 1:
+            t = getattr(reqs[0], attr)
+            if t.is_contiguous() and t.numel() == 2 * level * n:
+                return t.view(2, level, 1, n)
+        a = torch.empty((2, level, len(reqs), n), dtype=torch.int32, device="cuda")
+        for b, r in enumerate(reqs):
+            a[:, :, b].copy_(getattr(r, attr).reshape(2, level, n), non_blocking=True)
+        return a
 
     def nbytes(self, op, log_n, level, batch):
         n = 1 << log_n
@@ -220,15 +245,11 @@ class GpuBackend:
         s = self.streams[slot]
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            a = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
-            for b, r in enumerate(reqs):
-                a[:, :, b].copy_(r.ct_a.reshape(2, level, n), non_blocking=True)
-            out = torch.empty_like(a)
-            ws = ctx.workspace(level, B)
+            a = self._stage(reqs, "ct_a", level, n)
+            out = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
+            ws = self._workspace(slot, ctx, level, B)
             if r0.op == HMULT:
-                bb = torch.empty_like(a)
-                for b, r in enumerate(reqs):
-                    bb[:, :, b].copy_(r.ct_b.reshape(2, level, n), non_blocking=True)
+                bb = self._stage(reqs, "ct_b", level, n)
                 ctx.hmult(a, bb, self.evk[r0.log_n], level, out=out, ws=ws, stream=s)
             else:
                 bb = None
