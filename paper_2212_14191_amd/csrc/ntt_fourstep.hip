@@ -33,12 +33,15 @@
 // Data movement.  A work item is P rows x W columns (vectors) of one
 // polynomial, 1024 words per wave (4 waves, or 8 for the wide items of the
 // 256-point stage).  Items are staged through a three-deep LDS ring by
-// direct-to-LDS loads issued two items ahead.  Each wave transforms four sets
-// of vectors; a set fills the 16 rows of one MFMA tile with 16 / r vectors.  The intermediate array between the passes is tiled: block kb of
+// direct-to-LDS loads issued two items ahead.  Each wave transforms four
+// sets of vectors; a set fills the 16 rows of one MFMA tile with 16 / r
+// vectors.  The intermediate array between the passes is tiled: block kb of
 // 16 consecutive pass-1 outputs holds, for every pass-1 column c, the 16
 // words (kb, c) contiguously, so pass 1 writes runs of whole lines and pass 2
-// reads its items as contiguous 16 KiB blocks.  Pass 2 writes its canonical results
-// back in natural order through the LDS stage it has just consumed.
+// reads each item as one contiguous block.  Pass 2 writes its canonical
+// results back in natural order through the LDS stage it has just consumed;
+// for forward transforms it can instead finish a ModDown / RESCALE step in
+// that store (out (+)= (acc - y) m).
 #include <algorithm>
 #include <type_traits>
 
