@@ -261,13 +261,13 @@ __device__ __forceinline__ void lds_barrier() {
 // Wait until this wave's loads of the current item have landed.  Vector
 // memory operations of a wave complete in issue order, so it suffices that at
 // most as many operations remain outstanding as were issued after those
-// loads: in steady state the stores of the two previous items (16 each in
-// pass 1, 4 in pass 2) and the loads of the next item (4); fewer near the
-// start; without a next item everything is awaited.  Table loads issued in
-// between only make the wait stricter.
-template <bool kFirst>
+// loads: in steady state the stores of the two previous items (kSt each:
+// 16 in the narrow first passes, 4 otherwise) and the loads of the next item
+// (4); fewer near the start; without a next item everything is awaited.
+// Table loads issued in between only make the wait stricter.
+template <int kSt>
 __device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
-  constexpr int st = kFirst ? 16 : 4;
+  constexpr int st = kSt;
   if (!has_next) wait_vmcnt<0>();
   else if (n == 0) wait_vmcnt<4>();
   else if (n == 1) wait_vmcnt<4 + st>();
@@ -288,8 +288,14 @@ __global__ void __launch_bounds__(kWide ? 512 : 256, (kWide || kEpi) ? 2 : 3)
 fs_pass(const FsTable tab) {
   static_assert(!kEpi || (!kFirst && kR == 16), "the epilogue belongs to the forward second pass");
   using G = Geo<kFirst, kR, kWide>;
-  __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile];
+  // The wide first pass gathers each wave's results in a private LDS buffer
+  // (1024 words: 16 runs of 64 words, one per output block t, each a
+  // contiguous 256-byte run of the tiled array) and stores them with
+  // 16-byte stores; the narrow first passes store 64-byte runs directly.
+  constexpr bool kGather = kFirst && kWide;
+  __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile + (kGather ? G::waves * 1024 : 0)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t* const gather = kGather ? ring + kStages * G::tile + wave * 1024 : ring;
   const int i16 = lane & 15, g = lane >> 4;
   const Walk walk = make_walk(tab.total, tab.ipp_log);
   if (walk.p >= walk.p_end) return;
@@ -304,7 +310,10 @@ fs_pass(const FsTable tab) {
     const uint32_t natural = row * S + c0 + col;
     const uint32_t tiled = ((c0 + col) >> 4) * (16 * G::P) + 16 * row + (col & 15);
     ld_off[j] = kFirst ? natural : tiled;
-    if (kFirst) {
+    if (kGather) {
+      // 16 bytes of the run of output block t = 4 j + g: words 4 i16 ..
+      st_off[j] = (4 * j + g) * 16 * S + (c0 + 4 * wave) * 16 + 4 * i16;
+    } else if (kFirst) {
       // tiled store of output s + 16 t of column c0 + 4 (wave Mt + m) (+ set)
       int m, t;
       lane_out<kR>(g, j, m, t);
@@ -372,7 +381,7 @@ fs_pass(const FsTable tab) {
     }
     const bool has_next = p + walk.step < walk.p_end;
     if (kEpi) wait_item_epi(n, has_next);
-    else wait_item<kFirst>(n, has_next);
+    else wait_item<kFirst && !kWide ? 16 : 4>(n, has_next);
     lds_barrier();  // the item's tile is complete; the oldest stage is free
     uint4 e_acc[4], e_out[4];  // epilogue operands at the item's store positions
     if (kEpi) {
@@ -435,7 +444,14 @@ fs_pass(const FsTable tab) {
             y[j] = reduce_once(mul_shoup_lazy(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j].x, tw[j].y, q), q);
           level_b<kR>(y, lb, rj, g, q);
         }
-        if (kFirst) {
+        if (kGather) {
+          // output 16 t + i16 (t = 4 g + j) of column 4 wave + sg: word
+          // 16 sg + i16 of run t, with bits 4-5 XOR g (= t / 4) so that the
+          // four lane groups write disjoint banks
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            gather[(4 * g + j) * 64 + 16 * (sg ^ g) + i16] = twist_digits<kBigQ>(y[j], pt[sg][j], q);
+        } else if (kFirst) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) out[st_off[j] + 16 * sg] = twist_digits<kBigQ>(y[j], pt[sg][j], q);
         } else {
@@ -456,6 +472,18 @@ fs_pass(const FsTable tab) {
     if (!kDual || q > 0x7F7F7F7Fu) body(std::true_type{});
     else body(std::false_type{});
 
+    if (kGather) {
+      // this wave's runs t = 4 j + g, words 4 i16 .. 4 i16 + 3 (unswizzled).
+      // A wave's LDS accesses complete in order; the compiler fence keeps the
+      // 16-byte reads after the 4-byte writes (different access types).
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = 4 * j + g;
+        __builtin_nontemporal_store(*(const v4u*)(gather + t * 64 + 16 * ((i16 >> 2) ^ j) + 4 * (i16 & 3)),
+                                    (v4u*)(out + st_off[j]));
+      }
+    }
     if (!kFirst) {
       // results into the consumed stage in the slab layout, then 16-byte
       // streaming stores with the load's lane mapping (whole lines; the
