@@ -195,8 +195,25 @@ __device__ __forceinline__ uint32_t conv_fuse(int c0, int c1, int c2, int c3, ui
   return reduce_once(vhi + __umulhi(m, q) + (vlo != 0u), q);
 }
 
-__global__ void __launch_bounds__(kThreads)
+// The per-target constants (A operands, moduli, Montgomery and offset
+// constants) sit in LDS and are read per use, which keeps the kernel at four
+// resident waves per SIMD for latency hiding; targets beyond nout have zero
+// operands and modulus 1 (their results are not stored).
+__global__ void __launch_bounds__(kThreads, 4)
 conv_mfma_kernel(const ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) uint32_t s_a[kConvMaxOut * 32];
+  __shared__ __attribute__((aligned(16))) uint32_t s_q[kConvMaxOut], s_qn[kConvMaxOut], s_k[kConvMaxOut];
+  for (int i = threadIdx.x; i < kConvMaxOut * 32; i += kThreads) {
+    const uint32_t t = i / 32;
+    s_a[i] = t < a.nout ? a.a_tab[t][i % 32] : 0u;
+  }
+  if (threadIdx.x < kConvMaxOut) {
+    const uint32_t t = threadIdx.x;
+    s_q[t] = t < a.nout ? a.out_q[t] : 1u;
+    s_qn[t] = t < a.nout ? a.out_qneg[t] : 0u;
+    s_k[t] = t < a.nout ? a.out_k[t] : 0u;
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
   const uint64_t chunks = a.plane / 64;
   const uint64_t wave_id = (blockIdx.x * (uint64_t)kThreads + threadIdx.x) / 64;
@@ -205,22 +222,6 @@ conv_mfma_kernel(const ConvArgs a) {
   const bool h0 = r0 < (int)a.nin, h1 = r1 < (int)a.nin;
   const uint32_t q0 = h0 ? a.in_q[r0] : 1, q1 = h1 ? a.in_q[r1] : 1;
   const uint2 m0 = h0 ? a.in_mult[r0] : make_uint2(0, 0), m1 = h1 ? a.in_mult[r1] : make_uint2(0, 0);
-  // constant operands of the (at most two) 16-target blocks
-  long av[2][4];
-  uint32_t tq[2][4], tn[2][4], tk[2][4];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    const uint32_t ta = 16 * b + n;  // target of this lane's A row
-#pragma unroll
-    for (int j = 0; j < 4; ++j) av[b][j] = ta < a.nout ? *(const long*)(a.a_tab[ta] + 8 * j + 2 * g) : 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const uint32_t t = 16 * b + 4 * g + i;
-      tq[b][i] = t < a.nout ? a.out_q[t] : 1;
-      tn[b][i] = t < a.nout ? a.out_qneg[t] : 0;
-      tk[b][i] = t < a.nout ? a.out_k[t] : 0;
-    }
-  }
   const int blocks = a.nout > 16 ? 2 : 1;
   const v4i zero = {0, 0, 0, 0};
   // the next chunk's inputs are loaded while this one is converted
@@ -243,28 +244,35 @@ conv_mfma_kernel(const ConvArgs a) {
     const uint4 d1 = map4(x1, [&](uint32_t v, int) {
       return h1 ? balanced_digits((int32_t)(mul_shoup(v, m1.x, m1.y, q1) - (1u << 30))) : 0u;
     });
+    for (int b = 0; b < blocks; ++b) {
+      // A rows: target 16 b + n, K slice 8 g .. 8 g + 7 of each digit plane j
+      long av[4];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      if (b >= blocks) break;
-      const v4i bias = {(int)tq[b][0], (int)tq[b][1], (int)tq[b][2], (int)tq[b][3]};
+      for (int j = 0; j < 4; ++j) av[j] = *(const long*)(s_a + (16 * b + n) * 32 + 8 * j + 2 * g);
+      const int t0 = 16 * b + 4 * g;  // this lane's output targets t0 .. t0 + 3
+      const uint4 tq = *(const uint4*)(s_q + t0), tn = *(const uint4*)(s_qn + t0);
+      const v4i bias = {(int)tq.x, (int)tq.y, (int)tq.z, (int)tq.w};
       uint32_t res[4][4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const long bv = (long)((uint64_t)comp(d0, p) | ((uint64_t)comp(d1, p) << 32));
-        const v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][0], bv, bias, 0, 0, 0);
-        const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][1], bv, zero, 0, 0, 0);
-        const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][2], bv, bias, 0, 0, 0);
-        const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[b][3], bv, zero, 0, 0, 0);
+        const v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[0], bv, bias, 0, 0, 0);
+        const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[1], bv, zero, 0, 0, 0);
+        const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[2], bv, bias, 0, 0, 0);
+        const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(av[3], bv, zero, 0, 0, 0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          res[i][p] = add_mod(conv_fuse(c0[i], c1[i], c2[i], c3[i], tq[b][i], tn[b][i]), tk[b][i], tq[b][i]);
+        for (int i = 0; i < 4; ++i) res[i][p] = conv_fuse(c0[i], c1[i], c2[i], c3[i], comp(tq, i), comp(tn, i));
+        // one sub-tile's products in flight at a time (register budget)
+        __builtin_amdgcn_sched_barrier(0);
       }
+      const uint4 tk = *(const uint4*)(s_k + t0);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const uint32_t t = 16 * b + 4 * g + i;
+        const uint32_t t = t0 + i, q = comp(tq, i), k = comp(tk, i);
         if (t < a.nout)
           *(uint4*)(a.out + (uint64_t)a.out_plane[t] * a.plane + pos) =
-              make_uint4(res[i][0], res[i][1], res[i][2], res[i][3]);
+              make_uint4(add_mod(res[i][0], k, q), add_mod(res[i][1], k, q), add_mod(res[i][2], k, q),
+                         add_mod(res[i][3], k, q));
       }
     }
   }
@@ -297,9 +305,9 @@ rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
 hipError_t launch_conv_mfma(const ConvArgs& a, KernelId id, hipStream_t s) {
   const uint64_t chunks = a.plane / 64;
   const uint64_t blocks = (chunks + 3) / 4;  // 4 waves per block, one chunk each per round
-  // about one resident round: each wave then converts several chunks with
-  // its next inputs in flight
-  const uint32_t grid = (uint32_t)(blocks < 1536 ? (blocks ? blocks : 1) : 1536);
+  // about one resident round (four workgroups per CU on 256 CUs): each wave
+  // then converts several chunks with its next inputs in flight
+  const uint32_t grid = (uint32_t)(blocks < 1024 ? (blocks ? blocks : 1) : 1024);
   TFHE_TIMED(id, s, hipLaunchKernelGGL(conv_mfma_kernel, dim3(grid), dim3(kThreads), 0, s, a));
   return hipGetLastError();
 }

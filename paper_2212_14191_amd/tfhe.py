@@ -43,6 +43,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2212_14191_amd.build` (no CPU fallback exists)")
+    # The library and PyTorch must share one HIP runtime: with torch loaded
+    # first, the library's libamdhip64 dependency resolves to torch's copy.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     u32, u64, i32, vp, sz = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
     pu32 = ctypes.POINTER(u32)
