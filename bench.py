@@ -213,13 +213,15 @@ def main():
     if args.copy_calib:
         y.copy_(x)
         sync()
-    # measured bandwidth ceiling: a plain device copy of the same batch
-    # (reads and writes the algorithmic bytes of one pass launch)
-    for _ in range(args.warmup):
-        y.copy_(x)
-    copy_gbs = 2 * x.numel() * 4 * 10 / timed(lambda: y.copy_(x), 10, sync) / 1e9
     results = {}
     algos = ["mfma", "butterfly", "co"] if args.only is None else [args.only] if args.only != "hmult" else []
+    # measured bandwidth ceiling: a plain device copy of the same batch
+    # (reads and writes the algorithmic bytes of one pass launch)
+    copy_gbs = None
+    if algos:
+        for _ in range(args.warmup):
+            y.copy_(x)
+        copy_gbs = 2 * x.numel() * 4 * 10 / timed(lambda: y.copy_(x), 10, sync) / 1e9
     for algo in algos:
         def step(algo=algo):
             plan.fwd(x, out=y, algo=algo, ws=ws)
