@@ -135,10 +135,14 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs):
     torch.cuda.synchronize()
     slots, budget = 4, 48 << 30
 
+    # one long-lived backend: its streams, events and per-slot workspaces stay
+    # warm across the runs, as in a running server
+    backend = GpuBackend(ctxs, evks, rks, slots=slots)
+
     def run(count, seed, rate):
         mix = inputs.request_mix(seed, count, log_ns=log_ns, max_level=L, rotations=rots)
         arrivals = inputs.poisson_arrivals(seed, rate, count) if rate else np.zeros(count)
-        srv = Server(GpuBackend(ctxs, evks, rks, slots=slots), budget, slots=slots, max_batch=16)
+        srv = Server(backend, budget, slots=slots, max_batch=16)
         futs = []
         t0 = time.perf_counter()
         for i in range(count):

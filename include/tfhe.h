@@ -237,6 +237,21 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
                         const uint32_t* rotkey, uint32_t galois_elt, uint32_t level,
                         uint32_t batch, void* ws, size_t ws_bytes, tfhe_stream_t stream);
 
+/* HROTATE of a batch whose ciphertexts rotate by different amounts, in one
+ * batched launch sequence (operation-level batching, Sec. III-D): ciphertext
+ * b of ct_in is rotated by galois_elts[b] with the rotation key rotkeys[b],
+ * exactly as tfhe_rotate would do for it alone.
+ *   rotkeys: host array [batch] of device pointers, each [dnum][2][L+K][N]
+ *     (entries may repeat); galois_elts: host array [batch], each odd, < 2N.
+ *   ct_in, ct_out: device [2][level][batch][N], must not alias.
+ *   batch <= TFHE_ROTATE_MULTI_MAX; ws: >= tfhe_hmult_workspace_size bytes.
+ * The host arrays are read during the call only. */
+#define TFHE_ROTATE_MULTI_MAX 64
+tfhe_status tfhe_rotate_multi(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,
+                              const uint32_t* const* rotkeys, const uint32_t* galois_elts,
+                              uint32_t level, uint32_t batch, void* ws, size_t ws_bytes,
+                              tfhe_stream_t stream);
+
 /* Device workspace (bytes) tfhe_rescale needs at this level (>= 2) and
  * batch. */
 tfhe_status tfhe_rescale_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch,

@@ -119,9 +119,10 @@ static hipError_t moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp
   return a.nout ? launch_conv_mfma(a, K_MD_CONV, s) : hipSuccess;
 }
 
-// Key switching of d (NTT domain, [level][B][N]) with key [dnum][2][L+K][N];
+// Key switching of d (NTT domain, [level][B][N]) with keys [dnum][2][L+K][N]
+// (one for the batch, or one per batch element);
 // out0 (+)= ModDown(acc0), out1 (+)= ModDown(acc1).
-static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const uint32_t* key,
+static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const KeySet& keys,
                              uint32_t* out0, uint32_t* out1, bool acc0_add, bool acc1_add,
                              uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
   const tfhe_ntt_plan_s* p = c->plan;
@@ -161,7 +162,7 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   if ((e = ntt_units(p, fwd, nws, s)) != hipSuccess) return e;
   uint32_t* a0 = acc;
   uint32_t* a1 = acc + (uint64_t)ext * plane;
-  if ((e = launch_inner_product(d, up, key, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
+  if ((e = launch_inner_product(d, up, keys, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
                                 batch, c->log_n, s)) != hipSuccess)
     return e;
   // ModDown of both accumulators, their transforms fused
@@ -484,8 +485,11 @@ tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* 
   unsigned char* w = (unsigned char*)ws;
   uint32_t* d2 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
   hipError_t e = launch_tensor(ct_a, ct_b, ct_out, d2, ctx->plan->d_mod, level, batch, ctx->n, s);
+  KeySet keys{};
+  keys.count = 1;
+  keys.k[0] = evk;
   if (e == hipSuccess)
-    e = key_switch(ctx, d2, evk, ct_out, ct_out + plane, true, true, level, batch, w, s);
+    e = key_switch(ctx, d2, keys, ct_out, ct_out + plane, true, true, level, batch, w, s);
   return hip_check(e, "hmult");
 }
 
@@ -506,9 +510,44 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
   uint32_t* r1 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
   hipError_t e = frobenius_launch(ct_in, ct_out, galois_elt, level * batch, ctx->log_n, s);
   if (e == hipSuccess) e = frobenius_launch(ct_in + plane, r1, galois_elt, level * batch, ctx->log_n, s);
+  KeySet keys{};
+  keys.count = 1;
+  keys.k[0] = rotkey;
   if (e == hipSuccess)
-    e = key_switch(ctx, r1, rotkey, ct_out, ct_out + plane, true, false, level, batch, w, s);
+    e = key_switch(ctx, r1, keys, ct_out, ct_out + plane, true, false, level, batch, w, s);
   return hip_check(e, "rotate");
+}
+
+tfhe_status tfhe_rotate_multi(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,
+                              const uint32_t* const* rotkeys, const uint32_t* galois_elts,
+                              uint32_t level, uint32_t batch, void* ws, size_t ws_bytes,
+                              tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, ws, ws_bytes);
+  if (st != TFHE_OK || batch == 0) return st;
+  if (batch > kMaxRotBatch) return fail(TFHE_EINVAL, "rotate_multi: batch exceeds TFHE_ROTATE_MULTI_MAX");
+  if (!rotkeys || !galois_elts) return fail(TFHE_EINVAL, "rotate_multi: null key or Galois array");
+  if (!al16(ct_in) || !al16(ct_out)) return fail(TFHE_EINVAL, "rotate_multi: null or unaligned pointer");
+  KeySet keys{};
+  GaloisSet gs{};
+  keys.count = gs.batch = batch;
+  for (uint32_t b = 0; b < batch; ++b) {
+    if (!al16(rotkeys[b])) return fail(TFHE_EINVAL, "rotate_multi: null or unaligned rotation key");
+    if ((galois_elts[b] & 1) == 0 || galois_elts[b] >= 2 * ctx->n)
+      return fail(TFHE_EINVAL, "rotate_multi: galois elements must be odd and < 2N");
+    keys.k[b] = rotkeys[b];
+    gs.g[b] = galois_elts[b];
+  }
+  const uint64_t plane = (uint64_t)level * batch * ctx->n;
+  if (ct_in < ct_out + 2 * plane && ct_out < ct_in + 2 * plane)
+    return fail(TFHE_EINVAL, "rotate_multi: ct_out must not alias ct_in");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* w = (unsigned char*)ws;
+  uint32_t* r1 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
+  hipError_t e = frobenius_multi_launch(ct_in, ct_out, gs, level * batch, ctx->log_n, s);
+  if (e == hipSuccess) e = frobenius_multi_launch(ct_in + plane, r1, gs, level * batch, ctx->log_n, s);
+  if (e == hipSuccess)
+    e = key_switch(ctx, r1, keys, ct_out, ct_out + plane, true, false, level, batch, w, s);
+  return hip_check(e, "rotate_multi");
 }
 
 tfhe_status tfhe_rescale_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch,

@@ -52,7 +52,13 @@ hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, ui
 hipError_t launch_modup(const uint32_t* x, uint32_t* up, const ModConst* mods, const uint2* inv,
                         const uint2* conv, uint32_t d0, uint32_t nd, uint32_t level, uint32_t L,
                         uint32_t K, uint32_t batch, uint32_t n, hipStream_t s);
-hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const uint32_t* key,
+// Keys of a key switch: one for the whole batch (count = 1) or one per batch
+// element (count = batch <= kMaxRotBatch), each [dnum][2][L+K][N].
+struct KeySet {
+  uint32_t count;
+  const uint32_t* k[kMaxRotBatch];
+};
+hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const KeySet& keys,
                                 uint32_t* acc0, uint32_t* acc1, const ModConst* mods,
                                 uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,
                                 uint32_t K, uint32_t batch, uint32_t log_n, hipStream_t s);

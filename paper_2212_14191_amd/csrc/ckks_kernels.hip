@@ -88,7 +88,7 @@ modup_kernel(const uint4* __restrict__ x, uint4* __restrict__ up,
 // d2 (NTT domain) on the digit's own limbs and the ModUp result elsewhere.
 __global__ void __launch_bounds__(kThreads)
 inner_product_kernel(const uint4* __restrict__ d2, const uint4* __restrict__ up,
-                     const uint4* __restrict__ key, uint4* __restrict__ acc0,
+                     const KeySet keys, uint4* __restrict__ acc0,
                      uint4* __restrict__ acc1, const ModConst* __restrict__ mods,
                      uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L, uint32_t K,
                      uint32_t batch, uint32_t log_n) {
@@ -102,6 +102,8 @@ inner_product_kernel(const uint4* __restrict__ d2, const uint4* __restrict__ up,
     const uint32_t coef = (uint32_t)(i % n4);
     const uint32_t t = p < level ? p : L + (p - level);
     const ModConst m = mods[t];
+    // the key of this element's batch entry (one key for all when count = 1)
+    const uint4* key = (const uint4*)keys.k[keys.count == 1 ? 0 : (uint32_t)((i % bn4) / n4)];
     uint4 s0 = make_uint4(0, 0, 0, 0), s1 = s0;
     for (uint32_t j = 0; j < ndigits; ++j) {
       const bool own = p < level && p / alpha == j;
@@ -340,13 +342,13 @@ hipError_t launch_modup(const uint32_t* x, uint32_t* up, const ModConst* mods, c
   return hipGetLastError();
 }
 
-hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const uint32_t* key,
+hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const KeySet& keys,
                                 uint32_t* acc0, uint32_t* acc1, const ModConst* mods,
                                 uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,
                                 uint32_t K, uint32_t batch, uint32_t log_n, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)(level + K) * batch << log_n) / 4;
   TFHE_TIMED(K_INNER, s, hipLaunchKernelGGL(inner_product_kernel, dim3(grid_for(total4)), dim3(kThreads), 0, s,
-                                            (const uint4*)d2, (const uint4*)up, (const uint4*)key,
+                                            (const uint4*)d2, (const uint4*)up, keys,
                                             (uint4*)acc0, (uint4*)acc1, mods, alpha, ndigits, level, L, K,
                                             batch, log_n));
   return hipGetLastError();

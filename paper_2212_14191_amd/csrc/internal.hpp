@@ -126,6 +126,15 @@ hipError_t ew_launch(EwOp op, const ModConst* mods, const uint32_t* a, const uin
                      uint32_t* c, uint32_t limb_count, uint32_t batch, uint32_t n, hipStream_t s);
 hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, uint32_t rows,
                             uint32_t log_n, hipStream_t s);
+// Per-batch-element Galois elements of a multi-rotation: row r of the
+// [rows][N] array (rows = limbs x batch, batch fastest) uses g[r % batch].
+constexpr uint32_t kMaxRotBatch = TFHE_ROTATE_MULTI_MAX;
+struct GaloisSet {
+  uint32_t batch;
+  uint32_t g[kMaxRotBatch];
+};
+hipError_t frobenius_multi_launch(const uint32_t* in, uint32_t* out, const GaloisSet& gs, uint32_t rows,
+                                  uint32_t log_n, hipStream_t s);
 
 // ---- per-kernel event timing (timing.cpp)
 enum KernelId {

@@ -3,7 +3,9 @@ Sec. III-E: requests are collected, decomposed into batched kernel workflows
 and dispatched; keys and ciphertexts stay resident in HBM).
 
 A scheduler thread keeps up to `slots` batches in flight, each on its own
-HIP stream.  Pending requests are grouped by (op, N, level, galois element);
+HIP stream.  Pending requests are grouped by (op, N, level): rotations by
+different amounts share a batch (each ciphertext with its own Galois element
+and key, one batched launch sequence);
 whenever a slot is free, the oldest pending request and up to max_batch - 1
 compatible ones form a batch, provided its device memory (staged inputs,
 outputs, workspace) fits the remaining budget; otherwise admission waits
@@ -38,15 +40,17 @@ class Request:
 
     @property
     def key(self):
-        return (self.op, self.log_n, self.level, self.galois if self.op == ROTATE else 0)
+        """Batching key: rotations by different amounts batch together."""
+        return (self.op, self.log_n, self.level)
 
 
 class Server:
-    def __init__(self, backend, mem_budget_bytes, slots=4, max_batch=16, poll_s=0.0002):
+    def __init__(self, backend, mem_budget_bytes, slots=4, max_batch=16, poll_s=1e-5):
         self.backend = backend
         self.budget = int(mem_budget_bytes)
         self.slots = int(slots)
-        self.max_batch = int(max_batch)
+        # a backend may cap the batch (the GPU backend: TFHE_ROTATE_MULTI_MAX)
+        self.max_batch = min(int(max_batch), getattr(backend, "max_batch", int(max_batch)))
         self.poll_s = poll_s
         self._pending = collections.OrderedDict()  # id -> Request (FIFO)
         self._inflight = []                         # (handle, requests, nbytes, slot)
@@ -200,6 +204,8 @@ class GpuBackend:
     batch output.  Each slot keeps one workspace, grown to the largest batch
     it has run."""
 
+    max_batch = 64  # tfhe_rotate_multi's limit
+
     def __init__(self, contexts, relin_keys, rot_keys, slots=4):
         import torch
         self.torch = torch
@@ -207,6 +213,8 @@ class GpuBackend:
         self.evk = relin_keys        # log_n -> tensor
         self.rk = rot_keys           # (log_n, galois) -> tensor
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        # completion events, one per slot (a slot runs one batch at a time)
+        self.events = [torch.cuda.Event() for _ in range(slots)]
         # one workspace per slot, grown to the largest batch it has run (a
         # slot's next batch starts only after its previous one completed)
         self.ws = [None] * slots
@@ -253,8 +261,13 @@ class GpuBackend:
                 ctx.hmult(a, bb, self.evk[r0.log_n], level, out=out, ws=ws, stream=s)
             else:
                 bb = None
-                ctx.rotate(a, self.rk[(r0.log_n, r0.galois)], r0.galois, level, out=out, ws=ws, stream=s)
-            ev = torch.cuda.Event()
+                gal = [r.galois for r in reqs]
+                if all(g == gal[0] for g in gal):
+                    ctx.rotate(a, self.rk[(r0.log_n, r0.galois)], r0.galois, level, out=out, ws=ws, stream=s)
+                else:
+                    ctx.rotate_multi(a, [self.rk[(r0.log_n, g)] for g in gal], gal, level, out=out, ws=ws,
+                                     stream=s)
+            ev = self.events[slot]
             ev.record(s)
         return {"event": ev, "out": out, "keep": (a, bb, ws), "B": B}
 

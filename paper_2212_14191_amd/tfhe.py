@@ -79,6 +79,7 @@ def load():
         "tfhe_hmult_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
         "tfhe_hmult": ([vp, vp, vp, vp, vp, u32, u32, vp, sz, vp], i32),
         "tfhe_rotate": ([vp, vp, vp, vp, u32, u32, u32, vp, sz, vp], i32),
+        "tfhe_rotate_multi": ([vp, vp, vp, ctypes.POINTER(vp), pu32, u32, u32, vp, sz, vp], i32),
         "tfhe_rescale_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
         "tfhe_rescale": ([vp, vp, vp, u32, u32, vp, sz, vp], i32),
         "tfhe_cmult": ([vp, vp, vp, vp, u32, u32, vp], i32),
@@ -372,6 +373,26 @@ class CkksContext:
         if ws is None:
             ws = self.workspace(level, batch)
         _call("tfhe_rotate", self.handle, _ptr(ct), _ptr(out), _ptr(rotkey), galois, level, batch,
+              _ptr(ws), ws.numel(), _stream(stream))
+        return out
+
+    ROTATE_MULTI_MAX = 64
+
+    def rotate_multi(self, ct, rotkeys, galois, level, out=None, ws=None, stream=None):
+        """Ciphertext b of ct rotated by galois[b] with rotkeys[b] (one
+        batched launch sequence; tfhe_rotate_multi)."""
+        _, lv, batch, n = ct.shape
+        _check_residues(ct, "ct", (2, level, batch, self.n))
+        if len(rotkeys) != batch or len(galois) != batch:
+            raise ValueError("one rotation key and one Galois element per ciphertext")
+        for k in rotkeys:
+            _check_residues(k, "rotkey", (self.dnum, 2, self.L + self.K, self.n))
+        if out is None:
+            out = torch_empty_like(ct)
+        if ws is None:
+            ws = self.workspace(level, batch)
+        keys = (ctypes.c_void_p * batch)(*[k.data_ptr() for k in rotkeys])
+        _call("tfhe_rotate_multi", self.handle, _ptr(ct), _ptr(out), keys, _u32_array(galois), level, batch,
               _ptr(ws), ws.numel(), _stream(stream))
         return out
 

@@ -94,6 +94,51 @@ def test_rotate_matches_oracle(tf, log_n, r):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("log_n", [10, 13])
+def test_rotate_multi_matches_oracle(tf, log_n):
+    """Rotations by different amounts in one batch (repeated amounts,
+    conjugation, partial last digit at level 5): each ciphertext equals the
+    oracle's rotation of it alone and the single-amount entry point."""
+    n = 1 << log_n
+    L, K, dnum, level = 6, 2, 3, 5
+    pr, s, _, (a, e) = setup(n, L, K, dnum)
+    gal = [ckks.galois_element(1, n), ckks.galois_element(3, n), 2 * n - 1, ckks.galois_element(1, n),
+           ckks.galois_element(7, n)]
+    rks = {k: ckks.rotation_key(pr, s, k, a, e) for k in set(gal)}
+    drk = {k: to_dev(v) for k, v in rks.items()}
+    ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
+    m = inputs.small_messages(3, (len(gal), n))
+    ct = encrypt(pr, s, m, level, 4)
+    got = to_host(ctx.rotate_multi(to_dev(ct), [drk[k] for k in gal], gal, level))
+    for b, k in enumerate(gal):
+        one = np.ascontiguousarray(ct[:, :, b:b + 1])
+        want = ckks.rotate(pr, one, rks[k], k, level)
+        assert np.array_equal(got[:, :, b:b + 1], want), f"element {b}, galois {k}"
+        alone = to_host(ctx.rotate(to_dev(one), drk[k], k, level))
+        assert np.array_equal(alone, want)
+
+
+def test_rotate_multi_errors(tf):
+    n = 1 << 10
+    L, K, dnum, level = 6, 2, 3, 5
+    pr, s, _, (a, e) = setup(n, L, K, dnum)
+    k = ckks.galois_element(1, n)
+    rk = to_dev(ckks.rotation_key(pr, s, k, a, e))
+    ctx = tf.CkksContext(10, L, K, dnum, moduli=pr.moduli)
+    ct = to_dev(encrypt(pr, s, inputs.small_messages(0, (2, n)), level, 1))
+    with pytest.raises(tf.TfheError):
+        ctx.rotate_multi(ct, [rk, rk], [k, 2 * k], level)          # even Galois element
+    with pytest.raises(tf.TfheError):
+        ctx.rotate_multi(ct, [rk, rk], [k, 2 * n + 1], level)      # not below 2N
+    with pytest.raises(ValueError):
+        ctx.rotate_multi(ct, [rk], [k], level)                     # one key per ciphertext
+    big = torch.zeros((2, level, 65, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(tf.TfheError):
+        ctx.rotate_multi(big, [rk] * 65, [k] * 65, level)          # above TFHE_ROTATE_MULTI_MAX
+    with pytest.raises(tf.TfheError):
+        ctx.rotate_multi(ct, [rk, rk], [k, k], level, out=ct)      # output aliases the input
+
+
 @pytest.mark.slow
 def test_hmult_config4_full_size_sampled(tf):
     """N=2^16, L=24, K=8, dnum=3, h=192, 64 pairs on the GPU (MFMA NTT);

@@ -40,8 +40,9 @@ class OracleBackend:
             if r0.op == HMULT:
                 b = np.concatenate([r.ct_b for r in reqs], axis=2)
                 out = ckks.hmult(self.pr, a, b, self.evk, r0.level)
-            else:
-                out = ckks.rotate(self.pr, a, self.rks[r0.galois], r0.galois, r0.level)
+            else:  # a batch may mix rotation amounts
+                out = np.concatenate([ckks.rotate(self.pr, r.ct_a, self.rks[r.galois], r.galois, r.level)
+                                      for r in reqs], axis=2)
             h["out"] = [out[:, :, i:i + 1] for i in range(len(reqs))]
             with self.lock:
                 self.inflight_bytes -= nb
