@@ -83,12 +83,12 @@ static hipError_t modup_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* x, uint32
     a.out_k[a.nout] = c->h_up_k[(size_t)key_idx * (c->L + c->K) + t];
     a.a_tab[a.nout] = c->d_up_mfma + ((size_t)key_idx * (c->L + c->K) + t) * 32;
     if (++a.nout == kConvMaxOut) {
-      hipError_t e = launch_conv_mfma(a, K_MODUP, s);
+      hipError_t e = launch_conv_mfma(a, c->plan->num_cus, K_MODUP, s);
       if (e != hipSuccess) return e;
       a.nout = 0;
     }
   }
-  return a.nout ? launch_conv_mfma(a, K_MODUP, s) : hipSuccess;
+  return a.nout ? launch_conv_mfma(a, c->plan->num_cus, K_MODUP, s) : hipSuccess;
 }
 
 // ModDown conversion of the K special limbs to the level q-limbs.
@@ -111,12 +111,12 @@ static hipError_t moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp
     a.out_k[a.nout] = c->h_dn_k[i];
     a.a_tab[a.nout] = c->d_dn_mfma + (size_t)i * 32;
     if (++a.nout == kConvMaxOut) {
-      hipError_t e = launch_conv_mfma(a, K_MD_CONV, s);
+      hipError_t e = launch_conv_mfma(a, c->plan->num_cus, K_MD_CONV, s);
       if (e != hipSuccess) return e;
       a.nout = 0;
     }
   }
-  return a.nout ? launch_conv_mfma(a, K_MD_CONV, s) : hipSuccess;
+  return a.nout ? launch_conv_mfma(a, c->plan->num_cus, K_MD_CONV, s) : hipSuccess;
 }
 
 // Key switching of d (NTT domain, [level][B][N]) with keys [dnum][2][L+K][N]

@@ -69,7 +69,7 @@ hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint3
                                 const ModConst* mods, const uint2* pinv, uint32_t level,
                                 uint32_t batch, uint32_t n, bool accumulate, hipStream_t s,
                                 KernelId id = K_MD_FINAL);
-hipError_t launch_conv_mfma(const ConvArgs& a, KernelId id, hipStream_t s);
+hipError_t launch_conv_mfma(const ConvArgs& a, uint32_t num_cus, KernelId id, hipStream_t s);
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 

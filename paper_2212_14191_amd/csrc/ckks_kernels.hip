@@ -304,12 +304,13 @@ rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
 
 }  // namespace
 
-hipError_t launch_conv_mfma(const ConvArgs& a, KernelId id, hipStream_t s) {
+hipError_t launch_conv_mfma(const ConvArgs& a, uint32_t num_cus, KernelId id, hipStream_t s) {
   const uint64_t chunks = a.plane / 64;
   const uint64_t blocks = (chunks + 3) / 4;  // 4 waves per block, one chunk each per round
-  // about one resident round (four workgroups per CU on 256 CUs): each wave
-  // then converts several chunks with its next inputs in flight
-  const uint32_t grid = (uint32_t)(blocks < 1024 ? (blocks ? blocks : 1) : 1024);
+  // about one resident round (four workgroups per CU): each wave then
+  // converts several chunks with its next inputs in flight
+  const uint64_t resident = 4ull * (num_cus ? num_cus : 1);
+  const uint32_t grid = (uint32_t)(blocks < resident ? (blocks ? blocks : 1) : resident);
   TFHE_TIMED(id, s, hipLaunchKernelGGL(conv_mfma_kernel, dim3(grid), dim3(kThreads), 0, s, a));
   return hipGetLastError();
 }

@@ -168,3 +168,22 @@ def test_timeout_and_cancel(world):
     srv.drain(5)
     srv.close()
     assert len(be.launch_log) == 1
+
+
+def test_rotations_by_different_amounts_share_a_batch(world):
+    """Rotations of one (N, level) batch together whatever their amounts;
+    each result still equals that rotation alone."""
+    pr, evk, rks, gal, cts = world
+    be = OracleBackend(pr, evk, rks, delay_s=0.2)
+    srv = Server(be, mem_budget_bytes=1 << 30, slots=1, max_batch=8)
+    blocker = srv.submit(HMULT, 6, 2, cts[(2, 0)], cts[(2, 1)])   # occupies the only slot
+    time.sleep(0.05)
+    reqs = [(ROTATE, 4, cts[(4, i % 3)], None, gal[i % 2]) for i in range(4)]
+    futs = [srv.submit(op, 6, lv, a, b, g) for op, lv, a, b, g in reqs]
+    blocker.result(timeout=10)
+    got = [f.result(timeout=10) for f in futs]
+    srv.close()
+    sizes = sorted(b for _, _, b, _ in be.launch_log)
+    assert sizes == [1, 4]
+    for (op, lv, a, b, g), out in zip(reqs, got):
+        assert np.array_equal(out, ckks.rotate(pr, a, rks[g], g, lv))
