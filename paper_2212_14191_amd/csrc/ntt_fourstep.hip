@@ -110,14 +110,15 @@ __device__ __forceinline__ v4i mfma(v4i a, v4i b, v4i c) {
 }
 
 // Fusion and one Montgomery step: V 2^{-32} mod q, in [0, q + 2^17).
+// (V + m q) is a multiple of 2^32 below 2^64, so its high word is exact
+// (one v_mad_u64_u32).
 __device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, uint32_t q,
                                               uint32_t qneg) {
   const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
   const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
   const uint64_t V = ((uint64_t)hi << 16) + lo;
-  const uint32_t vlo = (uint32_t)V, vhi = (uint32_t)(V >> 32);
-  const uint32_t m = vlo * qneg;
-  return vhi + __umulhi(m, q) + (vlo != 0u);
+  const uint32_t m = (uint32_t)V * qneg;
+  return (uint32_t)(((uint64_t)m * q + V) >> 32);
 }
 
 // Twist (Shoup, t = {w, companion}) and re-slice into digits; r < 2^32.
