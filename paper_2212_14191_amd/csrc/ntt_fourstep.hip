@@ -121,13 +121,29 @@ __device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, ui
   return (uint32_t)(((uint64_t)m * q + V) >> 32);
 }
 
+// 64-bit a b + c as one v_mad_u64_u32 (the carry-out is discarded).  Used
+// where only the low word is needed, which the compiler would otherwise
+// split into a 32-bit multiply and an add.
+__device__ __forceinline__ uint64_t mad_u64(uint32_t a, uint32_t b, uint64_t c) {
+  uint64_t d, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=&v"(d), "=s"(carry) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 // Twist (Shoup, t = {w, companion}) and re-slice into digits; r < 2^32.
 // z - q lies in [-q, q), inside the digit window unless q > 0x7F7F7F7F.
+// For such q the digits of z - q are ((r w - h q) + (0x80808080 - q)) ^
+// 0x80808080 with h = floor(r w' / 2^32): two multiply-adds on the low word
+// (nq = -q, cq = 0x80808080 - q, both mod 2^32).
 template <bool kBigQ>
-__device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q) {
+__device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q, uint32_t nq, uint64_t cq) {
+  if (!kBigQ) {
+    const uint32_t h = __umulhi(r, t.y);
+    return (uint32_t)mad_u64(h, nq, mad_u64(r, t.x, cq)) ^ 0x80808080u;
+  }
   const uint32_t z = mul_shoup_lazy(r, t.x, t.y, q);  // [0, 2q)
   int32_t zz = (int32_t)(z - q);                      // [-q, q)
-  if (kBigQ) zz = zz > 0x7F7F7F7F ? zz - (int32_t)q : zz;
+  zz = zz > 0x7F7F7F7F ? zz - (int32_t)q : zz;
   return balanced_digits(zz);
 }
 
@@ -334,7 +350,8 @@ fs_pass(const FsTable tab) {
     if (walk.p + j * walk.step < walk.p_end) issue(walk.p + j * walk.step, j);
 
   const FourStepLimb* cur_limb = nullptr;
-  uint32_t q = 0, qneg = 0;
+  uint32_t q = 0, qneg = 0, nq = 0;
+  uint64_t cq = 0;  // 0x80808080 - q mod 2^32 (zero-extended), the twist's digit offset
   v4i opA[4], opB[4];
   uint2 tw[4];
   uint2 pt[4][4];  // pass 1: post-twist per set and register
@@ -353,6 +370,8 @@ fs_pass(const FsTable tab) {
       const PassTables* P = kFirst ? L.pass1 : L.pass2;
       q = L.q;
       qneg = L.qneg;
+      nq = 0u - q;
+      cq = (uint32_t)(0x80808080u - q);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         opA[j] = *(const v4i*)&P->opA[j][lane][0];
@@ -432,7 +451,7 @@ fs_pass(const FsTable tab) {
           v4i z;
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            z[j] = (int)twist_digits<kBigQ>(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j], q);
+            z[j] = (int)twist_digits<kBigQ>(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j], q, nq, cq);
           const v4i b0 = mfma(opB[0], z, bias);
           const v4i b1 = mfma(opB[1], z, zero);
           const v4i b2 = mfma(opB[2], z, bias);
@@ -451,10 +470,10 @@ fs_pass(const FsTable tab) {
           // four lane groups write disjoint banks
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            gather[(4 * g + j) * 64 + 16 * (sg ^ g) + i16] = twist_digits<kBigQ>(y[j], pt[sg][j], q);
+            gather[(4 * g + j) * 64 + 16 * (sg ^ g) + i16] = twist_digits<kBigQ>(y[j], pt[sg][j], q, nq, cq);
         } else if (kFirst) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) out[st_off[j] + 16 * sg] = twist_digits<kBigQ>(y[j], pt[sg][j], q);
+          for (int j = 0; j < 4; ++j) out[st_off[j] + 16 * sg] = twist_digits<kBigQ>(y[j], pt[sg][j], q, nq, cq);
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
