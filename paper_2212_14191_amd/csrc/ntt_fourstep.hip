@@ -109,18 +109,6 @@ __device__ __forceinline__ v4i mfma(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
 
-// Fusion and one Montgomery step: V 2^{-32} mod q, in [0, q + 2^17).
-// (V + m q) is a multiple of 2^32 below 2^64, so its high word is exact
-// (one v_mad_u64_u32).
-__device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, uint32_t q,
-                                              uint32_t qneg) {
-  const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
-  const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
-  const uint64_t V = ((uint64_t)hi << 16) + lo;
-  const uint32_t m = (uint32_t)V * qneg;
-  return (uint32_t)(((uint64_t)m * q + V) >> 32);
-}
-
 // 64-bit a b + c as one v_mad_u64_u32 (the carry-out is discarded).  Used
 // where only the low word is needed, which the compiler would otherwise
 // split into a 32-bit multiply and an add.
@@ -128,6 +116,18 @@ __device__ __forceinline__ uint64_t mad_u64(uint32_t a, uint32_t b, uint64_t c) 
   uint64_t d, carry;
   asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=&v"(d), "=s"(carry) : "v"(a), "v"(b), "v"(c));
   return d;
+}
+
+// Fusion and one Montgomery step: V 2^{-32} mod q, in [0, q + 2^17).
+// (V + m q) is a multiple of 2^32 below 2^64, so its high word is exact
+// (one v_mad_u64_u32).
+__device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, uint32_t q,
+                                              uint32_t qneg) {
+  const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
+  const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
+  const uint64_t V = mad_u64(hi, 0x10000u, lo);
+  const uint32_t m = (uint32_t)V * qneg;
+  return (uint32_t)(((uint64_t)m * q + V) >> 32);
 }
 
 // Twist (Shoup, t = {w, companion}) and re-slice into digits; r < 2^32.
