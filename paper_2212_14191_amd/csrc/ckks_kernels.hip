@@ -192,9 +192,9 @@ __device__ __forceinline__ uint32_t conv_fuse(int c0, int c1, int c2, int c3, ui
   const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
   const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
   const uint64_t V = ((uint64_t)hi << 16) + lo;
-  const uint32_t vlo = (uint32_t)V, vhi = (uint32_t)(V >> 32);
-  const uint32_t m = vlo * qneg;
-  return reduce_once(vhi + __umulhi(m, q) + (vlo != 0u), q);
+  const uint32_t m = (uint32_t)V * qneg;
+  // V + m q is a multiple of 2^32 below 2^64: its high word is exact
+  return reduce_once((uint32_t)(((uint64_t)m * q + V) >> 32), q);
 }
 
 // The per-target constants (A operands, moduli, Montgomery and offset
