@@ -54,7 +54,7 @@ typedef enum {
                                  INT8 matrix-core contractions over byte
                                  slices (Sec. III-C, Eq. 9, Eq. 10) */
   TFHE_NTT_FOURSTEP_VALU = 3  /* the same four-step passes with each 16 x 16
-                                 matrix product on the vector ALUs, 64-bit
+                                 matrix product on the vector ALUs, 96-bit
                                  accumulation and one reduction per output
                                  (Sec. III-B, Eq. 7 to Eq. 9); N = 2^16 only,
                                  tfhe_ntt_fwd / tfhe_ntt_inv only; never

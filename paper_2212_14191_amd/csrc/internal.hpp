@@ -36,8 +36,12 @@ struct PassTables {
 // Plain matrices of one 256-point pass (16 x 16 split) for the vector-ALU
 // GEMM variant, as Shoup pairs {w, companion}: level A WA[u][s], twist
 // T[s][v], level B WB[t][v].
+// Vector-ALU variant: the two 16-point matrices in Montgomery form with
+// R = 2^64 (W 2^64 mod q), stored output-major (WA[s][u], WB[t][v]), and the
+// twist as Shoup pairs T[s][v].
 struct CoPass {
-  uint2 WA[16][16], T[16][16], WB[16][16];
+  uint32_t WA[16][16], WB[16][16];
+  uint2 T[16][16];
 };
 
 // Device-side description of one limb for the four-step kernels.

@@ -610,17 +610,34 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 // the general-purpose cores, one modular reduction per output), N = 2^16.
 // Same passes, tables, work items and data movement as the matrix-core
 // kernel (narrow items); each 16-point level is a 16 x 16 matrix product in
-// which a thread forms one output from 16 lazy Shoup products (each in
-// [0, 2q)) summed in 64 bits and reduced once ("reduce every 16").
+// which a thread forms one output from 16 full products of canonical
+// residues summed in 96 bits and reduced once by two Montgomery steps
+// against matrices stored as W 2^64 mod q ("reduce every 16").
 //   level A: thread (v, col) computes Y[s][v] = T[s][v] sum_u WA[u][s] x[16u+v]
 //   level B: thread (s, col) computes out[s+16t] = sum_v WB[t][v] Y[s][v]
 // Level-A results go through LDS at (col 16 + s) 17 + v, conflict-free for
 // both access patterns.
-__device__ __forceinline__ uint32_t reduce36(uint64_t acc, uint32_t q, uint2 one, uint2 two32) {
-  // acc < 32 q: lo mod q (Shoup by 1) plus hi 2^32 mod q (Shoup by 2^32 mod q)
-  const uint32_t lo = reduce_once(mul_shoup_lazy((uint32_t)acc, one.x, one.y, q), q);
-  const uint32_t hi = mul_shoup((uint32_t)(acc >> 32), two32.x, two32.y, q);
-  return add_mod(lo, hi, q);
+// One multiply-accumulate step of a 96-bit sum: acc + a b as one
+// v_mad_u64_u32 whose carry-out (through VCC) is added into k.
+__device__ __forceinline__ uint64_t mac96(uint32_t a, uint32_t b, uint64_t acc, uint32_t& k) {
+  uint64_t d;
+  asm("v_mad_u64_u32 %0, vcc, %2, %3, %4\n\tv_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
+      : "=&v"(d), "+v"(k)
+      : "v"(a), "v"(b), "v"(acc)
+      : "vcc");
+  return d;
+}
+
+// S 2^{-64} mod q in [0, q) for S = k 2^64 + acc < 2^67 (sixteen products of
+// residues below 2^31): two Montgomery steps.  The first leaves
+// T = (S + m1 q) / 2^32 < 2^36, the second (T + m2 q) / 2^32 < q + 16.
+__device__ __forceinline__ uint32_t redc96(uint64_t acc, uint32_t k, uint32_t q, uint32_t qneg) {
+  const uint32_t m1 = (uint32_t)acc * qneg;
+  const uint64_t t = mac96(m1, q, acc, k);  // low word 0
+  const uint32_t th = (uint32_t)(t >> 32);
+  const uint32_t m2 = th * qneg;
+  const uint32_t u = (uint32_t)(mad_u64(m2, q, ((uint64_t)k << 32) | th) >> 32);
+  return reduce_once(u, q);
 }
 
 template <bool kFirst>
@@ -630,7 +647,7 @@ co_pass(const FsTable tab) {
   constexpr int kCoStages = 2;  // one item ahead: leaves LDS for three workgroups per CU
   __shared__ __attribute__((aligned(16))) uint32_t ring[kCoStages * G::tile];
   __shared__ uint32_t ybuf[16 * 16 * 17];
-  __shared__ uint2 mats[512];  // WA[u][s] then WB[t][v] of the current limb (broadcast reads)
+  __shared__ __attribute__((aligned(16))) uint32_t mats[512];  // WA[s][u] then WB[t][v] (broadcast reads)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lo16 = tid & 15, col = tid >> 4;  // level A: v = lo16; level B: s = lo16
   const Walk walk = make_walk(tab.total, tab.ipp_log);
@@ -655,8 +672,7 @@ co_pass(const FsTable tab) {
 
   const FourStepLimb* cur_limb = nullptr;
   const CoPass* M = nullptr;
-  uint32_t q = 0;
-  uint2 one = make_uint2(0, 0), two32 = one;
+  uint32_t q = 0, qneg = 0;
   uint2 tv[16], post[16];  // T[s][v] of this thread's v; post-twist of (col, s + 16 t)
   int st = 0;
   uint32_t n = 0;
@@ -667,12 +683,10 @@ co_pass(const FsTable tab) {
       const FourStepLimb L = *limb;
       M = kFirst ? L.co1 : L.co2;
       q = L.q;
+      qneg = L.qneg;
       lds_barrier();  // every wave is done with the previous limb's matrices
       mats[tid] = M->WA[tid >> 4][tid & 15];
       mats[256 + tid] = M->WB[tid >> 4][tid & 15];
-      one = make_uint2(1, shoup_companion(1, q));
-      const uint32_t r32 = (uint32_t)((1ull << 32) % q);
-      two32 = make_uint2(r32, shoup_companion(r32, q));
 #pragma unroll
       for (int s2 = 0; s2 < 16; ++s2) tv[s2] = M->T[s2][lo16];
       if (kFirst) {
@@ -696,12 +710,16 @@ co_pass(const FsTable tab) {
 #pragma unroll
     for (int s2 = 0; s2 < 16; ++s2) {
       uint64_t acc = 0;
+      uint32_t k = 0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const uint2 w = mats[u * 16 + s2];
-        acc += mul_shoup_lazy(x[u], w.x, w.y, q);
+      for (int u4 = 0; u4 < 4; ++u4) {
+        const uint4 w = *(const uint4*)(mats + s2 * 16 + 4 * u4);
+        acc = mac96(x[4 * u4], w.x, acc, k);
+        acc = mac96(x[4 * u4 + 1], w.y, acc, k);
+        acc = mac96(x[4 * u4 + 2], w.z, acc, k);
+        acc = mac96(x[4 * u4 + 3], w.w, acc, k);
       }
-      ybuf[(col * 16 + s2) * 17 + lo16] = mul_shoup(reduce36(acc, q, one, two32), tv[s2].x, tv[s2].y, q);
+      ybuf[(col * 16 + s2) * 17 + lo16] = mul_shoup(redc96(acc, k, q, qneg), tv[s2].x, tv[s2].y, q);
     }
     lds_barrier();
     // level B
@@ -712,12 +730,16 @@ co_pass(const FsTable tab) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
       uint64_t acc = 0;
+      uint32_t k = 0;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const uint2 w = mats[256 + t * 16 + v];
-        acc += mul_shoup_lazy(y[v], w.x, w.y, q);
+      for (int v4 = 0; v4 < 4; ++v4) {
+        const uint4 w = *(const uint4*)(mats + 256 + t * 16 + 4 * v4);
+        acc = mac96(y[4 * v4], w.x, acc, k);
+        acc = mac96(y[4 * v4 + 1], w.y, acc, k);
+        acc = mac96(y[4 * v4 + 2], w.z, acc, k);
+        acc = mac96(y[4 * v4 + 3], w.w, acc, k);
       }
-      const uint32_t r = reduce36(acc, q, one, two32);
+      const uint32_t r = redc96(acc, k, q, qneg);
       if (kFirst) {
         // post-twist, tiled store: block t, column c0 + col, word s
         out[t * 16 * S + (c0 + col) * 16 + lo16] = mul_shoup(r, post[t].x, post[t].y, q);

@@ -177,11 +177,12 @@ struct FsHostLimb {
 };
 
 static void co_pass(CoPass& c, const Mat16& WA, const Mat16& T, const Mat16& WB, uint32_t q) {
+  const uint32_t r32 = (uint32_t)((1ull << 32) % q), r64 = mulm(r32, r32, q);
   for (int a = 0; a < 16; ++a)
     for (int b = 0; b < 16; ++b) {
-      c.WA[a][b] = make_uint2(WA[a][b], shoup_companion(WA[a][b], q));
+      c.WA[b][a] = mulm(WA[a][b], r64, q);  // WA is [u][s]: stored [s][u]
       c.T[a][b] = make_uint2(T[a][b], shoup_companion(T[a][b], q));
-      c.WB[a][b] = make_uint2(WB[a][b], shoup_companion(WB[a][b], q));
+      c.WB[a][b] = mulm(WB[a][b], r64, q);  // [t][v]
     }
 }
 
