@@ -18,6 +18,7 @@ scheduler with a CPU backend.
 """
 import collections
 import concurrent.futures
+import heapq
 import threading
 import time
 
@@ -28,7 +29,7 @@ HMULT, ROTATE = 0, 1
 
 class Request:
     __slots__ = ("op", "log_n", "level", "galois", "ct_a", "ct_b", "future", "t_submit", "t_done",
-                 "deadline")
+                 "deadline", "ready")
 
     def __init__(self, op, log_n, level, galois, ct_a, ct_b, timeout_s):
         self.op, self.log_n, self.level, self.galois = op, log_n, level, galois
@@ -37,6 +38,7 @@ class Request:
         self.t_submit = time.perf_counter()
         self.t_done = None
         self.deadline = None if timeout_s is None else self.t_submit + timeout_s
+        self.ready = None  # backend-specific readiness marker of the inputs
 
     @property
     def key(self):
@@ -53,6 +55,8 @@ class Server:
         self.max_batch = min(int(max_batch), getattr(backend, "max_batch", int(max_batch)))
         self.poll_s = poll_s
         self._pending = collections.OrderedDict()  # id -> Request (FIFO)
+        self._by_key = {}                           # batching key -> deque of ids (FIFO)
+        self._deadlines = []                        # heap of (deadline, id)
         self._inflight = []                         # (handle, requests, nbytes, slot)
         self._free_slots = list(range(self.slots))
         self._used = 0
@@ -78,10 +82,16 @@ class Server:
         if need > self.budget:
             req.future.set_exception(MemoryError(f"request needs {need} B > budget {self.budget} B"))
             return req.future
+        prepare = getattr(self.backend, "prepare", None)
+        if prepare is not None:  # e.g. mark when the inputs are ready (caller's thread)
+            prepare(req)
         with self._lock:
             if self._t0 is None:
                 self._t0 = req.t_submit
             self._pending[self._next_id] = req
+            self._by_key.setdefault(req.key, collections.deque()).append(self._next_id)
+            if req.deadline is not None:
+                heapq.heappush(self._deadlines, (req.deadline, self._next_id))
             self._next_id += 1
             self._lock.notify()
         return req.future
@@ -124,18 +134,42 @@ class Server:
         self._thread.join()
 
     # ------------------------------------------------------------ scheduler
+    def _expired(self, r, now):
+        return r.future.cancelled() or (r.deadline is not None and now > r.deadline)
+
+    def _drop(self, rid):
+        """Remove a cancelled or timed-out request from the queue."""
+        r = self._pending.pop(rid)
+        q = self._by_key[r.key]
+        q.remove(rid)
+        if not q:
+            del self._by_key[r.key]
+        if not r.future.cancelled():
+            r.future.set_exception(TimeoutError("request timed out in the queue"))
+
     def _form_batch(self):
-        """Oldest pending request plus compatible ones, within the budget."""
+        """Oldest pending request plus compatible ones, within the budget.
+        Cost O(batch): requests are indexed by batching key, time-outs come
+        off a deadline heap, and cancellations are dropped when a candidate
+        is taken."""
         now = time.perf_counter()
-        for rid in [rid for rid, r in self._pending.items() if r.future.cancelled() or
-                    (r.deadline is not None and now > r.deadline)]:
-            r = self._pending.pop(rid)
-            if not r.future.cancelled():
-                r.future.set_exception(TimeoutError("request timed out in the queue"))
+        while self._deadlines and self._deadlines[0][0] < now:
+            _, rid = heapq.heappop(self._deadlines)
+            if rid in self._pending:
+                self._drop(rid)
+        while self._pending:
+            hid, head = next(iter(self._pending.items()))
+            if not self._expired(head, now):
+                break
+            self._drop(hid)
         if not self._pending:
             return None
-        head = next(iter(self._pending.values()))
-        ids = [rid for rid, r in self._pending.items() if r.key == head.key][: self.max_batch]
+        ids = []
+        for rid in self._by_key[head.key]:
+            if len(ids) == self.max_batch:
+                break
+            if not self._expired(self._pending[rid], now):
+                ids.append(rid)
         while ids:
             need = self.backend.nbytes(head.op, head.log_n, head.level, len(ids))
             if self._used + need <= self.budget:
@@ -174,6 +208,11 @@ class Server:
                         break
                     ids, nbytes = fb
                     reqs = [self._pending.pop(rid) for rid in ids]
+                    q = self._by_key[reqs[0].key]
+                    for rid in ids:  # the batch is a FIFO prefix of its key's live ids
+                        q.remove(rid)
+                    if not q:
+                        del self._by_key[reqs[0].key]
                     for r in reqs:
                         r.future.set_running_or_notify_cancel()
                     slot = self._free_slots.pop()
@@ -215,12 +254,28 @@ class GpuBackend:
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         # completion events, one per slot (a slot runs one batch at a time)
         self.events = [torch.cuda.Event() for _ in range(slots)]
+        self._wsb = {}  # (log_n, level, batch) -> workspace bytes
         # one workspace per slot, grown to the largest batch it has run (a
         # slot's next batch starts only after its previous one completed)
         self.ws = [None] * slots
 
+    def prepare(self, req):
+        """Called in the submitting thread: an event on its current stream
+        marks when the request's inputs are ready."""
+        st = self.torch.cuda.current_stream()
+        ev = self.torch.cuda.Event()
+        ev.record(st)
+        req.ready = (st.cuda_stream, ev)
+
+    def _ws_bytes(self, log_n, level, batch):
+        k = (log_n, level, batch)
+        b = self._wsb.get(k)
+        if b is None:
+            b = self._wsb[k] = max(self.ctx[log_n].workspace_bytes(level, batch), 256)
+        return b
+
     def _workspace(self, slot, ctx, level, batch):
-        need = max(ctx.workspace_bytes(level, batch), 256)
+        need = self._ws_bytes(ctx.log_n, level, batch)
         w = self.ws[slot]
         if w is None or w.numel() < need:
             w = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
@@ -243,7 +298,7 @@ class GpuBackend:
         n = 1 << log_n
         ct = 2 * level * batch * n * 4
         inputs = 2 * ct if op == HMULT else ct
-        return inputs + ct + self.ctx[log_n].workspace_bytes(level, batch)
+        return inputs + ct + self._ws_bytes(log_n, level, batch)
 
     def launch(self, slot, reqs):
         torch = self.torch
@@ -251,7 +306,19 @@ class GpuBackend:
         ctx = self.ctx[r0.log_n]
         B, level, n = len(reqs), r0.level, 1 << r0.log_n
         s = self.streams[slot]
-        s.wait_stream(torch.cuda.current_stream())
+        # inputs ready: the latest submission event of each submitting stream
+        # (events on one stream complete in order)
+        latest = {}
+        for r in reqs:
+            if r.ready is not None:
+                latest[r.ready[0]] = r.ready[1]
+            else:
+                latest[None] = None
+        for key, ev in latest.items():
+            if ev is None:
+                s.wait_stream(torch.cuda.current_stream())
+            else:
+                s.wait_event(ev)
         with torch.cuda.stream(s):
             a = self._stage(reqs, "ct_a", level, n)
             out = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
