@@ -62,8 +62,8 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
 
 // ModUp conversion of digit [d0, d0 + nd) on the matrix cores: every
 // extended-basis position outside the digit, in launches of <= 32 targets.
-static hipError_t modup_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* x, uint32_t* up, uint32_t key_idx,
-                             uint32_t d0, uint32_t nd, uint32_t level, uint64_t plane, hipStream_t s) {
+static void modup_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* x, uint32_t* up, uint32_t key_idx,
+                       uint32_t d0, uint32_t nd, uint32_t level, uint64_t plane, ConvQueue& cq) {
   ConvArgs a;
   a.in = x + (uint64_t)d0 * plane;
   a.out = up;
@@ -83,17 +83,16 @@ static hipError_t modup_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* x, uint32
     a.out_k[a.nout] = c->h_up_k[(size_t)key_idx * (c->L + c->K) + t];
     a.a_tab[a.nout] = c->d_up_mfma + ((size_t)key_idx * (c->L + c->K) + t) * 32;
     if (++a.nout == kConvMaxOut) {
-      hipError_t e = launch_conv_mfma(a, c->plan->num_cus, K_MODUP, s);
-      if (e != hipSuccess) return e;
+      cq.q.push_back(a);
       a.nout = 0;
     }
   }
-  return a.nout ? launch_conv_mfma(a, c->plan->num_cus, K_MODUP, s) : hipSuccess;
+  if (a.nout) cq.q.push_back(a);
 }
 
 // ModDown conversion of the K special limbs to the level q-limbs.
-static hipError_t moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp, uint32_t* conv,
-                                    uint32_t level, uint64_t plane, hipStream_t s) {
+static void moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp, uint32_t* conv,
+                              uint32_t level, uint64_t plane, ConvQueue& cq) {
   ConvArgs a;
   a.in = tp;
   a.out = conv;
@@ -111,12 +110,11 @@ static hipError_t moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp
     a.out_k[a.nout] = c->h_dn_k[i];
     a.a_tab[a.nout] = c->d_dn_mfma + (size_t)i * 32;
     if (++a.nout == kConvMaxOut) {
-      hipError_t e = launch_conv_mfma(a, c->plan->num_cus, K_MD_CONV, s);
-      if (e != hipSuccess) return e;
+      cq.q.push_back(a);
       a.nout = 0;
     }
   }
-  return a.nout ? launch_conv_mfma(a, c->plan->num_cus, K_MD_CONV, s) : hipSuccess;
+  if (a.nout) cq.q.push_back(a);
 }
 
 // Key switching of d (NTT domain, [level][B][N]) with keys [dnum][2][L+K][N]
@@ -144,14 +142,16 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   // Dcomp + ModUp of every digit, then one fused NTT of all converted limbs:
   // the q-limbs before and after the digit, and the p-limbs
   std::vector<NttUnit> fwd;
+  ConvQueue cq;  // the matrix-core conversions of all digits, launched together
   for (uint32_t j = 0; j < digits; ++j) {
     const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
     const uint32_t key_idx = d0 + nd - 1;
     uint32_t* upj = up + (uint64_t)j * ext * plane;
-    if ((e = mfma_conv ? modup_mfma(c, x, upj, key_idx, d0, nd, level, plane, s)
-                       : launch_modup(x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
-                                      c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd,
-                                      level, c->L, c->K, batch, c->n, s)) != hipSuccess)
+    if (mfma_conv)
+      modup_mfma(c, x, upj, key_idx, d0, nd, level, plane, cq);
+    else if ((e = launch_modup(x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
+                               c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
+                               c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
     uint32_t* after = upj + (uint64_t)(d0 + nd) * plane;
     uint32_t* pl = upj + (uint64_t)level * plane;
@@ -159,6 +159,7 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
     if (level > d0 + nd) fwd.push_back(NttUnit{p, false, after, after, d0 + nd, level - d0 - nd, batch});
     fwd.push_back(NttUnit{p, false, pl, pl, c->L, c->K, batch});
   }
+  if ((e = cq.flush(p->num_cus, K_MODUP, s)) != hipSuccess) return e;
   if ((e = ntt_units(p, fwd, nws, s)) != hipSuccess) return e;
   uint32_t* a0 = acc;
   uint32_t* a1 = acc + (uint64_t)ext * plane;
@@ -173,10 +174,12 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
                      nws, s)) != hipSuccess)
     return e;
   for (int comp = 0; comp < 2; ++comp)
-    if ((e = mfma_conv ? moddown_conv_mfma(c, comp ? tp1 : tp, comp ? conv1 : conv, level, plane, s)
-                       : launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
-                                             c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
+    if (mfma_conv)
+      moddown_conv_mfma(c, comp ? tp1 : tp, comp ? conv1 : conv, level, plane, cq);
+    else if ((e = launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
+                                      c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
+  if ((e = cq.flush(p->num_cus, K_MD_CONV, s)) != hipSuccess) return e;
   if (p->algo == TFHE_NTT_FOURSTEP_MFMA) {
     // the transform's second pass finishes ModDown in its store epilogue:
     // out (+)= (acc - NTT(conv)) P^{-1}

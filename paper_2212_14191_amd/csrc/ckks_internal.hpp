@@ -69,7 +69,19 @@ hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint3
                                 const ModConst* mods, const uint2* pinv, uint32_t level,
                                 uint32_t batch, uint32_t n, bool accumulate, hipStream_t s,
                                 KernelId id = K_MD_FINAL);
-hipError_t launch_conv_mfma(const ConvArgs& a, uint32_t num_cus, KernelId id, hipStream_t s);
+// Several conversions of one plane size in one launch (blockIdx.y selects).
+constexpr int kConvPerLaunch = 3;
+struct ConvSet {
+  uint32_t count;
+  ConvArgs a[kConvPerLaunch];
+};
+static_assert(sizeof(ConvSet) <= 4096, "a ConvSet is passed as a kernel argument");
+hipError_t launch_conv_mfma(const ConvSet& set, uint32_t num_cus, KernelId id, hipStream_t s);
+// Collects conversions and launches them kConvPerLaunch at a time.
+struct ConvQueue {
+  std::vector<ConvArgs> q;
+  hipError_t flush(uint32_t num_cus, KernelId id, hipStream_t s);
+};
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 

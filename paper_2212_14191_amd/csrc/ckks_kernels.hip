@@ -202,7 +202,8 @@ __device__ __forceinline__ uint32_t conv_fuse(int c0, int c1, int c2, int c3, ui
 // resident waves per SIMD for latency hiding; targets beyond nout have zero
 // operands and modulus 1 (their results are not stored).
 __global__ void __launch_bounds__(kThreads, 4)
-conv_mfma_kernel(const ConvArgs a) {
+conv_mfma_kernel(const ConvSet set) {
+  const ConvArgs& a = set.a[blockIdx.y];
   __shared__ __attribute__((aligned(16))) uint32_t s_a[kConvMaxOut * 32];
   __shared__ __attribute__((aligned(16))) uint32_t s_q[kConvMaxOut], s_qn[kConvMaxOut], s_k[kConvMaxOut];
   for (int i = threadIdx.x; i < kConvMaxOut * 32; i += kThreads) {
@@ -304,15 +305,27 @@ rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
 
 }  // namespace
 
-hipError_t launch_conv_mfma(const ConvArgs& a, uint32_t num_cus, KernelId id, hipStream_t s) {
-  const uint64_t chunks = a.plane / 64;
+hipError_t launch_conv_mfma(const ConvSet& set, uint32_t num_cus, KernelId id, hipStream_t s) {
+  const uint64_t chunks = set.a[0].plane / 64;  // every conversion of a set has one plane size
   const uint64_t blocks = (chunks + 3) / 4;  // 4 waves per block, one chunk each per round
   // about one resident round (four workgroups per CU): each wave then
   // converts several chunks with its next inputs in flight
   const uint64_t resident = 4ull * (num_cus ? num_cus : 1);
   const uint32_t grid = (uint32_t)(blocks < resident ? (blocks ? blocks : 1) : resident);
-  TFHE_TIMED(id, s, hipLaunchKernelGGL(conv_mfma_kernel, dim3(grid), dim3(kThreads), 0, s, a));
+  TFHE_TIMED(id, s, hipLaunchKernelGGL(conv_mfma_kernel, dim3(grid, set.count), dim3(kThreads), 0, s, set));
   return hipGetLastError();
+}
+
+hipError_t ConvQueue::flush(uint32_t num_cus, KernelId id, hipStream_t s) {
+  for (size_t i = 0; i < q.size(); i += kConvPerLaunch) {
+    ConvSet set{};
+    set.count = (uint32_t)std::min<size_t>(kConvPerLaunch, q.size() - i);
+    for (uint32_t k = 0; k < set.count; ++k) set.a[k] = q[i + k];
+    hipError_t e = launch_conv_mfma(set, num_cus, id, s);
+    if (e != hipSuccess) return e;
+  }
+  q.clear();
+  return hipSuccess;
 }
 
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
