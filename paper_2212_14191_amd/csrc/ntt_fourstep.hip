@@ -37,8 +37,12 @@
 // sets of vectors; a set fills the 16 rows of one MFMA tile with 16 / r
 // vectors.  The intermediate array between the passes is tiled: block kb of
 // 16 consecutive pass-1 outputs holds, for every pass-1 column c, the 16
-// words (kb, c) contiguously, so pass 1 writes runs of whole lines and pass 2
-// reads each item as one contiguous block.  Pass 2 writes its canonical
+// words (kb, c) contiguously, so pass 1 writes runs of whole lines (the wide
+// first pass gathers each wave's results in a private LDS buffer and stores
+// 256-byte runs) and pass 2 reads each item as one contiguous block.  The
+// fusion's Montgomery step, the twist and the digit offset use 64-bit
+// multiply-adds (v_mad_u64_u32 issues at the full VALU rate on gfx950), which
+// keeps the passes close to the memory-only rate.  Pass 2 writes its canonical
 // results back in natural order through the LDS stage it has just consumed;
 // for forward transforms it can instead finish a ModDown / RESCALE step in
 // that store (out (+)= (acc - y) m).

@@ -187,3 +187,24 @@ def test_rotations_by_different_amounts_share_a_batch(world):
     assert sizes == [1, 4]
     for (op, lv, a, b, g), out in zip(reqs, got):
         assert np.array_equal(out, ckks.rotate(pr, a, rks[g], g, lv))
+
+
+class FailingBackend(OracleBackend):
+    """Raises on every launch at level 4."""
+
+    def launch(self, slot, reqs):
+        if reqs[0].level == 4:
+            raise RuntimeError("launch failed")
+        return super().launch(slot, reqs)
+
+
+def test_launch_failure_surfaces_and_frees_the_slot(world):
+    pr, evk, rks, _, cts = world
+    srv = Server(FailingBackend(pr, evk, rks), mem_budget_bytes=1 << 30, slots=1, max_batch=4)
+    bad = srv.submit(HMULT, 6, 4, cts[(4, 0)], cts[(4, 1)])
+    good = srv.submit(HMULT, 6, 2, cts[(2, 0)], cts[(2, 1)])
+    with pytest.raises(RuntimeError):
+        bad.result(timeout=10)
+    out = good.result(timeout=10)   # the slot was freed and reused
+    srv.close()
+    assert np.array_equal(out, ckks.hmult(pr, cts[(2, 0)], cts[(2, 1)], evk, 2))
