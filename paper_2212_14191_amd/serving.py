@@ -247,11 +247,14 @@ class GpuBackend:
 
     def __init__(self, contexts, relin_keys, rot_keys, slots=4):
         import torch
+        from . import tfhe
+        self.tfhe = tfhe
         self.torch = torch
         self.ctx = contexts          # log_n -> CkksContext
         self.evk = relin_keys        # log_n -> tensor
         self.rk = rot_keys           # (log_n, galois) -> tensor
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self._sptr = [s.cuda_stream for s in self.streams]  # raw HIP stream handles
         # completion events, one per slot (a slot runs one batch at a time)
         self.events = [torch.cuda.Event() for _ in range(slots)]
         self._wsb = {}  # (log_n, level, batch) -> workspace bytes
@@ -260,8 +263,19 @@ class GpuBackend:
         self.ws = [None] * slots
 
     def prepare(self, req):
-        """Called in the submitting thread: an event on its current stream
-        marks when the request's inputs are ready."""
+        """Called in the submitting thread: checks the inputs (so that the
+        scheduler can pass raw pointers) and records an event on the
+        submitter's current stream that marks when they are ready."""
+        ctx = self.ctx.get(req.log_n)
+        if ctx is None:
+            raise ValueError(f"no context for N = 2^{req.log_n}")
+        shape = (2, req.level, 1, ctx.n)
+        for t in ((req.ct_a, req.ct_b) if req.op == HMULT else (req.ct_a,)):
+            if (t.dtype != self.torch.int32 or not t.is_cuda or not t.is_contiguous()
+                    or t.numel() != 2 * req.level * ctx.n):
+                raise ValueError(f"ciphertexts must be contiguous int32 device tensors of {shape} elements")
+        if req.op == ROTATE and (req.log_n, req.galois) not in self.rk:
+            raise ValueError(f"no rotation key for Galois element {req.galois}")
         st = self.torch.cuda.current_stream()
         ev = self.torch.cuda.Event()
         ev.record(st)
@@ -319,23 +333,30 @@ class GpuBackend:
                 s.wait_stream(torch.cuda.current_stream())
             else:
                 s.wait_event(ev)
-        with torch.cuda.stream(s):
-            a = self._stage(reqs, "ct_a", level, n)
-            out = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
-            ws = self._workspace(slot, ctx, level, B)
-            if r0.op == HMULT:
-                bb = self._stage(reqs, "ct_b", level, n)
-                ctx.hmult(a, bb, self.evk[r0.log_n], level, out=out, ws=ws, stream=s)
+        # this thread only launches batches: allocations below belong to s
+        torch.cuda.set_stream(s)
+        a = self._stage(reqs, "ct_a", level, n)
+        out = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
+        ws = self._workspace(slot, ctx, level, B)
+        sp = self._sptr[slot]
+        # inputs were checked in prepare(): raw pointers into the C ABI
+        tfhe = self.tfhe
+        if r0.op == HMULT:
+            bb = self._stage(reqs, "ct_b", level, n)
+            tfhe._call("tfhe_hmult", ctx.handle, a.data_ptr(), bb.data_ptr(), out.data_ptr(),
+                       self.evk[r0.log_n].data_ptr(), level, B, ws.data_ptr(), ws.numel(), sp)
+        else:
+            bb = None
+            gal = [r.galois for r in reqs]
+            if all(g == gal[0] for g in gal):
+                tfhe._call("tfhe_rotate", ctx.handle, a.data_ptr(), out.data_ptr(),
+                           self.rk[(r0.log_n, r0.galois)].data_ptr(), r0.galois, level, B, ws.data_ptr(),
+                           ws.numel(), sp)
             else:
-                bb = None
-                gal = [r.galois for r in reqs]
-                if all(g == gal[0] for g in gal):
-                    ctx.rotate(a, self.rk[(r0.log_n, r0.galois)], r0.galois, level, out=out, ws=ws, stream=s)
-                else:
-                    ctx.rotate_multi(a, [self.rk[(r0.log_n, g)] for g in gal], gal, level, out=out, ws=ws,
-                                     stream=s)
-            ev = self.events[slot]
-            ev.record(s)
+                ctx.rotate_multi(a, [self.rk[(r0.log_n, g)] for g in gal], gal, level, out=out, ws=ws,
+                                 stream=s)
+        ev = self.events[slot]
+        ev.record(s)
         return {"event": ev, "out": out, "keep": (a, bb, ws), "B": B}
 
     def done(self, h):
