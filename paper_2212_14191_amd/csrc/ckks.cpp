@@ -511,8 +511,10 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
   hipStream_t s = (hipStream_t)stream;
   unsigned char* w = (unsigned char*)ws;
   uint32_t* r1 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
-  hipError_t e = frobenius_launch(ct_in, ct_out, galois_elt, level * batch, ctx->log_n, s);
-  if (e == hipSuccess) e = frobenius_launch(ct_in + plane, r1, galois_elt, level * batch, ctx->log_n, s);
+  GaloisSet gs{};
+  gs.batch = 1;
+  gs.g[0] = galois_elt;
+  hipError_t e = launch_frobenius_pair(ct_in, ct_out, ct_in + plane, r1, gs, level * batch, ctx->log_n, s);
   KeySet keys{};
   keys.count = 1;
   keys.k[0] = rotkey;
@@ -546,8 +548,7 @@ tfhe_status tfhe_rotate_multi(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t
   hipStream_t s = (hipStream_t)stream;
   unsigned char* w = (unsigned char*)ws;
   uint32_t* r1 = (uint32_t*)(w + ks_layout(ctx, level, batch).d2);
-  hipError_t e = frobenius_multi_launch(ct_in, ct_out, gs, level * batch, ctx->log_n, s);
-  if (e == hipSuccess) e = frobenius_multi_launch(ct_in + plane, r1, gs, level * batch, ctx->log_n, s);
+  hipError_t e = launch_frobenius_pair(ct_in, ct_out, ct_in + plane, r1, gs, level * batch, ctx->log_n, s);
   if (e == hipSuccess)
     e = key_switch(ctx, r1, keys, ct_out, ct_out + plane, true, false, level, batch, w, s);
   return hip_check(e, "rotate_multi");

@@ -82,6 +82,10 @@ struct ConvQueue {
   std::vector<ConvArgs> q;
   hipError_t flush(uint32_t num_cus, KernelId id, hipStream_t s);
 };
+// FrobeniusMap of both ciphertext components (in0 -> out0, in1 -> out1, each
+// [rows][N]) in one launch; row r uses gs.g[r % gs.batch].
+hipError_t launch_frobenius_pair(const uint32_t* in0, uint32_t* out0, const uint32_t* in1, uint32_t* out1,
+                                 const GaloisSet& gs, uint32_t rows, uint32_t log_n, hipStream_t s);
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 

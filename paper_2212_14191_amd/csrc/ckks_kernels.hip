@@ -281,6 +281,25 @@ conv_mfma_kernel(const ConvSet set) {
   }
 }
 
+// FrobeniusMap out_j = in_{pi(j)} of two arrays in one launch (the two
+// components of a ciphertext), with the Galois element of each row's batch
+// element.
+__global__ void __launch_bounds__(kThreads)
+frobenius_pair_kernel(const uint32_t* __restrict__ in0, uint32_t* __restrict__ out0,
+                      const uint32_t* __restrict__ in1, uint32_t* __restrict__ out1, const GaloisSet gs,
+                      uint64_t per, uint32_t log_n) {
+  const uint32_t n = 1u << log_n, mask2n = 2 * n - 1;
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < 2 * per;
+       i += (uint64_t)gridDim.x * kThreads) {
+    const bool second = i >= per;
+    const uint64_t k = second ? i - per : i;
+    const uint32_t j = (uint32_t)(k & (n - 1));
+    const uint32_t galois = gs.g[(uint32_t)((k >> log_n) % gs.batch)];
+    const uint32_t src = (((2 * j + 1) * galois) & mask2n) >> 1;
+    (second ? out1 : out0)[k] = (second ? in1 : in0)[(k - j) + src];
+  }
+}
+
 // RESCALE broadcast: t holds the two components' top limbs in the
 // coefficient domain, [2][B][N] in [0, q_top); u[c][i] = t[c] mod q_i for
 // i < top.  Every modulus exceeds 2^29 and t < 2^31 < 4 q_i, so two
@@ -326,6 +345,14 @@ hipError_t ConvQueue::flush(uint32_t num_cus, KernelId id, hipStream_t s) {
   }
   q.clear();
   return hipSuccess;
+}
+
+hipError_t launch_frobenius_pair(const uint32_t* in0, uint32_t* out0, const uint32_t* in1, uint32_t* out1,
+                                 const GaloisSet& gs, uint32_t rows, uint32_t log_n, hipStream_t s) {
+  const uint64_t per = (uint64_t)rows << log_n;
+  TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_pair_kernel, dim3(grid_for(2 * per)), dim3(kThreads), 0, s,
+                                           in0, out0, in1, out1, gs, per, log_n));
+  return hipGetLastError();
 }
 
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
