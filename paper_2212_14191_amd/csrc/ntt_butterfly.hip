@@ -65,6 +65,54 @@ __device__ __forceinline__ void gs_bfly(uint32_t* lds, uint32_t j, uint32_t t, u
   lds[j + t] = mul_shoup(sub_mod(u, v, q), w.x, w.y, q);
 }
 
+// Two consecutive stages per LDS round trip (radix-4 step) on the four
+// elements p, p + d, p + 2d, p + 3d (d in words).
+// Cooley-Tukey stages of strides 2d and d: (0,2), (1,3) with wa, then (0,1)
+// with wb0 and (2,3) with wb1.
+__device__ __forceinline__ void ct_bfly4(uint32_t* lds, uint32_t p, uint32_t d, uint2 wa, uint2 wb0, uint2 wb1,
+                                         uint32_t q) {
+  uint32_t x0 = lds[p], x1 = lds[p + d], x2 = lds[p + 2 * d], x3 = lds[p + 3 * d];
+  uint32_t v = mul_shoup(x2, wa.x, wa.y, q);
+  x2 = sub_mod(x0, v, q);
+  x0 = add_mod(x0, v, q);
+  v = mul_shoup(x3, wa.x, wa.y, q);
+  x3 = sub_mod(x1, v, q);
+  x1 = add_mod(x1, v, q);
+  v = mul_shoup(x1, wb0.x, wb0.y, q);
+  x1 = sub_mod(x0, v, q);
+  x0 = add_mod(x0, v, q);
+  v = mul_shoup(x3, wb1.x, wb1.y, q);
+  x3 = sub_mod(x2, v, q);
+  x2 = add_mod(x2, v, q);
+  lds[p] = x0;
+  lds[p + d] = x1;
+  lds[p + 2 * d] = x2;
+  lds[p + 3 * d] = x3;
+}
+
+// Gentleman-Sande stages of strides d and 2d: (0,1) with wa0 and (2,3) with
+// wa1, then (0,2), (1,3) with wb.
+__device__ __forceinline__ void gs_bfly4(uint32_t* lds, uint32_t p, uint32_t d, uint2 wa0, uint2 wa1, uint2 wb,
+                                         uint32_t q) {
+  uint32_t x0 = lds[p], x1 = lds[p + d], x2 = lds[p + 2 * d], x3 = lds[p + 3 * d];
+  uint32_t u = x0;
+  x0 = add_mod(u, x1, q);
+  x1 = mul_shoup(sub_mod(u, x1, q), wa0.x, wa0.y, q);
+  u = x2;
+  x2 = add_mod(u, x3, q);
+  x3 = mul_shoup(sub_mod(u, x3, q), wa1.x, wa1.y, q);
+  u = x0;
+  x0 = add_mod(u, x2, q);
+  x2 = mul_shoup(sub_mod(u, x2, q), wb.x, wb.y, q);
+  u = x1;
+  x1 = add_mod(u, x3, q);
+  x3 = mul_shoup(sub_mod(u, x3, q), wb.x, wb.y, q);
+  lds[p] = x0;
+  lds[p + d] = x1;
+  lds[p + 2 * d] = x2;
+  lds[p + 3 * d] = x3;
+}
+
 // ---------------------------------------------------------- single pass
 // item = polynomial of the unit
 __global__ void __launch_bounds__(kThreads) bf_single(const BfTable tab) {
@@ -80,20 +128,33 @@ __global__ void __launch_bounds__(kThreads) bf_single(const BfTable tab) {
   if (!U.inverse) {
     for (uint32_t i = threadIdx.x; i < n; i += kThreads) lds[i] = src[i];
     __syncthreads();
-    for (uint32_t m = 1, t = n >> 1; m < n; m <<= 1, t >>= 1) {
-      for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) {
-        uint32_t i = b / t, j = 2 * i * t + (b % t);
-        ct_bfly(lds, j, t, w[m + i], q);
+    uint32_t m = 1, t = n >> 1;
+    for (; t >= 2; m <<= 2, t >>= 2) {  // stages (m, t) and (2m, t/2)
+      for (uint32_t b = threadIdx.x; b < (n >> 2); b += kThreads) {
+        const uint32_t g = b / (t >> 1), e0 = 2 * g * t + b % (t >> 1);
+        ct_bfly4(lds, e0, t >> 1, w[m + g], w[2 * m + 2 * g], w[2 * m + 2 * g + 1], q);
       }
+      __syncthreads();
+    }
+    if (t == 1) {  // odd stage count: the last stage alone
+      for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) ct_bfly(lds, 2 * b, 1, w[m + b], q);
       __syncthreads();
     }
     for (uint32_t kk = threadIdx.x; kk < n; kk += kThreads) dst[kk] = lds[brev(kk, log_n)];
   } else {
     for (uint32_t kk = threadIdx.x; kk < n; kk += kThreads) lds[brev(kk, log_n)] = src[kk];
     __syncthreads();
-    for (uint32_t h = n >> 1, t = 1; h >= 1; h >>= 1, t <<= 1) {
+    uint32_t h = n >> 1, t = 1;
+    for (; 4 * t <= n; h >>= 2, t <<= 2) {  // stages (h, t) and (h/2, 2t)
+      for (uint32_t b = threadIdx.x; b < (n >> 2); b += kThreads) {
+        const uint32_t I = b / t, e0 = 4 * I * t + b % t;
+        gs_bfly4(lds, e0, t, w[h + 2 * I], w[h + 2 * I + 1], w[(h >> 1) + I], q);
+      }
+      __syncthreads();
+    }
+    if (t < n) {  // odd stage count: the last stage alone
       for (uint32_t b = threadIdx.x; b < (n >> 1); b += kThreads) {
-        uint32_t i = b / t, j = 2 * i * t + (b % t);
+        const uint32_t i = b / t, j = 2 * i * t + (b % t);
         gs_bfly(lds, j, t, w[h + i], q);
       }
       __syncthreads();
@@ -127,20 +188,38 @@ __global__ void __launch_bounds__(kThreads) bf_cols(const BfTable tab) {
   }
   __syncthreads();
   const uint32_t nb = (R / 2) * kBlk;  // butterflies per stage
+  const uint32_t nu = (R / 4) * kBlk;  // radix-4 units per pair of stages
   if (!U.inverse) {
-    for (uint32_t m = 1, tr = R / 2; m < R; m <<= 1, tr >>= 1) {
+    uint32_t m = 1, tr = R / 2;
+    for (; tr >= 2; m <<= 2, tr >>= 2) {  // stages (m, tr) and (2m, tr/2)
+      for (uint32_t b = threadIdx.x; b < nu; b += kThreads) {
+        const uint32_t c = b % kBlk, u = b / kBlk;
+        const uint32_t g = u / (tr >> 1), e0 = 2 * g * tr + u % (tr >> 1);
+        ct_bfly4(lds, e0 * kBlk + c, (tr >> 1) * kBlk, w[m + g], w[2 * m + 2 * g], w[2 * m + 2 * g + 1], q);
+      }
+      __syncthreads();
+    }
+    if (tr == 1) {  // odd stage count: the last stage alone
       for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        uint32_t c = b % kBlk, rb = b / kBlk;
-        uint32_t i = rb / tr, r = 2 * i * tr + (rb % tr);
-        ct_bfly(lds, r * kBlk + c, tr * kBlk, w[m + i], q);
+        const uint32_t c = b % kBlk, rb = b / kBlk;
+        ct_bfly(lds, 2 * rb * kBlk + c, kBlk, w[m + rb], q);
       }
       __syncthreads();
     }
   } else {
-    for (uint32_t h = R / 2, tr = 1; h >= 1; h >>= 1, tr <<= 1) {
+    uint32_t h = R / 2, tr = 1;
+    for (; 4 * tr <= R; h >>= 2, tr <<= 2) {  // stages (h, tr) and (h/2, 2tr)
+      for (uint32_t b = threadIdx.x; b < nu; b += kThreads) {
+        const uint32_t c = b % kBlk, u = b / kBlk;
+        const uint32_t I = u / tr, e0 = 4 * I * tr + u % tr;
+        gs_bfly4(lds, e0 * kBlk + c, tr * kBlk, w[h + 2 * I], w[h + 2 * I + 1], w[(h >> 1) + I], q);
+      }
+      __syncthreads();
+    }
+    if (tr < R) {  // odd stage count: the last stage alone
       for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        uint32_t c = b % kBlk, rb = b / kBlk;
-        uint32_t i = rb / tr, r = 2 * i * tr + (rb % tr);
+        const uint32_t c = b % kBlk, rb = b / kBlk;
+        const uint32_t i = rb / tr, r = 2 * i * tr + (rb % tr);
         gs_bfly(lds, r * kBlk + c, tr * kBlk, w[h + i], q);
       }
       __syncthreads();
@@ -186,26 +265,28 @@ __global__ void __launch_bounds__(kThreads) bf_rows(const BfTable tab) {
     }
   }
   __syncthreads();
-  const uint32_t nb = kBlk * kRow / 2;
+  // the 8 stages of a row of 256 run as 4 radix-4 steps; group g of stage
+  // (m, t) in row `row` uses twiddle m + row 256 / (2t) + g
+  const uint32_t nu = kBlk * kRow / 4;
   if (!inv) {
-    for (uint32_t m = R, t = kRow / 2; m < n; m <<= 1, t >>= 1) {
-      for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        uint32_t i = b / (kRow / 2), bb = b % (kRow / 2);
-        uint32_t row = brev(kBlk * rb + i, log_r);
-        uint32_t g = bb / t, j = 2 * g * t + (bb % t);
-        uint32_t grp = (row * kRow + j) / (2 * t);
-        ct_bfly(lds, i * kRow + j, t, w[m + grp], q);
+    for (uint32_t m = R, t = kRow / 2; t >= 2; m <<= 2, t >>= 2) {  // stages (m, t) and (2m, t/2)
+      for (uint32_t b = threadIdx.x; b < nu; b += kThreads) {
+        const uint32_t i = b / (kRow / 4), u = b % (kRow / 4);
+        const uint32_t row = brev(kBlk * rb + i, log_r);
+        const uint32_t g = u / (t >> 1), e0 = 2 * g * t + u % (t >> 1);
+        const uint32_t oa = m + row * (kRow / (2 * t)) + g, ob = 2 * m + row * (kRow / t) + 2 * g;
+        ct_bfly4(lds, i * kRow + e0, t >> 1, w[oa], w[ob], w[ob + 1], q);
       }
       __syncthreads();
     }
   } else {
-    for (uint32_t h = n / 2, t = 1; h >= R; h >>= 1, t <<= 1) {
-      for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        uint32_t i = b / (kRow / 2), bb = b % (kRow / 2);
-        uint32_t row = brev(kBlk * rb + i, log_r);
-        uint32_t g = bb / t, j = 2 * g * t + (bb % t);
-        uint32_t grp = (row * kRow + j) / (2 * t);
-        gs_bfly(lds, i * kRow + j, t, w[h + grp], q);
+    for (uint32_t h = n / 2, t = 1; 4 * t <= kRow; h >>= 2, t <<= 2) {  // stages (h, t) and (h/2, 2t)
+      for (uint32_t b = threadIdx.x; b < nu; b += kThreads) {
+        const uint32_t i = b / (kRow / 4), u = b % (kRow / 4);
+        const uint32_t row = brev(kBlk * rb + i, log_r);
+        const uint32_t I = u / t, e0 = 4 * I * t + u % t;
+        const uint32_t oa = h + row * (kRow / (2 * t)) + 2 * I, ob = (h >> 1) + row * (kRow / (4 * t)) + I;
+        gs_bfly4(lds, i * kRow + e0, t, w[oa], w[oa + 1], w[ob], q);
       }
       __syncthreads();
     }
