@@ -48,8 +48,8 @@ typedef enum {
   TFHE_NTT_AUTO = 0,          /* the library's choice (tuned table, else MFMA
                                  when available for N, else butterfly) */
   TFHE_NTT_BUTTERFLY = 1,     /* radix-2 Cooley-Tukey / Gentleman-Sande
-                                 butterflies on the vector ALUs (Sec. II-A,
-                                 Fig. 2) */
+                                 butterflies on the vector ALUs, two stages
+                                 per LDS round trip (Sec. II-A, Fig. 2) */
   TFHE_NTT_FOURSTEP_MFMA = 2, /* four-step NTT whose DFT stages are exact
                                  INT8 matrix-core contractions over byte
                                  slices (Sec. III-C, Eq. 9, Eq. 10) */

@@ -13,6 +13,9 @@
 // N  > 2^12: two passes over an R x 256 view (R = N/256): the stages with
 // butterfly stride >= 256 act within columns (pass A), the rest within rows
 // of 256 (pass B); the intermediate goes through the caller's workspace.
+// Stages run in pairs: each thread takes four elements through two radix-2
+// stages in registers between LDS round trips (a radix-4 step); an odd stage
+// count ends with one single stage.
 //
 // Every kernel walks a descriptor table, so one launch can cover transforms
 // of different N, moduli and direction (operation-level batching, Sec. III-D).
