@@ -46,20 +46,6 @@ frobenius_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, ui
   }
 }
 
-// The same map with the Galois element of each row's batch element.
-__global__ void __launch_bounds__(kThreads)
-frobenius_multi_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, const GaloisSet gs,
-                       uint64_t total, uint32_t log_n) {
-  const uint32_t n = 1u << log_n, mask2n = 2 * n - 1;
-  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
-       i += (uint64_t)gridDim.x * kThreads) {
-    const uint32_t j = (uint32_t)(i & (n - 1));
-    const uint32_t galois = gs.g[(uint32_t)((i >> log_n) % gs.batch)];
-    const uint32_t src = (((2 * j + 1) * galois) & mask2n) >> 1;
-    out[i] = in[(i - j) + src];
-  }
-}
-
 // out[l][b][i] = in[b][i] mod q_l for small signed integers in (-2^31, 2^31).
 __global__ void __launch_bounds__(kThreads)
 load_small_kernel(const ModConst* __restrict__ mods, const int32_t* __restrict__ in,
@@ -119,14 +105,6 @@ hipError_t frobenius_launch(const uint32_t* in, uint32_t* out, uint32_t galois, 
   const uint64_t total = (uint64_t)rows << log_n;
   TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, in, out,
                      galois, total, log_n));
-  return hipGetLastError();
-}
-
-hipError_t frobenius_multi_launch(const uint32_t* in, uint32_t* out, const GaloisSet& gs, uint32_t rows,
-                                  uint32_t log_n, hipStream_t s) {
-  const uint64_t total = (uint64_t)rows << log_n;
-  TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_multi_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s,
-                                           in, out, gs, total, log_n));
   return hipGetLastError();
 }
 

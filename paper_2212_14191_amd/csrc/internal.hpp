@@ -137,8 +137,6 @@ struct GaloisSet {
   uint32_t batch;
   uint32_t g[kMaxRotBatch];
 };
-hipError_t frobenius_multi_launch(const uint32_t* in, uint32_t* out, const GaloisSet& gs, uint32_t rows,
-                                  uint32_t log_n, hipStream_t s);
 
 // ---- per-kernel event timing (timing.cpp)
 enum KernelId {
