@@ -286,6 +286,62 @@ tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t*
                                uint32_t galois_elt, uint32_t limb_count, uint32_t batch,
                                tfhe_stream_t stream);
 
+/* ---------------------------------------------------------------- serving */
+
+/* Request dispatcher (the API layer of Sec. III-E with operation-level
+ * batching, Sec. III-D): callers submit single-ciphertext HMULT and HROTATE
+ * requests; a dispatcher thread groups requests of equal (operation, N,
+ * level) into batches of up to max_batch, runs each batch on one of `slots`
+ * streams with one batched tfhe_hmult / tfhe_rotate / tfhe_rotate_multi
+ * call, and reports each request's completion through tfhe_server_poll.
+ * The result of a request is exactly what that call computes for it alone.
+ *
+ * tfhe_server_create: pool is caller-owned device memory, 256-byte aligned,
+ * pool_bytes >= 256*slots, split evenly among the slots; it holds each
+ * batch's gathered inputs, outputs and workspace and must outlive the
+ * server.  The server belongs to the device current at creation.
+ *   slots in [1, 16]; max_batch in [1, TFHE_ROTATE_MULTI_MAX].
+ * Errors: TFHE_EINVAL, TFHE_ENOMEM (host), TFHE_EHIP. */
+typedef struct tfhe_server_s* tfhe_server;
+tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_batch, void* pool,
+                               size_t pool_bytes);
+
+/* Registers the context of ring dimension 2^ctx.log_n (replacing an
+ * earlier one of that N) and its relinearisation key evk (device, layout as
+ * for tfhe_hmult).  Both must outlive the server. */
+tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint32_t* evk);
+
+/* Registers the rotation key (device, layout as for tfhe_rotate) of Galois
+ * element galois_elt (odd, < 2N) for the context of N = 2^log_n. */
+tfhe_status tfhe_server_add_rotation_key(tfhe_server s, uint32_t log_n, uint32_t galois_elt,
+                                         const uint32_t* rotkey);
+
+/* Queues one request and returns at once.
+ *   op 0: HMULT of ct_a and ct_b (galois_elt ignored); op 1: HROTATE of
+ *     ct_a by galois_elt (ct_b ignored; ct_out must not alias ct_a).
+ *   ct_a, ct_b, ct_out: device [2][level][N], NTT domain, 16-byte aligned;
+ *     the inputs must stay unchanged and all three allocated until the
+ *     request completes.
+ *   The request waits for the work queued on `stream` before this call
+ *   (the inputs may still be in production there).
+ *   tag: the caller's identifier, returned by tfhe_server_poll.
+ * Errors (nothing queued): TFHE_EINVAL (no context for N, level out of
+ * [1, L], no rotation key for galois_elt, null or unaligned pointer),
+ * TFHE_ENOMEM (one request alone exceeds a slot's share of the pool),
+ * TFHE_EHIP. */
+tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint32_t level,
+                               const uint32_t* ct_a, const uint32_t* ct_b, uint32_t galois_elt,
+                               uint32_t* ct_out, uint64_t tag, tfhe_stream_t stream);
+
+/* Moves up to `max` completed requests into tags[] / status[] (host
+ * arrays) and returns how many.  status is TFHE_OK once the result is in
+ * ct_out (the device work has finished), else the error of its batch. */
+uint32_t tfhe_server_poll(tfhe_server s, uint64_t* tags, int32_t* status, uint32_t max);
+
+/* Waits for the batches in flight, then frees the server; requests not yet
+ * dispatched are dropped without completion. */
+tfhe_status tfhe_server_destroy(tfhe_server s);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Per-kernel timing.  While enabled, the library brackets every kernel it

@@ -1,0 +1,396 @@
+// Native request dispatcher for HMULT / HROTATE serving (the API layer of
+// Sec. III-E: requests are collected, grouped into batched kernel workflows
+// and dispatched; keys and ciphertexts stay resident in device memory).
+//
+// One dispatcher thread owns `slots` HIP streams.  Pending requests are
+// indexed by batching key (op, N, level); whenever a slot is free, the
+// oldest request and up to max_batch - 1 others of its key form a batch whose
+// staging buffers and workspace fit the slot's share of the caller's memory
+// pool (otherwise the batch is halved until it fits).  A batch of one runs in
+// place on the request's own buffers; a larger one is gathered into the
+// (component, limb, batch, coefficient) layout, run, and scattered back.
+// Rotations by different amounts share a batch (one key and Galois element
+// per ciphertext).  Every request waits for an event recorded on its
+// submitter's stream at submission.  Completed tags are collected by
+// tfhe_server_poll.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "ckks_internal.hpp"
+
+namespace tfhe {
+namespace {
+
+constexpr int kThreads = 256;
+
+// Copies between per-request ciphertexts [2][level][N] and the batch layout
+// [2][level][B][N] (gather: to the batch; scatter: from it).
+struct PtrSet {
+  const uint32_t* src[kMaxRotBatch];
+  uint32_t* dst[kMaxRotBatch];
+};
+
+template <bool kGather>
+__global__ void __launch_bounds__(kThreads)
+batch_copy_kernel(const PtrSet p, const uint32_t* __restrict__ bsrc, uint32_t* __restrict__ bdst,
+                  uint32_t rows, uint32_t batch, uint32_t n4) {
+  // one element = 16 bytes; rows = 2 * level (component, limb)
+  const uint64_t total = (uint64_t)rows * batch * n4;
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t k = (uint32_t)(i % n4);
+    const uint64_t rb = i / n4;
+    const uint32_t b = (uint32_t)(rb % batch), row = (uint32_t)(rb / batch);
+    const uint64_t own = (uint64_t)row * n4 + k;  // position in a request's [2][level][N]
+    if (kGather)
+      ((uint4*)bdst)[i] = ((const uint4*)p.src[b])[own];
+    else
+      ((uint4*)p.dst[b])[own] = ((const uint4*)bsrc)[i];
+  }
+}
+
+uint32_t copy_grid(uint64_t items) {
+  const uint64_t blocks = (items + kThreads - 1) / kThreads;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, 4096));
+}
+
+struct Req {
+  uint32_t op, log_n, level, galois;
+  const uint32_t *a, *b;
+  uint32_t* out;
+  uint64_t tag, seq;     // caller's tag; arrival number
+  hipEvent_t ready;      // recorded on the submitter's stream
+  tfhe_ckks_ctx ctx;     // resolved at submission, so that launches read
+  const uint32_t* key;   // no shared map: evk (HMULT) or rotation key
+};
+
+struct Key {
+  uint32_t op, log_n, level;
+  bool operator<(const Key& o) const {
+    return std::tie(op, log_n, level) < std::tie(o.op, o.log_n, o.level);
+  }
+};
+
+struct Slot {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  unsigned char* mem = nullptr;  // this slot's share of the pool
+  size_t bytes = 0;
+  std::vector<Req> reqs;         // the batch in flight (empty: free)
+  int status = TFHE_OK;          // launch status of that batch
+};
+
+struct Ctx {
+  tfhe_ckks_ctx ctx = nullptr;
+  const uint32_t* evk = nullptr;
+  std::map<uint32_t, const uint32_t*> rk;  // Galois element -> rotation key
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace tfhe
+
+using namespace tfhe;
+
+struct tfhe_server_s {
+  int device = 0;
+  uint32_t max_batch = 16;
+  std::vector<Slot> slots;
+  std::map<uint32_t, Ctx> ctxs;  // log_n -> context
+  std::mutex mu;
+  std::condition_variable cv;
+  std::map<Key, std::deque<Req>> pending;  // per batching key, FIFO
+  std::deque<std::pair<uint64_t, Key>> order;  // arrival order (seq, key)
+  uint64_t next_seq = 0;
+  std::vector<std::pair<uint64_t, int32_t>> done;
+  std::vector<hipEvent_t> event_pool;
+  bool stop = false;
+  std::thread th;
+
+  // slot memory a batch of B requests of key k needs (caller holds mu)
+  size_t need(const Key& k, uint32_t B) const {
+    const size_t ct = (size_t)2 * k.level * B * ((size_t)1 << k.log_n) * 4;
+    size_t ws = 0;
+    tfhe_hmult_workspace_size(ctxs.at(k.log_n).ctx, k.level, B, &ws);
+    const size_t staging = B > 1 ? (k.op == 0 ? 3 : 2) * align256(ct) : 0;
+    return staging + align256(ws);
+  }
+  void run();
+  int launch(Slot& sl, std::vector<Req>& reqs);
+};
+
+int tfhe_server_s::launch(Slot& sl, std::vector<Req>& reqs) {
+  const Req& r0 = reqs[0];
+  const uint32_t B = (uint32_t)reqs.size(), level = r0.level, n = 1u << r0.log_n;
+  for (const Req& r : reqs)
+    if (hipStreamWaitEvent(sl.s, r.ready, 0) != hipSuccess) return TFHE_EHIP;
+  size_t ws_bytes = 0;
+  tfhe_hmult_workspace_size(r0.ctx, level, B, &ws_bytes);
+  unsigned char* p = sl.mem;
+  const uint32_t *a = r0.a, *b = r0.b;
+  uint32_t* out = r0.out;
+  const size_t ct = (size_t)2 * level * B * n * 4;
+  PtrSet ps{};
+  const uint32_t rows = 2 * level, n4 = n / 4;
+  if (B > 1) {
+    uint32_t* sa = (uint32_t*)p;
+    p += align256(ct);
+    for (uint32_t k = 0; k < B; ++k) ps.src[k] = reqs[k].a;
+    hipLaunchKernelGGL(batch_copy_kernel<true>, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0, sl.s,
+                       ps, nullptr, sa, rows, B, n4);
+    a = sa;
+    if (r0.op == 0) {
+      uint32_t* sb = (uint32_t*)p;
+      p += align256(ct);
+      for (uint32_t k = 0; k < B; ++k) ps.src[k] = reqs[k].b;
+      hipLaunchKernelGGL(batch_copy_kernel<true>, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0,
+                         sl.s, ps, nullptr, sb, rows, B, n4);
+      b = sb;
+    }
+    out = (uint32_t*)p;
+    p += align256(ct);
+  }
+  void* ws = p;
+  tfhe_status st;
+  if (r0.op == 0) {
+    st = tfhe_hmult(r0.ctx, a, b, out, r0.key, level, B, ws, ws_bytes, (tfhe_stream_t)sl.s);
+  } else {
+    bool same = true;
+    for (const Req& r : reqs) same = same && r.galois == r0.galois;
+    if (same) {
+      st = tfhe_rotate(r0.ctx, a, out, r0.key, r0.galois, level, B, ws, ws_bytes,
+                       (tfhe_stream_t)sl.s);
+    } else {
+      std::vector<const uint32_t*> keys(B);
+      std::vector<uint32_t> gal(B);
+      for (uint32_t k = 0; k < B; ++k) {
+        keys[k] = reqs[k].key;
+        gal[k] = reqs[k].galois;
+      }
+      st = tfhe_rotate_multi(r0.ctx, a, out, keys.data(), gal.data(), level, B, ws, ws_bytes,
+                             (tfhe_stream_t)sl.s);
+    }
+  }
+  if (st != TFHE_OK) return st;
+  if (B > 1) {
+    for (uint32_t k = 0; k < B; ++k) ps.dst[k] = reqs[k].out;
+    hipLaunchKernelGGL(batch_copy_kernel<false>, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0,
+                       sl.s, ps, out, nullptr, rows, B, n4);
+  }
+  if (hipGetLastError() != hipSuccess) return TFHE_EHIP;
+  if (hipEventRecord(sl.done, sl.s) != hipSuccess) return TFHE_EHIP;
+  return TFHE_OK;
+}
+
+void tfhe_server_s::run() {
+  hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  while (!stop) {
+    bool busy = false;
+    // completions
+    for (Slot& sl : slots) {
+      if (sl.reqs.empty()) continue;
+      const hipError_t q = sl.status == TFHE_OK ? hipEventQuery(sl.done) : hipSuccess;
+      if (q == hipErrorNotReady) {
+        busy = true;
+        continue;
+      }
+      const int32_t status = sl.status != TFHE_OK ? sl.status : (q == hipSuccess ? TFHE_OK : TFHE_EHIP);
+      for (const Req& r : sl.reqs) {
+        done.emplace_back(r.tag, status);
+        event_pool.push_back(r.ready);
+      }
+      sl.reqs.clear();
+    }
+    // admissions
+    for (Slot& sl : slots) {
+      if (!sl.reqs.empty() || order.empty()) continue;
+      // oldest live request (entries of already batched requests are stale)
+      while (!order.empty()) {
+        auto it = pending.find(order.front().second);
+        if (it != pending.end() && !it->second.empty() && it->second.front().seq == order.front().first) break;
+        order.pop_front();
+      }
+      if (order.empty()) break;
+      const Key key = order.front().second;
+      std::deque<Req>& q = pending[key];
+      uint32_t B = std::min<uint32_t>((uint32_t)q.size(), max_batch);
+      while (B > 1 && need(key, B) > sl.bytes) B /= 2;
+      if (need(key, B) > sl.bytes) break;  // even one request does not fit (rejected at submission)
+      std::vector<Req> reqs(q.begin(), q.begin() + B);
+      q.erase(q.begin(), q.begin() + B);
+      if (q.empty()) pending.erase(key);
+      order.pop_front();
+      lk.unlock();
+      int st = launch(sl, reqs);
+      // a failed batch reports at once: let what it queued finish first
+      if (st != TFHE_OK) hipStreamSynchronize(sl.s);
+      lk.lock();
+      sl.reqs = std::move(reqs);
+      sl.status = st;
+      busy = true;
+    }
+    if (busy || !order.empty()) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(10));
+      lk.lock();
+    } else {
+      cv.wait(lk);
+    }
+  }
+  // drain what is in flight before the thread ends
+  lk.unlock();
+  for (Slot& sl : slots)
+    if (!sl.reqs.empty()) hipStreamSynchronize(sl.s);
+}
+
+extern "C" {
+
+tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_batch, void* pool,
+                               size_t pool_bytes) {
+  if (!out) return fail(TFHE_EINVAL, "server_create: null out");
+  *out = nullptr;
+  if (slots < 1 || slots > 16) return fail(TFHE_EINVAL, "server_create: slots in [1, 16]");
+  if (max_batch < 1 || max_batch > kMaxRotBatch)
+    return fail(TFHE_EINVAL, "server_create: max_batch in [1, TFHE_ROTATE_MULTI_MAX]");
+  if (!pool || (uintptr_t)pool % 256 || pool_bytes < 256 * (size_t)slots)
+    return fail(TFHE_EINVAL, "server_create: pool must be 256-byte aligned device memory");
+  tfhe_server_s* s = new (std::nothrow) tfhe_server_s();
+  if (!s) return fail(TFHE_ENOMEM, "server_create: host allocation");
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(TFHE_EHIP, "server_create: no current device");
+  }
+  s->max_batch = max_batch;
+  s->slots.resize(slots);
+  const size_t share = pool_bytes / slots / 256 * 256;
+  for (uint32_t i = 0; i < slots; ++i) {
+    Slot& sl = s->slots[i];
+    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      tfhe_server_destroy(s);
+      return fail(TFHE_EHIP, "server_create: stream or event creation");
+    }
+    sl.mem = (unsigned char*)pool + i * share;
+    sl.bytes = share;
+  }
+  s->th = std::thread([s] { s->run(); });
+  *out = s;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint32_t* evk) {
+  if (!s || !ctx || !evk) return fail(TFHE_EINVAL, "server_add_context: null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  Ctx& c = s->ctxs[ctx->log_n];
+  c.ctx = ctx;
+  c.evk = evk;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_server_add_rotation_key(tfhe_server s, uint32_t log_n, uint32_t galois_elt,
+                                         const uint32_t* rotkey) {
+  if (!s || !rotkey) return fail(TFHE_EINVAL, "server_add_rotation_key: null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->ctxs.find(log_n);
+  if (it == s->ctxs.end()) return fail(TFHE_EINVAL, "server_add_rotation_key: no context for this N");
+  if ((galois_elt & 1) == 0 || galois_elt >= 2 * it->second.ctx->n)
+    return fail(TFHE_EINVAL, "server_add_rotation_key: galois element must be odd and < 2N");
+  it->second.rk[galois_elt] = rotkey;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint32_t level, const uint32_t* ct_a,
+                               const uint32_t* ct_b, uint32_t galois_elt, uint32_t* ct_out, uint64_t tag,
+                               tfhe_stream_t stream) {
+  if (!s) return fail(TFHE_EINVAL, "server_submit: null server");
+  if (op > 1) return fail(TFHE_EINVAL, "server_submit: op is 0 (HMULT) or 1 (HROTATE)");
+  hipEvent_t ev = nullptr;
+  Req req;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->ctxs.find(log_n);
+    if (it == s->ctxs.end()) return fail(TFHE_EINVAL, "server_submit: no context for this N");
+    const Ctx& c = it->second;
+    if (level < 1 || level > c.ctx->L) return fail(TFHE_EINVAL, "server_submit: level must be in [1, L]");
+    const auto al16 = [](const void* p) { return p && (uintptr_t)p % 16 == 0; };
+    if (!al16(ct_a) || !al16(ct_out) || (op == 0 && !al16(ct_b)))
+      return fail(TFHE_EINVAL, "server_submit: null or unaligned ciphertext");
+    if (op == 1 && ct_a == ct_out) return fail(TFHE_EINVAL, "server_submit: rotation input and output alias");
+    const uint32_t* key = c.evk;
+    if (op == 1) {
+      auto k = c.rk.find(galois_elt);
+      if (k == c.rk.end()) return fail(TFHE_EINVAL, "server_submit: no rotation key for this element");
+      key = k->second;
+    }
+    req = Req{op, log_n, level, galois_elt, ct_a, ct_b, ct_out, tag, 0, nullptr, c.ctx, key};
+    if (s->need(Key{op, log_n, level}, 1) > s->slots[0].bytes)
+      return fail(TFHE_ENOMEM, "server_submit: one request exceeds a slot's share of the pool");
+    if (!s->event_pool.empty()) {
+      ev = s->event_pool.back();
+      s->event_pool.pop_back();
+    }
+  }
+  if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+    return fail(TFHE_EHIP, "server_submit: event creation");
+  if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+    hipEventDestroy(ev);
+    return fail(TFHE_EHIP, "server_submit: event record");
+  }
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    const Key k{op, log_n, level};
+    req.seq = s->next_seq++;
+    req.ready = ev;
+    s->pending[k].push_back(req);
+    s->order.emplace_back(req.seq, k);
+  }
+  s->cv.notify_one();
+  return TFHE_OK;
+}
+
+uint32_t tfhe_server_poll(tfhe_server s, uint64_t* tags, int32_t* status, uint32_t max) {
+  if (!s || !tags || !status) return 0;
+  std::lock_guard<std::mutex> g(s->mu);
+  const uint32_t k = (uint32_t)std::min<size_t>(max, s->done.size());
+  for (uint32_t i = 0; i < k; ++i) {
+    tags[i] = s->done[i].first;
+    status[i] = s->done[i].second;
+  }
+  s->done.erase(s->done.begin(), s->done.begin() + k);
+  return k;
+}
+
+tfhe_status tfhe_server_destroy(tfhe_server s) {
+  if (!s) return TFHE_OK;
+  if (s->th.joinable()) {
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      s->stop = true;
+    }
+    s->cv.notify_one();
+    s->th.join();
+  }
+  for (Slot& sl : s->slots) {
+    for (Req& r : sl.reqs) hipEventDestroy(r.ready);
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.s) hipStreamDestroy(sl.s);
+  }
+  for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
+  for (auto& kv : s->pending)
+    for (Req& r : kv.second) hipEventDestroy(r.ready);
+  delete s;
+  return TFHE_OK;
+}
+
+}  // extern "C"

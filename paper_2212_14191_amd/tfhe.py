@@ -84,6 +84,12 @@ def load():
         "tfhe_rescale": ([vp, vp, vp, u32, u32, vp, sz, vp], i32),
         "tfhe_cmult": ([vp, vp, vp, vp, u32, u32, vp], i32),
         "tfhe_hadd": ([vp, vp, vp, vp, u32, u32, vp], i32),
+        "tfhe_server_create": ([ctypes.POINTER(vp), u32, u32, vp, sz], i32),
+        "tfhe_server_add_context": ([vp, vp, vp], i32),
+        "tfhe_server_add_rotation_key": ([vp, u32, u32, vp], i32),
+        "tfhe_server_submit": ([vp, u32, u32, u32, vp, vp, u32, vp, u64, vp], i32),
+        "tfhe_server_poll": ([vp, ctypes.POINTER(u64), ctypes.POINTER(i32), u32], u32),
+        "tfhe_server_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -435,3 +441,91 @@ class CkksContext:
             out = torch_empty_like(ct_a)
         _call("tfhe_hadd", self.handle, _ptr(ct_a), _ptr(ct_b), _ptr(out), level, batch, _stream(stream))
         return out
+
+
+class NativeServer:
+    """The library's request dispatcher (tfhe_server_*): single-ciphertext
+    HMULT / HROTATE requests in, batched launches on `slots` streams, tagged
+    completions out.  Holds references to each request's tensors until its
+    completion has been polled."""
+
+    HMULT, ROTATE = 0, 1
+
+    def __init__(self, slots=2, max_batch=16, pool_bytes=1 << 30):
+        import torch
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+        h = ctypes.c_void_p()
+        _call("tfhe_server_create", ctypes.byref(h), slots, max_batch, _ptr(self.pool), pool_bytes)
+        self.handle = h
+        self._ctx = {}       # log_n -> (CkksContext, evk, {galois: rotkey})
+        self._live = {}      # tag -> tensors the request reads or writes
+        self._next = 0
+        cap = 4096
+        self._tags = (ctypes.c_uint64 * cap)()
+        self._status = (ctypes.c_int * cap)()
+        self._cap = cap
+
+    def add_context(self, ctx, evk, rotkeys=None):
+        """Registers ctx (CkksContext), its relinearisation key and a dict
+        {galois element: rotation key}."""
+        _check_residues(evk, "evk", (ctx.dnum, 2, ctx.L + ctx.K, ctx.n))
+        _call("tfhe_server_add_context", self.handle, ctx.handle, _ptr(evk))
+        keys = {}
+        for g, k in (rotkeys or {}).items():
+            _check_residues(k, "rotkey", (ctx.dnum, 2, ctx.L + ctx.K, ctx.n))
+            _call("tfhe_server_add_rotation_key", self.handle, ctx.log_n, int(g), _ptr(k))
+            keys[int(g)] = k
+        self._ctx[ctx.log_n] = (ctx, evk, keys)
+
+    def submit(self, op, ct_a, ct_b=None, galois=0, out=None, stream=None):
+        """Queues one request on ciphertext(s) of shape [2][level][N] (or
+        [2][level][1][N]); returns (tag, out)."""
+        level, n = ct_a.shape[1], ct_a.shape[-1]
+        if ct_a.numel() != 2 * level * n:
+            raise ValueError("one ciphertext [2][level][N] per request")
+        log_n = n.bit_length() - 1
+        if log_n not in self._ctx:
+            raise ValueError(f"no context registered for N = {n}")
+        _check_residues(ct_a, "ct_a")
+        if op == self.HMULT:
+            _check_residues(ct_b, "ct_b", ct_a.shape)
+        if out is None:
+            out = torch_empty_like(ct_a)
+        _check_residues(out, "out", ct_a.shape)
+        tag = self._next
+        self._next += 1
+        _call("tfhe_server_submit", self.handle, op, log_n, level, _ptr(ct_a), _ptr(ct_b), galois, _ptr(out),
+              tag, _stream(stream))
+        self._live[tag] = (ct_a, ct_b, out)
+        return tag, out
+
+    def hmult(self, ct_a, ct_b, out=None, stream=None):
+        return self.submit(self.HMULT, ct_a, ct_b, 0, out, stream)
+
+    def rotate(self, ct, galois, out=None, stream=None):
+        return self.submit(self.ROTATE, ct, None, galois, out, stream)
+
+    def poll(self):
+        """Completed requests as a list of (tag, status name or None)."""
+        k = load().tfhe_server_poll(self.handle, self._tags, self._status, self._cap)
+        res = []
+        for i in range(k):
+            t, st = self._tags[i], self._status[i]
+            self._live.pop(t, None)
+            res.append((t, None if st == TFHE_OK else status_name(st)))
+        return res
+
+    def pending(self):
+        return len(self._live)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().tfhe_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

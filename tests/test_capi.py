@@ -76,3 +76,24 @@ def test_ckks_ctx_rejects_bad_shape(tf):
     with pytest.raises(tf.TfheError) as ei:
         tf.CkksContext(16, 24, 8, 2)      # alpha = 12 > 8
     assert ei.value.status == tf.TFHE_EUNSUPPORTED
+
+
+def test_server_rejects_bad_arguments(tf):
+    """tfhe_server_* argument checks that precede any HIP call."""
+    lib = tf.load()
+    h = ctypes.c_void_p()
+    fake_pool = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails first
+    assert lib.tfhe_server_create(None, 1, 1, fake_pool, 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 0, 1, fake_pool, 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 17, 1, fake_pool, 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 1, 0, fake_pool, 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 1, 65, fake_pool, 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 1, 4, None, 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 1, 4, ctypes.c_void_p((1 << 20) + 16), 1 << 20) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_create(ctypes.byref(h), 4, 4, fake_pool, 512) == tf.TFHE_EINVAL
+    assert h.value is None
+    assert lib.tfhe_server_submit(None, 0, 10, 1, None, None, 0, None, 0, None) == tf.TFHE_EINVAL
+    assert lib.tfhe_server_add_context(None, None, None) == tf.TFHE_EINVAL
+    tags, status = (ctypes.c_uint64 * 4)(), (ctypes.c_int * 4)()
+    assert lib.tfhe_server_poll(None, tags, status, 4) == 0
+    assert lib.tfhe_server_destroy(None) == tf.TFHE_OK

@@ -70,3 +70,105 @@ def test_alone_equals_mix_on_gpu(world):
     for x, y in zip(alone, mixed):
         assert torch.equal(x, y)
     assert st["completed"] == len(reqs) and st["p99_ms"] is not None
+
+
+def drain(srv, count, timeout=60.0):
+    import time
+    done, t0 = {}, time.perf_counter()
+    while len(done) < count:
+        for tag, st in srv.poll():
+            done[tag] = st
+        assert time.perf_counter() - t0 < timeout, f"{len(done)} of {count} completed"
+    return done
+
+
+def alone_results(world, reqs):
+    ctxs, evks, rks, _ = world
+    out = []
+    for op, ln, lv, a, b, g in reqs:
+        if op == 0:
+            out.append(ctxs[ln].hmult(a, b, evks[ln], lv))
+        else:
+            out.append(ctxs[ln].rotate(a, rks[(ln, g)], g, lv))
+    torch.cuda.synchronize()
+    return out
+
+
+def native_server(world, **kw):
+    from paper_2212_14191_amd import tfhe
+    ctxs, evks, rks, _ = world
+    srv = tfhe.NativeServer(**kw)
+    for ln, ctx in ctxs.items():
+        srv.add_context(ctx, evks[ln], {g: k for (l2, g), k in rks.items() if l2 == ln})
+    return srv
+
+
+@pytest.mark.parametrize("slots,max_batch,pool_mib", [(1, 1, 256), (4, 8, 1024), (2, 16, 24)])
+def test_native_server_alone_equals_mix(world, slots, max_batch, pool_mib):
+    """The library's dispatcher (tfhe_server_*) returns, for every request of
+    a mixed stream, exactly the single-request tfhe_hmult / tfhe_rotate
+    result; the 24 MiB pool forces batches to be split to fit."""
+    reqs = requests(world, 48, 1)
+    alone = alone_results(world, reqs)
+    srv = native_server(world, slots=slots, max_batch=max_batch, pool_bytes=pool_mib << 20)
+    outs = {}
+    for op, ln, lv, a, b, g in reqs:
+        tag, out = srv.submit(op, a, b, g or 0)
+        outs[tag] = out
+    done = drain(srv, len(reqs))
+    assert all(st is None for st in done.values()), done
+    for tag, x in zip(sorted(outs), alone):
+        assert torch.equal(outs[tag], x), tag
+    assert srv.pending() == 0
+    srv.close()
+
+
+def test_native_server_waits_for_the_submitting_stream(world):
+    """A request whose input is still being written on the submitter's stream
+    sees the finished input."""
+    ctxs, evks, _, cts = world
+    a, b = cts[(12, 6, 0)], cts[(12, 6, 1)]
+    want = ctxs[12].hmult(a, b, evks[12], 6)
+    srv = native_server(world, slots=2, max_batch=4, pool_bytes=256 << 20)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a2 = torch.zeros_like(a)
+        torch.cuda._sleep(20_000_000)  # hold the stream a few ms before the copy
+        a2.copy_(a)
+        tag, out = srv.hmult(a2, b, stream=s)
+    done = drain(srv, 1)
+    assert done[tag] is None
+    assert torch.equal(out, want)
+    srv.close()
+
+
+def test_native_server_rejects_bad_requests(world):
+    from paper_2212_14191_amd import tfhe
+    _, _, _, cts = world
+    srv = native_server(world, slots=1, max_batch=4, pool_bytes=64 << 20)
+    c = cts[(10, 2, 0)]
+    with pytest.raises(tfhe.TfheError):
+        srv.rotate(c, 7)  # no key registered for this Galois element
+    with pytest.raises(tfhe.TfheError):
+        srv.rotate(c, pow(5, 1, 2 << 10), out=c)  # output aliases the input
+    c7 = torch.zeros((2, 7, 1, 1 << 10), dtype=torch.int32, device="cuda")
+    with pytest.raises(tfhe.TfheError):
+        srv.hmult(c7, c7)  # level above L
+    with pytest.raises(ValueError):
+        srv.hmult(torch.zeros((2, 2, 1, 1 << 11), dtype=torch.int32, device="cuda"), c)  # no context for N
+    tiny = native_server(world, slots=4, max_batch=4, pool_bytes=1 << 20)
+    with pytest.raises(tfhe.TfheError):
+        tiny.hmult(cts[(12, 6, 0)], cts[(12, 6, 1)])  # one request exceeds a slot's share
+    assert srv.poll() == [] and tiny.poll() == []
+    srv.close()
+    tiny.close()
+
+
+def test_native_server_close_with_requests_in_flight(world):
+    """Closing waits for dispatched batches; nothing faults or hangs."""
+    reqs = requests(world, 16, 2)
+    srv = native_server(world, slots=2, max_batch=4, pool_bytes=512 << 20)
+    for op, ln, lv, a, b, g in reqs:
+        srv.submit(op, a, b, g or 0)
+    srv.close()
+    torch.cuda.synchronize()
