@@ -162,7 +162,8 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs):
         return st
 
     # the library's own dispatcher (tfhe_server_*), same mix, same keys
-    native = tfhe.NativeServer(slots=slots, max_batch=16, pool_bytes=slots * (3 << 30))
+    native_slots = 8  # worker threads / streams of the native dispatcher
+    native = tfhe.NativeServer(slots=native_slots, max_batch=16, pool_bytes=native_slots * (3 << 30))
     for ln in log_ns:
         native.add_context(ctxs[ln], evks[ln], {g: k for (l2, g), k in rks.items() if l2 == ln})
 
@@ -196,11 +197,12 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs):
         return {"throughput_per_s": count / (np.max(t_done) - t_sub[0]),
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
-    out = {"requests": n_req, "slots": slots, "max_batch": 16}
+    out = {"requests": n_req, "max_batch": 16}
     for name, fn in (("python", run), ("native", run_native)):
-        fn(min(64, n_sat), 99, 0)  # warm-up
+        fn(min(500, n_sat), 99, 0)  # warm-up
         sat = fn(n_sat, 98, 0)
-        res = {"saturated_ops_per_s": round(sat["throughput_per_s"], 1), "runs": []}
+        res = {"slots": native_slots if name == "native" else slots,
+               "saturated_ops_per_s": round(sat["throughput_per_s"], 1), "runs": []}
         for frac in fracs:
             rate = frac * sat["throughput_per_s"]
             st = fn(n_req, 3, rate)
@@ -222,7 +224,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-hmult", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=1500)
+    ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult"], default=None,
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -348,7 +350,8 @@ def main():
 
     serving = None
     if not args.skip_serving and args.only is None:
-        serving = serving_leg(args.serving_requests, args.serving_requests, (0.5, 0.9), torch, tfhe, inputs)
+        serving = serving_leg(args.serving_requests, args.serving_requests, (0.25, 0.5, 0.75, 0.9), torch, tfhe,
+                              inputs)
         log("serving", json.dumps(serving))
 
     cpu = None
@@ -398,7 +401,7 @@ def main():
         line["rescale_ops_per_s"] = round(hmult["rescale"]["ops_per_s"], 1)
         line["hmult"] = hmult
     if serving:
-        line["p99_ms"] = serving["native"]["runs"][0]["p99_ms"]
+        line["p99_ms"] = next(r["p99_ms"] for r in serving["native"]["runs"] if r["load"] == 0.5)
         line["serving"] = serving
     print(json.dumps(line), flush=True)
 

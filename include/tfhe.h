@@ -290,10 +290,11 @@ tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t*
 
 /* Request dispatcher (the API layer of Sec. III-E with operation-level
  * batching, Sec. III-D): callers submit single-ciphertext HMULT and HROTATE
- * requests; a dispatcher thread groups requests of equal (operation, N,
- * level) into batches of up to max_batch, runs each batch on one of `slots`
- * streams with one batched tfhe_hmult / tfhe_rotate / tfhe_rotate_multi
- * call, and reports each request's completion through tfhe_server_poll.
+ * requests; `slots` worker threads, each with its own stream, group
+ * requests of equal (operation, N, level) into batches of up to max_batch,
+ * run each batch with one batched tfhe_hmult / tfhe_rotate /
+ * tfhe_rotate_multi call, and report each request's completion through
+ * tfhe_server_poll.
  * The result of a request is exactly what that call computes for it alone.
  *
  * tfhe_server_create: pool is caller-owned device memory, 256-byte aligned,

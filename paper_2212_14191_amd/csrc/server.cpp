@@ -2,11 +2,12 @@
 // Sec. III-E: requests are collected, grouped into batched kernel workflows
 // and dispatched; keys and ciphertexts stay resident in device memory).
 //
-// One dispatcher thread owns `slots` HIP streams.  Pending requests are
-// indexed by batching key (op, N, level); whenever a slot is free, the
-// oldest request and up to max_batch - 1 others of its key form a batch whose
-// staging buffers and workspace fit the slot's share of the caller's memory
-// pool (otherwise the batch is halved until it fits).  A batch of one runs in
+// Each of `slots` worker threads owns a HIP stream and an equal share of the
+// caller's memory pool.  Pending requests are indexed by batching key (op,
+// N, level); whenever a worker is free, the oldest request and up to
+// max_batch - 1 others of its key form a batch whose staging buffers and
+// workspace fit the worker's share (otherwise the batch is halved until it
+// fits).  A batch of one runs in
 // place on the request's own buffers; a larger one is gathered into the
 // (component, limb, batch, coefficient) layout, run, and scattered back.
 // Rotations by different amounts share a batch (one key and Galois element
@@ -16,7 +17,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -85,8 +85,6 @@ struct Slot {
   hipEvent_t done = nullptr;
   unsigned char* mem = nullptr;  // this slot's share of the pool
   size_t bytes = 0;
-  std::vector<Req> reqs;         // the batch in flight (empty: free)
-  int status = TFHE_OK;          // launch status of that batch
 };
 
 struct Ctx {
@@ -115,7 +113,7 @@ struct tfhe_server_s {
   std::vector<std::pair<uint64_t, int32_t>> done;
   std::vector<hipEvent_t> event_pool;
   bool stop = false;
-  std::thread th;
+  std::vector<std::thread> workers;
 
   // slot memory a batch of B requests of key k needs (caller holds mu)
   size_t need(const Key& k, uint32_t B) const {
@@ -125,7 +123,8 @@ struct tfhe_server_s {
     const size_t staging = B > 1 ? (k.op == 0 ? 3 : 2) * align256(ct) : 0;
     return staging + align256(ws);
   }
-  void run();
+  bool take(const Slot& sl, std::vector<Req>& reqs);
+  void worker(Slot& sl);
   int launch(Slot& sl, std::vector<Req>& reqs);
 };
 
@@ -192,66 +191,54 @@ int tfhe_server_s::launch(Slot& sl, std::vector<Req>& reqs) {
   return TFHE_OK;
 }
 
-void tfhe_server_s::run() {
+// Takes the next batch for slot sl: the oldest pending request and up to
+// max_batch - 1 later ones of its key, halved until it fits the slot's
+// memory.  Caller holds mu.
+bool tfhe_server_s::take(const Slot& sl, std::vector<Req>& reqs) {
+  // entries of requests already batched with an older one are stale
+  while (!order.empty()) {
+    auto it = pending.find(order.front().second);
+    if (it != pending.end() && !it->second.empty() && it->second.front().seq == order.front().first) break;
+    order.pop_front();
+  }
+  if (order.empty()) return false;
+  const Key key = order.front().second;
+  std::deque<Req>& q = pending[key];
+  uint32_t B = std::min<uint32_t>((uint32_t)q.size(), max_batch);
+  while (B > 1 && need(key, B) > sl.bytes) B /= 2;
+  if (need(key, B) > sl.bytes) return false;  // cannot happen: submission checks one request
+  reqs.assign(q.begin(), q.begin() + B);
+  q.erase(q.begin(), q.begin() + B);
+  if (q.empty()) pending.erase(key);
+  order.pop_front();
+  return true;
+}
+
+// One worker per slot: take a batch, launch it on the slot's stream, wait
+// for it (spinning: a completed batch is reported within microseconds),
+// report it, repeat.  Workers launch concurrently.
+void tfhe_server_s::worker(Slot& sl) {
   hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
-  while (!stop) {
-    bool busy = false;
-    // completions
-    for (Slot& sl : slots) {
-      if (sl.reqs.empty()) continue;
-      const hipError_t q = sl.status == TFHE_OK ? hipEventQuery(sl.done) : hipSuccess;
-      if (q == hipErrorNotReady) {
-        busy = true;
-        continue;
-      }
-      const int32_t status = sl.status != TFHE_OK ? sl.status : (q == hipSuccess ? TFHE_OK : TFHE_EHIP);
-      for (const Req& r : sl.reqs) {
-        done.emplace_back(r.tag, status);
-        event_pool.push_back(r.ready);
-      }
-      sl.reqs.clear();
-    }
-    // admissions
-    for (Slot& sl : slots) {
-      if (!sl.reqs.empty() || order.empty()) continue;
-      // oldest live request (entries of already batched requests are stale)
-      while (!order.empty()) {
-        auto it = pending.find(order.front().second);
-        if (it != pending.end() && !it->second.empty() && it->second.front().seq == order.front().first) break;
-        order.pop_front();
-      }
-      if (order.empty()) break;
-      const Key key = order.front().second;
-      std::deque<Req>& q = pending[key];
-      uint32_t B = std::min<uint32_t>((uint32_t)q.size(), max_batch);
-      while (B > 1 && need(key, B) > sl.bytes) B /= 2;
-      if (need(key, B) > sl.bytes) break;  // even one request does not fit (rejected at submission)
-      std::vector<Req> reqs(q.begin(), q.begin() + B);
-      q.erase(q.begin(), q.begin() + B);
-      if (q.empty()) pending.erase(key);
-      order.pop_front();
-      lk.unlock();
-      int st = launch(sl, reqs);
-      // a failed batch reports at once: let what it queued finish first
-      if (st != TFHE_OK) hipStreamSynchronize(sl.s);
-      lk.lock();
-      sl.reqs = std::move(reqs);
-      sl.status = st;
-      busy = true;
-    }
-    if (busy || !order.empty()) {
-      lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(10));
-      lk.lock();
+  for (;;) {
+    std::vector<Req> reqs;
+    while (!stop && !take(sl, reqs)) cv.wait(lk);
+    if (reqs.empty()) break;  // stopping
+    lk.unlock();
+    int st = launch(sl, reqs);
+    if (st == TFHE_OK) {
+      hipError_t q;
+      while ((q = hipEventQuery(sl.done)) == hipErrorNotReady) std::this_thread::yield();
+      if (q != hipSuccess) st = TFHE_EHIP;
     } else {
-      cv.wait(lk);
+      hipStreamSynchronize(sl.s);  // a failed batch reports at once: let what it queued finish first
+    }
+    lk.lock();
+    for (const Req& r : reqs) {
+      done.emplace_back(r.tag, st);
+      event_pool.push_back(r.ready);
     }
   }
-  // drain what is in flight before the thread ends
-  lk.unlock();
-  for (Slot& sl : slots)
-    if (!sl.reqs.empty()) hipStreamSynchronize(sl.s);
 }
 
 extern "C" {
@@ -284,7 +271,7 @@ tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_ba
     sl.mem = (unsigned char*)pool + i * share;
     sl.bytes = share;
   }
-  s->th = std::thread([s] { s->run(); });
+  for (Slot& sl : s->slots) s->workers.emplace_back([s, &sl] { s->worker(sl); });
   *out = s;
   return TFHE_OK;
 }
@@ -373,16 +360,13 @@ uint32_t tfhe_server_poll(tfhe_server s, uint64_t* tags, int32_t* status, uint32
 
 tfhe_status tfhe_server_destroy(tfhe_server s) {
   if (!s) return TFHE_OK;
-  if (s->th.joinable()) {
-    {
-      std::lock_guard<std::mutex> g(s->mu);
-      s->stop = true;
-    }
-    s->cv.notify_one();
-    s->th.join();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
   }
+  s->cv.notify_all();
+  for (std::thread& t : s->workers) t.join();  // each finishes its batch in flight
   for (Slot& sl : s->slots) {
-    for (Req& r : sl.reqs) hipEventDestroy(r.ready);
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.s) hipStreamDestroy(sl.s);
   }
