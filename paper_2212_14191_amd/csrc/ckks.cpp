@@ -204,6 +204,27 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   return hipSuccess;
 }
 
+hipError_t hmult_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& a, const CtPtrs& b, uint32_t* out,
+                      const uint32_t* evk, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
+  const uint64_t plane = (uint64_t)level * batch * c->n;
+  uint32_t* d2 = (uint32_t*)(ws + ks_layout(c, level, batch).d2);
+  hipError_t e = launch_tensor_ptrs(a, b, out, d2, c->plan->d_mod, level, batch, c->log_n, s);
+  KeySet keys{};
+  keys.count = 1;
+  keys.k[0] = evk;
+  if (e == hipSuccess) e = key_switch(c, d2, keys, out, out + plane, true, true, level, batch, ws, s);
+  return e;
+}
+
+hipError_t rotate_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& in, uint32_t* out, const KeySet& keys,
+                       const GaloisSet& gs, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
+  const uint64_t plane = (uint64_t)level * batch * c->n;
+  uint32_t* r1 = (uint32_t*)(ws + ks_layout(c, level, batch).d2);
+  hipError_t e = launch_frobenius_pair_ptrs(in, out, r1, gs, level, batch, c->log_n, s);
+  if (e == hipSuccess) e = key_switch(c, r1, keys, out, out + plane, true, false, level, batch, ws, s);
+  return e;
+}
+
 // RESCALE workspace: the top limbs in the coefficient domain [2][B][N], their
 // broadcast to the remaining limbs [2][top][B][N], the transforms' workspace.
 struct RsLayout {

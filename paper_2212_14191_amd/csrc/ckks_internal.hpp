@@ -89,6 +89,30 @@ hipError_t launch_frobenius_pair(const uint32_t* in0, uint32_t* out0, const uint
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 
+// A batch of separately allocated ciphertexts [2][level][N], read as one
+// [2][level][batch][N] array: element b lives at p[b].
+struct CtPtrs {
+  const uint32_t* p[kMaxRotBatch];
+};
+// launch_tensor / launch_frobenius_pair reading their inputs through CtPtrs
+// (outputs in the batch layout).
+hipError_t launch_tensor_ptrs(const CtPtrs& a, const CtPtrs& b, uint32_t* out, uint32_t* d2,
+                              const ModConst* mods, uint32_t level, uint32_t batch, uint32_t log_n,
+                              hipStream_t s);
+hipError_t launch_frobenius_pair_ptrs(const CtPtrs& in, uint32_t* out0, uint32_t* out1, const GaloisSet& gs,
+                                      uint32_t level, uint32_t batch, uint32_t log_n, hipStream_t s);
+
 }  // namespace tfhe
 
 struct tfhe_ckks_ctx_s : tfhe::CkksCtxImpl {};
+
+namespace tfhe {
+// HMULT / HROTATE of a batch whose inputs are separate ciphertexts (the
+// request dispatcher's batches), with the result in the batch layout
+// [2][level][batch][N] at out.  Arguments are not validated (the caller
+// has); ws holds at least tfhe_hmult_workspace_size bytes, 256-aligned.
+hipError_t hmult_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& a, const CtPtrs& b, uint32_t* out,
+                      const uint32_t* evk, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s);
+hipError_t rotate_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& in, uint32_t* out, const KeySet& keys,
+                       const GaloisSet& gs, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s);
+}  // namespace tfhe

@@ -300,6 +300,48 @@ frobenius_pair_kernel(const uint32_t* __restrict__ in0, uint32_t* __restrict__ o
   }
 }
 
+// tensor_kernel with the inputs read from separate ciphertexts [2][level][N]
+// (a.p[b], b.p[b]); output index i = (limb batch + b) N/4 + k.
+__global__ void __launch_bounds__(kThreads)
+tensor_ptrs_kernel(const CtPtrs a, const CtPtrs b, uint4* out, uint4* __restrict__ d2,
+                   const ModConst* __restrict__ mods, uint32_t level, uint32_t batch, uint32_t log_n4) {
+  const uint64_t n4 = 1ull << log_n4, plane4 = (uint64_t)level * batch * n4;
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < plane4;
+       i += (uint64_t)gridDim.x * kThreads) {
+    const uint32_t rb = (uint32_t)(i >> log_n4), limb = rb / batch, e = rb - limb * batch;
+    const uint64_t own = ((uint64_t)limb << log_n4) + (i & (n4 - 1)), comp1 = (uint64_t)level << log_n4;
+    const uint4* A = (const uint4*)a.p[e];
+    const uint4* B = (const uint4*)b.p[e];
+    const ModConst m = mods[limb];
+    const uint4 c0 = A[own], c1 = A[comp1 + own], e0 = B[own], e1 = B[comp1 + own];
+    d2[i] = map4(c1, [&](uint32_t x, int k) { return mul_mod(x, comp(e1, k), m); });
+    out[i] = map4(c0, [&](uint32_t x, int k) { return mul_mod(x, comp(e0, k), m); });
+    out[plane4 + i] = map4(c0, [&](uint32_t x, int k) {
+      return add_mod(mul_mod(x, comp(e1, k), m), mul_mod(comp(c1, k), comp(e0, k), m), m.q);
+    });
+  }
+}
+
+// frobenius_pair_kernel with the input components read from separate
+// ciphertexts [2][level][N] (in.p[b]); outputs [level][batch][N].
+__global__ void __launch_bounds__(kThreads)
+frobenius_pair_ptrs_kernel(const CtPtrs in, uint32_t* __restrict__ out0, uint32_t* __restrict__ out1,
+                           const GaloisSet gs, uint32_t level, uint32_t batch, uint32_t log_n) {
+  const uint32_t n = 1u << log_n, mask2n = 2 * n - 1;
+  const uint64_t per = ((uint64_t)level * batch) << log_n;
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < 2 * per;
+       i += (uint64_t)gridDim.x * kThreads) {
+    const bool second = i >= per;
+    const uint64_t k = second ? i - per : i;
+    const uint32_t j = (uint32_t)(k & (n - 1)), row = (uint32_t)(k >> log_n);
+    const uint32_t limb = row / batch, e = row - limb * batch;
+    const uint32_t galois = gs.g[e % gs.batch];
+    const uint32_t src = (((2 * j + 1) * galois) & mask2n) >> 1;
+    const uint64_t base = ((uint64_t)(second ? level + limb : limb)) << log_n;
+    (second ? out1 : out0)[k] = in.p[e][base + src];
+  }
+}
+
 // RESCALE broadcast: t holds the two components' top limbs in the
 // coefficient domain, [2][B][N] in [0, q_top); u[c][i] = t[c] mod q_i for
 // i < top.  Every modulus exceeds 2^29 and t < 2^31 < 4 q_i, so two
@@ -352,6 +394,23 @@ hipError_t launch_frobenius_pair(const uint32_t* in0, uint32_t* out0, const uint
   const uint64_t per = (uint64_t)rows << log_n;
   TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_pair_kernel, dim3(grid_for(2 * per)), dim3(kThreads), 0, s,
                                            in0, out0, in1, out1, gs, per, log_n));
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor_ptrs(const CtPtrs& a, const CtPtrs& b, uint32_t* out, uint32_t* d2,
+                              const ModConst* mods, uint32_t level, uint32_t batch, uint32_t log_n,
+                              hipStream_t s) {
+  const uint64_t plane4 = ((uint64_t)level * batch) << (log_n - 2);
+  TFHE_TIMED(K_TENSOR, s, hipLaunchKernelGGL(tensor_ptrs_kernel, dim3(grid_for(plane4)), dim3(kThreads), 0, s, a, b,
+                                             (uint4*)out, (uint4*)d2, mods, level, batch, log_n - 2));
+  return hipGetLastError();
+}
+
+hipError_t launch_frobenius_pair_ptrs(const CtPtrs& in, uint32_t* out0, uint32_t* out1, const GaloisSet& gs,
+                                      uint32_t level, uint32_t batch, uint32_t log_n, hipStream_t s) {
+  const uint64_t per = ((uint64_t)level * batch) << log_n;
+  TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_pair_ptrs_kernel, dim3(grid_for(2 * per)), dim3(kThreads), 0,
+                                           s, in, out0, out1, gs, level, batch, log_n));
   return hipGetLastError();
 }
 

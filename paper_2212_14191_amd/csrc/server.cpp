@@ -5,13 +5,14 @@
 // Each of `slots` worker threads owns a HIP stream and an equal share of the
 // caller's memory pool.  Pending requests are indexed by batching key (op,
 // N, level); whenever a worker is free, the oldest request and up to
-// max_batch - 1 others of its key form a batch whose staging buffers and
+// max_batch - 1 others of its key form a batch whose result buffer and
 // workspace fit the worker's share (otherwise the batch is halved until it
-// fits).  A batch of one runs in
-// place on the request's own buffers; a larger one is gathered into the
-// (component, limb, batch, coefficient) layout, run, and scattered back.
-// Rotations by different amounts share a batch (one key and Galois element
-// per ciphertext).  Every request waits for an event recorded on its
+// fits).  A batch of one runs in place on the request's own buffers; a
+// larger one reads its inputs where they are (through a table of
+// per-request pointers), computes into a result buffer in the (component,
+// limb, batch, coefficient) layout and is scattered back.  Rotations by
+// different amounts share a batch (one key and Galois element per
+// ciphertext).  Every request waits for an event recorded on its
 // submitter's stream at submission.  Completed tags are collected by
 // tfhe_server_poll.
 #include <hip/hip_runtime.h>
@@ -32,29 +33,22 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Copies between per-request ciphertexts [2][level][N] and the batch layout
-// [2][level][B][N] (gather: to the batch; scatter: from it).
-struct PtrSet {
-  const uint32_t* src[kMaxRotBatch];
-  uint32_t* dst[kMaxRotBatch];
+// Copies a batch result [2][level][B][N] out to the requests' own
+// ciphertexts [2][level][N] (dst[b]); one element = 16 bytes, rows =
+// 2 level (component, limb).
+struct OutPtrs {
+  uint32_t* p[kMaxRotBatch];
 };
 
-template <bool kGather>
 __global__ void __launch_bounds__(kThreads)
-batch_copy_kernel(const PtrSet p, const uint32_t* __restrict__ bsrc, uint32_t* __restrict__ bdst,
-                  uint32_t rows, uint32_t batch, uint32_t n4) {
-  // one element = 16 bytes; rows = 2 * level (component, limb)
+scatter_kernel(const uint4* __restrict__ src, const OutPtrs dst, uint32_t rows, uint32_t batch, uint32_t n4) {
   const uint64_t total = (uint64_t)rows * batch * n4;
   for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
        i += (uint64_t)gridDim.x * kThreads) {
     const uint32_t k = (uint32_t)(i % n4);
     const uint64_t rb = i / n4;
     const uint32_t b = (uint32_t)(rb % batch), row = (uint32_t)(rb / batch);
-    const uint64_t own = (uint64_t)row * n4 + k;  // position in a request's [2][level][N]
-    if (kGather)
-      ((uint4*)bdst)[i] = ((const uint4*)p.src[b])[own];
-    else
-      ((uint4*)p.dst[b])[own] = ((const uint4*)bsrc)[i];
+    ((uint4*)dst.p[b])[(uint64_t)row * n4 + k] = src[i];
   }
 }
 
@@ -120,7 +114,7 @@ struct tfhe_server_s {
     const size_t ct = (size_t)2 * k.level * B * ((size_t)1 << k.log_n) * 4;
     size_t ws = 0;
     tfhe_hmult_workspace_size(ctxs.at(k.log_n).ctx, k.level, B, &ws);
-    const size_t staging = B > 1 ? (k.op == 0 ? 3 : 2) * align256(ct) : 0;
+    const size_t staging = B > 1 ? align256(ct) : 0;  // the batch result
     return staging + align256(ws);
   }
   bool take(const Slot& sl, std::vector<Req>& reqs);
@@ -135,56 +129,38 @@ int tfhe_server_s::launch(Slot& sl, std::vector<Req>& reqs) {
     if (hipStreamWaitEvent(sl.s, r.ready, 0) != hipSuccess) return TFHE_EHIP;
   size_t ws_bytes = 0;
   tfhe_hmult_workspace_size(r0.ctx, level, B, &ws_bytes);
-  unsigned char* p = sl.mem;
-  const uint32_t *a = r0.a, *b = r0.b;
-  uint32_t* out = r0.out;
-  const size_t ct = (size_t)2 * level * B * n * 4;
-  PtrSet ps{};
-  const uint32_t rows = 2 * level, n4 = n / 4;
-  if (B > 1) {
-    uint32_t* sa = (uint32_t*)p;
-    p += align256(ct);
-    for (uint32_t k = 0; k < B; ++k) ps.src[k] = reqs[k].a;
-    hipLaunchKernelGGL(batch_copy_kernel<true>, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0, sl.s,
-                       ps, nullptr, sa, rows, B, n4);
-    a = sa;
-    if (r0.op == 0) {
-      uint32_t* sb = (uint32_t*)p;
-      p += align256(ct);
-      for (uint32_t k = 0; k < B; ++k) ps.src[k] = reqs[k].b;
-      hipLaunchKernelGGL(batch_copy_kernel<true>, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0,
-                         sl.s, ps, nullptr, sb, rows, B, n4);
-      b = sb;
-    }
-    out = (uint32_t*)p;
-    p += align256(ct);
-  }
-  void* ws = p;
-  tfhe_status st;
-  if (r0.op == 0) {
-    st = tfhe_hmult(r0.ctx, a, b, out, r0.key, level, B, ws, ws_bytes, (tfhe_stream_t)sl.s);
+  bool same = true;  // one Galois element for the whole batch
+  for (const Req& r : reqs) same = same && r.galois == r0.galois;
+  if (B == 1) {
+    // in place on the request's own buffers, through the public entry points
+    void* ws = sl.mem;
+    tfhe_status st = r0.op == 0
+        ? tfhe_hmult(r0.ctx, r0.a, r0.b, r0.out, r0.key, level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s)
+        : tfhe_rotate(r0.ctx, r0.a, r0.out, r0.key, r0.galois, level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s);
+    if (st != TFHE_OK) return st;
   } else {
-    bool same = true;
-    for (const Req& r : reqs) same = same && r.galois == r0.galois;
-    if (same) {
-      st = tfhe_rotate(r0.ctx, a, out, r0.key, r0.galois, level, B, ws, ws_bytes,
-                       (tfhe_stream_t)sl.s);
-    } else {
-      std::vector<const uint32_t*> keys(B);
-      std::vector<uint32_t> gal(B);
-      for (uint32_t k = 0; k < B; ++k) {
-        keys[k] = reqs[k].key;
-        gal[k] = reqs[k].galois;
-      }
-      st = tfhe_rotate_multi(r0.ctx, a, out, keys.data(), gal.data(), level, B, ws, ws_bytes,
-                             (tfhe_stream_t)sl.s);
+    // inputs read where they are; the result goes to the slot's staging
+    // buffer in the batch layout, then out to each request
+    uint32_t* out = (uint32_t*)sl.mem;
+    unsigned char* ws = sl.mem + align256((size_t)2 * level * B * n * 4);
+    CtPtrs a{}, b{};
+    KeySet keys{};
+    GaloisSet gs{};
+    for (uint32_t k = 0; k < B; ++k) {
+      a.p[k] = reqs[k].a;
+      b.p[k] = reqs[k].b;
+      keys.k[k] = reqs[k].key;
+      gs.g[k] = reqs[k].galois;
     }
-  }
-  if (st != TFHE_OK) return st;
-  if (B > 1) {
-    for (uint32_t k = 0; k < B; ++k) ps.dst[k] = reqs[k].out;
-    hipLaunchKernelGGL(batch_copy_kernel<false>, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0,
-                       sl.s, ps, out, nullptr, rows, B, n4);
+    keys.count = gs.batch = (r0.op == 1 && !same) ? B : 1;
+    const hipError_t e = r0.op == 0 ? hmult_ptrs(r0.ctx, a, b, out, r0.key, level, B, ws, sl.s)
+                                    : rotate_ptrs(r0.ctx, a, out, keys, gs, level, B, ws, sl.s);
+    if (e != hipSuccess) return fail(TFHE_EHIP, "server: batch launch failed");
+    OutPtrs dst{};
+    for (uint32_t k = 0; k < B; ++k) dst.p[k] = reqs[k].out;
+    const uint32_t rows = 2 * level, n4 = n / 4;
+    hipLaunchKernelGGL(scatter_kernel, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0, sl.s,
+                       (const uint4*)out, dst, rows, B, n4);
   }
   if (hipGetLastError() != hipSuccess) return TFHE_EHIP;
   if (hipEventRecord(sl.done, sl.s) != hipSuccess) return TFHE_EHIP;
