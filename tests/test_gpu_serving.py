@@ -172,3 +172,56 @@ def test_native_server_close_with_requests_in_flight(world):
         srv.submit(op, a, b, g or 0)
     srv.close()
     torch.cuda.synchronize()
+
+
+def test_native_server_full_size_requests():
+    """Config-5 shapes: N = 2^16, L = 24, K = 8, dnum = 3; HMULT at level 24
+    and 1, rotations by two amounts at level 13, in batches the dispatcher
+    forms (inputs read in place, results scattered).  Every result equals the
+    single-request call; one rotation is also checked against the oracle."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import ckks
+    from paper_2212_14191_amd import tfhe
+    from paper_2212_14191_amd.scheme import Scheme
+    ln, L, K, dnum = 16, 24, 8, 3
+    n = 1 << ln
+    ctx = tfhe.CkksContext(ln, L, K, dnum)
+    sch = Scheme(ctx)
+    s = inputs.ternary_secret(1, n, 192)
+    a = inputs.uniform_residues(1, ctx.moduli, (dnum, n), stream=1).transpose(1, 0, 2)
+    e = inputs.gaussian_error(2, (dnum, n), stream=1)
+    evk = sch.relin_key(s, a, e)
+    gal = [pow(5, 1, 2 * n), pow(5, 64, 2 * n)]
+    rks = {g: sch.rotation_key(s, g, a, e) for g in gal}
+    cts = {}
+    for level in (1, 13, 24):
+        for i in range(3):
+            m = inputs.small_messages(i, (1, n))
+            c1 = inputs.uniform_residues(20 + i, ctx.moduli[:level], (1, n), stream=5)
+            cts[(level, i)] = sch.encrypt(s, m, c1, inputs.gaussian_error(2, (1, n), stream=30 + i), level)
+    reqs = [(0, 24, 0, 1, None), (0, 24, 1, 2, None), (0, 24, 2, 0, None), (0, 24, 1, 1, None),
+            (1, 13, 0, None, gal[0]), (1, 13, 1, None, gal[1]), (1, 13, 2, None, gal[0]),
+            (1, 13, 0, None, gal[1]), (0, 1, 0, 2, None), (0, 1, 1, 0, None)]
+    srv = tfhe.NativeServer(slots=2, max_batch=8, pool_bytes=8 << 30)
+    srv.add_context(ctx, evk, rks)
+    outs = []
+    for op, lv, i, j, g in reqs:
+        if op == 0:
+            outs.append(srv.hmult(cts[(lv, i)], cts[(lv, j)])[1])
+        else:
+            outs.append(srv.rotate(cts[(lv, i)], g)[1])
+    done = drain(srv, len(reqs), timeout=120)
+    assert all(st is None for st in done.values()), done
+    for (op, lv, i, j, g), got in zip(reqs, outs):
+        if op == 0:
+            want = ctx.hmult(cts[(lv, i)], cts[(lv, j)], evk, lv)
+        else:
+            want = ctx.rotate(cts[(lv, i)], rks[g], g, lv)
+        assert torch.equal(got, want), (op, lv, i, j, g)
+    srv.close()
+    pr = ckks.Params(n, L=L, K=K, dnum=dnum, moduli=list(ctx.moduli))
+    ct = cts[(13, 1)].cpu().numpy().view(np.uint32)
+    rk = rks[gal[1]].cpu().numpy().view(np.uint32)
+    want = ckks.rotate(pr, ct, rk, gal[1], 13)
+    assert np.array_equal(outs[5].cpu().numpy().view(np.uint32), want)
