@@ -308,12 +308,14 @@ tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_ba
                                size_t pool_bytes);
 
 /* Registers the context of ring dimension 2^ctx.log_n (replacing an
- * earlier one of that N) and its relinearisation key evk (device, layout as
- * for tfhe_hmult).  Both must outlive the server. */
+ * earlier one of that N for later submissions; requests already queued
+ * keep theirs) and its relinearisation key evk (device, layout as for
+ * tfhe_hmult, 16-byte aligned).  Both must outlive the server. */
 tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint32_t* evk);
 
-/* Registers the rotation key (device, layout as for tfhe_rotate) of Galois
- * element galois_elt (odd, < 2N) for the context of N = 2^log_n. */
+/* Registers the rotation key (device, layout as for tfhe_rotate, 16-byte
+ * aligned; it must outlive the server) of Galois element galois_elt (odd,
+ * < 2N) for the context of N = 2^log_n. */
 tfhe_status tfhe_server_add_rotation_key(tfhe_server s, uint32_t log_n, uint32_t galois_elt,
                                          const uint32_t* rotkey);
 
@@ -340,7 +342,8 @@ tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint3
 uint32_t tfhe_server_poll(tfhe_server s, uint64_t* tags, int32_t* status, uint32_t max);
 
 /* Waits for the batches in flight, then frees the server; requests not yet
- * dispatched are dropped without completion. */
+ * dispatched are dropped without completion.  The other tfhe_server_* calls
+ * may come from any thread, but none may overlap this one. */
 tfhe_status tfhe_server_destroy(tfhe_server s);
 
 /* ------------------------------------------------------------ measurement */

@@ -69,8 +69,9 @@ struct Req {
 
 struct Key {
   uint32_t op, log_n, level;
+  tfhe_ckks_ctx ctx;  // requests submitted before a context was replaced batch apart
   bool operator<(const Key& o) const {
-    return std::tie(op, log_n, level) < std::tie(o.op, o.log_n, o.level);
+    return std::tie(op, log_n, level, ctx) < std::tie(o.op, o.log_n, o.level, o.ctx);
   }
 };
 
@@ -109,11 +110,11 @@ struct tfhe_server_s {
   bool stop = false;
   std::vector<std::thread> workers;
 
-  // slot memory a batch of B requests of key k needs (caller holds mu)
-  size_t need(const Key& k, uint32_t B) const {
-    const size_t ct = (size_t)2 * k.level * B * ((size_t)1 << k.log_n) * 4;
+  // slot memory a batch of B requests like r needs
+  static size_t need(const Req& r, uint32_t B) {
+    const size_t ct = (size_t)2 * r.level * B * ((size_t)1 << r.log_n) * 4;
     size_t ws = 0;
-    tfhe_hmult_workspace_size(ctxs.at(k.log_n).ctx, k.level, B, &ws);
+    tfhe_hmult_workspace_size(r.ctx, r.level, B, &ws);
     const size_t staging = B > 1 ? align256(ct) : 0;  // the batch result
     return staging + align256(ws);
   }
@@ -181,8 +182,8 @@ bool tfhe_server_s::take(const Slot& sl, std::vector<Req>& reqs) {
   const Key key = order.front().second;
   std::deque<Req>& q = pending[key];
   uint32_t B = std::min<uint32_t>((uint32_t)q.size(), max_batch);
-  while (B > 1 && need(key, B) > sl.bytes) B /= 2;
-  if (need(key, B) > sl.bytes) return false;  // cannot happen: submission checks one request
+  while (B > 1 && need(q.front(), B) > sl.bytes) B /= 2;
+  if (need(q.front(), B) > sl.bytes) return false;  // cannot happen: submission checks one request
   reqs.assign(q.begin(), q.begin() + B);
   q.erase(q.begin(), q.begin() + B);
   if (q.empty()) pending.erase(key);
@@ -254,6 +255,7 @@ tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_ba
 
 tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint32_t* evk) {
   if (!s || !ctx || !evk) return fail(TFHE_EINVAL, "server_add_context: null argument");
+  if ((uintptr_t)evk % 16) return fail(TFHE_EINVAL, "server_add_context: evk not 16-byte aligned");
   std::lock_guard<std::mutex> g(s->mu);
   Ctx& c = s->ctxs[ctx->log_n];
   c.ctx = ctx;
@@ -264,6 +266,7 @@ tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint
 tfhe_status tfhe_server_add_rotation_key(tfhe_server s, uint32_t log_n, uint32_t galois_elt,
                                          const uint32_t* rotkey) {
   if (!s || !rotkey) return fail(TFHE_EINVAL, "server_add_rotation_key: null argument");
+  if ((uintptr_t)rotkey % 16) return fail(TFHE_EINVAL, "server_add_rotation_key: key not 16-byte aligned");
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->ctxs.find(log_n);
   if (it == s->ctxs.end()) return fail(TFHE_EINVAL, "server_add_rotation_key: no context for this N");
@@ -297,7 +300,7 @@ tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint3
       key = k->second;
     }
     req = Req{op, log_n, level, galois_elt, ct_a, ct_b, ct_out, tag, 0, nullptr, c.ctx, key};
-    if (s->need(Key{op, log_n, level}, 1) > s->slots[0].bytes)
+    if (tfhe_server_s::need(req, 1) > s->slots[0].bytes)
       return fail(TFHE_ENOMEM, "server_submit: one request exceeds a slot's share of the pool");
     if (!s->event_pool.empty()) {
       ev = s->event_pool.back();
@@ -312,7 +315,7 @@ tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint3
   }
   {
     std::lock_guard<std::mutex> g(s->mu);
-    const Key k{op, log_n, level};
+    const Key k{op, log_n, level, req.ctx};
     req.seq = s->next_seq++;
     req.ready = ev;
     s->pending[k].push_back(req);
