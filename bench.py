@@ -109,7 +109,7 @@ def cpu_baseline(qs, psis, budget_s=12.0):
                       f"({transforms} limb-transforms, {dt:.1f} s)"}
 
 
-def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs):
+def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native")):
     """Config 5: Poisson HMULT / rotate requests, N in {2^13..2^16}, levels
     uniform in 1..24, 8 rotation keys per N, keys and ciphertexts resident,
     memory-gated continuous batching.  Returns throughput and p50/p99."""
@@ -203,6 +203,8 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs):
 
     out = {"requests": n_req, "max_batch": 16}
     for name, fn in (("python", run), ("native", run_native)):
+        if name not in engines:
+            continue
         fn(min(500, n_sat), 99, 0)  # warm-up
         sat = fn(n_sat, 98, 0)
         res = {"slots": native_slots if name == "native" else slots,
@@ -229,7 +231,8 @@ def main():
     ap.add_argument("--skip-hmult", action="store_true")
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=10000)
-    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult"], default=None,
+    ap.add_argument("--serving-engine", choices=["both", "python", "native"], default="both")
+    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving"], default=None,
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of the input batch (a known-size "
@@ -249,20 +252,22 @@ def main():
 
     qs = tfhe.tfhe_find_primes(31, 1 << 17, LIMBS)
     plan = tfhe.NttPlan(LOG_N, qs)
-    log(f"generating {LIMBS}x{BATCH}x{n} uniform residues")
-    x_host = inputs.uniform_residues(0, qs, (BATCH, n))
-    x = torch.from_numpy(x_host.view(np.int32)).cuda()
-    del x_host
-    y = torch.empty_like(x)
-    z = torch.empty_like(x)
-    ws = plan.workspace(LIMBS, BATCH, "mfma")
     units = LIMBS * BATCH
-
-    if args.copy_calib:
-        y.copy_(x)
-        sync()
     results = {}
-    algos = ["mfma", "butterfly", "co"] if args.only is None else [args.only] if args.only != "hmult" else []
+    algos = (["mfma", "butterfly", "co"] if args.only is None else
+             [] if args.only in ("hmult", "serving") else [args.only])
+    x = y = z = ws = None
+    if algos:
+        log(f"generating {LIMBS}x{BATCH}x{n} uniform residues")
+        x_host = inputs.uniform_residues(0, qs, (BATCH, n))
+        x = torch.from_numpy(x_host.view(np.int32)).cuda()
+        del x_host
+        y = torch.empty_like(x)
+        z = torch.empty_like(x)
+        ws = plan.workspace(LIMBS, BATCH, "mfma")
+        if args.copy_calib:
+            y.copy_(x)
+            sync()
     # measured bandwidth ceiling: a plain device copy of the same batch
     # (reads and writes the algorithmic bytes of one pass launch)
     copy_gbs = None
@@ -353,9 +358,10 @@ def main():
         del cts, out, hws, evk, ctx, rs_out, rws
 
     serving = None
-    if not args.skip_serving and args.only is None:
+    if not args.skip_serving and args.only in (None, "serving"):
+        engines = ("python", "native") if args.serving_engine == "both" else (args.serving_engine,)
         serving = serving_leg(args.serving_requests, args.serving_requests, (0.25, 0.5, 0.75, 0.9), torch, tfhe,
-                              inputs)
+                              inputs, engines)
         log("serving", json.dumps(serving))
 
     cpu = None
@@ -364,8 +370,8 @@ def main():
         log("cpu", json.dumps(cpu))
 
     head = results.get("mfma") or results.get("butterfly") or results.get("co")
-    if head is None:  # --only hmult (profiling runs)
-        print(json.dumps({"hmult": hmult}), flush=True)
+    if head is None:  # --only hmult / serving (profiling runs)
+        print(json.dumps({"hmult": hmult, "serving": serving}), flush=True)
         return
     kname, kstat = max(head["kernels"].items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
     bytes_per_launch = 2 * units * n * 4  # one read and one write of every residue
