@@ -176,20 +176,26 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         arrivals = inputs.poisson_arrivals(seed, rate, count) if rate else np.zeros(count)
         t_sub, t_done = np.zeros(count), np.full(count, np.nan)
         first, i, completed = {}, 0, 0
+        ops, lns, lvs, rts = (mix[k].tolist() for k in ("op", "log_n", "level", "rot"))
         t0 = time.perf_counter()
         while completed < count:
             now = time.perf_counter() - t0
-            while i < count and arrivals[i] <= now:
-                ln, lv = int(mix["log_n"][i]), int(mix["level"][i])
+            batch, idx = [], []
+            while i < count and arrivals[i] <= now:  # everything that has arrived, in one call
+                ln, lv = lns[i], lvs[i]
                 c = pool[(ln, lv)]
-                if mix["op"][i] == 0:
-                    tag, _ = native.hmult(c[0], c[1])
+                if ops[i] == 0:
+                    batch.append((0, c[0], c[1], 0, None))
                 else:
-                    tag, _ = native.rotate(c[0], pow(5, int(mix["rot"][i]), 2 << ln))
-                first[tag] = i
-                t_sub[i] = time.perf_counter() - t0
+                    batch.append((1, c[0], None, pow(5, rts[i], 2 << ln), None))
+                idx.append(i)
                 i += 1
-                now = t_sub[i - 1]
+            if batch:
+                tags = native.submit_many(batch)
+                now = time.perf_counter() - t0
+                for (tag, _), k in zip(tags, idx):
+                    first[tag] = k
+                    t_sub[k] = now
             for tag, st in native.poll():
                 if st is not None:
                     raise RuntimeError(f"request {tag} failed: {st}")
@@ -240,7 +246,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the NTT/HMULT "
-              "path shards by ciphertext with no collective, see DESIGN.md", file=sys.stderr)
+              "path shards by ciphertext with no collective between GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch

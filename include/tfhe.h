@@ -336,6 +336,23 @@ tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint3
                                const uint32_t* ct_a, const uint32_t* ct_b, uint32_t galois_elt,
                                uint32_t* ct_out, uint64_t tag, tfhe_stream_t stream);
 
+/* One request of tfhe_server_submit_many (fields as the arguments of
+ * tfhe_server_submit). */
+typedef struct {
+  uint32_t op, log_n, level, galois_elt;
+  const uint32_t* ct_a;
+  const uint32_t* ct_b;
+  uint32_t* ct_out;
+  uint64_t tag;
+} tfhe_server_request;
+
+/* Queues reqs[0..count) (host array, read during the call) with the checks
+ * of tfhe_server_submit; all of them wait for the work queued on `stream`
+ * before this call.  If one fails its checks nothing is queued, the error
+ * is returned and *bad (if not NULL) is set to its index. */
+tfhe_status tfhe_server_submit_many(tfhe_server s, const tfhe_server_request* reqs, uint32_t count,
+                                    tfhe_stream_t stream, uint32_t* bad);
+
 /* Moves up to `max` completed requests into tags[] / status[] (host
  * arrays) and returns how many.  status is TFHE_OK once the result is in
  * ct_out (the device work has finished), else the error of its batch. */

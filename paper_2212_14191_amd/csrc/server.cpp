@@ -107,6 +107,7 @@ struct tfhe_server_s {
   uint64_t next_seq = 0;
   std::vector<std::pair<uint64_t, int32_t>> done;
   std::vector<hipEvent_t> event_pool;
+  std::map<hipEvent_t, uint32_t> ev_refs;  // readiness events in use -> requests holding them
   bool stop = false;
   std::vector<std::thread> workers;
 
@@ -118,6 +119,15 @@ struct tfhe_server_s {
     const size_t staging = B > 1 ? align256(ct) : 0;  // the batch result
     return staging + align256(ws);
   }
+  // a request holding e is done with it (caller holds mu)
+  void release_event(hipEvent_t e) {
+    auto it = ev_refs.find(e);
+    if (it != ev_refs.end() && --it->second == 0) {
+      ev_refs.erase(it);
+      event_pool.push_back(e);
+    }
+  }
+  tfhe_status check(const tfhe_server_request& q, Req& out);
   bool take(const Slot& sl, std::vector<Req>& reqs);
   void worker(Slot& sl);
   int launch(Slot& sl, std::vector<Req>& reqs);
@@ -126,8 +136,12 @@ struct tfhe_server_s {
 int tfhe_server_s::launch(Slot& sl, std::vector<Req>& reqs) {
   const Req& r0 = reqs[0];
   const uint32_t B = (uint32_t)reqs.size(), level = r0.level, n = 1u << r0.log_n;
-  for (const Req& r : reqs)
+  hipEvent_t waited = nullptr;  // requests submitted together share one event
+  for (const Req& r : reqs) {
+    if (r.ready == waited) continue;
     if (hipStreamWaitEvent(sl.s, r.ready, 0) != hipSuccess) return TFHE_EHIP;
+    waited = r.ready;
+  }
   size_t ws_bytes = 0;
   tfhe_hmult_workspace_size(r0.ctx, level, B, &ws_bytes);
   bool same = true;  // one Galois element for the whole batch
@@ -213,9 +227,32 @@ void tfhe_server_s::worker(Slot& sl) {
     lk.lock();
     for (const Req& r : reqs) {
       done.emplace_back(r.tag, st);
-      event_pool.push_back(r.ready);
+      release_event(r.ready);
     }
   }
+}
+
+// Validates one request and resolves its context and key (caller holds mu).
+tfhe_status tfhe_server_s::check(const tfhe_server_request& q, Req& out) {
+  if (q.op > 1) return fail(TFHE_EINVAL, "server_submit: op is 0 (HMULT) or 1 (HROTATE)");
+  auto it = ctxs.find(q.log_n);
+  if (it == ctxs.end()) return fail(TFHE_EINVAL, "server_submit: no context for this N");
+  const Ctx& c = it->second;
+  if (q.level < 1 || q.level > c.ctx->L) return fail(TFHE_EINVAL, "server_submit: level must be in [1, L]");
+  const auto al16 = [](const void* p) { return p && (uintptr_t)p % 16 == 0; };
+  if (!al16(q.ct_a) || !al16(q.ct_out) || (q.op == 0 && !al16(q.ct_b)))
+    return fail(TFHE_EINVAL, "server_submit: null or unaligned ciphertext");
+  if (q.op == 1 && q.ct_a == q.ct_out) return fail(TFHE_EINVAL, "server_submit: rotation input and output alias");
+  const uint32_t* key = c.evk;
+  if (q.op == 1) {
+    auto k = c.rk.find(q.galois_elt);
+    if (k == c.rk.end()) return fail(TFHE_EINVAL, "server_submit: no rotation key for this element");
+    key = k->second;
+  }
+  out = Req{q.op, q.log_n, q.level, q.galois_elt, q.ct_a, q.ct_b, q.ct_out, q.tag, 0, nullptr, c.ctx, key};
+  if (need(out, 1) > slots[0].bytes)
+    return fail(TFHE_ENOMEM, "server_submit: one request exceeds a slot's share of the pool");
+  return TFHE_OK;
 }
 
 extern "C" {
@@ -276,32 +313,22 @@ tfhe_status tfhe_server_add_rotation_key(tfhe_server s, uint32_t log_n, uint32_t
   return TFHE_OK;
 }
 
-tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint32_t level, const uint32_t* ct_a,
-                               const uint32_t* ct_b, uint32_t galois_elt, uint32_t* ct_out, uint64_t tag,
-                               tfhe_stream_t stream) {
+tfhe_status tfhe_server_submit_many(tfhe_server s, const tfhe_server_request* reqs, uint32_t count,
+                                    tfhe_stream_t stream, uint32_t* bad) {
   if (!s) return fail(TFHE_EINVAL, "server_submit: null server");
-  if (op > 1) return fail(TFHE_EINVAL, "server_submit: op is 0 (HMULT) or 1 (HROTATE)");
+  if (count == 0) return TFHE_OK;
+  if (!reqs) return fail(TFHE_EINVAL, "server_submit_many: null request array");
+  std::vector<Req> batch(count);
   hipEvent_t ev = nullptr;
-  Req req;
   {
     std::lock_guard<std::mutex> g(s->mu);
-    auto it = s->ctxs.find(log_n);
-    if (it == s->ctxs.end()) return fail(TFHE_EINVAL, "server_submit: no context for this N");
-    const Ctx& c = it->second;
-    if (level < 1 || level > c.ctx->L) return fail(TFHE_EINVAL, "server_submit: level must be in [1, L]");
-    const auto al16 = [](const void* p) { return p && (uintptr_t)p % 16 == 0; };
-    if (!al16(ct_a) || !al16(ct_out) || (op == 0 && !al16(ct_b)))
-      return fail(TFHE_EINVAL, "server_submit: null or unaligned ciphertext");
-    if (op == 1 && ct_a == ct_out) return fail(TFHE_EINVAL, "server_submit: rotation input and output alias");
-    const uint32_t* key = c.evk;
-    if (op == 1) {
-      auto k = c.rk.find(galois_elt);
-      if (k == c.rk.end()) return fail(TFHE_EINVAL, "server_submit: no rotation key for this element");
-      key = k->second;
+    for (uint32_t i = 0; i < count; ++i) {
+      const tfhe_status st = s->check(reqs[i], batch[i]);
+      if (st != TFHE_OK) {
+        if (bad) *bad = i;
+        return st;
+      }
     }
-    req = Req{op, log_n, level, galois_elt, ct_a, ct_b, ct_out, tag, 0, nullptr, c.ctx, key};
-    if (tfhe_server_s::need(req, 1) > s->slots[0].bytes)
-      return fail(TFHE_ENOMEM, "server_submit: one request exceeds a slot's share of the pool");
     if (!s->event_pool.empty()) {
       ev = s->event_pool.back();
       s->event_pool.pop_back();
@@ -315,14 +342,25 @@ tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint3
   }
   {
     std::lock_guard<std::mutex> g(s->mu);
-    const Key k{op, log_n, level, req.ctx};
-    req.seq = s->next_seq++;
-    req.ready = ev;
-    s->pending[k].push_back(req);
-    s->order.emplace_back(req.seq, k);
+    s->ev_refs[ev] = count;
+    for (Req& r : batch) {
+      const Key k{r.op, r.log_n, r.level, r.ctx};
+      r.seq = s->next_seq++;
+      r.ready = ev;
+      s->pending[k].push_back(r);
+      s->order.emplace_back(r.seq, k);
+    }
   }
-  s->cv.notify_one();
+  if (count == 1) s->cv.notify_one();
+  else s->cv.notify_all();
   return TFHE_OK;
+}
+
+tfhe_status tfhe_server_submit(tfhe_server s, uint32_t op, uint32_t log_n, uint32_t level, const uint32_t* ct_a,
+                               const uint32_t* ct_b, uint32_t galois_elt, uint32_t* ct_out, uint64_t tag,
+                               tfhe_stream_t stream) {
+  const tfhe_server_request r{op, log_n, level, galois_elt, ct_a, ct_b, ct_out, tag};
+  return tfhe_server_submit_many(s, &r, 1, stream, nullptr);
 }
 
 uint32_t tfhe_server_poll(tfhe_server s, uint64_t* tags, int32_t* status, uint32_t max) {
@@ -350,8 +388,7 @@ tfhe_status tfhe_server_destroy(tfhe_server s) {
     if (sl.s) hipStreamDestroy(sl.s);
   }
   for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
-  for (auto& kv : s->pending)
-    for (Req& r : kv.second) hipEventDestroy(r.ready);
+  for (auto& kv : s->ev_refs) hipEventDestroy(kv.first);  // held by requests never dispatched
   delete s;
   return TFHE_OK;
 }

@@ -22,6 +22,13 @@ ALGOS = {"auto": AUTO, "butterfly": BUTTERFLY, "mfma": FOURSTEP_MFMA, "co": FOUR
 _lib = None
 
 
+class ServerRequest(ctypes.Structure):
+    """tfhe_server_request."""
+    _fields_ = [("op", ctypes.c_uint32), ("log_n", ctypes.c_uint32), ("level", ctypes.c_uint32),
+                ("galois_elt", ctypes.c_uint32), ("ct_a", ctypes.c_void_p), ("ct_b", ctypes.c_void_p),
+                ("ct_out", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
 class NttDesc(ctypes.Structure):
     """tfhe_ntt_desc: one transform of a fused batch."""
     _fields_ = [("plan", ctypes.c_void_p), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
@@ -88,6 +95,7 @@ def load():
         "tfhe_server_add_context": ([vp, vp, vp], i32),
         "tfhe_server_add_rotation_key": ([vp, u32, u32, vp], i32),
         "tfhe_server_submit": ([vp, u32, u32, u32, vp, vp, u32, vp, u64, vp], i32),
+        "tfhe_server_submit_many": ([vp, ctypes.POINTER(ServerRequest), u32, vp, ctypes.POINTER(u32)], i32),
         "tfhe_server_poll": ([vp, ctypes.POINTER(u64), ctypes.POINTER(i32), u32], u32),
         "tfhe_server_destroy": ([vp], i32),
     }
@@ -498,6 +506,35 @@ class NativeServer:
               tag, _stream(stream))
         self._live[tag] = (ct_a, ct_b, out)
         return tag, out
+
+    def submit_many(self, reqs, stream=None):
+        """Queues several requests in one call (one readiness event for all):
+        reqs is a list of (op, ct_a, ct_b or None, galois, out or None).
+        Returns [(tag, out)]; nothing is queued if one request is rejected."""
+        arr = (ServerRequest * len(reqs))()
+        res, live = [], []
+        for i, (op, a, b, g, out) in enumerate(reqs):
+            level, n = a.shape[1], a.shape[-1]
+            if a.numel() != 2 * level * n:
+                raise ValueError("one ciphertext [2][level][N] per request")
+            _check_residues(a, "ct_a")
+            if op == self.HMULT:
+                _check_residues(b, "ct_b", a.shape)
+            if out is None:
+                out = torch_empty_like(a)
+            _check_residues(out, "out", a.shape)
+            tag = self._next + i
+            r = arr[i]
+            r.op, r.log_n, r.level, r.galois_elt = op, n.bit_length() - 1, level, int(g or 0)
+            r.ct_a, r.ct_b, r.ct_out, r.tag = a.data_ptr(), b.data_ptr() if b is not None else 0, out.data_ptr(), tag
+            res.append((tag, out))
+            live.append((a, b, out))
+        bad = ctypes.c_uint32()
+        _call("tfhe_server_submit_many", self.handle, arr, len(reqs), _stream(stream), ctypes.byref(bad))
+        self._next += len(reqs)
+        for (tag, _), t in zip(res, live):
+            self._live[tag] = t
+        return res
 
     def hmult(self, ct_a, ct_b, out=None, stream=None):
         return self.submit(self.HMULT, ct_a, ct_b, 0, out, stream)

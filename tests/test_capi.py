@@ -97,3 +97,12 @@ def test_server_rejects_bad_arguments(tf):
     tags, status = (ctypes.c_uint64 * 4)(), (ctypes.c_int * 4)()
     assert lib.tfhe_server_poll(None, tags, status, 4) == 0
     assert lib.tfhe_server_destroy(None) == tf.TFHE_OK
+
+
+def test_server_request_struct_and_batched_submit_checks(tf):
+    assert ctypes.sizeof(tf.ServerRequest) == 48  # uint32 x 4, three pointers, uint64
+    lib = tf.load()
+    arr = (tf.ServerRequest * 2)()
+    bad = ctypes.c_uint32(7)
+    assert lib.tfhe_server_submit_many(None, arr, 2, None, ctypes.byref(bad)) == tf.TFHE_EINVAL
+    assert bad.value == 7

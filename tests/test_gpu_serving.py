@@ -225,3 +225,27 @@ def test_native_server_full_size_requests():
     rk = rks[gal[1]].cpu().numpy().view(np.uint32)
     want = ckks.rotate(pr, ct, rk, gal[1], 13)
     assert np.array_equal(outs[5].cpu().numpy().view(np.uint32), want)
+
+
+def test_native_server_submit_many(world):
+    """Requests queued in groups (one readiness event per group) give the
+    single-request results; a group with one bad request queues nothing."""
+    from paper_2212_14191_amd import tfhe
+    reqs = requests(world, 30, 3)
+    alone = alone_results(world, reqs)
+    srv = native_server(world, slots=3, max_batch=8, pool_bytes=512 << 20)
+    _, _, _, cts = world
+    bad_group = [(0, cts[(10, 2, 0)], cts[(10, 2, 1)], 0, None), (1, cts[(10, 2, 0)], None, 7, None)]
+    with pytest.raises(tfhe.TfheError):
+        srv.submit_many(bad_group)  # the second has no rotation key: nothing is queued
+    assert srv.pending() == 0
+    outs = []
+    for lo in range(0, len(reqs), 7):
+        group = [(op, a, b, g or 0, None) for op, ln, lv, a, b, g in reqs[lo:lo + 7]]
+        outs += srv.submit_many(group)
+    done = drain(srv, len(reqs))
+    assert all(st is None for st in done.values()), done
+    assert sorted(done) == [tag for tag, _ in outs]
+    for (tag, out), want in zip(outs, alone):
+        assert torch.equal(out, want), tag
+    srv.close()
