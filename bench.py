@@ -109,7 +109,7 @@ def cpu_baseline(qs, psis, budget_s=12.0):
                       f"({transforms} limb-transforms, {dt:.1f} s)"}
 
 
-def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native")):
+def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native"), native_slots=8):
     """Config 5: Poisson HMULT / rotate requests, N in {2^13..2^16}, levels
     uniform in 1..24, 8 rotation keys per N, keys and ciphertexts resident,
     memory-gated continuous batching.  Returns throughput and p50/p99."""
@@ -166,7 +166,6 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         return st
 
     # the library's own dispatcher (tfhe_server_*), same mix, same keys
-    native_slots = 8  # worker threads / streams of the native dispatcher
     native = tfhe.NativeServer(slots=native_slots, max_batch=16, pool_bytes=native_slots * (3 << 30))
     for ln in log_ns:
         native.add_context(ctxs[ln], evks[ln], {g: k for (l2, g), k in rks.items() if l2 == ln})
@@ -238,6 +237,8 @@ def main():
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-engine", choices=["both", "python", "native"], default="both")
+    ap.add_argument("--native-slots", type=int, default=8,
+                    help="worker threads (one stream each) of the native dispatcher")
     ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving"], default=None,
                     help="time one leg only (for profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -367,7 +368,7 @@ def main():
     if not args.skip_serving and args.only in (None, "serving"):
         engines = ("python", "native") if args.serving_engine == "both" else (args.serving_engine,)
         serving = serving_leg(args.serving_requests, args.serving_requests, (0.25, 0.5, 0.75, 0.9), torch, tfhe,
-                              inputs, engines)
+                              inputs, engines, args.native_slots)
         log("serving", json.dumps(serving))
 
     cpu = None
