@@ -396,8 +396,9 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "negacyclic NTT+INTT, N=2^16, 44 limbs x 128 polys, four-step INT8 MFMA"
-                   if "mfma" in results else "negacyclic NTT+INTT, N=2^16, 44 limbs x 128 polys, butterfly",
+        "config": {"workload": "negacyclic NTT+INTT, N=2^16, 44 limbs x 128 polys, " +
+                   ("four-step INT8 MFMA" if "mfma" in results else
+                    "butterfly" if "butterfly" in results else "four-step vector-ALU GEMM"),
                    "log_n": LOG_N, "limbs": LIMBS, "batch": BATCH, "primes": "31-bit, q = 1 mod 2^17"},
         "roofline": {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
