@@ -209,7 +209,7 @@ bool tfhe_server_s::take(const Slot& sl, std::vector<Req>& reqs) {
 // for it (spinning: a completed batch is reported within microseconds),
 // report it, repeat.  Workers launch concurrently.
 void tfhe_server_s::worker(Slot& sl) {
-  hipSetDevice(device);
+  (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     std::vector<Req> reqs;
@@ -222,7 +222,7 @@ void tfhe_server_s::worker(Slot& sl) {
       while ((q = hipEventQuery(sl.done)) == hipErrorNotReady) std::this_thread::yield();
       if (q != hipSuccess) st = TFHE_EHIP;
     } else {
-      hipStreamSynchronize(sl.s);  // a failed batch reports at once: let what it queued finish first
+      (void)hipStreamSynchronize(sl.s);  // a failed batch reports at once: let what it queued finish first
     }
     lk.lock();
     for (const Req& r : reqs) {
@@ -337,7 +337,7 @@ tfhe_status tfhe_server_submit_many(tfhe_server s, const tfhe_server_request* re
   if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
     return fail(TFHE_EHIP, "server_submit: event creation");
   if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
-    hipEventDestroy(ev);
+    (void)hipEventDestroy(ev);
     return fail(TFHE_EHIP, "server_submit: event record");
   }
   {
@@ -384,11 +384,11 @@ tfhe_status tfhe_server_destroy(tfhe_server s) {
   s->cv.notify_all();
   for (std::thread& t : s->workers) t.join();  // each finishes its batch in flight
   for (Slot& sl : s->slots) {
-    if (sl.done) hipEventDestroy(sl.done);
-    if (sl.s) hipStreamDestroy(sl.s);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.s) (void)hipStreamDestroy(sl.s);
   }
-  for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
-  for (auto& kv : s->ev_refs) hipEventDestroy(kv.first);  // held by requests never dispatched
+  for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  for (auto& kv : s->ev_refs) (void)hipEventDestroy(kv.first);  // held by requests never dispatched
   delete s;
   return TFHE_OK;
 }
