@@ -365,9 +365,11 @@ tfhe_status tfhe_server_destroy(tfhe_server s);
 
 /* ------------------------------------------------------------ measurement */
 
-/* Per-kernel timing.  While enabled, the library brackets every kernel it
- * launches with a pair of HIP events recorded on that kernel's stream.
- * tfhe_timing_enable(0 or 1) also discards earlier records. */
+/* Per-kernel timing.  While enabled, the library brackets every kernel of
+ * the transform, element-wise and CKKS entry points (also when the request
+ * dispatcher runs them; its result scatter is not timed) with a pair of
+ * HIP events recorded on that kernel's stream.  tfhe_timing_enable(0 or 1)
+ * also discards earlier records. */
 tfhe_status tfhe_timing_enable(int enable);
 
 /* Launch count and summed event-measured duration (ms) of the kernel named
