@@ -267,3 +267,27 @@ def test_cmult_hadd_match_oracle(tf):
     a = to_dev(c1)
     ctx.hadd(a, to_dev(c2), level, out=a)   # in place
     assert np.array_equal(to_host(a), ckks.hadd(pr, c1, c2, level))
+
+
+def test_rotate_multi_at_the_batch_limit(tf):
+    """TFHE_ROTATE_MULTI_MAX (64) ciphertexts, three rotation amounts and
+    conjugation interleaved: each equals its rotation alone (one also
+    against the oracle)."""
+    n = 1 << 10
+    L, K, dnum, level = 6, 2, 3, 4
+    pr, s, _, (a, e) = setup(n, L, K, dnum)
+    kinds = [ckks.galois_element(1, n), ckks.galois_element(2, n), ckks.galois_element(5, n), 2 * n - 1]
+    B = tf.CkksContext.ROTATE_MULTI_MAX
+    gal = [kinds[b % 4] for b in range(B)]
+    rks = {k: ckks.rotation_key(pr, s, k, a, e) for k in kinds}
+    drk = {k: to_dev(v) for k, v in rks.items()}
+    ctx = tf.CkksContext(10, L, K, dnum, moduli=pr.moduli)
+    m = inputs.small_messages(5, (B, n))
+    ct = encrypt(pr, s, m, level, 6)
+    got = to_host(ctx.rotate_multi(to_dev(ct), [drk[k] for k in gal], gal, level))
+    for b in range(B):
+        one = to_dev(np.ascontiguousarray(ct[:, :, b:b + 1]))
+        alone = to_host(ctx.rotate(one, drk[gal[b]], gal[b], level))
+        assert np.array_equal(got[:, :, b:b + 1], alone), b
+    want = ckks.rotate(pr, np.ascontiguousarray(ct[:, :, 41:42]), rks[gal[41]], gal[41], level)
+    assert np.array_equal(got[:, :, 41:42], want)

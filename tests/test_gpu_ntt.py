@@ -270,3 +270,22 @@ def test_valu_gemm_variant_matches_oracle(tf):
         small.fwd(to_dev(inputs.uniform_residues(1, qs[:1], (1, 1 << 15))), algo="co")
     with pytest.raises(tf.TfheError):
         tf.ntt_batch([(plan, y, torch.empty_like(y), False, 0)], algo="co")
+
+
+def test_fused_batch_beyond_one_launch_table(tf):
+    """More units than one launch's descriptor table holds (40 for the
+    four-step passes, 32 for the butterfly): 83 transforms of N = 2^12 with
+    different limb offsets, batches and directions, each equal to the oracle."""
+    plan = tf.NttPlan(12, PRIMES31[:4])
+    n = 1 << 12
+    items, refs = [], []
+    for k in range(83):
+        lb, limbs, b, inv = k % 3, 1 + (k % 2), 1 + (k % 3), bool(k % 2)
+        x = inputs.uniform_residues(900 + k, plan.q[lb:lb + limbs], (b, n))
+        X = to_dev(x)
+        items.append((plan, X, torch.empty_like(X), inv, lb))
+        refs.append(oracle.ntt(x, plan.q[lb:lb + limbs], plan.psi[lb:lb + limbs], inverse=inv)[0])
+    for algo in ("mfma", "butterfly"):
+        outs = tf.ntt_batch(items, algo=algo)
+        for k, (o, r) in enumerate(zip(outs, refs)):
+            assert np.array_equal(to_host(o), r), (algo, k)
