@@ -249,3 +249,19 @@ def test_native_server_submit_many(world):
     for (tag, out), want in zip(outs, alone):
         assert torch.equal(out, want), tag
     srv.close()
+
+
+def test_native_server_full_pointer_table(world):
+    """64 requests of one key (the pointer-table limit) form one batch when
+    max_batch is 64 and the pool holds it; each equals its single call."""
+    ctxs, evks, rks, cts = world
+    g = pow(5, 3, 2 << 10)
+    reqs = [(1, 10, 5, cts[(10, 5, k % 2)], None, g) for k in range(64)]
+    srv = native_server(world, slots=1, max_batch=64, pool_bytes=256 << 20)
+    outs = srv.submit_many([(op, a, b, gg, None) for op, ln, lv, a, b, gg in reqs])
+    done = drain(srv, len(reqs))
+    assert all(st is None for st in done.values()), done
+    alone = [ctxs[10].rotate(cts[(10, 5, k)], rks[(10, g)], g, 5) for k in range(2)]
+    for k, (tag, out) in enumerate(outs):
+        assert torch.equal(out, alone[k % 2]), tag
+    srv.close()
