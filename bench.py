@@ -383,7 +383,22 @@ def main():
         hmult["rescale"] = {"ops_per_s": HM_BATCH * args.hmult_steps / dt,
                             "ms_per_batch": 1e3 * dt / args.hmult_steps, "kernels": rk}
         log("rescale", json.dumps(hmult["rescale"]))
-        del cts, out, hws, evk, ctx, rs_out, rws
+        # CMULT (plaintext = the first ciphertext's c0, in the NTT domain) and
+        # HADD at the same shape: element-wise, HBM-bound; algorithmic bytes:
+        # CMULT reads the ciphertext and the plaintext once and writes the
+        # result (2.5 ciphertexts), HADD reads two and writes one (3)
+        pt = cts[0][0].contiguous()
+        ew_out = torch.empty_like(out)
+        ct_bytes = cts[0].numel() * 4
+        for name, fn, nbytes in (("cmult", lambda: ctx.cmult(cts[0], pt, level, out=ew_out), 2.5 * ct_bytes),
+                                 ("hadd", lambda: ctx.hadd(cts[0], cts[1], level, out=ew_out), 3 * ct_bytes)):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            dt = timed(fn, args.hmult_steps, sync)
+            hmult[name] = {"ops_per_s": HM_BATCH * args.hmult_steps / dt,
+                           "gb_per_s": nbytes * args.hmult_steps / dt / 1e9}
+            log(name, json.dumps(hmult[name]))
+        del cts, out, hws, evk, ctx, rs_out, rws, pt, ew_out
 
     serving = None
     if not args.skip_serving and args.only in (None, "serving"):
@@ -438,6 +453,8 @@ def main():
     if hmult:
         line["hmult_ops_per_s"] = round(hmult["ops_per_s"], 1)
         line["rescale_ops_per_s"] = round(hmult["rescale"]["ops_per_s"], 1)
+        line["cmult_ops_per_s"] = round(hmult["cmult"]["ops_per_s"], 1)
+        line["hadd_ops_per_s"] = round(hmult["hadd"]["ops_per_s"], 1)
         line["hmult"] = hmult
     if serving:
         if "native" in serving:
