@@ -106,3 +106,20 @@ def test_server_request_struct_and_batched_submit_checks(tf):
     bad = ctypes.c_uint32(7)
     assert lib.tfhe_server_submit_many(None, arr, 2, None, ctypes.byref(bad)) == tf.TFHE_EINVAL
     assert bad.value == 7
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/tfhe.h compiles as strict C99 (no C++ or HIP types cross the
+    ABI) and its request struct has the layout the binding declares."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "h.c"
+    src.write_text('#include "tfhe.h"\n'
+                   "int main(void) { return (int)sizeof(tfhe_server_request) != 48; }\n")
+    exe = tmp_path / "h"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    assert subprocess.run([str(exe)]).returncode == 0
