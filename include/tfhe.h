@@ -310,7 +310,10 @@ tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_ba
 /* Registers the context of ring dimension 2^ctx.log_n (replacing an
  * earlier one of that N for later submissions; requests already queued
  * keep theirs) and its relinearisation key evk (device, layout as for
- * tfhe_hmult, 16-byte aligned).  Both must outlive the server. */
+ * tfhe_hmult, 16-byte aligned).  Registering a different context for an N
+ * drops the rotation keys registered for the previous one (re-registering
+ * the same context keeps them).  Contexts and keys must outlive the server:
+ * queued requests hold raw pointers to them. */
 tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint32_t* evk);
 
 /* Registers the rotation key (device, layout as for tfhe_rotate, 16-byte

@@ -42,11 +42,22 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
   const size_t plane = (size_t)batch * c->n * sizeof(uint32_t);
   const uint32_t digits = (level + c->alpha - 1) / c->alpha;
   const uint32_t ext = level + c->K;
-  // the largest fused NTT: every digit's converted limbs
-  const size_t ntt_planes = std::max<size_t>(std::max<size_t>(level, 2 * c->K),
-                                             (size_t)digits * ext - level);
-  // per-unit 256-byte rounding of the workspace slices
-  const size_t ntt_bytes = plane * ntt_planes + 256 * (3 * digits + 2);
+  // The transform region holds the largest of key_switch's four fused
+  // transforms, each unit's slice rounded to 256 bytes as fs_run_units /
+  // bf_run_units lay them out: INTT of the input (level limbs); the NTT of
+  // every digit's converted limbs; the INTT of both accumulators' K special
+  // limbs; the final NTT of both components (2 x level limbs).
+  const tfhe_ntt_plan_s* p = c->plan;
+  const bool mfma = p->algo == TFHE_NTT_FOURSTEP_MFMA;
+  auto ws = [&](uint32_t limbs) {
+    return limbs ? align256(unit_ws_bytes(NttUnit{p, false, nullptr, nullptr, 0, limbs, batch}, mfma)) : 0;
+  };
+  size_t modup = 0;
+  for (uint32_t j = 0; j < digits; ++j) {
+    const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
+    modup += ws(d0) + ws(level - d0 - nd) + ws(c->K);
+  }
+  const size_t ntt_bytes = std::max(std::max(ws(level), modup), std::max(2 * ws(c->K), 2 * ws(level)));
   KsLayout l;
   size_t off = 0;
   l.d2 = off; off += align256(plane * level);

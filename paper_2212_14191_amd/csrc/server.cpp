@@ -295,6 +295,8 @@ tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint
   if ((uintptr_t)evk % 16) return fail(TFHE_EINVAL, "server_add_context: evk not 16-byte aligned");
   std::lock_guard<std::mutex> g(s->mu);
   Ctx& c = s->ctxs[ctx->log_n];
+  // rotation keys belong to the context they were registered for
+  if (c.ctx != ctx) c.rk.clear();
   c.ctx = ctx;
   c.evk = evk;
   return TFHE_OK;

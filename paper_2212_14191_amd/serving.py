@@ -62,7 +62,7 @@ class Server:
         self._used = 0
         self._peak_used = 0
         self._lock = threading.Condition()
-        self._done = []
+        self._done = []                             # (t_submit, t_done) of completed requests
         self._stop = False
         self._next_id = 0
         self._t0 = None
@@ -98,9 +98,9 @@ class Server:
 
     def stats(self):
         with self._lock:
-            lat = np.array([r.t_done - r.t_submit for r in self._done if r.t_done is not None])
+            lat = np.array([t1 - t0 for t0, t1 in self._done])
             n = len(lat)
-            span = (max(r.t_done for r in self._done) - self._t0) if n else 0.0
+            span = (max(t1 for _, t1 in self._done) - self._t0) if n else 0.0
             return {
                 "completed": n,
                 "throughput_per_s": n / span if span > 0 else 0.0,
@@ -193,9 +193,12 @@ class Server:
                         t = time.perf_counter()
                         for r, o in zip(reqs, outs):
                             r.t_done = t
+                            # the scheduler keeps only the timing: inputs
+                            # and outputs belong to the callers from here on
+                            r.ct_a = r.ct_b = r.ready = None
                             if not r.future.cancelled():
                                 r.future.set_result(o)
-                            self._done.append(r)
+                            self._done.append((r.t_submit, t))
                         self._used -= nbytes
                         self._free_slots.append(slot)
                     else:
@@ -279,7 +282,7 @@ class GpuBackend:
         st = self.torch.cuda.current_stream()
         ev = self.torch.cuda.Event()
         ev.record(st)
-        req.ready = (st.cuda_stream, ev)
+        req.ready = (st.cuda_stream, ev, st)
 
     def _ws_bytes(self, log_n, level, batch):
         k = (log_n, level, batch)
@@ -357,11 +360,19 @@ class GpuBackend:
                                  stream=s)
         ev = self.events[slot]
         ev.record(s)
+        # the result block is allocated on s but read by the submitters on
+        # their streams: the caching allocator must not hand it out again on
+        # s before their work on it has finished
+        users = {r.ready[0]: r.ready[2] for r in reqs if r.ready is not None}
+        for st in users.values():
+            out.record_stream(st)
         return {"event": ev, "out": out, "keep": (a, bb, ws), "B": B}
 
     def done(self, h):
         return h["event"].query()
 
     def results(self, h):
+        """Per-request views of the batch output; the futures resolve after
+        the batch's device work has completed."""
         out = h["out"]
         return [out[:, :, b:b + 1] for b in range(h["B"])]

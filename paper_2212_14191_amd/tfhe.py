@@ -466,6 +466,8 @@ class NativeServer:
         _call("tfhe_server_create", ctypes.byref(h), slots, max_batch, _ptr(self.pool), pool_bytes)
         self.handle = h
         self._ctx = {}       # log_n -> (CkksContext, evk, {galois: rotkey})
+        self._keep = []      # every context and key ever registered (queued
+                             # requests hold raw pointers to them until close())
         self._live = {}      # tag -> tensors the request reads or writes
         self._next = 0
         cap = 4096
@@ -475,15 +477,22 @@ class NativeServer:
 
     def add_context(self, ctx, evk, rotkeys=None):
         """Registers ctx (CkksContext), its relinearisation key and a dict
-        {galois element: rotation key}."""
+        {galois element: rotation key}.  Registering the same context again
+        adds rotation keys to those it has; a different context for the same
+        N starts from none (the dispatcher drops the earlier ones).  Every
+        context and key stays referenced until close()."""
         _check_residues(evk, "evk", (ctx.dnum, 2, ctx.L + ctx.K, ctx.n))
-        _call("tfhe_server_add_context", self.handle, ctx.handle, _ptr(evk))
-        keys = {}
-        for g, k in (rotkeys or {}).items():
+        for k in (rotkeys or {}).values():
             _check_residues(k, "rotkey", (ctx.dnum, 2, ctx.L + ctx.K, ctx.n))
-            _call("tfhe_server_add_rotation_key", self.handle, ctx.log_n, int(g), _ptr(k))
-            keys[int(g)] = k
+        _call("tfhe_server_add_context", self.handle, ctx.handle, _ptr(evk))
+        self._keep.append((ctx, evk))
+        prev = self._ctx.get(ctx.log_n)
+        keys = dict(prev[2]) if prev is not None and prev[0] is ctx else {}
         self._ctx[ctx.log_n] = (ctx, evk, keys)
+        for g, k in (rotkeys or {}).items():
+            _call("tfhe_server_add_rotation_key", self.handle, ctx.log_n, int(g), _ptr(k))
+            self._keep.append(k)
+            keys[int(g)] = k
 
     def submit(self, op, ct_a, ct_b=None, galois=0, out=None, stream=None):
         """Queues one request on ciphertext(s) of shape [2][level][N] (or
@@ -560,6 +569,7 @@ class NativeServer:
             load().tfhe_server_destroy(self.handle)
             self.handle = None
             self._live.clear()
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -208,3 +208,26 @@ def test_launch_failure_surfaces_and_frees_the_slot(world):
     out = good.result(timeout=10)   # the slot was freed and reused
     srv.close()
     assert np.array_equal(out, ckks.hmult(pr, cts[(2, 0)], cts[(2, 1)], evk, 2))
+
+
+def test_served_requests_release_their_inputs(world):
+    """After completion the scheduler keeps only timings: the callers'
+    ciphertexts are no longer referenced by it (a long-running server does
+    not grow outside its memory budget)."""
+    import gc
+    import weakref
+    pr, evk, rks, gal, cts = world
+    srv = Server(OracleBackend(pr, evk, rks, delay_s=0.002), mem_budget_bytes=1 << 30, slots=2, max_batch=4)
+    refs, futs = [], []
+    for i in range(12):
+        a, b = cts[(4, i % 3)].copy(), cts[(4, (i + 1) % 3)].copy()
+        refs += [weakref.ref(a), weakref.ref(b)]
+        futs.append(srv.submit(HMULT, 6, 4, a, b))
+        del a, b
+    outs = [f.result(timeout=30) for f in futs]
+    assert srv.drain(10)
+    gc.collect()
+    assert all(r() is None for r in refs)
+    assert srv.stats()["completed"] == 12
+    srv.close()
+    assert len(outs) == 12
