@@ -52,11 +52,11 @@ typedef enum {
                                  per LDS round trip (Sec. II-A, Fig. 2) */
   TFHE_NTT_FOURSTEP_MFMA = 2, /* four-step NTT whose DFT stages are exact
                                  INT8 matrix-core contractions over byte
-                                 slices (Sec. III-C, Eq. 9, Eq. 10) */
+                                 slices (Sec. IV-C, Eq. 9, Eq. 10) */
   TFHE_NTT_FOURSTEP_VALU = 3  /* the same four-step passes with each 16 x 16
                                  matrix product on the vector ALUs, 96-bit
                                  accumulation and one reduction per output
-                                 (Sec. III-B, Eq. 7 to Eq. 9); N = 2^16 only,
+                                 (Sec. IV-B, Eq. 7 to Eq. 9); N = 2^16 only,
                                  tfhe_ntt_fwd / tfhe_ntt_inv only; never
                                  chosen by AUTO */
 } tfhe_ntt_algo;
@@ -88,7 +88,7 @@ tfhe_status tfhe_default_psi(uint32_t q, uint32_t log_n, uint32_t* psi);
 /* Create an immutable plan for N = 2^log_n over n_limbs primes.
  *   q[n_limbs], psi[n_limbs]: host arrays; psi may be NULL (default root).
  *   algo: transform used by tfhe_ntt_fwd/inv; AUTO picks per N.
- * Builds the twiddle tables of both algorithms on the device (Sec. III-B:
+ * Builds the twiddle tables of both algorithms on the device (Sec. IV-B:
  * "pre-computed in the initialization and reused").  Synchronous.
  * log_n in [4, 16]; the MFMA algorithm covers log_n in [12, 16] (N = N1 x 256).
  * Errors: TFHE_ENOTNTT for a bad modulus/root, TFHE_EINVAL, TFHE_ENOMEM. */
@@ -138,7 +138,7 @@ tfhe_status tfhe_ntt_inv(tfhe_ntt_plan plan, tfhe_ntt_algo algo, const uint32_t*
                          uint32_t limb_begin, uint32_t limb_count, uint32_t batch, void* ws,
                          size_t ws_bytes, tfhe_stream_t stream);
 
-/* Operation-level batching (Sec. III-D): one fused launch per kernel pass
+/* Operation-level batching (Sec. IV-D): one fused launch per kernel pass
  * covers every descriptor, whatever its N, modulus set, limb range, batch
  * and direction.  Descriptors are host structs; they are copied into the
  * launch, so the array may be reused after the call returns. */
@@ -165,7 +165,7 @@ tfhe_status tfhe_ntt_batch_workspace_size(const tfhe_ntt_desc* descs, uint32_t c
 tfhe_status tfhe_ntt_batch(const tfhe_ntt_desc* descs, uint32_t count, tfhe_ntt_algo algo,
                            void* ws, size_t ws_bytes, tfhe_stream_t stream);
 
-/* Element-wise kernels of Sec. III-A over the same layout (a, b, c device,
+/* Element-wise kernels of Sec. IV-A over the same layout (a, b, c device,
  * [limb_count][batch][N]; c may alias a or b):
  *   Hada-Mult c = a o b mod q;  Ele-Add c = a + b mod q;  Ele-Sub c = a - b mod q. */
 tfhe_status tfhe_pointwise_mul(tfhe_ntt_plan plan, const uint32_t* a, const uint32_t* b,
@@ -217,7 +217,7 @@ tfhe_status tfhe_hmult_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_
  * pairs, ct_out = (d0, d1) + KeySwitch(d2) with d0 = c0c0', d1 = c0c1' +
  * c1c0', d2 = c1c1'.  KeySwitch = INTT, Dcomp into digits, ModUp by fast
  * basis conversion (no overflow correction), NTT, inner product with evk,
- * ModDown (no rounding offset) (Sec. III-A).  No rescale.
+ * ModDown (no rounding offset) (Sec. IV-A).  No rescale.
  *   ct_a, ct_b, ct_out: device [2][level][batch][N], NTT domain; ct_out may
  *     alias ct_a or ct_b.
  *   evk: device [dnum][2][L+K][N], NTT domain, evk[j] = (b_j, a_j) with
@@ -229,7 +229,7 @@ tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* 
 
 /* HROTATE (Sec. II-B): ct_out = (sigma(c0), 0) + KeySwitch_rk(sigma(c1)),
  * sigma the automorphism X -> X^galois_elt applied in the NTT domain as the
- * FrobeniusMap permutation of Sec. III-A: out_j = in_{pi(j)},
+ * FrobeniusMap permutation of Sec. IV-A: out_j = in_{pi(j)},
  * pi(j) = ((2j+1) galois_elt mod 2N - 1)/2.  galois_elt odd, < 2N (5^r mod
  * 2N rotates the slots by r).  rotkey: device [dnum][2][L+K][N] for
  * s' = sigma(s).  ct_in, ct_out: device [2][level][batch][N], must not alias. */
@@ -238,7 +238,7 @@ tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_o
                         uint32_t batch, void* ws, size_t ws_bytes, tfhe_stream_t stream);
 
 /* HROTATE of a batch whose ciphertexts rotate by different amounts, in one
- * batched launch sequence (operation-level batching, Sec. III-D): ciphertext
+ * batched launch sequence (operation-level batching, Sec. IV-D): ciphertext
  * b of ct_in is rotated by galois_elts[b] with the rotation key rotkeys[b],
  * exactly as tfhe_rotate would do for it alone.
  *   rotkeys: host array [batch] of device pointers, each [dnum][2][L+K][N]
@@ -280,7 +280,7 @@ tfhe_status tfhe_cmult(tfhe_ckks_ctx ctx, const uint32_t* ct, const uint32_t* pt
 tfhe_status tfhe_hadd(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b, uint32_t* ct_out,
                       uint32_t level, uint32_t batch, tfhe_stream_t stream);
 
-/* FrobeniusMap alone (Sec. III-A): out_j = in_{pi(j)} on every polynomial of
+/* FrobeniusMap alone (Sec. IV-A): out_j = in_{pi(j)} on every polynomial of
  * a [limb_count][batch][N] array (NTT domain).  out must not alias in. */
 tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t* out,
                                uint32_t galois_elt, uint32_t limb_count, uint32_t batch,
@@ -288,8 +288,8 @@ tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t*
 
 /* ---------------------------------------------------------------- serving */
 
-/* Request dispatcher (the API layer of Sec. III-E with operation-level
- * batching, Sec. III-D): callers submit single-ciphertext HMULT and HROTATE
+/* Request dispatcher (the API layer of Sec. IV-E with operation-level
+ * batching, Sec. IV-D): callers submit single-ciphertext HMULT and HROTATE
  * requests; `slots` worker threads, each with its own stream, group
  * requests of equal (operation, N, level) into batches of up to max_batch,
  * run each batch with one batched tfhe_hmult / tfhe_rotate /

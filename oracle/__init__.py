@@ -14,7 +14,7 @@ Modules:
                   direct O(N^2) NTT (Eq. 4), radix-2 NTT (Sec. II-A, Fig. 2),
                   schoolbook negacyclic product; numpy element-wise ops.
   oracle.ckks     RNS CKKS: keys, encryption, decryption, HMULT, rotation
-                  (Sec. II-B, Sec. III-A), hybrid key switching.
+                  (Sec. II-B, Sec. IV-A), hybrid key switching.
   oracle.tiny     pure-Python (big-int) references for tiny sizes.
 """
 import ctypes
@@ -174,7 +174,7 @@ def _qcol(qs, ndim):
 
 
 def mul(a, b, qs):
-    """Hada-Mult: (a o b) mod q per limb (Sec. III-A)."""
+    """Hada-Mult: (a o b) mod q per limb (Sec. IV-A)."""
     q = _qcol(qs, np.ndim(a))
     return ((np.asarray(a, np.uint64) * np.asarray(b, np.uint64)) % q).astype(np.uint32)
 

@@ -3,12 +3,12 @@ HROTATE with hybrid (generalised) key switching.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The paper fixes the operations (Sec. II-B: HMULT, HROTATE; Sec. III-A,
+The paper fixes the operations (Sec. II-B: HMULT, HROTATE; Sec. IV-A,
 Table 2: their kernels) and the hybrid key switching it adopts (Sec. II-B,
 "Generalized Key-Switching": Q split into dnum slices Q_j of alpha limbs, a
 special modulus P larger than every Q_j).  Its algorithm listings are images
 that did not survive, so the steps below follow the standard hybrid key
-switching the paper cites, in the order the text names them (Sec. III-A:
+switching the paper cites, in the order the text names them (Sec. IV-A:
 Dcomp, ModUp, Inner-product, ModDown), with these readings:
 
 * ct = (c0, c1) with Dec(ct) = c0 + c1*s (mod Q_l); encryption of m is
@@ -128,7 +128,7 @@ def automorphism_int(s, k):
 
 
 def galois_element(r, n):
-    """Galois element 5^r mod 2N of a slot rotation by r (FrobeniusMap, Sec. III-A)."""
+    """Galois element 5^r mod 2N of a slot rotation by r (FrobeniusMap, Sec. IV-A)."""
     return pow(5, r % (n // 2), 2 * n)
 
 

@@ -1,6 +1,6 @@
 """Self-written autotuner (the API layer "generates the best batch size for
 the different involved kernels according to the hardware resources",
-Sec. III-E; the best batch differs per kernel, Sec. VI).
+Sec. IV-E; the best batch differs per kernel, Sec. VI).
 
 * NTT: for a (log N, limbs, batch) shape, times forward + inverse for each
   candidate (algorithm x 256-point item width x persistent four-step

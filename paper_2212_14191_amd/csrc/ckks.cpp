@@ -1,4 +1,4 @@
-// RNS-CKKS context and the HMULT / HROTATE operations (Sec. II-B, Sec. III-A,
+// RNS-CKKS context and the HMULT / HROTATE operations (Sec. II-B, Sec. IV-A,
 // Table 2) as stream-ordered kernel sequences on the device.
 //
 // Key switching follows the hybrid method the paper adopts (Sec. II-B,

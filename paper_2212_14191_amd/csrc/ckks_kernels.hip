@@ -1,4 +1,4 @@
-// Kernels of HMULT / HROTATE / RESCALE other than the NTT (Sec. III-A, Table 2):
+// Kernels of HMULT / HROTATE / RESCALE other than the NTT (Sec. IV-A, Table 2):
 // the tensor product (Hada-Mult, Ele-Add), the fast basis conversion (Conv)
 // of ModUp and ModDown, the key-switching inner product (Hada-Mult, Ele-Add)
 // and the ModDown finalisation (Ele-Sub, Hada-Mult).  All run over the

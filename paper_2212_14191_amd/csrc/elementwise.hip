@@ -1,4 +1,4 @@
-// Element-wise kernels of the hierarchical reconstruction (Sec. III-A,
+// Element-wise kernels of the hierarchical reconstruction (Sec. IV-A,
 // Table 2): Hada-Mult, Ele-Add, Ele-Sub and FrobeniusMap, over the
 // (limb, batch, N) layout.  All are HBM-bound: 16-byte accesses, one pass.
 #include "internal.hpp"

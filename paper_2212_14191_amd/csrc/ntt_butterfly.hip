@@ -18,7 +18,7 @@
 // count ends with one single stage.
 //
 // Every kernel walks a descriptor table, so one launch can cover transforms
-// of different N, moduli and direction (operation-level batching, Sec. III-D).
+// of different N, moduli and direction (operation-level batching, Sec. IV-D).
 #include <algorithm>
 
 #include "internal.hpp"

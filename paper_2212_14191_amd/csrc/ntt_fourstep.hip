@@ -1,4 +1,4 @@
-// Four-step NTT on INT8 matrix cores (Sec. III-B/III-C, Eq. 9 and Eq. 10),
+// Four-step NTT on INT8 matrix cores (Sec. IV-B/IV-C, Eq. 9 and Eq. 10),
 // re-designed for gfx950, for N = N1 x 256 with N1 = 16 r, r in {1,..,16}.
 //
 // With n = 256 n1 + n2 and k = k1 + N1 k2 (phi = psi^256 of order 2 N1,
@@ -15,7 +15,7 @@
 // T[s][v], then level B, an r-point transform over v: on the matrix cores
 // when r = 16, as VALU butterflies when r < 16.
 //
-// Exactness (the segment-fusion idea of Sec. III-C, Fig. 4): every operand
+// Exactness (the segment-fusion idea of Sec. IV-C, Fig. 4): every operand
 // enters the matrix core as four balanced signed byte digits.  A data word x
 // (taken in [-0x80808080, 0x7F7F7F7F]) is x = sum_d 2^{8d} x_d; a twiddle w
 // is supplied as the digits j of W^(d) = 2^{8d} w mod q for d = 0..3.  With
@@ -610,7 +610,7 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 
 
 // ---------------------------------------------------------------------------
-// Vector-ALU GEMM variant ("CO", Sec. III-B: the NTT as matrix products on
+// Vector-ALU GEMM variant ("CO", Sec. IV-B: the NTT as matrix products on
 // the general-purpose cores, one modular reduction per output), N = 2^16.
 // Same passes, tables, work items and data movement as the matrix-core
 // kernel (narrow items); each 16-point level is a 16 x 16 matrix product in

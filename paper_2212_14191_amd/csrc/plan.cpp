@@ -1,6 +1,6 @@
 // NTT plan construction: modulus and root validation, and the twiddle tables
 // of both transform algorithms, built once per (N, prime set) on the host and
-// copied to the device (Sec. III-B: the twiddle matrices are fixed by N and q,
+// copied to the device (Sec. IV-B: the twiddle matrices are fixed by N and q,
 // pre-computed at initialisation and reused by every NTT).
 #include <string.h>
 

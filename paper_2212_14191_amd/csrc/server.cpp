@@ -1,5 +1,5 @@
 // Native request dispatcher for HMULT / HROTATE serving (the API layer of
-// Sec. III-E: requests are collected, grouped into batched kernel workflows
+// Sec. IV-E: requests are collected, grouped into batched kernel workflows
 // and dispatched; keys and ciphertexts stay resident in device memory).
 //
 // Each of `slots` worker threads owns a HIP stream and an equal share of the

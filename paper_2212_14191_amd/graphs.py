@@ -1,5 +1,5 @@
 """Graph capture of batched operations (operation-level batching with fixed
-shapes, Sec. III-D): one HMULT or HROTATE of a (N, level, batch) shape is
+shapes, Sec. IV-D): one HMULT or HROTATE of a (N, level, batch) shape is
 recorded once as a HIP graph on static buffers and replayed, which removes the
 per-kernel launch cost of the ~20-launch key-switching sequence.
 

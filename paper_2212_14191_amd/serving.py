@@ -1,5 +1,5 @@
 """Continuous-batching request loop for HMULT / HROTATE (the API layer of
-Sec. III-E: requests are collected, decomposed into batched kernel workflows
+Sec. IV-E: requests are collected, decomposed into batched kernel workflows
 and dispatched; keys and ciphertexts stay resident in HBM).
 
 A scheduler thread keeps up to `slots` batches in flight, each on its own
