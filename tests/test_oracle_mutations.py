@@ -1,8 +1,10 @@
 """Planted mistakes in the oracle must fail its pins (CPU only).  Each
 mutant is a plausible slip in one step of RESCALE (a swapped operand, a
 wrong constant, an off-by-one limb, the rounding reading in place of the
-floor); the pin tests run with the mutant in
-place of the oracle's function and must fail."""
+floor) or of key switching, the tensor product and the automorphism (a
+dropped inverse in ModUp, a flipped sign in ModDown, exchanged tensor
+operands, a missing negation); the pin tests run with the mutant in place
+of the oracle's function and must fail."""
 import numpy as np
 import pytest
 
@@ -55,3 +57,101 @@ def test_rescale_mutants_fail_pins(kind, monkeypatch):
 def test_rescale_unmutated_passes_pins():
     pins.test_rescale_is_floor_division_by_top_modulus(4)
     pins.test_rescale_decrypts_to_scaled_message(6)
+
+
+# ------------------------------------------------------------ key switching
+# Four slips in the key switch and the operations around it, each planted
+# in place of one oracle function: ModUp without the (Q_j/q_i)^{-1} factor,
+# ModDown with the subtraction's sign flipped, the tensor product with the
+# second ciphertext's components exchanged in d1, and the automorphism
+# without the negation of wrapped coefficients (X^N = -1).
+
+def _mod_up_without_inverse(pr, x, digit, level):
+    ext = pr.ext_limbs(level)
+    Qj = 1
+    for i in digit:
+        Qj *= pr.q[i]
+    out = np.empty((len(ext),) + x.shape[1:], dtype=np.uint32)
+    for pos, t in enumerate(ext):
+        if t in digit:
+            out[pos] = x[t]
+            continue
+        m = pr.moduli[t]
+        acc = np.zeros(x.shape[1:], dtype=np.uint64)
+        for i in digit:
+            c = np.uint64((Qj // pr.q[i]) % m)
+            acc = (acc + (x[i].astype(np.uint64) % np.uint64(m)) * c % np.uint64(m)) % np.uint64(m)
+        out[pos] = acc.astype(np.uint32)
+    return out
+
+
+def _mod_down_sign_flipped(pr, acc_ntt, level):
+    # (conv - acc) P^{-1} instead of (acc - conv) P^{-1}
+    good = _ORIG["mod_down"](pr, acc_ntt, level)
+    qs = pr.mods(range(level))
+    return oracle.sub(np.zeros_like(good), good, qs)
+
+
+def _tensor_exchanged(pr, ct_a, ct_b, level):
+    qs = pr.mods(range(level))
+    c0, c1 = ct_a[0], ct_a[1]
+    e0, e1 = ct_b[0], ct_b[1]
+    d0 = oracle.mul(c0, e0, qs)
+    d1 = oracle.add(oracle.mul(c0, e0, qs), oracle.mul(c1, e1, qs), qs)
+    d2 = oracle.mul(c1, e1, qs)
+    return d0, d1, d2
+
+
+def _automorphism_without_negation(x, k, qs):
+    x = np.asarray(x, dtype=np.uint32)
+    n = x.shape[-1]
+    dest = (np.arange(n, dtype=np.int64) * k) % (2 * n) % n
+    out = np.empty_like(x)
+    out[..., dest] = x
+    return out
+
+
+_ORIG = {"mod_down": ckks.mod_down}
+
+KS_PINS = {
+    "mod_up": lambda: pins.test_mod_up_is_lift_plus_small_multiple(),
+    "gadget": lambda: pins.test_gadget_identity(),
+    "mod_down": lambda: pins.test_mod_down_divides_by_p(),
+    "trivial": lambda: pins.test_hmult_trivial_ciphertexts_exact(),
+    "hmult_dec": lambda: pins.test_hmult_decrypts_to_product(5),
+    "automorphism": lambda: pins.test_automorphism_is_ntt_permutation(),
+    "rotate_dec": lambda: pins.test_rotate_decrypts_to_rotated_message("rot5"),
+}
+
+KS_MUTANTS = {
+    # mutant: (oracle function replaced, replacement, pins it must fail)
+    "modup_inverse": ("mod_up", _mod_up_without_inverse, {"mod_up", "hmult_dec", "rotate_dec"}),
+    "moddown_sign": ("mod_down", _mod_down_sign_flipped, {"mod_down", "hmult_dec", "rotate_dec"}),
+    "tensor_exchanged": ("tensor", _tensor_exchanged, {"trivial", "hmult_dec"}),
+    "automorphism_sign": ("automorphism_coeff", _automorphism_without_negation,
+                          {"automorphism", "rotate_dec"}),
+}
+
+
+def _failing_pins():
+    """Names of the pins that fail (an assertion, or an error such as a
+    decrypted value too large for the pin's int64 rounding)."""
+    failed = set()
+    for name, pin in KS_PINS.items():
+        try:
+            pin()
+        except Exception:
+            failed.add(name)
+    return failed
+
+
+@pytest.mark.parametrize("kind", sorted(KS_MUTANTS))
+def test_key_switch_mutants_fail_pins(kind, monkeypatch):
+    fn, repl, must = KS_MUTANTS[kind]
+    monkeypatch.setattr(ckks, fn, repl)
+    failed = _failing_pins()
+    assert must <= failed, f"mutant {kind}: pins {sorted(must - failed)} still pass"
+
+
+def test_key_switch_unmutated_passes_pins():
+    assert _failing_pins() == set()
