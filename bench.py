@@ -31,6 +31,11 @@ LOG_N, LIMBS, BATCH = 16, 44, 128
 HM_L, HM_K, HM_DNUM, HM_BATCH = 24, 8, 3, 64
 METRIC = "NTT KOPS & HMULT ops/s at N=2^16, MFMA vs butterfly; p99 request latency"
 HBM_PEAK_GBS = 8000.0
+MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the part
+# int8 matrix-core work of one four-step pass at N = 2^16 (a 256-point stage
+# split 16 x 16): per 256 coefficients, 8 v_mfma_i32_16x16x64_i8 (two
+# 16-point levels x 4 twiddle digit planes) of 16 x 16 x 64 multiply-adds
+I8_OPS_PER_COEFF_PASS = 8 * 16 * 16 * 64 * 2 // 256
 
 
 # Sources that determine the four-step kernels' memory traffic; the profile
@@ -47,20 +52,34 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
-    calibration), or None when the summary is missing or was taken from
-    different kernel sources."""
+def profile_record(key):
+    """The JSON record `key: {...}` of the committed rocprofv3 summary, or
+    None when it is missing or was taken from different kernel sources."""
     try:
         with open(TRAFFIC_PROFILE) as f:
-            m = re.search(r"^traffic: (\{.*\})$", f.read(), re.M)
+            m = re.search(r"^" + key + r": (\{.*\})$", f.read(), re.M)
         d = json.loads(m.group(1)) if m else None
     except (OSError, ValueError):
         return None
     if not d or d.get("source_sha256") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch", {}).get(kernel)
+    return d
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when the summary is missing or stale."""
+    d = profile_record("traffic")
+    return d.get("bytes_per_launch", {}).get(kernel) if d else None
+
+
+def measured_mfma(kernel):
+    """Matrix-core counters per launch of `kernel` from the committed
+    summary (SQ_INSTS_VALU_MFMA_MOPS_I8, SQ_VALU_MFMA_BUSY_CYCLES,
+    GRBM_GUI_ACTIVE, and what they imply), or None when missing or stale."""
+    d = profile_record("mfma")
+    return d.get("per_launch", {}).get(kernel) if d else None
 
 
 def log(*a):
@@ -76,21 +95,36 @@ def timed(fn, steps, sync):
     return time.perf_counter() - t0
 
 
-def cpu_baseline(qs, psis, budget_s=12.0):
-    """The oracle's radix-2 NTT+INTT on a bounded sample of the same
-    workload (whole limb-polynomials of N = 2^16), all host cores."""
+def host_cpu():
+    """CPU model name and the number of cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def _oracle_ntt_rate(qs, psis, budget_s, threads):
+    """Forward + inverse radix-2 oracle transforms of whole N = 2^16
+    limb-polynomials on `threads` host threads (0 = all), sized from a warm
+    probe over every limb to take about budget_s."""
     import oracle
     from paper_2212_14191_amd import inputs
     n = 1 << LOG_N
     # probe on every limb (per-limb tables are built once per call and
     # amortised over the polynomials, as in the sample itself)
-    probe_batch = 8
+    probe_batch = 8 if threads != 1 else 1
     probe_units = LIMBS * probe_batch
     x = inputs.uniform_residues(0, qs[:LIMBS], (probe_batch, n))
-    oracle.ntt(x, qs[:LIMBS], psis[:LIMBS])  # loads the library, starts the thread pool
+    oracle.ntt(x, qs[:LIMBS], psis[:LIMBS], threads=threads)  # loads the library, starts the thread pool
     t0 = time.perf_counter()
-    X, used = oracle.ntt(x, qs[:LIMBS], psis[:LIMBS])
-    oracle.ntt(X, qs[:LIMBS], psis[:LIMBS], inverse=True)
+    X, used = oracle.ntt(x, qs[:LIMBS], psis[:LIMBS], threads=threads)
+    oracle.ntt(X, qs[:LIMBS], psis[:LIMBS], inverse=True, threads=threads)
     dt = time.perf_counter() - t0
     per_unit = dt / probe_units
     units = int(max(probe_units, min(LIMBS * BATCH, budget_s / max(per_unit, 1e-6))))
@@ -98,15 +132,53 @@ def cpu_baseline(qs, psis, budget_s=12.0):
     batch = max(1, units // limbs)
     x = inputs.uniform_residues(0, qs[:limbs], (batch, n))
     t0 = time.perf_counter()
-    X, used = oracle.ntt(x, qs[:limbs], psis[:limbs])
-    back, _ = oracle.ntt(X, qs[:limbs], psis[:limbs], inverse=True)
+    X, used = oracle.ntt(x, qs[:limbs], psis[:limbs], threads=threads)
+    back, _ = oracle.ntt(X, qs[:limbs], psis[:limbs], inverse=True, threads=threads)
     dt = time.perf_counter() - t0
     assert np.array_equal(back, x)
     transforms = 2 * limbs * batch
-    return {"value": transforms / dt / 1e3, "unit": "KOPS (10^3 limb-transforms/s)", "cores": int(used),
-            "kind": "oracle",
-            "sample": f"{limbs} limbs x {batch} polys of N=2^16, forward+inverse radix-2 "
-                      f"({transforms} limb-transforms, {dt:.1f} s)"}
+    return (transforms / dt / 1e3, int(used),
+            f"{limbs} limbs x {batch} polys of N=2^16, forward+inverse radix-2 ({transforms} limb-transforms, "
+            f"{dt:.1f} s)")
+
+
+def _oracle_hmult_time():
+    """The oracle's HMULT of one ciphertext pair at the HMULT benchmark
+    shape (N = 2^16, L = 24, K = 8, dnum = 3, level 24); keys and
+    encryption are set-up, outside the clock."""
+    from oracle import ckks
+    from paper_2212_14191_amd import inputs
+    n = 1 << LOG_N
+    pr = ckks.Params(n, L=HM_L, K=HM_K, dnum=HM_DNUM)
+    s = inputs.ternary_secret(1, n, 192)
+    a = inputs.uniform_residues(1, pr.moduli, (HM_DNUM, n), stream=1).transpose(1, 0, 2)
+    e = inputs.gaussian_error(2, (HM_DNUM, n), stream=1)
+    evk = ckks.relin_key(pr, s, a, e)
+    cts = []
+    for k in range(2):
+        m = inputs.small_messages(0, (1, n), stream=k)
+        c1 = inputs.uniform_residues(10 + k, pr.mods(range(HM_L)), (1, n), stream=5)
+        cts.append(ckks.encrypt(pr, s, m, c1, inputs.gaussian_error(2, (1, n), stream=20 + k), HM_L))
+    t0 = time.perf_counter()
+    ckks.hmult(pr, cts[0], cts[1], evk, HM_L)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(qs, psis, budget_s=10.0):
+    """The oracle as it stands, on the host: its radix-2 NTT+INTT on a
+    bounded sample of the same workload (whole limb-polynomials of
+    N = 2^16) on all host cores and on one core, and its HMULT of one pair
+    at the HMULT benchmark shape."""
+    model, nproc = host_cpu()
+    kops, used, sample = _oracle_ntt_rate(qs, psis, budget_s, 0)
+    kops1, _, sample1 = _oracle_ntt_rate(qs, psis, budget_s / 3, 1)
+    hm_s = _oracle_hmult_time()
+    return {"value": kops, "unit": "KOPS (10^3 limb-transforms/s)", "cores": used, "kind": "oracle",
+            "sample": sample, "cpu_model": model, "nproc": nproc,
+            "single_core": {"value": kops1, "unit": "KOPS", "cores": 1, "sample": sample1},
+            "hmult": {"ms_per_op": round(1e3 * hm_s, 1), "ops_per_s": round(1 / hm_s, 3), "cores": used,
+                      "sample": "1 ciphertext pair, N=2^16, L=24, K=8, dnum=3, level 24 "
+                                "(numpy element-wise steps, C transforms on all cores)"}}
 
 
 def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native"), native_slots=8):
@@ -419,6 +491,15 @@ def main():
     kname, kstat = max(head["kernels"].items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
     bytes_per_launch = 2 * units * n * 4  # one read and one write of every residue
     achieved = bytes_per_launch / (kstat["avg_ms"] * 1e-3) / 1e9
+    mfma_line = None
+    if "mfma" in results:
+        # the same launch against the int8 matrix-core peak (the kernel is
+        # HBM-bound; this is the second roofline, its matrix-core share)
+        ops = units * n * I8_OPS_PER_COEFF_PASS
+        tops = ops / (kstat["avg_ms"] * 1e-3) / 1e12
+        mfma_line = {"kernel": kname, "bound": "hbm", "achieved": round(tops, 1), "peak": MFMA_I8_PEAK_TOPS,
+                     "unit": "TOPS (int8)", "frac": round(tops / MFMA_I8_PEAK_TOPS, 4),
+                     "algorithmic_ops_per_launch": ops, "counters": measured_mfma(kname)}
     line = {
         "metric": METRIC,
         "value": round(head["kops"], 1),
@@ -442,6 +523,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(kstat["avg_ms"], 4),
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "roofline_mfma": mfma_line,
         "cpu_baseline": cpu,
     }
     if "butterfly" in results and "mfma" in results:
