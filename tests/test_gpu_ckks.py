@@ -139,10 +139,62 @@ def test_rotate_multi_errors(tf):
         ctx.rotate_multi(ct, [rk, rk], [k, k], level, out=ct)      # output aliases the input
 
 
+_KEYS = {}
+
+
+def serving_setup(log_n):
+    """Keys of the serving shapes (L = 24, K = 8, dnum = 3, default moduli:
+    every q-limb lies at or below 0x7F7F7F7F), cached per N."""
+    if log_n not in _KEYS:
+        n = 1 << log_n
+        pr, s, evk, (a, e) = setup(n, 24, 8, 3)
+        k = ckks.galois_element(5, n)
+        _KEYS[log_n] = (pr, s, evk, k, ckks.rotation_key(pr, s, k, a, e))
+    return _KEYS[log_n]
+
+
+@pytest.mark.parametrize("level", [1, 9, 17, 24])
+@pytest.mark.parametrize("log_n", [14, 15])
+def test_hmult_rotate_serving_shapes_match_oracle(tf, log_n, level):
+    """HMULT and HROTATE at the serving mix's N = 2^14 and 2^15 (L = 24,
+    K = 8, dnum = 3) at levels with one partial digit (1, 9, 17) and three
+    full digits (24), bit-exact against the oracle; from level 9 on the
+    HMULT result of the first ciphertext also decrypts to m1 * m2."""
+    n = 1 << log_n
+    pr, s, evk, k, rk = serving_setup(log_n)
+    assert max(pr.q) <= 0x7F7F7F7F
+    ctx = tf.CkksContext(log_n, 24, 8, 3, moduli=pr.moduli)
+    m1 = inputs.small_messages(log_n, (2, n))
+    m2 = inputs.small_messages(log_n, (2, n), stream=1)
+    ca, cb = encrypt(pr, s, m1, level, 11), encrypt(pr, s, m2, level, 12)
+    got = to_host(ctx.hmult(to_dev(ca), to_dev(cb), to_dev(evk), level))
+    assert np.array_equal(got, ckks.hmult(pr, ca, cb, evk, level))
+    if level >= 3:      # the decryption bound needs Q_l > 2^60 * N * 16^2 * 2
+        dec = ckks.decrypt(pr, s, got[:, :, :1], level)[0]
+        d2 = 1 << 60
+        prod = ckks.negacyclic_int(m1[0], m2[0])
+        assert np.array_equal(np.array([(int(v) + d2 // 2) // d2 for v in dec]), prod)
+    got_r = to_host(ctx.rotate(to_dev(ca), to_dev(rk), k, level))
+    assert np.array_equal(got_r, ckks.rotate(pr, ca, rk, k, level))
+
+
+@pytest.mark.slow
+def test_rotate_full_size_level24(tf):
+    """HROTATE at N = 2^16, level 24 (L = 24, K = 8, dnum = 3) on a batch of
+    three, bit-exact against the oracle."""
+    pr, s, _, k, rk = serving_setup(16)
+    n = 1 << 16
+    ctx = tf.CkksContext(16, 24, 8, 3, moduli=pr.moduli)
+    ct = encrypt(pr, s, inputs.small_messages(16, (3, n)), 24, 13)
+    got = to_host(ctx.rotate(to_dev(ct), to_dev(rk), k, 24))
+    assert np.array_equal(got, ckks.rotate(pr, ct, rk, k, 24))
+
+
 @pytest.mark.slow
 def test_hmult_config4_full_size_sampled(tf):
     """N=2^16, L=24, K=8, dnum=3, h=192, 64 pairs on the GPU (MFMA NTT);
-    two sampled pairs equal the oracle bit for bit and decrypt to m1*m2."""
+    sampled pairs (the first, both sides of the middle, an interior one and
+    the last) equal the oracle bit for bit and decrypt to m1*m2."""
     n, L, K, dnum, level, B = 1 << 16, 24, 8, 3, 24, 64
     pr, s, evk, _ = setup(n, L, K, dnum)
     ctx = tf.CkksContext(16, L, K, dnum, moduli=pr.moduli)
@@ -150,7 +202,7 @@ def test_hmult_config4_full_size_sampled(tf):
     m2 = inputs.small_messages(0, (B, n), stream=1)
     ca, cb = encrypt(pr, s, m1, level, 1), encrypt(pr, s, m2, level, 2)
     got = to_host(ctx.hmult(to_dev(ca), to_dev(cb), to_dev(evk), level))
-    for b in (0, 37):
+    for b in (0, 31, 32, 37, 63):
         want = ckks.hmult(pr, ca[:, :, b:b + 1], cb[:, :, b:b + 1], evk, level)
         assert np.array_equal(got[:, :, b:b + 1], want), b
         dec = ckks.decrypt(pr, s, got[:, :, b:b + 1], level)[0]

@@ -62,6 +62,39 @@ def test_mfma_matches_oracle(tf, log_n, batch):
     assert np.array_equal(to_host(back), x)
 
 
+# One prime from each window the four-step kernel treats differently: above
+# 0x7F7F7F7F (the digit window of a centered residue needs the correction),
+# a 31-bit prime at or below it (the correction-free body, which every
+# default CKKS q-limb takes), and a 30-bit prime.
+WINDOWS = {
+    "q31_above_window": [q for q in PRIMES31 if q > 0x7F7F7F7F][:1],
+    "q31_in_window": [q for q in oracle.ntt_primes(40, 31, 1 << 17) if q <= 0x7F7F7F7F][:1],
+    "q30": oracle.ntt_primes(1, 30, 1 << 17),
+}
+
+
+@pytest.mark.parametrize("window", sorted(WINDOWS))
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16])
+def test_mfma_matches_oracle_per_prime_window(tf, log_n, window):
+    """The MFMA transform at every N = 2^12..2^16 for a prime of each window,
+    forward and inverse against the oracle (ragged batch of 3, plus edge
+    values 0, q - 1 and residues straddling 0x7F7F7F7F)."""
+    n = 1 << log_n
+    qs = WINDOWS[window]
+    assert len(qs) == 1
+    q = qs[0]
+    plan = tf.NttPlan(log_n, qs, algo="mfma")
+    assert plan.algo == tf.FOURSTEP_MFMA
+    x = inputs.uniform_residues(200 + log_n, qs, (3, n))
+    x[0, 1, : n // 2] = q - 1
+    x[0, 1, n // 2:] = np.minimum(np.uint32(0x7F7F7F70) + np.arange(n // 2, dtype=np.uint32) % 32, q - 1)
+    x[0, 2, :7] = 0
+    ref = oracle.ntt_fwd(x, qs, plan.psi)
+    assert np.array_equal(to_host(plan.fwd(to_dev(x), algo="mfma")), ref)
+    assert np.array_equal(to_host(plan.inv(to_dev(ref), algo="mfma")), x)
+    assert np.array_equal(to_host(plan.inv(to_dev(x), algo="mfma")), oracle.ntt_inv(x, qs, plan.psi))
+
+
 @pytest.mark.parametrize("log_n,wide", [(12, 0), (13, 0), (14, 0), (15, 0), (13, 2), (14, 2),
                                          (15, 1), (16, 1), (16, 2)])
 def test_mfma_equals_butterfly_ragged(tf, log_n, wide):

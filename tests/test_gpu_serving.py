@@ -265,3 +265,89 @@ def test_native_server_full_pointer_table(world):
     for k, (tag, out) in enumerate(outs):
         assert torch.equal(out, alone[k % 2]), tag
     srv.close()
+
+
+@pytest.fixture(scope="module")
+def serving_world():
+    """The serving mix's smaller shapes: N = 2^13, 2^14, 2^15 with L = 24,
+    K = 8, dnum = 3 and the default moduli (every q-limb at or below
+    0x7F7F7F7F), ciphertexts at levels 1, 9, 17 and 24, two rotation keys per
+    N; keys and ciphertexts made on the device from seeded draws."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_14191_amd import tfhe
+    from paper_2212_14191_amd.scheme import Scheme
+    L, K, dnum = 24, 8, 3
+    ctxs, evks, rks, cts, host = {}, {}, {}, {}, {}
+    for ln in (13, 14, 15):
+        n = 1 << ln
+        ctx = tfhe.CkksContext(ln, L, K, dnum)
+        sch = Scheme(ctx)
+        s = inputs.ternary_secret(1, n, 192)
+        a = inputs.uniform_residues(1, ctx.moduli, (dnum, n), stream=1).transpose(1, 0, 2)
+        e = inputs.gaussian_error(2, (dnum, n), stream=1)
+        ctxs[ln], evks[ln] = ctx, sch.relin_key(s, a, e)
+        for r in (1, 64):
+            g = pow(5, r, 2 * n)
+            rks[(ln, g)] = sch.rotation_key(s, g, a, e)
+        for level in (1, 9, 17, 24):
+            for i in range(2):
+                m = inputs.small_messages(ln + i, (1, n))
+                c1 = inputs.uniform_residues(40 + i, ctx.moduli[:level], (1, n), stream=5)
+                cts[(ln, level, i)] = sch.encrypt(s, m, c1, inputs.gaussian_error(2, (1, n), stream=50 + i),
+                                                  level)
+    return ctxs, evks, rks, cts
+
+
+def serving_requests(world, count, seed):
+    _, _, _, cts = world
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        ln = int(rng.choice([13, 14, 15]))
+        level = int(rng.choice([1, 9, 17, 24]))
+        if rng.random() < 0.5:
+            out.append((0, ln, level, cts[(ln, level, 0)], cts[(ln, level, 1)], None))
+        else:
+            g = pow(5, int(rng.choice([1, 64])), 2 << ln)
+            out.append((1, ln, level, cts[(ln, level, int(rng.integers(2)))], None, g))
+    return out
+
+
+def test_serving_shapes_alone_equal_mix_and_oracle(serving_world):
+    """48 requests over N = 2^13..2^15 and levels 1..24 through the native
+    dispatcher (4 slots, batches up to 8) and through the Python scheduler:
+    every result equals the single-request call, and one HMULT and one
+    rotation per N equal the oracle."""
+    from oracle import ckks
+    from paper_2212_14191_amd import tfhe
+    from paper_2212_14191_amd.serving import GpuBackend, Server
+    ctxs, evks, rks, _ = serving_world
+    reqs = serving_requests(serving_world, 48, 7)
+    alone = alone_results(serving_world, reqs)
+    srv = tfhe.NativeServer(slots=4, max_batch=8, pool_bytes=2 << 30)
+    for ln, ctx in ctxs.items():
+        srv.add_context(ctx, evks[ln], {g: k for (l2, g), k in rks.items() if l2 == ln})
+    outs = srv.submit_many([(op, a, b, g or 0, None) for op, ln, lv, a, b, g in reqs])
+    done = drain(srv, len(reqs), timeout=120)
+    assert all(st is None for st in done.values()), done
+    for (tag, out), want in zip(outs, alone):
+        assert torch.equal(out, want), tag
+    srv.close()
+    be = GpuBackend(ctxs, evks, rks, slots=4)
+    py = Server(be, mem_budget_bytes=4 << 30, slots=4, max_batch=8)
+    futs = [py.submit(op, ln, lv, a, b, g) for op, ln, lv, a, b, g in reqs]
+    for f, want in zip(futs, alone):
+        assert torch.equal(f.result(timeout=120), want)
+    py.close()
+    to_np = lambda t: t.cpu().numpy().view(np.uint32)
+    for ln in (13, 14, 15):
+        pr = ckks.Params(1 << ln, L=24, K=8, dnum=3, moduli=list(ctxs[ln].moduli))
+        for op in (0, 1):
+            k = next(i for i, r in enumerate(reqs) if r[0] == op and r[1] == ln)
+            _, _, lv, a, b, g = reqs[k]
+            if op == 0:
+                want = ckks.hmult(pr, to_np(a), to_np(b), to_np(evks[ln]), lv)
+            else:
+                want = ckks.rotate(pr, to_np(a), to_np(rks[(ln, g)]), g, lv)
+            assert np.array_equal(to_np(outs[k][1]), want), (ln, op, lv)
