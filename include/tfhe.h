@@ -227,6 +227,27 @@ tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* 
                        uint32_t* ct_out, const uint32_t* evk, uint32_t level, uint32_t batch,
                        void* ws, size_t ws_bytes, tfhe_stream_t stream);
 
+/* tfhe_hmult without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that forbid allocation on their hot path).  It runs the
+ * same kernels as tfhe_hmult (same results, bit for bit) with the
+ * workspace placed in a fixed device array of TFHE_HMULT_NOALLOC_MAX_BYTES
+ * that the library holds on every GPU it has created a context on, until
+ * the process ends; the array's address is resolved once per device by
+ * tfhe_ckks_ctx_create.  The caller still passes inputs and outputs (same
+ * layout and rules as tfhe_hmult).
+ *   Returns TFHE_EINVAL when tfhe_hmult_workspace_size(level, batch)
+ *   exceeds TFHE_HMULT_NOALLOC_MAX_BYTES (at N = 2^16, L = 24, K = 8,
+ *   dnum = 3: batch 1 at every level).
+ *   Every call on one GPU uses that GPU's one array, whatever the context
+ *   or stream: calls that may overlap on one GPU (different streams, or
+ *   threads without ordering) race and give undefined results; order them
+ *   on one stream.  Nothing in the array needs clearing between calls. */
+#define TFHE_HMULT_NOALLOC_MAX_BYTES (128u << 20)
+tfhe_status tfhe_hmult_noalloc(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
+                               uint32_t* ct_out, const uint32_t* evk, uint32_t level,
+                               uint32_t batch, tfhe_stream_t stream);
+
 /* HROTATE (Sec. II-B): ct_out = (sigma(c0), 0) + KeySwitch_rk(sigma(c1)),
  * sigma the automorphism X -> X^galois_elt applied in the NTT domain as the
  * FrobeniusMap permutation of Sec. IV-A: out_j = in_{pi(j)},

@@ -8,6 +8,7 @@
 // accumulates over the digits, and ModDown divides by P (no rounding offset).
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <set>
 #include <vector>
@@ -15,6 +16,33 @@
 #include "ckks_internal.hpp"
 
 namespace tfhe {
+
+// Scratch memory of tfhe_hmult_noalloc: a fixed device array in the code
+// object, one copy per GPU.  Its name is a host-side stand-in; host code
+// uses only the device address resolved per device by scratch_bind.
+static __device__ __attribute__((aligned(256))) unsigned char scratch[TFHE_HMULT_NOALLOC_MAX_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<unsigned char*> g_scratch_ptr;  // per device ordinal, null until bound
+
+// Resolves this device's copy of `scratch` (the device must be current).
+// Called once per device, at context creation.
+static tfhe_status scratch_bind(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0) return fail(TFHE_EINVAL, "scratch_bind: bad device");
+  if ((size_t)dev < g_scratch_ptr.size() && g_scratch_ptr[dev]) return TFHE_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return hip_check(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize(dev + 1, nullptr);
+  g_scratch_ptr[dev] = (unsigned char*)ptr;
+  return TFHE_OK;
+}
+
+static unsigned char* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (dev >= 0 && (size_t)dev < g_scratch_ptr.size()) ? g_scratch_ptr[dev] : nullptr;
+}
 
 tfhe_status plan_build(tfhe_ntt_plan_s* p);
 void plan_free(tfhe_ntt_plan_s* p);
@@ -478,7 +506,7 @@ tfhe_status tfhe_ckks_ctx_create(tfhe_ckks_ctx* out, uint32_t log_n, uint32_t L,
     return st;
   }
   c->plan = plan;
-  if ((st = ctx_build(c)) != TFHE_OK) {
+  if ((st = scratch_bind(plan->device)) != TFHE_OK || (st = ctx_build(c)) != TFHE_OK) {
     ctx_free(c);
     delete c;
     return st;
@@ -508,11 +536,12 @@ tfhe_status tfhe_hmult_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_
   return TFHE_OK;
 }
 
-tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
-                       uint32_t* ct_out, const uint32_t* evk, uint32_t level, uint32_t batch,
-                       void* ws, size_t ws_bytes, tfhe_stream_t stream) {
-  tfhe_status st = check_ct_call(ctx, level, batch, ws, ws_bytes);
-  if (st != TFHE_OK || batch == 0) return st;
+}  // extern "C"
+
+// The launch sequence of tfhe_hmult with a validated workspace.
+static tfhe_status hmult_run(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
+                             uint32_t* ct_out, const uint32_t* evk, uint32_t level, uint32_t batch,
+                             void* ws, tfhe_stream_t stream) {
   if (!al16(ct_a) || !al16(ct_b) || !al16(ct_out) || !al16(evk))
     return fail(TFHE_EINVAL, "hmult: null or unaligned pointer");
   hipStream_t s = (hipStream_t)stream;
@@ -526,6 +555,32 @@ tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* 
   if (e == hipSuccess)
     e = key_switch(ctx, d2, keys, ct_out, ct_out + plane, true, true, level, batch, w, s);
   return hip_check(e, "hmult");
+}
+
+extern "C" {
+
+tfhe_status tfhe_hmult(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
+                       uint32_t* ct_out, const uint32_t* evk, uint32_t level, uint32_t batch,
+                       void* ws, size_t ws_bytes, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, ws, ws_bytes);
+  if (st != TFHE_OK || batch == 0) return st;
+  return hmult_run(ctx, ct_a, ct_b, ct_out, evk, level, batch, ws, stream);
+}
+
+tfhe_status tfhe_hmult_noalloc(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const uint32_t* ct_b,
+                               uint32_t* ct_out, const uint32_t* evk, uint32_t level,
+                               uint32_t batch, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, level, batch, nullptr, 0, false);
+  if (st != TFHE_OK || batch == 0) return st;
+  const size_t need = ks_layout(ctx, level, batch).total;
+  if (need > (size_t)TFHE_HMULT_NOALLOC_MAX_BYTES)
+    return fail(TFHE_EINVAL, "hmult_noalloc: this level and batch need " + std::to_string(need) +
+                                 " bytes of scratch, above TFHE_HMULT_NOALLOC_MAX_BYTES (" +
+                                 std::to_string((size_t)TFHE_HMULT_NOALLOC_MAX_BYTES) +
+                                 "); use a smaller batch or tfhe_hmult with a workspace");
+  unsigned char* w = scratch_of(ctx->plan->device);
+  if (!w) return fail(TFHE_EINVAL, "hmult_noalloc: scratch not bound on this device");
+  return hmult_run(ctx, ct_a, ct_b, ct_out, evk, level, batch, w, stream);
 }
 
 tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,

@@ -85,6 +85,7 @@ def load():
         "tfhe_ckks_ctx_plan": ([vp, ctypes.POINTER(vp)], i32),
         "tfhe_hmult_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
         "tfhe_hmult": ([vp, vp, vp, vp, vp, u32, u32, vp, sz, vp], i32),
+        "tfhe_hmult_noalloc": ([vp, vp, vp, vp, vp, u32, u32, vp], i32),
         "tfhe_rotate": ([vp, vp, vp, vp, u32, u32, u32, vp, sz, vp], i32),
         "tfhe_rotate_multi": ([vp, vp, vp, ctypes.POINTER(vp), pu32, u32, u32, vp, sz, vp], i32),
         "tfhe_rescale_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
@@ -361,6 +362,22 @@ class CkksContext:
     def workspace(self, level, batch):
         import torch
         return torch.empty(max(self.workspace_bytes(level, batch), 256), dtype=torch.uint8, device="cuda")
+
+    NOALLOC_MAX_BYTES = 128 << 20  # TFHE_HMULT_NOALLOC_MAX_BYTES
+
+    def hmult_noalloc(self, ct_a, ct_b, evk, level, out, stream=None):
+        """tfhe_hmult_noalloc: HMULT with the library's fixed per-GPU scratch
+        array instead of a workspace; allocates nothing (`out` is required).
+        Calls that overlap on one GPU race."""
+        _, lv, batch, n = ct_a.shape
+        if lv != level:
+            raise ValueError("ciphertext level mismatch")
+        for t, nm in ((ct_a, "ct_a"), (ct_b, "ct_b"), (out, "out")):
+            _check_residues(t, nm, (2, level, batch, self.n))
+        _check_residues(evk, "evk", (self.dnum, 2, self.L + self.K, self.n))
+        _call("tfhe_hmult_noalloc", self.handle, _ptr(ct_a), _ptr(ct_b), _ptr(out), _ptr(evk), level, batch,
+              _stream(stream))
+        return out
 
     def hmult(self, ct_a, ct_b, evk, level, out=None, ws=None, stream=None):
         """HMULT of ct_a, ct_b: int32 [2][level][batch][N] (NTT domain)."""
