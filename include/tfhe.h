@@ -111,8 +111,20 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *                            0 = library default (wide for N >= 2^15),
  *                            1 = always 16 vectors (4 waves), 2 = 32 vectors
  *                            (8 waves) whenever N >= 2^13
+ *   TFHE_PARAM_FS_PASSES     HBM round trips of a four-step transform
+ *                            (the paper's Stages 1-5 as one pipeline,
+ *                            Sec. IV-C): 0 = library default, 1 = one (the
+ *                            polynomial stays in LDS; N = 2^12..2^15, and not
+ *                            for the ModDown / RESCALE epilogue, which keep
+ *                            two), 2 = two (a transposed intermediate in the
+ *                            workspace between two passes)
  * Not thread-safe against concurrent compute calls on the same plan. */
-typedef enum { TFHE_PARAM_FS_WG_PER_CU = 1, TFHE_PARAM_AUTO_ALGO = 2, TFHE_PARAM_FS_WIDE = 3 } tfhe_plan_param;
+typedef enum {
+  TFHE_PARAM_FS_WG_PER_CU = 1,
+  TFHE_PARAM_AUTO_ALGO = 2,
+  TFHE_PARAM_FS_WIDE = 3,
+  TFHE_PARAM_FS_PASSES = 4
+} tfhe_plan_param;
 tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t value);
 tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t* value);
 
@@ -398,7 +410,7 @@ tfhe_status tfhe_timing_enable(int enable);
 
 /* Launch count and summed event-measured duration (ms) of the kernel named
  * `kernel` since timing was enabled; waits for the recorded events.  Names:
- * ntt_mfma_pass1, ntt_mfma_pass2, ntt_co_pass1, ntt_co_pass2, ntt_bf_single,
+ * ntt_mfma_pass1, ntt_mfma_pass2, ntt_mfma_onepass, ntt_co_pass1, ntt_co_pass2, ntt_bf_single,
  * ntt_bf_cols, ntt_bf_rows,
  * elementwise, ckks_tensor, ckks_modup, ckks_inner, ckks_moddown_conv,
  * ckks_moddown_final, frobenius, ckks_rescale_bcast, ckks_rescale_final.

@@ -14,7 +14,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtfhe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan.cpp", "capi.cpp", "ckks.cpp", "server.cpp", "ntt_butterfly.hip", "ntt_fourstep.hip",
+SOURCES = ["plan.cpp", "capi.cpp", "ckks.cpp", "server.cpp", "ntt_butterfly.hip", "ntt_fourstep.hip", "ntt_onepass.hip",
            "elementwise.hip", "ckks_kernels.hip", "timing.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",

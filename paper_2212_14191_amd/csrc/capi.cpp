@@ -188,6 +188,10 @@ tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, i
       if (value < 0 || value > 2) return fail(TFHE_EINVAL, "fs_wide must be 0, 1 or 2");
       plan->fs_wide = (uint32_t)value;
       return TFHE_OK;
+    case TFHE_PARAM_FS_PASSES:
+      if (value < 0 || value > 2) return fail(TFHE_EINVAL, "fs_passes must be 0, 1 or 2");
+      plan->fs_passes = (uint32_t)value;
+      return TFHE_OK;
   }
   return fail(TFHE_EINVAL, "unknown plan parameter");
 }
@@ -198,6 +202,7 @@ tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, i
     case TFHE_PARAM_FS_WG_PER_CU: *value = plan->fs_wg_per_cu; return TFHE_OK;
     case TFHE_PARAM_AUTO_ALGO: *value = plan->algo; return TFHE_OK;
     case TFHE_PARAM_FS_WIDE: *value = plan->fs_wide; return TFHE_OK;
+    case TFHE_PARAM_FS_PASSES: *value = plan->fs_passes; return TFHE_OK;
   }
   return fail(TFHE_EINVAL, "unknown plan parameter");
 }

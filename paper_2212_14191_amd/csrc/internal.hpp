@@ -44,6 +44,23 @@ struct CoPass {
   uint2 T[16][16];
 };
 
+// Tables of the one-pass four-step kernel (N = 2^12..2^15) for one limb and
+// direction; its first pass uses the two-pass kernel's pass-1 tables.
+//   p2       second pass.  Forward (256-point): level B's twiddles unscaled
+//            and the twist carrying 2^64, so opB equals opA (the 16-point DFT
+//            matrix is symmetric).  Inverse (N1-point): opA with the level-A
+//            index u = g + 4c for lane (i, g), dword c, instead of 4g + c.
+//   post_b   [lane][j][set] first-pass post-twist, the factor fixed per lane:
+//            P(4m + set, out) (times 2^32 after a matrix-core level B), Shoup
+//   post_a   [step][lane][j] the factor of a step whose first column quad is
+//            Q0 = step * 16 / r: P(4 Q0 + 4m, out) / P(4m, out), times 2^32
+//            (Montgomery form); (m, out) as lane / register j hold them.
+struct OnePassTables {
+  PassTables p2;
+  uint2 post_b[64][4][4];
+  uint32_t post_a[32][64][4];
+};
+
 // Device-side description of one limb for the four-step kernels.
 struct FourStepLimb {
   const PassTables* pass1;  // first pass (its post-twist: post1)
@@ -52,6 +69,7 @@ struct FourStepLimb {
   const CoPass* co1;        // vector-ALU variant (N = 2^16 only): pass matrices
   const CoPass* co2;
   const uint2* co_post;     // [256 columns][256 outputs]: post-twist of pass 1
+  const OnePassTables* op;  // one-pass kernel (N = 2^12..2^15), else null
   uint32_t q, qneg;         // modulus and -q^{-1} mod 2^32
 };
 
@@ -64,6 +82,7 @@ struct tfhe_plan_impl {
   uint32_t num_cus = 256;         // compute units of the device
   uint32_t fs_wg_per_cu = 0;      // persistent four-step workgroups per CU (0: occupancy)
   uint32_t fs_wide = 0;           // 256-point stage items: 0 auto, 1 narrow, 2 wide when possible
+  uint32_t fs_passes = 0;         // four-step HBM passes: 0 auto, 1 one pass (N = 2^12..2^15), 2 two
   std::vector<uint32_t> q, psi;
   // device arrays
   ModConst* d_mod = nullptr;      // [n_limbs]
@@ -141,7 +160,7 @@ struct GaloisSet {
 // ---- per-kernel event timing (timing.cpp)
 enum KernelId {
   K_FS_PASS1 = 0, K_FS_PASS2, K_BF_SINGLE, K_BF_COLS, K_BF_ROWS, K_EW, K_TENSOR, K_MODUP,
-  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL, K_CO_PASS1, K_CO_PASS2
+  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL, K_CO_PASS1, K_CO_PASS2, K_OP
 };
 bool timing_on();
 void* timing_begin(int id, hipStream_t s);

@@ -49,13 +49,10 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "internal.hpp"
+#include "fourstep_dev.hpp"
 
 namespace tfhe {
 namespace {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kStages = 3;   // LDS ring depth (items)
 
@@ -85,125 +82,6 @@ struct Geo {
   static_assert(!kWide || kR == 16, "wide items are for the 256-point stage");
 };
 
-// Descriptor table of a fused launch (passed by value as a kernel argument):
-// unit k covers global polynomials [item_begin[k], item_begin[k+1]).  Every
-// unit of a launch has the same N and direction.
-constexpr int kMaxUnits = 40;
-struct FsUnit {
-  const uint32_t* in;
-  uint32_t* out;
-  const FourStepLimb* limbs;  // tables of the unit's first limb
-  uint32_t batch;
-  uint32_t item_begin;
-  // second-pass epilogue (forward transforms): out = (acc - y) m_l, or
-  // out += (acc - y) m_l, with m_l the Shoup pair of the unit's limb l
-  const uint32_t* acc;
-  const uint2* mult;
-  uint32_t accumulate;
-};
-struct FsTable {
-  uint32_t count, total;  // units, polynomials
-  uint32_t log_n;
-  uint32_t cols;          // S = N / P: columns of this pass (row stride in natural order)
-  uint32_t ipp_log;       // log2 of the items per polynomial (N / item words)
-  FsUnit u[kMaxUnits];
-};
-
-__device__ __forceinline__ v4i mfma(v4i a, v4i b, v4i c) {
-  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
-}
-
-// 64-bit a b + c as one v_mad_u64_u32 (the carry-out is discarded).  Used
-// where only the low word is needed, which the compiler would otherwise
-// split into a 32-bit multiply and an add.
-__device__ __forceinline__ uint64_t mad_u64(uint32_t a, uint32_t b, uint64_t c) {
-  uint64_t d, carry;
-  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=&v"(d), "=s"(carry) : "v"(a), "v"(b), "v"(c));
-  return d;
-}
-
-// Fusion and one Montgomery step: V 2^{-32} mod q, in [0, q + 2^17).
-// (V + m q) is a multiple of 2^32 below 2^64, so its high word is exact
-// (one v_mad_u64_u32).
-__device__ __forceinline__ uint32_t fuse_redc(int c0, int c1, int c2, int c3, uint32_t q,
-                                              uint32_t qneg) {
-  const uint32_t lo = (uint32_t)c0 + ((uint32_t)c1 << 8);
-  const uint32_t hi = (uint32_t)c2 + ((uint32_t)c3 << 8);
-  const uint64_t V = mad_u64(hi, 0x10000u, lo);
-  const uint32_t m = (uint32_t)V * qneg;
-  return (uint32_t)(((uint64_t)m * q + V) >> 32);
-}
-
-// Twist (Shoup, t = {w, companion}) and re-slice into digits; r < 2^32.
-// z - q lies in [-q, q), inside the digit window unless q > 0x7F7F7F7F.
-// For such q the digits of z - q are ((r w - h q) + (0x80808080 - q)) ^
-// 0x80808080 with h = floor(r w' / 2^32): two multiply-adds on the low word
-// (nq = -q, cq = 0x80808080 - q, both mod 2^32).
-template <bool kBigQ>
-__device__ __forceinline__ uint32_t twist_digits(uint32_t r, uint2 t, uint32_t q, uint32_t nq, uint64_t cq) {
-  if (!kBigQ) {
-    const uint32_t h = __umulhi(r, t.y);
-    return (uint32_t)mad_u64(h, nq, mad_u64(r, t.x, cq)) ^ 0x80808080u;
-  }
-  const uint32_t z = mul_shoup_lazy(r, t.x, t.y, q);  // [0, 2q)
-  int32_t zz = (int32_t)(z - q);                      // [-q, q)
-  zz = zz > 0x7F7F7F7F ? zz - (int32_t)q : zz;
-  return balanced_digits(zz);
-}
-
-// After level A, lane (s, g) register j holds MFMA row i = 4g + j, i.e.
-// vector m = i / kR, element v = i % kR.  After level B register j holds
-// output t of vector m (the output index is s + 16 t).
-template <int kR>
-__device__ __forceinline__ void lane_out(int g, int j, int& m, int& t) {
-  if (kR == 16) { m = 0; t = 4 * g + j; }
-  else if (kR == 8) { m = g >> 1; t = 2 * j + (g & 1); }
-  else if (kR == 4) { m = g; t = j; }
-  else if (kR == 2) { m = 2 * g + (j >> 1); t = j & 1; }
-  else { m = 4 * g + j; t = 0; }
-}
-
-// Radix-4 DFT y_t = sum_v x_v w4^{vt} (w4 of order 4) on residues in [0, q).
-__device__ __forceinline__ void dft4(uint32_t* x, uint2 w4, uint32_t q) {
-  const uint32_t a0 = add_mod(x[0], x[2], q), a1 = sub_mod(x[0], x[2], q);
-  const uint32_t b0 = add_mod(x[1], x[3], q);
-  const uint32_t b1 = mul_shoup(sub_mod(x[1], x[3], q), w4.x, w4.y, q);
-  x[0] = add_mod(a0, b0, q);
-  x[1] = add_mod(a1, b1, q);
-  x[2] = sub_mod(a0, b0, q);
-  x[3] = sub_mod(a1, b1, q);
-}
-
-// Level B for kR < 16: the kR-point cyclic DFT over v of y (residues in
-// [0, q)), with lb[x] = rho^x for the root rho of order kR.  For kR = 8 the
-// eight inputs of a vector sit in lanes g and g ^ 1 (four each): lane
-// parity h computes the outputs t = 2 j + h from e_j = z_j + z_{j+4} (h = 0)
-// or o_j = (z_j - z_{j+4}) rho^j (h = 1) with a radix-4 DFT by rho^2.
-template <int kR>
-__device__ __forceinline__ void level_b(uint32_t* y, const uint2* lb, const uint2* rj, int g,
-                                        uint32_t q) {
-  if (kR == 2) {
-#pragma unroll
-    for (int j = 0; j < 4; j += 2) {
-      const uint32_t a = y[j], b = y[j + 1];
-      y[j] = add_mod(a, b, q);
-      y[j + 1] = sub_mod(a, b, q);
-    }
-  } else if (kR == 4) {
-    dft4(y, lb[1], q);
-  } else if (kR == 8) {
-    const bool h = g & 1;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t other = (uint32_t)__shfl_xor((int)y[j], 16);
-      const uint32_t lo = h ? other : y[j], hi = h ? y[j] : other;  // z_j, z_{j+4}
-      const uint32_t d = h ? sub_mod(lo, hi, q) : add_mod(lo, hi, q);
-      y[j] = mul_shoup(d, rj[j].x, rj[j].y, q);
-    }
-    dft4(y, lb[2], q);
-  }
-}
-
 // Work distribution.  The grid is a multiple of 16.  Workgroup w belongs to
 // group w / 16, which owns a contiguous range of polynomials; within the
 // group, slot j = 2 (c % 8) + c / 8 of workgroup c = w % 16 selects its item
@@ -227,29 +105,6 @@ __device__ __forceinline__ Walk make_walk(uint32_t total_polys, uint32_t ipp_log
   return w;
 }
 
-struct Item {
-  uint32_t unit, limb;
-  size_t poly_base;  // word offset of the polynomial within the unit's arrays
-};
-// Global polynomial p -> (unit, limb, offset); `k` is a running unit index
-// (p only increases along a walk).
-__device__ __forceinline__ Item locate(const FsTable& t, uint32_t p, uint32_t& k) {
-  while (k + 1 < t.count && p >= t.u[k + 1].item_begin) ++k;
-  const uint32_t local = p - t.u[k].item_begin;
-  Item it;
-  it.unit = k;
-  it.limb = local / t.u[k].batch;
-  it.poly_base = (size_t)local << t.log_n;
-  return it;
-}
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-
 // Each wave loads slabs 4 wave .. 4 wave + 3 of an item: one 16-byte
 // direct-to-LDS load per lane per slab (streaming hint: every byte is read
 // once); lane L's bytes land at the slab base + 16 L.  Issued as inline assembly so that the compiler does not serialise
@@ -269,14 +124,6 @@ __device__ __forceinline__ void issue_tile(const uint32_t* src, const uint32_t* 
         : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
         : "memory", "m0");
   }
-}
-
-// Workgroup barrier without the memory fence of __syncthreads (which would
-// wait for every outstanding load): LDS accesses of this wave are completed
-// first; the direct-to-LDS loads are covered by wait_item.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  __builtin_amdgcn_s_barrier();
 }
 
 // Wait until this wave's loads of the current item have landed.  Vector
@@ -789,6 +636,12 @@ size_t fs_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_
   return (size_t)limb_count * batch * p->n * sizeof(uint32_t);
 }
 
+// Whether four-step transforms of this plan take the one-pass kernel.
+static bool use_onepass(const tfhe_ntt_plan_s* p) {
+  if (!op_supported(p->log_n) || p->fs_passes == 2) return false;
+  return p->fs_passes == 1;
+}
+
 // Fused launches: units are grouped by (N, direction), in order of first
 // appearance; per group, pass 1 of every unit (in -> unit workspace), then
 // pass 2 of every unit (workspace -> out), kMaxUnits units per launch pair.
@@ -817,8 +670,14 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     t1.cols = inverse ? N1 : 256;  // N / P of pass 1
     t2.cols = inverse ? 256 : N1;
     const uint32_t r1 = inverse ? 16 : r, r2 = inverse ? r : 16;
+    // one HBM round trip where the one-pass kernel covers the shape
+    const bool one = !epi && use_onepass(p0);
     auto flush = [&]() {
       if (t1.total == 0) return;
+      if (one) {
+        (void)op_run(p0, inverse, t1, s);
+        return;
+      }
       launch_pass_r<true>(p0, r1, t1, s);
       if (!epi) launch_pass_r<false>(p0, r2, t2, s);
       else if (use_wide(p0, t2.cols)) launch_pass<false, 16, true, true>(p0, t2, s);
@@ -838,7 +697,7 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
         t1.total = t2.total = 0;
       }
       const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;
-      t1.u[t1.count++] = FsUnit{u.in, mids[k], tabs, u.batch, t1.total, nullptr, nullptr, 0};
+      t1.u[t1.count++] = FsUnit{u.in, one ? u.out : mids[k], tabs, u.batch, t1.total, nullptr, nullptr, 0};
       t2.u[t2.count++] = FsUnit{mids[k], u.out, tabs, u.batch, t2.total, u.acc, u.epi_mult, u.epi_add ? 1u : 0u};
       t1.total += polys;
       t2.total += polys;

@@ -118,8 +118,12 @@ static void lane_output(int r, int lane, int j, int* m, int* t) {
 // A operand: lane (t, g) holds v = 4g + c.  The twist carries the factor 2^32
 // that cancels the Montgomery reduction of the level-A fusion; wb_scale
 // multiplies WB (2^32 when level B is the transform's last).
+// ua selects the level-A index of lane (i, g), dword c: u = 4g + c (false)
+// or u = g + 4c (true; the one-pass kernel's second pass).  tw_scale is the
+// twist's factor (2^32 by default).
 static void build_pass(PassTables& pt, int r, const Mat16& WA, const Mat16& T, const Mat16& WB,
-                       uint32_t q, uint32_t wb_scale, const uint32_t* lb) {
+                       uint32_t q, uint32_t wb_scale, const uint32_t* lb, bool ua = false,
+                       uint32_t tw_scale = 0) {
   memset(&pt, 0, sizeof(pt));
   uint32_t p2[4];
   for (int d = 0; d < 4; ++d) p2[d] = pow_mod(2, 8 * d, q);
@@ -128,8 +132,9 @@ static void build_pass(PassTables& pt, int r, const Mat16& WA, const Mat16& T, c
       int col = lane % 16, g = lane / 16;
       for (int c = 0; c < 4; ++c) {
         uint32_t a = 0, b = 0;
+        const int u = ua ? g + 4 * c : 4 * g + c;
         for (int d = 0; d < 4; ++d) {
-          a |= (uint32_t)(uint8_t)digit(mulm(p2[d], WA[4 * g + c][col], q), q, j) << (8 * d);
+          a |= (uint32_t)(uint8_t)digit(mulm(p2[d], WA[u][col], q), q, j) << (8 * d);
           if (r == 16) {
             uint32_t wb = mulm(WB[col][4 * g + c], wb_scale, q);
             b |= (uint32_t)(uint8_t)digit(mulm(p2[d], wb, q), q, j) << (8 * d);
@@ -140,10 +145,11 @@ static void build_pass(PassTables& pt, int r, const Mat16& WA, const Mat16& T, c
       }
     }
   uint32_t r32 = (uint32_t)((1ull << 32) % q);
+  if (!tw_scale) tw_scale = r32;
   for (int lane = 0; lane < 64; ++lane)
     for (int j = 0; j < 4; ++j) {
       const int v = (4 * (lane / 16) + j) % r;
-      uint32_t w = mulm(T[lane % 16][v], r32, q);
+      uint32_t w = mulm(T[lane % 16][v], tw_scale, q);
       pt.twist[lane][j] = make_uint2(w, shoup_companion(w, q));
     }
   for (int i = 0; i < 16; ++i) {
@@ -169,8 +175,31 @@ static void build_post(uint2* post, int r, int ncols, uint32_t q, uint32_t scale
       }
 }
 
+// One-pass kernel: the first pass's post-twist P(col, out) split into a
+// per-lane factor and a per-step factor (see OnePassTables).
+template <typename F>
+static void build_onepass_post(OnePassTables& op, int r1, int ncols, uint32_t q, uint32_t scale, F P) {
+  const uint32_t r32 = (uint32_t)((1ull << 32) % q);
+  const int mt = 16 / r1, steps = ncols / (4 * mt);
+  memset(op.post_a, 0, sizeof(op.post_a));
+  for (int lane = 0; lane < 64; ++lane)
+    for (int j = 0; j < 4; ++j) {
+      int m, t;
+      lane_output(r1, lane, j, &m, &t);
+      const int out = lane % 16 + 16 * t;
+      for (int sg = 0; sg < 4; ++sg) {
+        const uint32_t w = mulm(P(4 * m + sg, out), scale, q);
+        op.post_b[lane][j][sg] = make_uint2(w, shoup_companion(w, q));
+      }
+      const uint32_t base_inv = inv_mod(P(4 * m, out), q);
+      for (int st = 0; st < steps; ++st)
+        op.post_a[st][lane][j] = mulm(mulm(P(4 * st * mt + 4 * m, out), base_inv, q), r32, q);
+    }
+}
+
 struct FsHostLimb {
   PassTables p1, p2;
+  OnePassTables op;
   std::vector<uint2> post;
   CoPass c1, c2;               // N = 2^16: plain matrices for the vector-ALU variant
   std::vector<uint2> co_post;  // [column][output]
@@ -241,6 +270,18 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint3
     auto P = [&](int n2, int k1) { return pow_mod(psi, (uint64_t)(2 * k1 + 1) * n2 % twoN, q); };
     build_post(L.post.data(), r, 256, q, r == 16 ? r32 : 1, P);
     if (r == 16) co_post(P);
+    if (r < 16) {
+      // one-pass second pass: the 256-point stage with unscaled level-B
+      // twiddles and the twist carrying 2^64
+      for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) {
+          WA[a][b] = pow_mod(om, 16ull * a * b, q);
+          T[a][b] = mulm(pow_mod(om, (uint64_t)a * b, q), r32, q);
+          WB[a][b] = WA[a][b];
+        }
+      build_pass(L.op.p2, 16, WA, T, WB, q, 1, nullptr);
+      build_onepass_post(L.op, r, 256, q, 1, P);
+    }
   } else {
     cyc256(L.p1, omi, 1);
     if (r == 16) {
@@ -262,11 +303,13 @@ static void build_fourstep_limb(FsHostLimb& L, uint32_t log_n, uint32_t q, uint3
       const uint32_t rho = pow_mod(phii, 32, q);
       for (int i = 0; i < 16; ++i) lb[i] = i < 8 ? pow_mod(rho, i, q) : pow_mod(phii, 16ull * (i - 8), q);
       build_pass(L.p2, r, WA, T, WB, q, 1, lb);
+      build_pass(L.op.p2, r, WA, T, WB, q, 1, lb, true);
     }
     // column k1, output n2: psi^{-(2 k1 + 1) n2}
     auto P = [&](int k1, int n2) { return pow_mod(psii, (uint64_t)(2 * k1 + 1) * n2 % twoN, q); };
     build_post(L.post.data(), 16, (int)N1, q, r32, P);
     if (r == 16) co_post(P);
+    if (r < 16) build_onepass_post(L.op, 16, (int)N1, q, r32, P);
   }
 }
 
@@ -316,7 +359,9 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
     const size_t post_elems = 256 * 64 * 4;
     const bool co = p->log_n == 16;
     const size_t co_bytes = co ? 2 * sizeof(CoPass) + 256 * 256 * sizeof(uint2) : 0;
-    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint2) + co_bytes;
+    const bool one = p->log_n <= 15;  // one-pass kernel tables
+    const size_t op_bytes = one ? sizeof(OnePassTables) : 0;
+    const size_t per = 2 * sizeof(PassTables) + post_elems * sizeof(uint2) + co_bytes + op_bytes;
     const size_t total = per * 2 * L;
     std::vector<unsigned char> blob(total);
     std::vector<FourStepLimb> hf(L), hi(L);
@@ -338,6 +383,12 @@ tfhe_status plan_build(tfhe_ntt_plan_s* p) {
         f.post1 = (const uint2*)(dbase + off + 2 * sizeof(PassTables));
         f.co1 = f.co2 = nullptr;
         f.co_post = nullptr;
+        f.op = nullptr;
+        if (one) {
+          const size_t o3 = off + 2 * sizeof(PassTables) + post_elems * sizeof(uint2) + co_bytes;
+          memcpy(&blob[o3], &H.op, sizeof(OnePassTables));
+          f.op = (const OnePassTables*)(dbase + o3);
+        }
         if (co) {
           const size_t o2 = off + 2 * sizeof(PassTables) + post_elems * sizeof(uint2);
           memcpy(&blob[o2], &H.c1, sizeof(CoPass));

@@ -322,3 +322,47 @@ def test_fused_batch_beyond_one_launch_table(tf):
         outs = tf.ntt_batch(items, algo=algo)
         for k, (o, r) in enumerate(zip(outs, refs)):
             assert np.array_equal(to_host(o), r), (algo, k)
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15])
+def test_mfma_one_and_two_passes_match_oracle(tf, log_n, passes):
+    """The four-step transform with one HBM round trip (polynomial resident
+    in LDS) and with two, at N = 2^12..2^15: forward and inverse against the
+    oracle for limbs from all three prime windows, on a ragged batch of 7
+    polynomials (workgroups end on partial polynomial ranges), in place."""
+    n = 1 << log_n
+    qs = [WINDOWS[w][0] for w in sorted(WINDOWS)] + PRIMES31[1:3]
+    plan = tf.NttPlan(log_n, qs, algo="mfma")
+    plan.set_param("fs_passes", passes)
+    assert plan.get_param("fs_passes") == passes
+    x = inputs.uniform_residues(300 + log_n, qs, (7, n))
+    x[0, 0, :5] = [0, qs[0] - 1, 1, qs[0] - 2, 0x7F7F7F7F % qs[0]]
+    ref = oracle.ntt_fwd(x, qs, plan.psi)
+    X = to_dev(x)
+    plan.fwd(X, out=X, algo="mfma")
+    assert np.array_equal(to_host(X), ref)
+    plan.inv(X, out=X, algo="mfma")
+    assert np.array_equal(to_host(X), x)
+    assert np.array_equal(to_host(plan.inv(to_dev(x), algo="mfma")), oracle.ntt_inv(x, qs, plan.psi))
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15])
+def test_mfma_one_pass_large_batch_equals_two_pass(tf, log_n):
+    """A batch of 8 limbs x 129 polynomials (more polynomials than
+    workgroups, ranges crossing limbs): one pass == two passes bit for bit,
+    both directions; sampled polynomials against the oracle."""
+    n = 1 << log_n
+    qs = PRIMES31[:4] + [WINDOWS["q31_in_window"][0]] + oracle.ntt_primes(3, 30, 1 << 17)
+    plan = tf.NttPlan(log_n, qs, algo="mfma")
+    x = to_dev(inputs.uniform_residues(400 + log_n, qs, (129, n)))
+    plan.set_param("fs_passes", 2)
+    f2, i2 = plan.fwd(x, algo="mfma"), plan.inv(x, algo="mfma")
+    plan.set_param("fs_passes", 1)
+    f1, i1 = plan.fwd(x, algo="mfma"), plan.inv(x, algo="mfma")
+    assert torch.equal(f1, f2)
+    assert torch.equal(i1, i2)
+    xs = to_host(x)
+    for l, b in ((0, 0), (3, 128), (7, 64)):
+        got = to_host(f1)[l:l + 1, b:b + 1]
+        assert np.array_equal(got, oracle.ntt_fwd(xs[l:l + 1, b:b + 1], qs[l:l + 1], plan.psi[l:l + 1]))
