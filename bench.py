@@ -181,10 +181,12 @@ def cpu_baseline(qs, psis, budget_s=10.0):
                                 "(numpy element-wise steps, C transforms on all cores)"}}
 
 
-def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native"), native_slots=8):
+def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native"), native_slots=8,
+                table=None):
     """Config 5: Poisson HMULT / rotate requests, N in {2^13..2^16}, levels
     uniform in 1..24, 8 rotation keys per N, keys and ciphertexts resident,
     memory-gated continuous batching.  Returns throughput and p50/p99."""
+    from paper_2212_14191_amd import autotune
     from paper_2212_14191_amd.scheme import Scheme
     from paper_2212_14191_amd.serving import GpuBackend, Server
     L, K, dnum = HM_L, HM_K, HM_DNUM
@@ -198,6 +200,8 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         a = inputs.uniform_residues(1, ctx.moduli, (dnum, n), stream=1).transpose(1, 0, 2)
         e = inputs.gaussian_error(2, (dnum, n), stream=1)
         ctxs[ln], evks[ln] = ctx, sch.relin_key(s, a, e)
+        if table is not None:
+            autotune.apply(ctx.plan, table, L, 64)
         for r in rots:
             g = pow(5, r, 2 * n)
             rks[(ln, g)] = sch.rotation_key(s, g, a, e)
@@ -211,6 +215,9 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
     torch.cuda.synchronize()
     slots, budget = 4, 48 << 30
 
+    # per-N batch limits the autotuner chose (HMULT at level 24), else 16
+    by_n = autotune.serving_batches(table, log_ns, L) if table is not None else {}
+
     # one long-lived backend: its streams, events and per-slot workspaces stay
     # warm across the runs, as in a running server
     backend = GpuBackend(ctxs, evks, rks, slots=slots)
@@ -218,7 +225,7 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
     def run(count, seed, rate):
         mix = inputs.request_mix(seed, count, log_ns=log_ns, max_level=L, rotations=rots)
         arrivals = inputs.poisson_arrivals(seed, rate, count) if rate else np.zeros(count)
-        srv = Server(backend, budget, slots=slots, max_batch=16)
+        srv = Server(backend, budget, slots=slots, max_batch=16, max_batch_by_n=by_n)
         futs = []
         t0 = time.perf_counter()
         for i in range(count):
@@ -241,6 +248,8 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
     native = tfhe.NativeServer(slots=native_slots, max_batch=16, pool_bytes=native_slots * (3 << 30))
     for ln in log_ns:
         native.add_context(ctxs[ln], evks[ln], {g: k for (l2, g), k in rks.items() if l2 == ln})
+        if ln in by_n:
+            native.set_max_batch(ln, by_n[ln])
 
     def run_native(count, seed, rate):
         # The client prepares every request (inputs resident, outputs
@@ -295,7 +304,7 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         return {"throughput_per_s": count / (np.max(t_done) - t_sub[0]),
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
-    out = {"requests": n_req, "max_batch": 16}
+    out = {"requests": n_req, "max_batch": 16, "max_batch_by_n": {str(k): v for k, v in by_n.items()}}
     for name, fn in (("python", run), ("native", run_native)):
         if name not in engines:
             continue
@@ -373,7 +382,19 @@ def main():
         for _ in range(args.warmup):
             y.copy_(x)
         copy_gbs = 2 * x.numel() * 4 * 10 / timed(lambda: y.copy_(x), 10, sync) / 1e9
+    # the autotuner's persisted choices (written on the GPU by
+    # `python -m paper_2212_14191_amd.autotune`); absent entries keep the
+    # library defaults
+    from paper_2212_14191_amd import autotune
+    table = autotune.load_default()
+    tuning = {"table": os.path.relpath(autotune.TABLE_PATH, ROOT) if table.entries else None}
     for algo in algos:
+        if algo == "mfma":
+            tuning["ntt"] = autotune.apply(plan, table, LIMBS, BATCH)
+        else:
+            for name in autotune.PLAN_PARAMS:
+                plan.set_param(name, 0)
+
         def step(algo=algo):
             plan.fwd(x, out=y, algo=algo, ws=ws)
             plan.inv(y, out=z, algo=algo, ws=ws)
@@ -410,6 +431,7 @@ def main():
         t_setup = time.perf_counter()
         ctx = tfhe.CkksContext(LOG_N, HM_L, HM_K, HM_DNUM)
         setup["ckks_context_s"] = round(time.perf_counter() - t_setup, 3)
+        tuning["hmult_ntt"] = autotune.apply(ctx.plan, table, HM_L, HM_BATCH)
         sch = Scheme(ctx)
         s = inputs.ternary_secret(1, n, 192)
         a = inputs.uniform_residues(1, ctx.moduli, (HM_DNUM, n), stream=1).transpose(1, 0, 2)
@@ -476,7 +498,8 @@ def main():
     if not args.skip_serving and args.only in (None, "serving"):
         engines = ("python", "native") if args.serving_engine == "both" else (args.serving_engine,)
         serving = serving_leg(args.serving_requests, args.serving_requests, (0.25, 0.5, 0.75, 0.9), torch, tfhe,
-                              inputs, engines, args.native_slots)
+                              inputs, engines, args.native_slots, table)
+        tuning["serving_max_batch"] = serving.get("max_batch_by_n")
         log("serving", json.dumps(serving))
 
     cpu = None
@@ -524,6 +547,7 @@ def main():
                      "avg_launch_ms": round(kstat["avg_ms"], 4),
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "roofline_mfma": mfma_line,
+        "tuning": tuning,
         "cpu_baseline": cpu,
     }
     if "butterfly" in results and "mfma" in results:

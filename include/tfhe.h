@@ -349,6 +349,12 @@ tfhe_status tfhe_server_create(tfhe_server* out, uint32_t slots, uint32_t max_ba
  * queued requests hold raw pointers to them. */
 tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint32_t* evk);
 
+/* Batch limit for requests of N = 2^log_n (a context must be registered):
+ * the best batch size differs per kernel shape (Sec. IV-E, Sec. VI-E),
+ * which the autotuner measures; 0 restores the server's max_batch.
+ *   max_batch in [0, TFHE_ROTATE_MULTI_MAX]. */
+tfhe_status tfhe_server_set_max_batch(tfhe_server s, uint32_t log_n, uint32_t max_batch);
+
 /* Registers the rotation key (device, layout as for tfhe_rotate, 16-byte
  * aligned; it must outlive the server) of Galois element galois_elt (odd,
  * < 2N) for the context of N = 2^log_n. */

@@ -1,21 +1,37 @@
 """Self-written autotuner (the API layer "generates the best batch size for
 the different involved kernels according to the hardware resources",
-Sec. IV-E; the best batch differs per kernel, Sec. VI).
+Sec. IV-E; the best batch differs per kernel, Sec. VI-E).
 
 * NTT: for a (log N, limbs, batch) shape, times forward + inverse for each
-  candidate (algorithm x 256-point item width x persistent four-step
-  workgroups per CU) and keeps the fastest.
+  candidate (algorithm x HBM round trips of the four-step transform, one or
+  two x 256-point item width x persistent four-step workgroups per CU) and
+  keeps the fastest.  Every candidate's round trip must be the identity.
 * HMULT: sweeps the batch size at a (log N, level) and keeps the smallest
   batch within `slack` of the best throughput (small batches keep latency
   low in the serving loop).
-Results persist as JSON; `apply` writes the NTT choice into a plan.
+
+Results persist as JSON (TuneTable).  `apply` writes a tuned NTT choice into
+a plan; `serving_batches` turns the HMULT entries into per-N batch limits
+for both serving engines (Server(max_batch_by_n=...),
+NativeServer.set_max_batch).  The table shipped with the package
+(TABLE_PATH) is written on the GPU by
+
+    python -m paper_2212_14191_amd.autotune --out paper_2212_14191_amd/tune_mi355x.json
+
+Knobs the search does not cover: the LDS ring depth of the two-pass kernel
+(a compile-time constant) and the N1 x 256 split itself (fixed by the
+operand tables; the one-pass kernel is the structural alternative).
 """
 import json
 import os
 import time
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE_PATH = os.path.join(HERE, "tune_mi355x.json")
+
 NTT_WG_CANDIDATES = (0, 1, 2, 3, 4, 6, 8)
 NTT_WIDE_CANDIDATES = (1, 2)   # narrow / wide 256-point items (0 = library default)
+HMULT_BATCHES = (1, 2, 4, 8, 16, 32, 64)
 
 
 def ntt_key(log_n, limbs, batch):
@@ -63,15 +79,44 @@ class TuneTable:
         os.replace(tmp, path)
 
 
+def load_default():
+    """The table shipped with the package (empty when absent)."""
+    return TuneTable(TABLE_PATH)
+
+
+PLAN_PARAMS = ("fs_passes", "fs_wide", "fs_wg_per_cu")
+
+
 def apply(plan, table, limbs, batch):
-    """Set a plan's tuned parameters for this shape, if the table has them."""
+    """Set a plan's tuned parameters for this shape, if the table has them.
+    Returns the applied entry (or None)."""
     e = table.get(ntt_key(plan.log_n, limbs, batch))
     if not e:
-        return False
+        return None
     plan.set_param("auto_algo", {"butterfly": 1, "mfma": 2}[e["algo"]])
-    plan.set_param("fs_wg_per_cu", e.get("fs_wg_per_cu", 0))
-    plan.set_param("fs_wide", e.get("fs_wide", 0))
-    return True
+    for name in PLAN_PARAMS:
+        plan.set_param(name, e.get(name, 0))
+    return e
+
+
+def serving_batches(table, log_ns, level):
+    """{log_n: tuned HMULT batch at `level`} for the N the table covers."""
+    out = {}
+    for ln in log_ns:
+        e = table.get(hmult_key(ln, level))
+        if e and "batch" in e:
+            out[ln] = int(e["batch"])
+    return out
+
+
+def ntt_candidates(log_n, mfma):
+    """(algo, fs_passes, fs_wide, fs_wg_per_cu) tuples to time."""
+    cands = [("butterfly", 0, 0, 0)]
+    if mfma:
+        cands += [("mfma", 2, wide, w) for wide in NTT_WIDE_CANDIDATES for w in NTT_WG_CANDIDATES]
+        if 12 <= log_n <= 15:
+            cands += [("mfma", 1, 0, 0)]
+    return cands
 
 
 def tune_ntt(plan, x, reps=5, warmup=1):
@@ -80,15 +125,15 @@ def tune_ntt(plan, x, reps=5, warmup=1):
     from . import tfhe
     limbs, batch, _ = x.shape
     y, z = torch.empty_like(x), torch.empty_like(x)
-    cands = [("butterfly", 0, 0)]
-    if plan.get_param("auto_algo") == tfhe.FOURSTEP_MFMA or _has_mfma(plan):
-        cands += [("mfma", wide, w) for wide in NTT_WIDE_CANDIDATES for w in NTT_WG_CANDIDATES]
-    ws = plan.workspace(limbs, batch, "mfma" if len(cands) > 1 else "butterfly")
+    mfma = plan.get_param("auto_algo") == tfhe.FOURSTEP_MFMA or _has_mfma(plan)
+    cands = ntt_candidates(plan.log_n, mfma)
+    ws = plan.workspace(limbs, batch, "mfma" if mfma else "butterfly")
     results = []
-    old = (plan.get_param("fs_wg_per_cu"), plan.get_param("fs_wide"))
-    for algo, wide, w in cands:
-        plan.set_param("fs_wg_per_cu", w)
+    old = {name: plan.get_param(name) for name in PLAN_PARAMS}
+    for algo, passes, wide, w in cands:
+        plan.set_param("fs_passes", passes)
         plan.set_param("fs_wide", wide)
+        plan.set_param("fs_wg_per_cu", w)
         for _ in range(warmup):
             plan.fwd(x, out=y, algo=algo, ws=ws)
             plan.inv(y, out=z, algo=algo, ws=ws)
@@ -100,10 +145,11 @@ def tune_ntt(plan, x, reps=5, warmup=1):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if not torch.equal(z, x):
-            raise RuntimeError(f"autotune: {algo}/{wide}/{w} failed the round trip")
-        results.append(({"algo": algo, "fs_wide": wide, "fs_wg_per_cu": w}, 2 * limbs * batch * reps / dt / 1e3))
-    plan.set_param("fs_wg_per_cu", old[0])
-    plan.set_param("fs_wide", old[1])
+            raise RuntimeError(f"autotune: {algo}/{passes}/{wide}/{w} failed the round trip")
+        cfg = {"algo": algo, "fs_passes": passes, "fs_wide": wide, "fs_wg_per_cu": w}
+        results.append((cfg, 2 * limbs * batch * reps / dt / 1e3))
+    for name, v in old.items():
+        plan.set_param(name, v)
     cfg, kops = pick_best(results)
     best = dict(cfg, kops=kops)
     return best, [dict(c, kops=k) for c, k in results]
@@ -117,7 +163,7 @@ def _has_mfma(plan):
         return False
 
 
-def tune_hmult_batch(ctx, make_inputs, level, batches=(1, 2, 4, 8, 16, 32, 64), reps=3, slack=0.05):
+def tune_hmult_batch(ctx, make_inputs, level, batches=HMULT_BATCHES, reps=3, slack=0.05):
     """make_inputs(batch) -> (ct_a, ct_b, evk) on the device.  Returns
     (chosen batch, {batch: HMULT/s})."""
     import torch
@@ -135,3 +181,61 @@ def tune_hmult_batch(ctx, make_inputs, level, batches=(1, 2, 4, 8, 16, 32, 64), 
         tput[b] = b * reps / (time.perf_counter() - t0)
         del a, bb, out, ws
     return pick_batch(tput, slack), tput
+
+
+def _random_residues(torch, moduli, batch, n):
+    """Uniform residues [len(moduli)][batch][n] drawn on the device (tuning
+    inputs: timing does not depend on the values)."""
+    t = torch.empty((len(moduli), batch, n), dtype=torch.int64, device="cuda")
+    for l, q in enumerate(moduli):
+        t[l].random_(0, q)
+    return t.to(torch.int32)
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="tune the NTT plans and HMULT batch sizes on this GPU")
+    ap.add_argument("--out", default=TABLE_PATH)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    import torch
+    from . import tfhe
+    tfhe.load()
+    torch.cuda.set_device(0)
+    table = TuneTable()
+    table.put("device", {"name": torch.cuda.get_device_name(0),
+                         "cus": torch.cuda.get_device_properties(0).multi_processor_count})
+    # NTT shapes: the transform benchmark (44 limbs x 128) and the serving
+    # shapes (24 limbs x 64) at every N of the four-step range
+    shapes = [(16, 44, 128)] + [(ln, 24, 64) for ln in (12, 13, 14, 15, 16)]
+    for ln, limbs, batch in shapes:
+        qs = tfhe.tfhe_find_primes(31, 1 << 17, limbs)
+        plan = tfhe.NttPlan(ln, qs)
+        x = _random_residues(torch, qs, batch, 1 << ln)
+        best, allr = tune_ntt(plan, x, reps=args.reps)
+        table.put(ntt_key(ln, limbs, batch), best)
+        print("ntt", ln, limbs, batch, json.dumps(best), flush=True)
+        del x, plan
+    # HMULT batch per N at the serving shapes (L = 24, K = 8, dnum = 3),
+    # level 24 and a middle level
+    for ln in (13, 14, 15, 16):
+        ctx = tfhe.CkksContext(ln, 24, 8, 3)
+        n = 1 << ln
+        evk = torch.cat([_random_residues(torch, ctx.moduli, 2, n).permute(1, 0, 2).reshape(1, 2, 32, n)
+                         for _ in range(3)])
+        for level in (24, 12):
+            def make(b, level=level):
+                qs = ctx.moduli[:level]
+                a = torch.stack([_random_residues(torch, qs, b, n) for _ in range(2)])
+                c = torch.stack([_random_residues(torch, qs, b, n) for _ in range(2)])
+                return a, c, evk.contiguous()
+            b, tput = tune_hmult_batch(ctx, make, level)
+            table.put(hmult_key(ln, level), {"batch": b, "ops_per_s": {str(k): round(v, 1) for k, v in tput.items()}})
+            print("hmult", ln, level, b, flush=True)
+        ctx.close()
+    table.save(args.out)
+    print("wrote", args.out)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,6 +86,7 @@ struct Ctx {
   tfhe_ckks_ctx ctx = nullptr;
   const uint32_t* evk = nullptr;
   std::map<uint32_t, const uint32_t*> rk;  // Galois element -> rotation key
+  uint32_t max_batch = 0;                  // this N's batch limit (0: the server's)
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -195,7 +196,9 @@ bool tfhe_server_s::take(const Slot& sl, std::vector<Req>& reqs) {
   if (order.empty()) return false;
   const Key key = order.front().second;
   std::deque<Req>& q = pending[key];
-  uint32_t B = std::min<uint32_t>((uint32_t)q.size(), max_batch);
+  auto ci = ctxs.find(key.log_n);
+  const uint32_t mb = ci != ctxs.end() && ci->second.max_batch ? ci->second.max_batch : max_batch;
+  uint32_t B = std::min<uint32_t>((uint32_t)q.size(), mb);
   while (B > 1 && need(q.front(), B) > sl.bytes) B /= 2;
   if (need(q.front(), B) > sl.bytes) return false;  // cannot happen: submission checks one request
   reqs.assign(q.begin(), q.begin() + B);
@@ -299,6 +302,16 @@ tfhe_status tfhe_server_add_context(tfhe_server s, tfhe_ckks_ctx ctx, const uint
   if (c.ctx != ctx) c.rk.clear();
   c.ctx = ctx;
   c.evk = evk;
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_server_set_max_batch(tfhe_server s, uint32_t log_n, uint32_t max_batch) {
+  if (!s) return fail(TFHE_EINVAL, "server_set_max_batch: null server");
+  if (max_batch > kMaxRotBatch) return fail(TFHE_EINVAL, "server_set_max_batch: max_batch above TFHE_ROTATE_MULTI_MAX");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->ctxs.find(log_n);
+  if (it == s->ctxs.end()) return fail(TFHE_EINVAL, "server_set_max_batch: no context for this N");
+  it->second.max_batch = max_batch;
   return TFHE_OK;
 }
 

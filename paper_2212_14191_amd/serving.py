@@ -47,12 +47,15 @@ class Request:
 
 
 class Server:
-    def __init__(self, backend, mem_budget_bytes, slots=4, max_batch=16, poll_s=1e-5):
+    def __init__(self, backend, mem_budget_bytes, slots=4, max_batch=16, poll_s=1e-5, max_batch_by_n=None):
         self.backend = backend
         self.budget = int(mem_budget_bytes)
         self.slots = int(slots)
         # a backend may cap the batch (the GPU backend: TFHE_ROTATE_MULTI_MAX)
-        self.max_batch = min(int(max_batch), getattr(backend, "max_batch", int(max_batch)))
+        cap = getattr(backend, "max_batch", int(max_batch))
+        self.max_batch = min(int(max_batch), cap)
+        # per-N limits (the autotuner's choice, autotune.serving_batches)
+        self.max_batch_by_n = {int(k): max(1, min(int(v), cap)) for k, v in (max_batch_by_n or {}).items()}
         self.poll_s = poll_s
         self._pending = collections.OrderedDict()  # id -> Request (FIFO)
         self._by_key = {}                           # batching key -> deque of ids (FIFO)
@@ -165,8 +168,9 @@ class Server:
         if not self._pending:
             return None
         ids = []
+        limit = self.max_batch_by_n.get(head.log_n, self.max_batch)
         for rid in self._by_key[head.key]:
-            if len(ids) == self.max_batch:
+            if len(ids) == limit:
                 break
             if not self._expired(self._pending[rid], now):
                 ids.append(rid)

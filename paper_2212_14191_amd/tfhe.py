@@ -95,6 +95,7 @@ def load():
         "tfhe_server_create": ([ctypes.POINTER(vp), u32, u32, vp, sz], i32),
         "tfhe_server_add_context": ([vp, vp, vp], i32),
         "tfhe_server_add_rotation_key": ([vp, u32, u32, vp], i32),
+        "tfhe_server_set_max_batch": ([vp, u32, u32], i32),
         "tfhe_server_submit": ([vp, u32, u32, u32, vp, vp, u32, vp, u64, vp], i32),
         "tfhe_server_submit_many": ([vp, ctypes.POINTER(ServerRequest), u32, vp, ctypes.POINTER(u32)], i32),
         "tfhe_server_poll": ([vp, ctypes.POINTER(u64), ctypes.POINTER(i32), u32], u32),
@@ -510,6 +511,11 @@ class NativeServer:
             _call("tfhe_server_add_rotation_key", self.handle, ctx.log_n, int(g), _ptr(k))
             self._keep.append(k)
             keys[int(g)] = k
+
+    def set_max_batch(self, log_n, max_batch):
+        """tfhe_server_set_max_batch: the batch limit of one N (0 = the
+        server's)."""
+        _call("tfhe_server_set_max_batch", self.handle, log_n, int(max_batch))
 
     def submit(self, op, ct_a, ct_b=None, galois=0, out=None, stream=None):
         """Queues one request on ciphertext(s) of shape [2][level][N] (or

@@ -1,5 +1,7 @@
-"""Autotuner selection logic and persistence (CPU), and a GPU tuning run
-whose chosen configuration gives the same bits as the default."""
+"""Autotuner: selection logic, persistence and application (CPU, with a
+stand-in plan), and on the GPU a tuning run whose chosen plan is checked
+against the oracle, plus an HMULT batch sweep whose chosen batch gives the
+oracle's results."""
 import numpy as np
 import pytest
 
@@ -28,21 +30,95 @@ def test_table_roundtrip(tmp_path):
     assert t2.get("missing") is None
 
 
+class FakePlan:
+    def __init__(self, log_n):
+        self.log_n = log_n
+        self.params = {}
+
+    def set_param(self, name, value):
+        self.params[name] = value
+
+
+def test_apply_and_serving_batches():
+    t = autotune.TuneTable()
+    t.put(autotune.ntt_key(14, 24, 64), {"algo": "mfma", "fs_passes": 1, "fs_wide": 0, "fs_wg_per_cu": 0})
+    t.put(autotune.hmult_key(14, 24), {"batch": 8})
+    t.put(autotune.hmult_key(16, 24), {"batch": 32})
+    plan = FakePlan(14)
+    e = autotune.apply(plan, t, 24, 64)
+    assert e["fs_passes"] == 1
+    assert plan.params == {"auto_algo": 2, "fs_passes": 1, "fs_wide": 0, "fs_wg_per_cu": 0}
+    assert autotune.apply(FakePlan(15), t, 24, 64) is None
+    assert autotune.serving_batches(t, (13, 14, 15, 16), 24) == {14: 8, 16: 32}
+
+
+def test_search_space_covers_passes():
+    c14 = autotune.ntt_candidates(14, True)
+    assert ("mfma", 1, 0, 0) in c14 and ("mfma", 2, 2, 0) in c14 and ("butterfly", 0, 0, 0) in c14
+    assert all(p == 2 for a, p, _, _ in autotune.ntt_candidates(16, True) if a == "mfma")
+    assert autotune.ntt_candidates(10, False) == [("butterfly", 0, 0, 0)]
+
+
+def test_shipped_table_is_well_formed():
+    t = autotune.load_default()
+    if not t.entries:
+        pytest.skip("no tune table shipped")
+    for k, v in t.entries.items():
+        if k.startswith("ntt:"):
+            assert v["algo"] in ("mfma", "butterfly") and v.get("fs_passes", 0) in (0, 1, 2)
+        elif k.startswith("hmult:"):
+            assert 1 <= v["batch"] <= 64
+
+
 @pytest.mark.gpu
-def test_tuned_plan_is_bit_identical():
+def test_tuned_plan_matches_oracle():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import oracle
     from paper_2212_14191_amd import inputs, tfhe
     qs = oracle.ntt_primes(4, 31, 1 << 17)
-    plan = tfhe.NttPlan(16, qs)
-    x_host = inputs.uniform_residues(0, qs, (8, 1 << 16))
+    plan = tfhe.NttPlan(14, qs)
+    x_host = inputs.uniform_residues(0, qs, (8, 1 << 14))
     x = torch.from_numpy(x_host.view(np.int32)).cuda()
-    ref = plan.fwd(x).clone()
     best, table = autotune.tune_ntt(plan, x, reps=2)
-    assert len(table) >= 2 and best["kops"] > 0
+    assert len(table) >= 16 and best["kops"] > 0
+    assert any(c["fs_passes"] == 1 for c in table)
     t = autotune.TuneTable()
-    t.put(autotune.ntt_key(16, 4, 8), best)
-    assert autotune.apply(plan, t, 4, 8)
-    assert torch.equal(plan.fwd(x), ref)
+    t.put(autotune.ntt_key(14, 4, 8), best)
+    assert autotune.apply(plan, t, 4, 8) == best
+    got = plan.fwd(x).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, oracle.ntt_fwd(x_host, qs, plan.psi))
+
+
+@pytest.mark.gpu
+def test_tune_hmult_batch_and_oracle():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import ckks
+    from paper_2212_14191_amd import inputs, tfhe
+    n, L, K, dnum, level = 1 << 12, 8, 4, 2, 6
+    pr = ckks.Params(n, L=L, K=K, dnum=dnum)
+    s = inputs.ternary_secret(1, n, 64)
+    a = inputs.uniform_residues(1, pr.moduli, (dnum, n), stream=1).transpose(1, 0, 2)
+    evk = ckks.relin_key(pr, s, a, inputs.gaussian_error(2, (dnum, n), stream=1))
+    ctx = tfhe.CkksContext(12, L, K, dnum, moduli=pr.moduli)
+    to_dev = lambda v: torch.from_numpy(np.ascontiguousarray(v).view(np.int32)).cuda()
+    evk_d = to_dev(evk)
+    made = {}
+
+    def make(b):
+        cts = []
+        for k in range(2):
+            m = inputs.small_messages(k, (b, n))
+            c1 = inputs.uniform_residues(5 + k, pr.mods(range(level)), (b, n), stream=5)
+            cts.append(ckks.encrypt(pr, s, m, c1, inputs.gaussian_error(2, (b, n), stream=9 + k), level))
+        made[b] = cts
+        return to_dev(cts[0]), to_dev(cts[1]), evk_d
+
+    batch, tput = autotune.tune_hmult_batch(ctx, make, level, batches=(1, 2, 4), reps=2)
+    assert batch in (1, 2, 4) and set(tput) == {1, 2, 4} and all(v > 0 for v in tput.values())
+    ca, cb = made[batch]
+    got = ctx.hmult(to_dev(ca), to_dev(cb), evk_d, level).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, ckks.hmult(pr, ca, cb, evk, level))

@@ -351,3 +351,25 @@ def test_serving_shapes_alone_equal_mix_and_oracle(serving_world):
             else:
                 want = ckks.rotate(pr, to_np(a), to_np(rks[(ln, g)]), g, lv)
             assert np.array_equal(to_np(outs[k][1]), want), (ln, op, lv)
+
+
+def test_native_server_per_n_batch_limit(world):
+    """tfhe_server_set_max_batch: a per-N limit (as the autotuner sets) keeps
+    every result equal to its single call; bad arguments are refused."""
+    from paper_2212_14191_amd import tfhe
+    reqs = requests(world, 24, 5)
+    alone = alone_results(world, reqs)
+    srv = native_server(world, slots=2, max_batch=16, pool_bytes=512 << 20)
+    srv.set_max_batch(10, 2)
+    srv.set_max_batch(12, 3)
+    outs = srv.submit_many([(op, a, b, g or 0, None) for op, ln, lv, a, b, g in reqs])
+    done = drain(srv, len(reqs))
+    assert all(st is None for st in done.values()), done
+    for (tag, out), want in zip(outs, alone):
+        assert torch.equal(out, want), tag
+    with pytest.raises(tfhe.TfheError):
+        srv.set_max_batch(11, 4)    # no context for N = 2^11
+    with pytest.raises(tfhe.TfheError):
+        srv.set_max_batch(10, 65)   # above TFHE_ROTATE_MULTI_MAX
+    srv.set_max_batch(10, 0)        # back to the server's limit
+    srv.close()
