@@ -40,15 +40,27 @@ I8_OPS_PER_COEFF_PASS = 8 * 16 * 16 * 64 * 2 // 256
 
 # Sources that determine the four-step kernels' memory traffic; the profile
 # summary records their hash next to the hardware byte counts.
-TRAFFIC_SOURCES = ("csrc/ntt_fourstep.hip", "csrc/internal.hpp", "csrc/modarith.hpp", "csrc/plan.cpp")
+# (and the tune table, which sets the launch shape the benchmark uses)
+TRAFFIC_SOURCES = ("csrc/ntt_fourstep.hip", "csrc/fourstep_dev.hpp", "csrc/internal.hpp", "csrc/modarith.hpp",
+                   "csrc/plan.cpp", "tune_mi355x.json")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ntt_mfma_n16_44x128.md")
+
+
+def _code_only(text):
+    """Source text without comments and blank lines (so that comment edits
+    do not invalidate a profile record)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*$", "", l).rstrip() for l in text.splitlines())
+    return "\n".join(l for l in lines if l.strip())
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
     for rel in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_2212_14191_amd", rel), "rb") as f:
-            h.update(f.read())
+        path = os.path.join(ROOT, "paper_2212_14191_amd", rel)
+        if os.path.exists(path):
+            with open(path) as f:
+                h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
@@ -181,6 +193,29 @@ def cpu_baseline(qs, psis, budget_s=10.0):
                                 "(numpy element-wise steps, C transforms on all cores)"}}
 
 
+P99_BOUND_MS = 5.0
+
+
+def sustainable_rate(fn, saturated, n_req, probes=7):
+    """Highest Poisson arrival rate (requests/s) whose p99 submit-to-done
+    latency stays at or below P99_BOUND_MS, by bisection on the fraction of
+    the saturated rate (each probe serves min(n_req, 4000) requests of the
+    same mix; the arrivals' seed differs from the load points')."""
+    count = min(n_req, 4000)
+    lo, hi, best = 0.0, 1.0, None
+    for _ in range(probes):
+        frac = (lo + hi) / 2
+        st = fn(count, 4, frac * saturated)
+        rec = {"rate_per_s": round(frac * saturated, 1), "throughput_per_s": round(st["throughput_per_s"], 1),
+               "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)}
+        if st["p99_ms"] <= P99_BOUND_MS:
+            lo, best = frac, rec
+        else:
+            hi = frac
+    return {"p99_bound_ms": P99_BOUND_MS, "requests_per_probe": count, "probes": probes,
+            "rate_per_s": best["rate_per_s"] if best else 0.0, "at_rate": best}
+
+
 def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native"), native_slots=8,
                 table=None):
     """Config 5: Poisson HMULT / rotate requests, N in {2^13..2^16}, levels
@@ -304,7 +339,8 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         return {"throughput_per_s": count / (np.max(t_done) - t_sub[0]),
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
-    out = {"requests": n_req, "max_batch": 16, "max_batch_by_n": {str(k): v for k, v in by_n.items()}}
+    out = {"requests": n_req, "max_batch": 16, "max_batch_by_n": {str(k): v for k, v in by_n.items()},
+           "p99_bound_ms": P99_BOUND_MS}
     for name, fn in (("python", run), ("native", run_native)):
         if name not in engines:
             continue
@@ -318,6 +354,7 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
             res["runs"].append({"load": frac, "rate_per_s": round(rate, 1),
                                 "throughput_per_s": round(st["throughput_per_s"], 1),
                                 "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)})
+        res["sustainable"] = sustainable_rate(fn, sat["throughput_per_s"], n_req)
         out[name] = res
     native.close()
     return out
@@ -565,6 +602,7 @@ def main():
     if serving:
         if "native" in serving:
             line["p99_ms"] = next(r["p99_ms"] for r in serving["native"]["runs"] if r["load"] == 0.5)
+            line["sustainable_requests_per_s"] = serving["native"]["sustainable"]["rate_per_s"]
         line["serving"] = serving
     line["setup"] = setup  # plan and context creation (host tables + upload), outside every timed region
     print(json.dumps(line), flush=True)
