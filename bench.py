@@ -236,7 +236,7 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         e = inputs.gaussian_error(2, (dnum, n), stream=1)
         ctxs[ln], evks[ln] = ctx, sch.relin_key(s, a, e)
         if table is not None:
-            autotune.apply(ctx.plan, table, L, 64)
+            autotune.apply_ckks(ctx, table, L, 64, L)
         for r in rots:
             g = pow(5, r, 2 * n)
             rks[(ln, g)] = sch.rotation_key(s, g, a, e)
@@ -468,7 +468,7 @@ def main():
         t_setup = time.perf_counter()
         ctx = tfhe.CkksContext(LOG_N, HM_L, HM_K, HM_DNUM)
         setup["ckks_context_s"] = round(time.perf_counter() - t_setup, 3)
-        tuning["hmult_ntt"] = autotune.apply(ctx.plan, table, HM_L, HM_BATCH)
+        tuning["hmult_ntt"] = autotune.apply_ckks(ctx, table, HM_L, HM_BATCH, HM_L)
         sch = Scheme(ctx)
         s = inputs.ternary_secret(1, n, 192)
         a = inputs.uniform_residues(1, ctx.moduli, (HM_DNUM, n), stream=1).transpose(1, 0, 2)

@@ -118,12 +118,20 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *                            for the ModDown / RESCALE epilogue, which keep
  *                            two), 2 = two (a transposed intermediate in the
  *                            workspace between two passes)
+ *   TFHE_PARAM_KS_INNER      key switching with a four-step plan (the plan
+ *                            of a CKKS context): 0 = library default (2),
+ *                            1 = the ModUp transforms' second pass fused
+ *                            with the key inner product (Sec. IV-A: NTT,
+ *                            then Inner-product, in one kernel), 2 = a
+ *                            separate inner-product kernel.  Same results;
+ *                            tfhe_hmult_workspace_size depends on it.
  * Not thread-safe against concurrent compute calls on the same plan. */
 typedef enum {
   TFHE_PARAM_FS_WG_PER_CU = 1,
   TFHE_PARAM_AUTO_ALGO = 2,
   TFHE_PARAM_FS_WIDE = 3,
-  TFHE_PARAM_FS_PASSES = 4
+  TFHE_PARAM_FS_PASSES = 4,
+  TFHE_PARAM_KS_INNER = 5
 } tfhe_plan_param;
 tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t value);
 tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t* value);
@@ -416,7 +424,8 @@ tfhe_status tfhe_timing_enable(int enable);
 
 /* Launch count and summed event-measured duration (ms) of the kernel named
  * `kernel` since timing was enabled; waits for the recorded events.  Names:
- * ntt_mfma_pass1, ntt_mfma_pass2, ntt_mfma_onepass, ntt_co_pass1, ntt_co_pass2, ntt_bf_single,
+ * ntt_mfma_pass1, ntt_mfma_pass2, ntt_mfma_onepass, ntt_mfma_pass2_inner, ntt_co_pass1,
+ * ntt_co_pass2, ntt_bf_single,
  * ntt_bf_cols, ntt_bf_rows,
  * elementwise, ckks_tensor, ckks_modup, ckks_inner, ckks_moddown_conv,
  * ckks_moddown_final, frobenius, ckks_rescale_bcast, ckks_rescale_final.

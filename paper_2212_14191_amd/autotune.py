@@ -4,8 +4,10 @@ Sec. IV-E; the best batch differs per kernel, Sec. VI-E).
 
 * NTT: for a (log N, limbs, batch) shape, times forward + inverse for each
   candidate (algorithm x HBM round trips of the four-step transform, one or
-  two x 256-point item width x persistent four-step workgroups per CU) and
-  keeps the fastest.  Every candidate's round trip must be the identity.
+  two x 256-point item width x persistent four-step workgroups per CU),
+  re-times the fastest few against the library default in interleaved
+  rounds and keeps the best (its entry records the default's rate beside
+  its own).  Every candidate's round trip must be the identity.
 * HMULT: sweeps the batch size at a (log N, level) and keeps the smallest
   batch within `slack` of the best throughput (small batches keep latency
   low in the serving loop).
@@ -99,6 +101,17 @@ def apply(plan, table, limbs, batch):
     return e
 
 
+def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
+    """Tuned plan parameters of a CKKS context's transforms and its key
+    switching variant (the inner product fused into the transforms or not).
+    Returns the applied entries."""
+    e = apply(ctx.plan, table, limbs, batch)
+    h = table.get(hmult_key(ctx.log_n, level))
+    if h and "ks_inner" in h:
+        ctx.plan.set_param("ks_inner", int(h["ks_inner"]))
+    return {"ntt": e, "ks_inner": h.get("ks_inner") if h else None}
+
+
 def serving_batches(table, log_ns, level):
     """{log_n: tuned HMULT batch at `level`} for the N the table covers."""
     out = {}
@@ -119,8 +132,40 @@ def ntt_candidates(log_n, mfma):
     return cands
 
 
-def tune_ntt(plan, x, reps=5, warmup=1):
-    """x: int32 [limbs][batch][N] on the device.  Returns (best, all)."""
+def _time_candidate(plan, cand, x, y, z, ws, reps, trials):
+    """Median over `trials` of the forward + inverse time of `reps` rounds
+    (seconds per round), with the candidate's parameters set; checks that
+    the round trip is the identity."""
+    import statistics
+    import torch
+    algo, passes, wide, w = cand
+    plan.set_param("fs_passes", passes)
+    plan.set_param("fs_wide", wide)
+    plan.set_param("fs_wg_per_cu", w)
+    for _ in range(2):
+        plan.fwd(x, out=y, algo=algo, ws=ws)
+        plan.inv(y, out=z, algo=algo, ws=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(trials):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.fwd(x, out=y, algo=algo, ws=ws)
+            plan.inv(y, out=z, algo=algo, ws=ws)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) / reps)
+    if not torch.equal(z, x):
+        raise RuntimeError(f"autotune: {algo}/{passes}/{wide}/{w} failed the round trip")
+    return statistics.median(times)
+
+
+def tune_ntt(plan, x, reps=5, trials=3, finalists=3, rounds=3):
+    """x: int32 [limbs][batch][N] on the device.  Every candidate is timed
+    (median of `trials`); the best `finalists` and the library default are
+    then timed again in `rounds` interleaved rounds (so that clock and
+    thermal drift hit them alike) and the best median wins.  Returns (best,
+    all)."""
+    import statistics
     import torch
     from . import tfhe
     limbs, batch, _ = x.shape
@@ -128,31 +173,25 @@ def tune_ntt(plan, x, reps=5, warmup=1):
     mfma = plan.get_param("auto_algo") == tfhe.FOURSTEP_MFMA or _has_mfma(plan)
     cands = ntt_candidates(plan.log_n, mfma)
     ws = plan.workspace(limbs, batch, "mfma" if mfma else "butterfly")
-    results = []
     old = {name: plan.get_param(name) for name in PLAN_PARAMS}
-    for algo, passes, wide, w in cands:
-        plan.set_param("fs_passes", passes)
-        plan.set_param("fs_wide", wide)
-        plan.set_param("fs_wg_per_cu", w)
-        for _ in range(warmup):
-            plan.fwd(x, out=y, algo=algo, ws=ws)
-            plan.inv(y, out=z, algo=algo, ws=ws)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            plan.fwd(x, out=y, algo=algo, ws=ws)
-            plan.inv(y, out=z, algo=algo, ws=ws)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if not torch.equal(z, x):
-            raise RuntimeError(f"autotune: {algo}/{passes}/{wide}/{w} failed the round trip")
-        cfg = {"algo": algo, "fs_passes": passes, "fs_wide": wide, "fs_wg_per_cu": w}
-        results.append((cfg, 2 * limbs * batch * reps / dt / 1e3))
+    first = [(c, _time_candidate(plan, c, x, y, z, ws, reps, trials)) for c in cands]
+    default = ("mfma", 0, 0, 0) if mfma else ("butterfly", 0, 0, 0)
+    top = [c for c, _ in sorted(first, key=lambda r: r[1])[:finalists]]
+    if default not in top:
+        top.append(default)
+    final = {c: [] for c in top}
+    for _ in range(rounds):
+        for c in top:
+            final[c].append(_time_candidate(plan, c, x, y, z, ws, reps, 1))
     for name, v in old.items():
         plan.set_param(name, v)
-    cfg, kops = pick_best(results)
-    best = dict(cfg, kops=kops)
-    return best, [dict(c, kops=k) for c, k in results]
+    units = 2 * limbs * batch
+    kops = lambda t: units / t / 1e3
+    scored = {c: statistics.median(ts) for c, ts in final.items()}
+    best_c = min(scored, key=scored.get)
+    as_cfg = lambda c: {"algo": c[0], "fs_passes": c[1], "fs_wide": c[2], "fs_wg_per_cu": c[3]}
+    best = dict(as_cfg(best_c), kops=kops(scored[best_c]), default_kops=kops(scored[default]))
+    return best, [dict(as_cfg(c), kops=kops(t)) for c, t in first]
 
 
 def _has_mfma(plan):
@@ -230,8 +269,21 @@ def main(argv=None):
                 c = torch.stack([_random_residues(torch, qs, b, n) for _ in range(2)])
                 return a, c, evk.contiguous()
             b, tput = tune_hmult_batch(ctx, make, level)
-            table.put(hmult_key(ln, level), {"batch": b, "ops_per_s": {str(k): round(v, 1) for k, v in tput.items()}})
-            print("hmult", ln, level, b, flush=True)
+            entry = {"batch": b, "ops_per_s": {str(k): round(v, 1) for k, v in tput.items()}}
+            # key-switching variant at the chosen batch: separate inner
+            # product (2) or fused into the transforms (1), interleaved rounds
+            inner = {}
+            for _ in range(3):
+                for mode in (2, 1):
+                    ctx.plan.set_param("ks_inner", mode)
+                    _, t = tune_hmult_batch(ctx, make, level, batches=(b,))
+                    inner.setdefault(mode, []).append(t[b])
+            ctx.plan.set_param("ks_inner", 0)
+            med = {m: sorted(v)[1] for m, v in inner.items()}
+            entry["ks_inner"] = max(med, key=med.get)
+            entry["ks_inner_ops_per_s"] = {str(m): round(v, 1) for m, v in med.items()}
+            table.put(hmult_key(ln, level), entry)
+            print("hmult", ln, level, b, entry["ks_inner"], flush=True)
         ctx.close()
     table.save(args.out)
     print("wrote", args.out)

@@ -192,6 +192,10 @@ tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, i
       if (value < 0 || value > 2) return fail(TFHE_EINVAL, "fs_passes must be 0, 1 or 2");
       plan->fs_passes = (uint32_t)value;
       return TFHE_OK;
+    case TFHE_PARAM_KS_INNER:
+      if (value < 0 || value > 2) return fail(TFHE_EINVAL, "ks_inner must be 0, 1 or 2");
+      plan->ks_inner = (uint32_t)value;
+      return TFHE_OK;
   }
   return fail(TFHE_EINVAL, "unknown plan parameter");
 }
@@ -203,6 +207,7 @@ tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, i
     case TFHE_PARAM_AUTO_ALGO: *value = plan->algo; return TFHE_OK;
     case TFHE_PARAM_FS_WIDE: *value = plan->fs_wide; return TFHE_OK;
     case TFHE_PARAM_FS_PASSES: *value = plan->fs_passes; return TFHE_OK;
+    case TFHE_PARAM_KS_INNER: *value = plan->ks_inner; return TFHE_OK;
   }
   return fail(TFHE_EINVAL, "unknown plan parameter");
 }

@@ -61,6 +61,14 @@ static hipError_t ntt_units(const tfhe_ntt_plan_s* p, const std::vector<NttUnit>
                                            : bf_run_units(u.data(), (uint32_t)u.size(), ws, s);
 }
 
+// Whether the ModUp transforms' second pass runs fused with the inner
+// product (ip_run): four-step plans that ask for it (TFHE_PARAM_KS_INNER =
+// 1; the separate kernels are the default, measured as fast or faster at
+// N = 2^15, 2^16).
+static bool fused_inner(const tfhe_ckks_ctx_s* c) {
+  return c->plan->algo == TFHE_NTT_FOURSTEP_MFMA && c->plan->ks_inner == 1;
+}
+
 // Workspace regions (byte offsets).
 struct KsLayout {
   size_t d2, x, up, acc, tp, conv, ntt, total;
@@ -85,6 +93,9 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
     const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
     modup += ws(d0) + ws(level - d0 - nd) + ws(c->K);
   }
+  // with the fused second pass + inner product, the ModUp transforms'
+  // intermediates sit in a regular [digits][level + K] array of planes
+  if (fused_inner(c)) modup = std::max(modup, align256(plane * (size_t)digits * ext));
   const size_t ntt_bytes = std::max(std::max(ws(level), modup), std::max(2 * ws(c->K), 2 * ws(level)));
   KsLayout l;
   size_t off = 0;
@@ -182,6 +193,10 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   // the q-limbs before and after the digit, and the p-limbs
   std::vector<NttUnit> fwd;
   ConvQueue cq;  // the matrix-core conversions of all digits, launched together
+  // fused: the transforms' first pass writes digit j's intermediate of
+  // position pos at inter + (j ext + pos) plane; ip_run finishes them
+  const bool fused = fused_inner(c);
+  uint32_t* inter = (uint32_t*)nws;
   for (uint32_t j = 0; j < digits; ++j) {
     const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
     const uint32_t key_idx = d0 + nd - 1;
@@ -192,19 +207,37 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
                                c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
                                c->L, c->K, batch, c->n, s)) != hipSuccess)
       return e;
-    uint32_t* after = upj + (uint64_t)(d0 + nd) * plane;
-    uint32_t* pl = upj + (uint64_t)level * plane;
-    if (d0) fwd.push_back(NttUnit{p, false, upj, upj, 0, d0, batch});
-    if (level > d0 + nd) fwd.push_back(NttUnit{p, false, after, after, d0 + nd, level - d0 - nd, batch});
-    fwd.push_back(NttUnit{p, false, pl, pl, c->L, c->K, batch});
+    uint32_t* outj = fused ? inter + (uint64_t)j * ext * plane : upj;
+    auto unit = [&](uint32_t pos, uint32_t limb_begin, uint32_t count) {
+      NttUnit u{p, false, upj + (uint64_t)pos * plane, outj + (uint64_t)pos * plane, limb_begin, count, batch};
+      u.pass1_only = fused;
+      fwd.push_back(u);
+    };
+    if (d0) unit(0, 0, d0);
+    if (level > d0 + nd) unit(d0 + nd, d0 + nd, level - d0 - nd);
+    unit(level, c->L, c->K);
   }
   if ((e = cq.flush(p->num_cus, K_MODUP, s)) != hipSuccess) return e;
   if ((e = ntt_units(p, fwd, nws, s)) != hipSuccess) return e;
   uint32_t* a0 = acc;
   uint32_t* a1 = acc + (uint64_t)ext * plane;
-  if ((e = launch_inner_product(d, up, keys, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
-                                batch, c->log_n, s)) != hipSuccess)
+  if (fused) {
+    IpArgs ia;
+    ia.inter = inter;
+    ia.d2 = d;
+    ia.acc = acc;
+    ia.batch = batch;
+    ia.level = level;
+    ia.L = c->L;
+    ia.K = c->K;
+    ia.alpha = c->alpha;
+    ia.digits = digits;
+    ia.keys = keys;
+    if ((e = ip_run(p, ia, s)) != hipSuccess) return e;
+  } else if ((e = launch_inner_product(d, up, keys, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
+                                       batch, c->log_n, s)) != hipSuccess) {
     return e;
+  }
   // ModDown of both accumulators, their transforms fused
   uint32_t* tp1 = tp + (uint64_t)c->K * plane;
   uint32_t* conv1 = conv + (uint64_t)level * plane;

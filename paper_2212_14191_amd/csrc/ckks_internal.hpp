@@ -58,6 +58,24 @@ struct KeySet {
   uint32_t count;
   const uint32_t* k[kMaxRotBatch];
 };
+
+// The ModUp forward transforms' second pass fused with the inner product
+// (ntt_fourstep.hip): for every extended-basis position t < level + K and
+// batch element b, acc_c[t][b] = sum_j y_j evk_j[c][t] with y_j the second
+// pass of digit j's tiled intermediate at (j, t, b) (t outside digit j) or
+// d2[t][b] (t in digit j, already in the NTT domain).  Layouts:
+//   inter [digits][level + K][batch][N] (pass-1 output, tiled per polynomial;
+//         slots of a digit's own limbs unused), d2 [level][batch][N],
+//   acc [2][level + K][batch][N], keys as KeySet (limb index t for q-limbs,
+//         L + t - level for the special ones).
+struct IpArgs {
+  const uint32_t* inter;
+  const uint32_t* d2;
+  uint32_t* acc;
+  uint32_t batch, level, L, K, alpha, digits;
+  KeySet keys;
+};
+hipError_t ip_run(const tfhe_ntt_plan_s* p, const IpArgs& a, hipStream_t s);
 hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const KeySet& keys,
                                 uint32_t* acc0, uint32_t* acc1, const ModConst* mods,
                                 uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,

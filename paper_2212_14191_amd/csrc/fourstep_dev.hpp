@@ -57,6 +57,14 @@ __device__ __forceinline__ uint64_t mad_u64(uint32_t a, uint32_t b, uint64_t c) 
   return d;
 }
 
+// a b 2^{-32} mod q as (V + m q) / 2^32, V = a b, m = -V q^{-1} mod 2^32:
+// below 2^32 for any a, b < 2^32, and below 2q for a, b < q (not reduced).
+__device__ __forceinline__ uint32_t mont_mul_lazy(uint32_t a, uint32_t b, uint32_t q, uint32_t qneg) {
+  const uint64_t V = mad_u64(a, b, 0);
+  const uint32_t m = (uint32_t)V * qneg;
+  return (uint32_t)(mad_u64(m, q, V) >> 32);
+}
+
 // Fusion and one Montgomery step: V 2^{-32} mod q, in [0, q + 2^17).
 // (V + m q) is a multiple of 2^32 below 2^64, so its high word is exact
 // (one v_mad_u64_u32).

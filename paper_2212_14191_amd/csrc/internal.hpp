@@ -83,6 +83,7 @@ struct tfhe_plan_impl {
   uint32_t fs_wg_per_cu = 0;      // persistent four-step workgroups per CU (0: occupancy)
   uint32_t fs_wide = 0;           // 256-point stage items: 0 auto, 1 narrow, 2 wide when possible
   uint32_t fs_passes = 0;         // four-step HBM passes: 0 auto, 1 one pass (N = 2^12..2^15), 2 two
+  uint32_t ks_inner = 0;          // key switching: 0 auto, 1 fused second pass + inner product, 2 separate
   std::vector<uint32_t> q, psi;
   // device arrays
   ModConst* d_mod = nullptr;      // [n_limbs]
@@ -117,6 +118,10 @@ struct NttUnit {
   const uint32_t* acc = nullptr;
   const uint2* epi_mult = nullptr;
   bool epi_add = false;
+  // Forward four-step transforms only: run the first pass alone, writing its
+  // tiled intermediate to `out` (the second pass is left to a fused
+  // consumer, ip_run)
+  bool pass1_only = false;
 };
 // Runs every unit with the four-step algorithm (all units need has_mfma) or
 // the butterfly; ws must hold the sum of the units' workspaces.
@@ -160,7 +165,7 @@ struct GaloisSet {
 // ---- per-kernel event timing (timing.cpp)
 enum KernelId {
   K_FS_PASS1 = 0, K_FS_PASS2, K_BF_SINGLE, K_BF_COLS, K_BF_ROWS, K_EW, K_TENSOR, K_MODUP,
-  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL, K_CO_PASS1, K_CO_PASS2, K_OP
+  K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL, K_CO_PASS1, K_CO_PASS2, K_OP, K_IP
 };
 bool timing_on();
 void* timing_begin(int id, hipStream_t s);

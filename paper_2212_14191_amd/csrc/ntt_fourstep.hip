@@ -49,6 +49,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "ckks_internal.hpp"
 #include "fourstep_dev.hpp"
 
 namespace tfhe {
@@ -457,6 +458,175 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 
 
 // ---------------------------------------------------------------------------
+// Second pass of the ModUp forward transforms fused with the key inner
+// product (Sec. IV-A, Table 2: NTT, then Inner-product): a workgroup takes
+// one extended-basis position t, batch element b and column block, runs the
+// second pass (the 256-point stage, narrow 16-vector item) on the tiled
+// intermediate of every digit j that does not hold t and multiplies each
+// result by evk_j[c][t] at its natural positions, adds d2[t] evk_own[c][t]
+// for the digit that holds t, and writes acc_0 and acc_1 once.  The
+// transformed limbs are never written: the separate transform store and the
+// inner product's re-read of them (a read and a write of every converted
+// limb) disappear.  The products are summed as Montgomery residues
+// (x k 2^{-32}) and scaled by 2^32 once at the end; every quantity is exact,
+// so the result equals the unfused sequence bit for bit.  Not pipelined: each
+// workgroup loads a tile, waits, computes; several workgroups per CU overlap.
+__global__ void __launch_bounds__(256, 2)
+ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* __restrict__ mods,
+        uint32_t log_n, uint32_t ipp) {
+  using G = Geo<false, 16, false>;
+  __shared__ __attribute__((aligned(16))) uint32_t tile[G::tile];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  const uint32_t ext = a.level + a.K;
+  const uint64_t N = 1ull << log_n;
+  const uint32_t S = (uint32_t)(N >> 8);  // second-pass columns (rows of the first)
+  const uint32_t total = ext * ipp * a.batch;
+  const FourStepLimb* cur = nullptr;
+  v4i opA[4], opB[4];
+  uint2 tw[4];
+  uint32_t q = 0, qneg = 0, nq = 0;
+  uint64_t cq = 0;
+  ModConst m{};
+  for (uint32_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const uint32_t b = w % a.batch, tb = w / a.batch;
+    const uint32_t blk = tb % ipp, t = tb / ipp;
+    const uint32_t pl = t < a.level ? t : a.L + (t - a.level);  // plan limb
+    const uint32_t c0 = blk * G::W;
+    uint32_t ld_off[4], st_off[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t row = G::Rs * (4 * wave + j) + lane % G::Rs, col = 4 * (lane / G::Rs);
+      st_off[j] = row * S + c0 + col;
+      ld_off[j] = ((c0 + col) >> 4) * (16 * G::P) + 16 * row + (col & 15);
+    }
+    if (limbs + pl != cur) {
+      cur = limbs + pl;
+      const FourStepLimb L = *cur;
+      q = L.q;
+      qneg = L.qneg;
+      nq = 0u - q;
+      cq = (uint32_t)(0x80808080u - q);
+      m = mods[pl];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        opA[j] = *(const v4i*)&L.pass2->opA[j][lane][0];
+        opB[j] = *(const v4i*)&L.pass2->opB[j][lane][0];
+        tw[j] = L.pass2->twist[lane][j];
+      }
+    }
+    const uint32_t* key = a.keys.k[a.keys.count == 1 ? 0 : b];
+    const uint64_t kplane = (uint64_t)(a.L + a.K) * N;  // one key component
+    const uint32_t own = t < a.level ? t / a.alpha : 0xFFFFFFFFu;
+    uint4 s0[4], s1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s0[j] = s1[j] = make_uint4(0, 0, 0, 0);
+    // y k 2^{-32} in [0, q), added into s
+    auto mac = [&](uint4& acc, const uint4& y, const uint4& k) {
+      acc.x = add_mod(acc.x, reduce_once(mont_mul_lazy(y.x, k.x, q, qneg), q), q);
+      acc.y = add_mod(acc.y, reduce_once(mont_mul_lazy(y.y, k.y, q, qneg), q), q);
+      acc.z = add_mod(acc.z, reduce_once(mont_mul_lazy(y.z, k.z, q, qneg), q), q);
+      acc.w = add_mod(acc.w, reduce_once(mont_mul_lazy(y.w, k.w, q, qneg), q), q);
+    };
+    for (uint32_t jd = 0; jd < a.digits; ++jd) {
+      if (jd == own) continue;
+      const uint32_t* src = a.inter + ((uint64_t)(jd * ext + t) * a.batch + b) * N;
+      issue_tile<G::pitch>(src, ld_off, tile, wave);
+      const uint32_t* k0p = key + (uint64_t)jd * 2 * kplane + (uint64_t)pl * N;
+      uint4 k0[4], k1[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        k0[j] = *(const uint4*)(k0p + st_off[j]);
+        k1[j] = *(const uint4*)(k0p + kplane + st_off[j]);
+      }
+      wait_vmcnt<0>();
+      lds_barrier();  // the tile has landed in every wave
+      uint4 rows[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int row = 16 * (4 * g + c) + i16;
+        rows[c] = *(const uint4*)(tile + (row / G::Rs) * G::pitch + (wave * G::Rs + row % G::Rs) * 4);
+      }
+      uint4 res[4];
+      auto body = [&](auto big_q) {
+        constexpr bool kBigQ = decltype(big_q)::value;
+        const v4i bias = {(int)q, (int)q, (int)q, (int)q};
+        const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) {
+          v4i x;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            x[c] = (int)(sg == 0 ? rows[c].x : sg == 1 ? rows[c].y : sg == 2 ? rows[c].z : rows[c].w);
+          const v4i a0 = mfma(x, opA[0], bias);
+          const v4i a1 = mfma(x, opA[1], zero);
+          const v4i a2 = mfma(x, opA[2], bias);
+          const v4i a3 = mfma(x, opA[3], zero);
+          v4i z;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            z[j] = (int)twist_digits<kBigQ>(fuse_redc(a0[j], a1[j], a2[j], a3[j], q, qneg), tw[j], q, nq, cq);
+          const v4i b0 = mfma(opB[0], z, bias);
+          const v4i b1 = mfma(opB[1], z, zero);
+          const v4i b2 = mfma(opB[2], z, bias);
+          const v4i b3 = mfma(opB[3], z, zero);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const uint32_t r = reduce_once(fuse_redc(b0[j], b1[j], b2[j], b3[j], q, qneg), q);
+            if (sg == 0) res[j].x = r;
+            else if (sg == 1) res[j].y = r;
+            else if (sg == 2) res[j].z = r;
+            else res[j].w = r;
+          }
+        }
+      };
+      if (q > 0x7F7F7F7Fu) body(std::true_type{});
+      else body(std::false_type{});
+      lds_barrier();  // every wave has read the tile
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = i16 + 16 * (4 * g + j);
+        *(uint4*)(tile + (row / G::Rs) * G::pitch + (wave * G::Rs + row % G::Rs) * 4) = res[j];
+      }
+      lds_barrier();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint4 y = *(const uint4*)(tile + (4 * wave + j) * G::pitch + lane * 4);
+        mac(s0[j], y, k0[j]);
+        mac(s1[j], y, k1[j]);
+      }
+      lds_barrier();  // before the next digit's tile overwrites the buffer
+    }
+    if (own != 0xFFFFFFFFu) {
+      const uint32_t* vp = a.d2 + ((uint64_t)t * a.batch + b) * N;
+      const uint32_t* k0p = key + (uint64_t)own * 2 * kplane + (uint64_t)pl * N;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint4 v = *(const uint4*)(vp + st_off[j]);
+        mac(s0[j], v, *(const uint4*)(k0p + st_off[j]));
+        mac(s1[j], v, *(const uint4*)(k0p + kplane + st_off[j]));
+      }
+    }
+    uint32_t* o0 = a.acc + ((uint64_t)t * a.batch + b) * N;
+    uint32_t* o1 = a.acc + ((uint64_t)(ext + t) * a.batch + b) * N;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint4 r0, r1;  // times 2^32: back from the Montgomery scale
+      r0.x = mul_shoup(s0[j].x, m.r, m.rp, q);
+      r0.y = mul_shoup(s0[j].y, m.r, m.rp, q);
+      r0.z = mul_shoup(s0[j].z, m.r, m.rp, q);
+      r0.w = mul_shoup(s0[j].w, m.r, m.rp, q);
+      r1.x = mul_shoup(s1[j].x, m.r, m.rp, q);
+      r1.y = mul_shoup(s1[j].y, m.r, m.rp, q);
+      r1.z = mul_shoup(s1[j].z, m.r, m.rp, q);
+      r1.w = mul_shoup(s1[j].w, m.r, m.rp, q);
+      __builtin_nontemporal_store(*(const v4u*)&r0, (v4u*)(o0 + st_off[j]));
+      __builtin_nontemporal_store(*(const v4u*)&r1, (v4u*)(o1 + st_off[j]));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Vector-ALU GEMM variant ("CO", Sec. IV-B: the NTT as matrix products on
 // the general-purpose cores, one modular reduction per output), N = 2^16.
 // Same passes, tables, work items and data movement as the matrix-core
@@ -652,6 +822,10 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
   {
     unsigned char* w = (unsigned char*)ws;
     for (uint32_t k = 0; k < count; ++k) {
+      if (units[k].pass1_only) {  // the caller's intermediate
+        mids[k] = units[k].out;
+        continue;
+      }
       mids[k] = (uint32_t*)w;
       w += (unit_ws_bytes(units[k], true) + 255) & ~(size_t)255;
     }
@@ -662,7 +836,8 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     const uint32_t log_n = units[lead].plan->log_n;
     const bool inverse = units[lead].inverse;
     const bool epi = units[lead].acc != nullptr;
-    if (epi && inverse) return hipErrorInvalidValue;
+    const bool p1only = units[lead].pass1_only;
+    if ((epi || p1only) && inverse) return hipErrorInvalidValue;
     const tfhe_ntt_plan_s* p0 = units[lead].plan;
     const uint32_t N = 1u << log_n, N1 = N >> 8, r = N1 / 16;
     FsTable t1, t2;
@@ -671,7 +846,7 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     t2.cols = inverse ? 256 : N1;
     const uint32_t r1 = inverse ? 16 : r, r2 = inverse ? r : 16;
     // one HBM round trip where the one-pass kernel covers the shape
-    const bool one = !epi && use_onepass(p0);
+    const bool one = !epi && !p1only && use_onepass(p0);
     auto flush = [&]() {
       if (t1.total == 0) return;
       if (one) {
@@ -679,6 +854,7 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
         return;
       }
       launch_pass_r<true>(p0, r1, t1, s);
+      if (p1only) return;
       if (!epi) launch_pass_r<false>(p0, r2, t2, s);
       else if (use_wide(p0, t2.cols)) launch_pass<false, 16, true, true>(p0, t2, s);
       else launch_pass<false, 16, false, true>(p0, t2, s);
@@ -687,7 +863,9 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     t1.total = t2.total = 0;
     for (uint32_t k = lead; k < count; ++k) {
       const NttUnit& u = units[k];
-      if (done[k] || u.plan->log_n != log_n || u.inverse != inverse || (u.acc != nullptr) != epi) continue;
+      if (done[k] || u.plan->log_n != log_n || u.inverse != inverse || (u.acc != nullptr) != epi ||
+          u.pass1_only != p1only)
+        continue;
       done[k] = true;
       const uint32_t polys = u.limb_count * u.batch;
       if (polys == 0) continue;
@@ -704,6 +882,22 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     }
     flush();
   }
+  return hipGetLastError();
+}
+
+hipError_t ip_run(const tfhe_ntt_plan_s* p, const IpArgs& a, hipStream_t s) {
+  if (!p->has_mfma || a.batch == 0) return a.batch == 0 ? hipSuccess : hipErrorInvalidValue;
+  using G = Geo<false, 16, false>;
+  const uint32_t ipp = p->n / G::item;  // second-pass items per polynomial
+  static int occ = 0;
+  if (occ == 0) {
+    int k = 0;
+    occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, ip_pass, G::threads, 0) == hipSuccess && k > 0 ? k : 1;
+  }
+  const uint64_t work = (uint64_t)(a.level + a.K) * ipp * a.batch;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(work, (uint64_t)p->num_cus * occ);
+  TFHE_TIMED(K_IP, s,
+             hipLaunchKernelGGL(ip_pass, dim3(grid), dim3(G::threads), 0, s, a, p->d_fs_fwd, p->d_mod, p->log_n, ipp));
   return hipGetLastError();
 }
 

@@ -67,14 +67,6 @@ __device__ __forceinline__ uint32_t sw_out(uint32_t w) {
   return (c << 8) | ((Q ^ X) << 2) | (w & 3u);
 }
 
-// (V + m q) / 2^32 with m = -V q^{-1} mod 2^32, V = a b: a b 2^{-32} mod q,
-// below 2^32 for a, b < 2^32 (not reduced).
-__device__ __forceinline__ uint32_t mont_lazy(uint32_t a, uint32_t b, uint32_t q, uint32_t qneg) {
-  const uint64_t V = mad_u64(a, b, 0);
-  const uint32_t m = (uint32_t)V * qneg;
-  return (uint32_t)(mad_u64(m, q, V) >> 32);
-}
-
 // The value, opaque to the optimiser: address arithmetic derived from it is
 // recomputed where it is used instead of being hoisted out of the
 // polynomial loop, where dozens of precomputed LDS addresses would occupy
@@ -221,7 +213,7 @@ op_kernel(const FsTable tab) {
         const int ai = opaque(i16), ag = opaque(g);  // for addresses
         if (st > 0) {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) pa[j] = mont_lazy(pa[j], pad[j], q, qneg);
+          for (int j = 0; j < 4; ++j) pa[j] = mont_mul_lazy(pa[j], pad[j], q, qneg);
         }
         uint4 rows[4];
 #pragma unroll
@@ -270,7 +262,7 @@ op_kernel(const FsTable tab) {
           }
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            o[j][sg] = twist_digits<kBigQ>(mont_lazy(y[j], pa[j], q, qneg), pb[j][sg], q, nq, cq);
+            o[j][sg] = twist_digits<kBigQ>(mont_mul_lazy(y[j], pa[j], q, qneg), pb[j][sg], q, nq, cq);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {

@@ -34,7 +34,8 @@ const char* kNames[] = {"ntt_mfma_pass1", "ntt_mfma_pass2", "ntt_bf_single", "nt
                         "ntt_bf_rows",    "elementwise",    "ckks_tensor",   "ckks_modup",
                         "ckks_inner",     "ckks_moddown_conv", "ckks_moddown_final", "frobenius",
                         "ckks_rescale_bcast", "ckks_rescale_final",
-                        "ntt_co_pass1",       "ntt_co_pass2",       "ntt_mfma_onepass"};
+                        "ntt_co_pass1",       "ntt_co_pass2",       "ntt_mfma_onepass",
+                        "ntt_mfma_pass2_inner"};
 constexpr int kNumNames = sizeof(kNames) / sizeof(kNames[0]);
 }  // namespace
 

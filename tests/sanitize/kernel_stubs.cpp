@@ -61,5 +61,6 @@ hipError_t launch_frobenius_pair_ptrs(const CtPtrs&, uint32_t*, uint32_t*, const
 hipError_t launch_rescale_bcast(const uint32_t*, uint32_t*, const ModConst*, uint32_t, uint32_t, uint32_t,
                                 hipStream_t) TFHE_STUB()
 hipError_t ConvQueue::flush(uint32_t, KernelId, hipStream_t) TFHE_STUB()
+hipError_t ip_run(const tfhe_ntt_plan_s*, const IpArgs&, hipStream_t) TFHE_STUB()
 
 }  // namespace tfhe

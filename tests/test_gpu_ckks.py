@@ -343,3 +343,30 @@ def test_rotate_multi_at_the_batch_limit(tf):
         assert np.array_equal(got[:, :, b:b + 1], alone), b
     want = ckks.rotate(pr, np.ascontiguousarray(ct[:, :, 41:42]), rks[gal[41]], gal[41], level)
     assert np.array_equal(got[:, :, 41:42], want)
+
+
+@pytest.mark.parametrize("log_n,L,K,dnum,level,B", [
+    (12, 8, 4, 2, 8, 3), (13, 24, 8, 3, 17, 2), (14, 12, 2, 6, 11, 2), (16, 24, 8, 3, 24, 3), (12, 8, 1, 1, 8, 2)])
+def test_fused_inner_product_equals_separate(tf, log_n, L, K, dnum, level, B):
+    """Key switching with the ModUp transforms' second pass fused with the
+    inner product (the default) and with the separate kernels: HMULT and a
+    mixed-amount HROTATE batch give the same bits, and the fused HMULT equals
+    the oracle (including K < alpha, where digits outnumber special primes)."""
+    n = 1 << log_n
+    pr, s, evk, (a, e) = setup(n, L, K, dnum)
+    ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
+    m1 = inputs.small_messages(log_n, (B, n))
+    m2 = inputs.small_messages(log_n, (B, n), stream=2)
+    ca, cb = encrypt(pr, s, m1, level, 21), encrypt(pr, s, m2, level, 22)
+    A, Bt, E = to_dev(ca), to_dev(cb), to_dev(evk)
+    gal = [ckks.galois_element(1 + b, n) for b in range(B)]
+    rks = [to_dev(ckks.rotation_key(pr, s, k, a, e)) for k in gal]
+    got = {}
+    for mode in (1, 2):
+        ctx.plan.set_param("ks_inner", mode)
+        got[mode] = (ctx.hmult(A, Bt, E, level).clone(), ctx.rotate_multi(A, rks, gal, level).clone())
+    assert torch.equal(got[1][0], got[2][0])
+    assert torch.equal(got[1][1], got[2][1])
+    b0 = 0 if log_n < 16 else B - 1
+    want = ckks.hmult(pr, ca[:, :, b0:b0 + 1], cb[:, :, b0:b0 + 1], evk, level)
+    assert np.array_equal(to_host(got[1][0])[:, :, b0:b0 + 1], want)
