@@ -248,7 +248,7 @@ fs_pass(const FsTable tab) {
           for (int j = 0; j < 4; ++j) pt[sg][j] = pp[j];
         }
       }
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      wait_vmcnt<0>();
       cur_limb = limb;
     }
     const bool has_next = p + walk.step < walk.p_end;
@@ -460,92 +460,147 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 // ---------------------------------------------------------------------------
 // Second pass of the ModUp forward transforms fused with the key inner
 // product (Sec. IV-A, Table 2: NTT, then Inner-product): a workgroup takes
-// one extended-basis position t, batch element b and column block, runs the
-// second pass (the 256-point stage, narrow 16-vector item) on the tiled
-// intermediate of every digit j that does not hold t and multiplies each
-// result by evk_j[c][t] at its natural positions, adds d2[t] evk_own[c][t]
-// for the digit that holds t, and writes acc_0 and acc_1 once.  The
-// transformed limbs are never written: the separate transform store and the
-// inner product's re-read of them (a read and a write of every converted
-// limb) disappear.  The products are summed as Montgomery residues
+// one extended-basis position t, batch element b and column block (an
+// "item"), and for every digit j (a "task") either runs the second pass
+// (the 256-point stage, narrow 16-vector item) on digit j's tiled
+// intermediate of t, or, for the digit that holds t, takes d2[t] as it is;
+// it multiplies the result by evk_j[c][t] at its natural positions and, after
+// the last digit, writes acc_0 and acc_1 once.  The transformed limbs are
+// never written: the separate transform store and the inner product's re-read
+// of them disappear.  Products are summed as Montgomery residues
 // (x k 2^{-32}) and scaled by 2^32 once at the end; every quantity is exact,
-// so the result equals the unfused sequence bit for bit.  Not pipelined: each
-// workgroup loads a tile, waits, computes; several workgroups per CU overlap.
+// so the result equals the unfused sequence bit for bit.
+// Pipelining: the task's source (tile or d2) and its two key blocks arrive
+// by direct-to-LDS loads; the next task's source is issued into the other
+// buffer as soon as this task's has landed, so one load is always in flight
+// behind the arithmetic.  Keys and d2 are loaded into each wave's own slots
+// of the output layout (slot (4 wave + j, lane) = natural positions st_off).
 __global__ void __launch_bounds__(256, 2)
 ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* __restrict__ mods,
         uint32_t log_n, uint32_t ipp) {
   using G = Geo<false, 16, false>;
-  __shared__ __attribute__((aligned(16))) uint32_t tile[G::tile];
+  // two source buffers, then the key blocks of components 0 and 1
+  __shared__ __attribute__((aligned(16))) uint32_t lds[4 * G::tile];
+  uint32_t* const kbuf = lds + 2 * G::tile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g = lane >> 4;
   const uint32_t ext = a.level + a.K;
   const uint64_t N = 1ull << log_n;
   const uint32_t S = (uint32_t)(N >> 8);  // second-pass columns (rows of the first)
-  const uint32_t total = ext * ipp * a.batch;
+  const uint32_t items = ext * ipp * a.batch;
+  const uint64_t kplane = (uint64_t)(a.L + a.K) * N;  // one key component
+  // per-lane offsets within a polynomial for column block blk
+  auto offsets = [&](uint32_t blk, uint32_t* ld, uint32_t* st) {
+    const uint32_t c0 = blk * G::W;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t row = G::Rs * (4 * wave + j) + lane % G::Rs, col = 4 * (lane / G::Rs);
+      st[j] = row * S + c0 + col;
+      ld[j] = ((c0 + col) >> 4) * (16 * G::P) + 16 * row + (col & 15);
+    }
+  };
+  struct Pos {
+    uint32_t b, blk, t, pl, own;
+  };
+  auto pos_of = [&](uint32_t w) {
+    Pos p;
+    p.b = w % a.batch;
+    const uint32_t tb = w / a.batch;
+    p.blk = tb % ipp;
+    p.t = tb / ipp;
+    p.pl = p.t < a.level ? p.t : a.L + (p.t - a.level);  // plan limb
+    p.own = p.t < a.level ? p.t / a.alpha : 0xFFFFFFFFu;
+    return p;
+  };
+  // 16 bytes per lane into this wave's slot (4 wave + j) of `dst` (output layout)
+  auto load_slots = [&](const uint32_t* src, const uint32_t* st, uint32_t* dst) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t lds_addr = (uint32_t)(uintptr_t)(lds_void_t*)(dst + (4 * wave + j) * G::pitch);
+      asm volatile(
+          "s_mov_b32 m0, %0\n\t"
+          "global_load_lds_dwordx4 %1, off"
+          :
+          : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(src + st[j])
+          : "memory", "m0");
+    }
+  };
+  // the source of task (item w, digit jd) into buffer buf: 4 loads per lane
+  auto issue_source = [&](uint32_t w, uint32_t jd, int buf) {
+    const Pos p = pos_of(w);
+    uint32_t ld[4], st[4];
+    offsets(p.blk, ld, st);
+    if (jd == p.own)
+      load_slots(a.d2 + ((uint64_t)p.t * a.batch + p.b) * N, st, lds + buf * G::tile);
+    else
+      issue_tile<G::pitch>(a.inter + ((uint64_t)(jd * ext + p.t) * a.batch + p.b) * N, ld, lds + buf * G::tile,
+                           wave);
+  };
+
+  const uint32_t tasks_per_item = a.digits;
+  const uint32_t my_items = blockIdx.x < items ? (items - 1 - blockIdx.x) / gridDim.x + 1 : 0;
+  const uint32_t ntasks = my_items * tasks_per_item;
+  if (ntasks == 0) return;
+  auto task_item = [&](uint32_t k) { return blockIdx.x + (k / tasks_per_item) * gridDim.x; };
+
   const FourStepLimb* cur = nullptr;
   v4i opA[4], opB[4];
   uint2 tw[4];
   uint32_t q = 0, qneg = 0, nq = 0;
   uint64_t cq = 0;
   ModConst m{};
-  for (uint32_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const uint32_t b = w % a.batch, tb = w / a.batch;
-    const uint32_t blk = tb % ipp, t = tb / ipp;
-    const uint32_t pl = t < a.level ? t : a.L + (t - a.level);  // plan limb
-    const uint32_t c0 = blk * G::W;
-    uint32_t ld_off[4], st_off[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t row = G::Rs * (4 * wave + j) + lane % G::Rs, col = 4 * (lane / G::Rs);
-      st_off[j] = row * S + c0 + col;
-      ld_off[j] = ((c0 + col) >> 4) * (16 * G::P) + 16 * row + (col & 15);
-    }
-    if (limbs + pl != cur) {
-      cur = limbs + pl;
+  uint64_t s0[4][4], s1[4][4];  // sums of products, kept below q 2^32
+  issue_source(task_item(0), 0, 0);
+  bool stored_after = false;  // the previous task ended its item (8 stores after this source)
+  for (uint32_t k = 0; k < ntasks; ++k) {
+    const int cb = k & 1;
+    uint32_t* const src = lds + cb * G::tile;
+    const uint32_t w = task_item(k), jd = k % tasks_per_item;
+    const Pos p = pos_of(w);
+    uint32_t ld[4], st[4];
+    offsets(p.blk, ld, st);
+    // this task's source: issued before the previous task's stores (if any)
+    if (stored_after) wait_vmcnt<8>();
+    else wait_vmcnt<0>();
+    if (jd == 0 && limbs + p.pl != cur) {
+      // rare: completed here, so that the pipeline carries no wait on these
+      cur = limbs + p.pl;
       const FourStepLimb L = *cur;
       q = L.q;
       qneg = L.qneg;
       nq = 0u - q;
       cq = (uint32_t)(0x80808080u - q);
-      m = mods[pl];
+      m = mods[p.pl];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         opA[j] = *(const v4i*)&L.pass2->opA[j][lane][0];
         opB[j] = *(const v4i*)&L.pass2->opB[j][lane][0];
         tw[j] = L.pass2->twist[lane][j];
       }
+      // the builtin (unlike an asm wait) tells the compiler these registers
+      // are ready, so it adds no vmcnt(0) at their first use downstream
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     }
-    const uint32_t* key = a.keys.k[a.keys.count == 1 ? 0 : b];
-    const uint64_t kplane = (uint64_t)(a.L + a.K) * N;  // one key component
-    const uint32_t own = t < a.level ? t / a.alpha : 0xFFFFFFFFu;
-    uint4 s0[4], s1[4];
+    lds_barrier();  // the source is in LDS; every wave is done with the other buffer and the keys
+    // this task's keys, then the next task's source
+    const uint32_t* key = a.keys.k[a.keys.count == 1 ? 0 : p.b];
+    const uint32_t* krow = key + (uint64_t)jd * 2 * kplane + (uint64_t)p.pl * N;
+    load_slots(krow, st, kbuf);
+    load_slots(krow + kplane, st, kbuf + G::tile);
+    const bool next = k + 1 < ntasks;
+    if (next) issue_source(task_item(k + 1), (k + 1) % tasks_per_item, cb ^ 1);
+    if (jd == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s0[j] = s1[j] = make_uint4(0, 0, 0, 0);
-    // y k 2^{-32} in [0, q), added into s
-    auto mac = [&](uint4& acc, const uint4& y, const uint4& k) {
-      acc.x = add_mod(acc.x, reduce_once(mont_mul_lazy(y.x, k.x, q, qneg), q), q);
-      acc.y = add_mod(acc.y, reduce_once(mont_mul_lazy(y.y, k.y, q, qneg), q), q);
-      acc.z = add_mod(acc.z, reduce_once(mont_mul_lazy(y.z, k.z, q, qneg), q), q);
-      acc.w = add_mod(acc.w, reduce_once(mont_mul_lazy(y.w, k.w, q, qneg), q), q);
-    };
-    for (uint32_t jd = 0; jd < a.digits; ++jd) {
-      if (jd == own) continue;
-      const uint32_t* src = a.inter + ((uint64_t)(jd * ext + t) * a.batch + b) * N;
-      issue_tile<G::pitch>(src, ld_off, tile, wave);
-      const uint32_t* k0p = key + (uint64_t)jd * 2 * kplane + (uint64_t)pl * N;
-      uint4 k0[4], k1[4];
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        k0[j] = *(const uint4*)(k0p + st_off[j]);
-        k1[j] = *(const uint4*)(k0p + kplane + st_off[j]);
-      }
-      wait_vmcnt<0>();
-      lds_barrier();  // the tile has landed in every wave
+        for (int e = 0; e < 4; ++e) s0[j][e] = s1[j][e] = 0;
+    }
+    if (jd != p.own) {
       uint4 rows[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int row = 16 * (4 * g + c) + i16;
-        rows[c] = *(const uint4*)(tile + (row / G::Rs) * G::pitch + (wave * G::Rs + row % G::Rs) * 4);
+        rows[c] = *(const uint4*)(src + (row / G::Rs) * G::pitch + (wave * G::Rs + row % G::Rs) * 4);
       }
       uint4 res[4];
       auto body = [&](auto big_q) {
@@ -582,46 +637,54 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
       };
       if (q > 0x7F7F7F7Fu) body(std::true_type{});
       else body(std::false_type{});
-      lds_barrier();  // every wave has read the tile
+      lds_barrier();  // every wave has read the source
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int row = i16 + 16 * (4 * g + j);
-        *(uint4*)(tile + (row / G::Rs) * G::pitch + (wave * G::Rs + row % G::Rs) * 4) = res[j];
-      }
-      lds_barrier();
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint4 y = *(const uint4*)(tile + (4 * wave + j) * G::pitch + lane * 4);
-        mac(s0[j], y, k0[j]);
-        mac(s1[j], y, k1[j]);
-      }
-      lds_barrier();  // before the next digit's tile overwrites the buffer
-    }
-    if (own != 0xFFFFFFFFu) {
-      const uint32_t* vp = a.d2 + ((uint64_t)t * a.batch + b) * N;
-      const uint32_t* k0p = key + (uint64_t)own * 2 * kplane + (uint64_t)pl * N;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint4 v = *(const uint4*)(vp + st_off[j]);
-        mac(s0[j], v, *(const uint4*)(k0p + st_off[j]));
-        mac(s1[j], v, *(const uint4*)(k0p + kplane + st_off[j]));
+        *(uint4*)(src + (row / G::Rs) * G::pitch + (wave * G::Rs + row % G::Rs) * 4) = res[j];
       }
     }
-    uint32_t* o0 = a.acc + ((uint64_t)t * a.batch + b) * N;
-    uint32_t* o1 = a.acc + ((uint64_t)(ext + t) * a.batch + b) * N;
+    // the keys (issued before the next source) have landed; the results in
+    // the output layout are complete in every wave
+    if (next) wait_vmcnt<4>();
+    else wait_vmcnt<0>();
+    lds_barrier();
+    // s += y k as one 64-bit multiply-add; with y, k < q < 2^31 the sum
+    // stays below q 2^32 + q^2 < 2^64, and taking q off its high word when
+    // that reaches q keeps s below q 2^32.  Whole-vector 16-byte reads:
+    // through uint4 the compiler splits the key reads into dword pairs,
+    // which conflict four ways across the wave.
+    auto mac = [&](uint64_t* acc, const v4u& y, const v4u& kk) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint64_t v = mad_u64(y[e], kk[e], acc[e]);
+        const uint32_t hi = (uint32_t)(v >> 32);
+        acc[e] = ((uint64_t)min(hi, hi - q) << 32) | (uint32_t)v;
+      }
+    };
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      uint4 r0, r1;  // times 2^32: back from the Montgomery scale
-      r0.x = mul_shoup(s0[j].x, m.r, m.rp, q);
-      r0.y = mul_shoup(s0[j].y, m.r, m.rp, q);
-      r0.z = mul_shoup(s0[j].z, m.r, m.rp, q);
-      r0.w = mul_shoup(s0[j].w, m.r, m.rp, q);
-      r1.x = mul_shoup(s1[j].x, m.r, m.rp, q);
-      r1.y = mul_shoup(s1[j].y, m.r, m.rp, q);
-      r1.z = mul_shoup(s1[j].z, m.r, m.rp, q);
-      r1.w = mul_shoup(s1[j].w, m.r, m.rp, q);
-      __builtin_nontemporal_store(*(const v4u*)&r0, (v4u*)(o0 + st_off[j]));
-      __builtin_nontemporal_store(*(const v4u*)&r1, (v4u*)(o1 + st_off[j]));
+      const int slot = (4 * wave + j) * G::pitch + lane * 4;
+      const v4u y = *(const v4u*)(src + slot);
+      mac(s0[j], y, *(const v4u*)(kbuf + slot));
+      mac(s1[j], y, *(const v4u*)(kbuf + G::tile + slot));
+    }
+    stored_after = jd + 1 == tasks_per_item;
+    if (stored_after) {
+      // s mod q: one Montgomery step (s + m q < 2q 2^32), then times 2^32
+      auto fin = [&](uint64_t v) {
+        const uint32_t mm = (uint32_t)v * qneg;
+        return mul_shoup(reduce_once((uint32_t)(mad_u64(mm, q, v) >> 32), q), m.r, m.rp, q);
+      };
+      uint32_t* o0 = a.acc + ((uint64_t)p.t * a.batch + p.b) * N;
+      uint32_t* o1 = a.acc + ((uint64_t)(ext + p.t) * a.batch + p.b) * N;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const v4u r0 = {fin(s0[j][0]), fin(s0[j][1]), fin(s0[j][2]), fin(s0[j][3])};
+        const v4u r1 = {fin(s1[j][0]), fin(s1[j][1]), fin(s1[j][2]), fin(s1[j][3])};
+        __builtin_nontemporal_store(r0, (v4u*)(o0 + st[j]));
+        __builtin_nontemporal_store(r1, (v4u*)(o1 + st[j]));
+      }
     }
   }
 }
@@ -714,7 +777,7 @@ co_pass(const FsTable tab) {
 #pragma unroll
         for (int t = 0; t < 16; ++t) post[t] = L.co_post[(c0 + col) * 256 + lo16 + 16 * t];
       }
-      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      wait_vmcnt<0>();
       cur_limb = limb;
     }
     // this item's loads were followed only by the previous item's stores
