@@ -268,6 +268,39 @@ tfhe_status tfhe_hmult_noalloc(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const ui
                                uint32_t* ct_out, const uint32_t* evk, uint32_t level,
                                uint32_t batch, tfhe_stream_t stream);
 
+/* HMULT of ciphertext pairs of different levels in one batched launch
+ * sequence (operation-level batching across levels, Sec. IV-D): pair i is
+ * multiplied at levels[i] exactly as tfhe_hmult would do for it alone (same
+ * result, bit for bit).  The pairs are grouped by level; each group's tensor
+ * product and key inner product are launched per group, and every NTT/INTT
+ * and basis conversion of all groups shares one launch per key-switching
+ * step (the transforms run over a descriptor table of the groups' limbs).
+ *   ct_a, ct_b, ct_out: host arrays [count] of device pointers, each a
+ *     single ciphertext [2][levels[i]][N], NTT domain, 16-byte aligned.  An
+ *     output may alias any input (results are written after every input has
+ *     been read); outputs must not overlap one another.
+ *   levels: host [count], each in [1, L]; count <= TFHE_HMULT_LEVELS_MAX.
+ *   evk: as for tfhe_hmult; ws: >= tfhe_hmult_levels_workspace_size bytes
+ *     for the same levels, 256-aligned.
+ * The host arrays are read during the call only. */
+#define TFHE_HMULT_LEVELS_MAX 64
+tfhe_status tfhe_hmult_levels_workspace_size(tfhe_ckks_ctx ctx, const uint32_t* levels, uint32_t count,
+                                             size_t* bytes);
+tfhe_status tfhe_hmult_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_a, const uint32_t* const* ct_b,
+                              uint32_t* const* ct_out, const uint32_t* levels, uint32_t count,
+                              const uint32_t* evk, void* ws, size_t ws_bytes, tfhe_stream_t stream);
+
+/* HROTATE of ciphertexts of different levels and rotation amounts in one
+ * batched launch sequence (as tfhe_hmult_levels): ciphertext i, ct_in[i]
+ * [2][levels[i]][N], is rotated by galois_elts[i] (odd, < 2N) with
+ * rotkeys[i] (layout as for tfhe_rotate; entries may repeat) into
+ * ct_out[i], exactly as tfhe_rotate would do for it alone.  Pointer rules,
+ * count and workspace (tfhe_hmult_levels_workspace_size of the same levels)
+ * as for tfhe_hmult_levels. */
+tfhe_status tfhe_rotate_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_in, uint32_t* const* ct_out,
+                               const uint32_t* const* rotkeys, const uint32_t* galois_elts, const uint32_t* levels,
+                               uint32_t count, void* ws, size_t ws_bytes, tfhe_stream_t stream);
+
 /* HROTATE (Sec. II-B): ct_out = (sigma(c0), 0) + KeySwitch_rk(sigma(c1)),
  * sigma the automorphism X -> X^galois_elt applied in the NTT domain as the
  * FrobeniusMap permutation of Sec. IV-A: out_j = in_{pi(j)},
@@ -332,15 +365,17 @@ tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t*
 /* Request dispatcher (the API layer of Sec. IV-E with operation-level
  * batching, Sec. IV-D): callers submit single-ciphertext HMULT and HROTATE
  * requests; `slots` worker threads, each with its own stream, group
- * requests of equal (operation, N, level) into batches of up to max_batch,
- * run each batch with one batched tfhe_hmult / tfhe_rotate /
- * tfhe_rotate_multi call, and report each request's completion through
+ * requests of equal (operation, N) into batches of up to max_batch, whatever
+ * their levels, run each batch as one mixed-level launch sequence (as
+ * tfhe_hmult_levels does; a batch of one with tfhe_hmult / tfhe_rotate on
+ * the request's own buffers), and report each request's completion through
  * tfhe_server_poll.
- * The result of a request is exactly what that call computes for it alone.
+ * The result of a request is exactly what tfhe_hmult / tfhe_rotate computes
+ * for it alone.
  *
  * tfhe_server_create: pool is caller-owned device memory, 256-byte aligned,
  * pool_bytes >= 256*slots, split evenly among the slots; it holds each
- * batch's gathered inputs, outputs and workspace and must outlive the
+ * batch's workspace (with its staged results) and must outlive the
  * server.  The server belongs to the device current at creation.
  *   slots in [1, 16]; max_batch in [1, TFHE_ROTATE_MULTI_MAX].
  * Errors: TFHE_EINVAL, TFHE_ENOMEM (host), TFHE_EHIP. */

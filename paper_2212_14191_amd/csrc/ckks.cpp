@@ -8,6 +8,7 @@
 // accumulates over the digits, and ModDown divides by P (no rounding offset).
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <set>
@@ -69,20 +70,25 @@ static bool fused_inner(const tfhe_ckks_ctx_s* c) {
   return c->plan->algo == TFHE_NTT_FOURSTEP_MFMA && c->plan->ks_inner == 1;
 }
 
-// Workspace regions (byte offsets).
+// Workspace of one key-switching batch: its own regions (byte offsets from
+// the batch's base) and the workspace of its four fused transforms.
 struct KsLayout {
-  size_t d2, x, up, acc, tp, conv, ntt, total;
+  size_t d2, x, up, acc, tp, conv;
+  size_t own;       // the own regions' total
+  size_t stage[4];  // INTT of the input; ModUp NTTs; ModDown INTTs; final NTTs
+  size_t inter;     // fused inner product: the ModUp intermediates (inside stage 1)
+  size_t ntt, total;  // the batch alone: transform region after the own ones
 };
 
 static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t batch) {
   const size_t plane = (size_t)batch * c->n * sizeof(uint32_t);
   const uint32_t digits = (level + c->alpha - 1) / c->alpha;
   const uint32_t ext = level + c->K;
-  // The transform region holds the largest of key_switch's four fused
-  // transforms, each unit's slice rounded to 256 bytes as fs_run_units /
-  // bf_run_units lay them out: INTT of the input (level limbs); the NTT of
-  // every digit's converted limbs; the INTT of both accumulators' K special
-  // limbs; the final NTT of both components (2 x level limbs).
+  // Each transform's region holds its units' slices, each rounded to 256
+  // bytes as fs_run_units / bf_run_units lay them out: INTT of the input
+  // (level limbs); the NTT of every digit's converted limbs; the INTT of
+  // both accumulators' K special limbs; the final NTT of both components
+  // (2 x level limbs).
   const tfhe_ntt_plan_s* p = c->plan;
   const bool mfma = p->algo == TFHE_NTT_FOURSTEP_MFMA;
   auto ws = [&](uint32_t limbs) {
@@ -93,11 +99,14 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
     const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
     modup += ws(d0) + ws(level - d0 - nd) + ws(c->K);
   }
+  KsLayout l;
   // with the fused second pass + inner product, the ModUp transforms'
   // intermediates sit in a regular [digits][level + K] array of planes
-  if (fused_inner(c)) modup = std::max(modup, align256(plane * (size_t)digits * ext));
-  const size_t ntt_bytes = std::max(std::max(ws(level), modup), std::max(2 * ws(c->K), 2 * ws(level)));
-  KsLayout l;
+  l.inter = fused_inner(c) ? align256(plane * (size_t)digits * ext) : 0;
+  l.stage[0] = ws(level);
+  l.stage[1] = std::max(modup, l.inter);
+  l.stage[2] = 2 * ws(c->K);
+  l.stage[3] = 2 * ws(level);
   size_t off = 0;
   l.d2 = off; off += align256(plane * level);
   l.x = off; off += align256(plane * level);
@@ -105,8 +114,9 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
   l.acc = off; off += align256(plane * 2 * ext);
   l.tp = off; off += align256(plane * 2 * c->K);
   l.conv = off; off += align256(plane * 2 * level);
-  l.ntt = off; off += align256(ntt_bytes);
-  l.total = off;
+  l.own = off;
+  l.ntt = off;
+  l.total = off + align256(*std::max_element(l.stage, l.stage + 4));
   return l;
 }
 
@@ -167,134 +177,247 @@ static void moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp, uint
   if (a.nout) cq.q.push_back(a);
 }
 
-// Key switching of d (NTT domain, [level][B][N]) with keys [dnum][2][L+K][N]
-// (one for the batch, or one per batch element);
-// out0 (+)= ModDown(acc0), out1 (+)= ModDown(acc1).
-static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const KeySet& keys,
-                             uint32_t* out0, uint32_t* out1, bool acc0_add, bool acc1_add,
-                             uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
+// One batch of a key switch: d (NTT domain, [level][batch][N]);
+// out0 (+)= ModDown(acc0), out1 (+)= ModDown(acc1).  own: the batch's
+// regions (KsLayout offsets); key0: its element 0's index in the key set.
+struct KsJob {
+  const uint32_t* d;
+  uint32_t key0;
+  uint32_t *out0, *out1;
+  bool add0, add1;
+  uint32_t level, batch;
+  unsigned char* own;
+};
+
+// Key switching of several batches (of different levels) with every
+// transform, basis conversion and inner product launched once for all of
+// them.  keys [dnum][2][L+K][N]: one for every element (count 1) or one per
+// element, batch g's from jobs[g].key0.  nws: the transforms' region, at
+// least the largest over the four stages of the batches' stage sums (the
+// fused inner product's intermediates of batch g at the sum of stage 1
+// before it).
+static hipError_t key_switch_multi(const tfhe_ckks_ctx_s* c, const KsJob* jobs, uint32_t nj, const KeySet& keys,
+                                   unsigned char* nws, hipStream_t s) {
+  if (nj > (uint32_t)kMaxIpGroups) return hipErrorInvalidValue;
   const tfhe_ntt_plan_s* p = c->plan;
-  const KsLayout lay = ks_layout(c, level, batch);
-  const uint64_t plane = (uint64_t)batch * c->n;
-  const uint32_t ext = level + c->K;
-  const uint32_t digits = (level + c->alpha - 1) / c->alpha;
-  uint32_t* x = (uint32_t*)(ws + lay.x);
-  uint32_t* up = (uint32_t*)(ws + lay.up);
-  uint32_t* acc = (uint32_t*)(ws + lay.acc);
-  uint32_t* tp = (uint32_t*)(ws + lay.tp);
-  uint32_t* conv = (uint32_t*)(ws + lay.conv);
-  void* nws = ws + lay.ntt;
-  // matrix-core conversion needs planes in whole 64-word chunks
-  const bool mfma_conv = plane % 64 == 0;
-  hipError_t e;
-  // INTT of the input (coefficient domain for the basis conversion)
-  if ((e = ntt_units(p, {NttUnit{p, true, d, x, 0, level, batch}}, nws, s)) != hipSuccess) return e;
-  // Dcomp + ModUp of every digit, then one fused NTT of all converted limbs:
-  // the q-limbs before and after the digit, and the p-limbs
-  std::vector<NttUnit> fwd;
-  ConvQueue cq;  // the matrix-core conversions of all digits, launched together
-  // fused: the transforms' first pass writes digit j's intermediate of
-  // position pos at inter + (j ext + pos) plane; ip_run finishes them
   const bool fused = fused_inner(c);
-  uint32_t* inter = (uint32_t*)nws;
-  for (uint32_t j = 0; j < digits; ++j) {
-    const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
-    const uint32_t key_idx = d0 + nd - 1;
-    uint32_t* upj = up + (uint64_t)j * ext * plane;
-    if (mfma_conv)
-      modup_mfma(c, x, upj, key_idx, d0, nd, level, plane, cq);
-    else if ((e = launch_modup(x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
-                               c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
-                               c->L, c->K, batch, c->n, s)) != hipSuccess)
-      return e;
-    uint32_t* outj = fused ? inter + (uint64_t)j * ext * plane : upj;
-    auto unit = [&](uint32_t pos, uint32_t limb_begin, uint32_t count) {
-      NttUnit u{p, false, upj + (uint64_t)pos * plane, outj + (uint64_t)pos * plane, limb_begin, count, batch};
-      u.pass1_only = fused;
-      fwd.push_back(u);
-    };
-    if (d0) unit(0, 0, d0);
-    if (level > d0 + nd) unit(d0 + nd, d0 + nd, level - d0 - nd);
-    unit(level, c->L, c->K);
+  struct Ptrs {
+    uint32_t *x, *up, *acc, *tp, *conv, *inter;
+    uint64_t plane;
+    uint32_t ext, digits;
+  };
+  std::vector<Ptrs> w(nj);
+  size_t inter_off = 0;
+  bool mfma_conv = true;  // matrix-core conversion needs planes in whole 64-word chunks
+  for (uint32_t g = 0; g < nj; ++g) {
+    const KsJob& j = jobs[g];
+    const KsLayout lay = ks_layout(c, j.level, j.batch);
+    w[g] = Ptrs{(uint32_t*)(j.own + lay.x),   (uint32_t*)(j.own + lay.up),   (uint32_t*)(j.own + lay.acc),
+                (uint32_t*)(j.own + lay.tp),  (uint32_t*)(j.own + lay.conv), (uint32_t*)(nws + inter_off),
+                (uint64_t)j.batch * c->n,     j.level + c->K,                (j.level + c->alpha - 1) / c->alpha};
+    inter_off += lay.stage[1];
+    mfma_conv = mfma_conv && w[g].plane % 64 == 0;
+  }
+  hipError_t e;
+  // INTT of the inputs (coefficient domain for the basis conversion)
+  std::vector<NttUnit> units;
+  for (uint32_t g = 0; g < nj; ++g)
+    units.push_back(NttUnit{p, true, jobs[g].d, w[g].x, 0, jobs[g].level, jobs[g].batch});
+  if ((e = ntt_units(p, units, nws, s)) != hipSuccess) return e;
+  // Dcomp + ModUp of every digit, then one fused NTT of all converted limbs:
+  // the q-limbs before and after the digit, and the p-limbs.  Fused: the
+  // transforms' first pass writes digit j's intermediate of position pos at
+  // inter + (j ext + pos) plane; ip_run finishes them.
+  units.clear();
+  ConvQueue cq;  // the matrix-core conversions, launched together
+  for (uint32_t g = 0; g < nj; ++g) {
+    const uint32_t level = jobs[g].level, batch = jobs[g].batch, ext = w[g].ext;
+    const uint64_t plane = w[g].plane;
+    for (uint32_t j = 0; j < w[g].digits; ++j) {
+      const uint32_t d0 = c->alpha * j, nd = std::min(c->alpha, level - d0);
+      const uint32_t key_idx = d0 + nd - 1;
+      uint32_t* upj = w[g].up + (uint64_t)j * ext * plane;
+      if (mfma_conv)
+        modup_mfma(c, w[g].x, upj, key_idx, d0, nd, level, plane, cq);
+      else if ((e = launch_modup(w[g].x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
+                                 c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
+                                 c->L, c->K, batch, c->n, s)) != hipSuccess)
+        return e;
+      uint32_t* outj = fused ? w[g].inter + (uint64_t)j * ext * plane : upj;
+      auto unit = [&](uint32_t pos, uint32_t limb_begin, uint32_t count) {
+        NttUnit u{p, false, upj + (uint64_t)pos * plane, outj + (uint64_t)pos * plane, limb_begin, count, batch};
+        u.pass1_only = fused;
+        units.push_back(u);
+      };
+      if (d0) unit(0, 0, d0);
+      if (level > d0 + nd) unit(d0 + nd, d0 + nd, level - d0 - nd);
+      unit(level, c->L, c->K);
+    }
   }
   if ((e = cq.flush(p->num_cus, K_MODUP, s)) != hipSuccess) return e;
-  if ((e = ntt_units(p, fwd, nws, s)) != hipSuccess) return e;
-  uint32_t* a0 = acc;
-  uint32_t* a1 = acc + (uint64_t)ext * plane;
-  if (fused) {
-    IpArgs ia;
-    ia.inter = inter;
-    ia.d2 = d;
-    ia.acc = acc;
-    ia.batch = batch;
-    ia.level = level;
-    ia.L = c->L;
-    ia.K = c->K;
-    ia.alpha = c->alpha;
-    ia.digits = digits;
-    ia.keys = keys;
-    if ((e = ip_run(p, ia, s)) != hipSuccess) return e;
-  } else if ((e = launch_inner_product(d, up, keys, a0, a1, p->d_mod, c->alpha, digits, level, c->L, c->K,
-                                       batch, c->log_n, s)) != hipSuccess) {
-    return e;
-  }
+  if ((e = ntt_units(p, units, nws, s)) != hipSuccess) return e;
+  IpSet ip{};
+  ip.count = nj;
+  ip.L = c->L;
+  ip.K = c->K;
+  ip.alpha = c->alpha;
+  ip.keys = keys;
+  for (uint32_t g = 0; g < nj; ++g)
+    ip.g[g] = IpGroup{fused ? w[g].inter : w[g].up, jobs[g].d, w[g].acc, jobs[g].level, jobs[g].batch,
+                      w[g].digits, jobs[g].key0, 0};
+  if ((e = fused ? ip_run(p, ip, s) : launch_inner_product(ip, p->d_mod, c->log_n, s)) != hipSuccess) return e;
   // ModDown of both accumulators, their transforms fused
-  uint32_t* tp1 = tp + (uint64_t)c->K * plane;
-  uint32_t* conv1 = conv + (uint64_t)level * plane;
-  if ((e = ntt_units(p, {NttUnit{p, true, a0 + (uint64_t)level * plane, tp, c->L, c->K, batch},
-                         NttUnit{p, true, a1 + (uint64_t)level * plane, tp1, c->L, c->K, batch}},
-                     nws, s)) != hipSuccess)
-    return e;
-  for (int comp = 0; comp < 2; ++comp)
-    if (mfma_conv)
-      moddown_conv_mfma(c, comp ? tp1 : tp, comp ? conv1 : conv, level, plane, cq);
-    else if ((e = launch_moddown_conv(comp ? tp1 : tp, comp ? conv1 : conv, p->d_mod, c->d_dn_invp,
-                                      c->d_dn_conv, level, c->L, c->K, batch, c->n, s)) != hipSuccess)
-      return e;
-  if ((e = cq.flush(p->num_cus, K_MD_CONV, s)) != hipSuccess) return e;
-  if (p->algo == TFHE_NTT_FOURSTEP_MFMA) {
-    // the transform's second pass finishes ModDown in its store epilogue:
-    // out (+)= (acc - NTT(conv)) P^{-1}
-    NttUnit u0{p, false, conv, out0, 0, level, batch};
-    NttUnit u1{p, false, conv1, out1, 0, level, batch};
-    u0.acc = a0;
-    u1.acc = a1;
-    u0.epi_mult = u1.epi_mult = c->d_dn_pinv;
-    u0.epi_add = acc0_add;
-    u1.epi_add = acc1_add;
-    return ntt_units(p, {u0, u1}, nws, s);
+  units.clear();
+  for (uint32_t g = 0; g < nj; ++g) {
+    const uint64_t plane = w[g].plane;
+    const uint32_t level = jobs[g].level, batch = jobs[g].batch;
+    uint32_t* a1 = w[g].acc + (uint64_t)w[g].ext * plane;
+    units.push_back(NttUnit{p, true, w[g].acc + (uint64_t)level * plane, w[g].tp, c->L, c->K, batch});
+    units.push_back(NttUnit{p, true, a1 + (uint64_t)level * plane, w[g].tp + (uint64_t)c->K * plane, c->L, c->K, batch});
   }
-  if ((e = ntt_units(p, {NttUnit{p, false, conv, conv, 0, level, batch},
-                         NttUnit{p, false, conv1, conv1, 0, level, batch}},
-                     nws, s)) != hipSuccess)
-    return e;
-  for (int comp = 0; comp < 2; ++comp)
-    if ((e = launch_moddown_final(comp ? a1 : a0, comp ? conv1 : conv, comp ? out1 : out0, p->d_mod,
-                                  c->d_dn_pinv, level, batch, c->n, comp ? acc1_add : acc0_add, s)) !=
-        hipSuccess)
-      return e;
+  if ((e = ntt_units(p, units, nws, s)) != hipSuccess) return e;
+  for (uint32_t g = 0; g < nj; ++g) {
+    const uint64_t plane = w[g].plane;
+    const uint32_t level = jobs[g].level;
+    for (int comp = 0; comp < 2; ++comp) {
+      const uint32_t* tpc = w[g].tp + (comp ? (uint64_t)c->K * plane : 0);
+      uint32_t* convc = w[g].conv + (comp ? (uint64_t)level * plane : 0);
+      if (mfma_conv)
+        moddown_conv_mfma(c, tpc, convc, level, plane, cq);
+      else if ((e = launch_moddown_conv(tpc, convc, p->d_mod, c->d_dn_invp, c->d_dn_conv, level, c->L, c->K,
+                                        jobs[g].batch, c->n, s)) != hipSuccess)
+        return e;
+    }
+  }
+  if ((e = cq.flush(p->num_cus, K_MD_CONV, s)) != hipSuccess) return e;
+  units.clear();
+  for (uint32_t g = 0; g < nj; ++g) {
+    const KsJob& j = jobs[g];
+    const uint64_t plane = w[g].plane;
+    uint32_t* conv1 = w[g].conv + (uint64_t)j.level * plane;
+    uint32_t* a1 = w[g].acc + (uint64_t)w[g].ext * plane;
+    if (p->algo == TFHE_NTT_FOURSTEP_MFMA) {
+      // the transform's second pass finishes ModDown in its store epilogue:
+      // out (+)= (acc - NTT(conv)) P^{-1}
+      NttUnit u0{p, false, w[g].conv, j.out0, 0, j.level, j.batch};
+      NttUnit u1{p, false, conv1, j.out1, 0, j.level, j.batch};
+      u0.acc = w[g].acc;
+      u1.acc = a1;
+      u0.epi_mult = u1.epi_mult = c->d_dn_pinv;
+      u0.epi_add = j.add0;
+      u1.epi_add = j.add1;
+      units.push_back(u0);
+      units.push_back(u1);
+    } else {
+      units.push_back(NttUnit{p, false, w[g].conv, w[g].conv, 0, j.level, j.batch});
+      units.push_back(NttUnit{p, false, conv1, conv1, 0, j.level, j.batch});
+    }
+  }
+  if ((e = ntt_units(p, units, nws, s)) != hipSuccess) return e;
+  if (p->algo == TFHE_NTT_FOURSTEP_MFMA) return hipSuccess;
+  for (uint32_t g = 0; g < nj; ++g) {
+    const KsJob& j = jobs[g];
+    const uint64_t plane = w[g].plane;
+    for (int comp = 0; comp < 2; ++comp)
+      if ((e = launch_moddown_final(w[g].acc + (comp ? (uint64_t)w[g].ext * plane : 0),
+                                    w[g].conv + (comp ? (uint64_t)j.level * plane : 0), comp ? j.out1 : j.out0,
+                                    p->d_mod, c->d_dn_pinv, j.level, j.batch, c->n, comp ? j.add1 : j.add0, s)) !=
+          hipSuccess)
+        return e;
+  }
   return hipSuccess;
 }
 
-hipError_t hmult_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& a, const CtPtrs& b, uint32_t* out,
-                      const uint32_t* evk, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
-  const uint64_t plane = (uint64_t)level * batch * c->n;
-  uint32_t* d2 = (uint32_t*)(ws + ks_layout(c, level, batch).d2);
-  hipError_t e = launch_tensor_ptrs(a, b, out, d2, c->plan->d_mod, level, batch, c->log_n, s);
-  KeySet keys{};
-  keys.count = 1;
-  keys.k[0] = evk;
-  if (e == hipSuccess) e = key_switch(c, d2, keys, out, out + plane, true, true, level, batch, ws, s);
-  return e;
+// Key switching of one batch with workspace ws (ks_layout(level, batch)).
+static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const KeySet& keys,
+                             uint32_t* out0, uint32_t* out1, bool acc0_add, bool acc1_add,
+                             uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
+  const KsJob job{d, 0, out0, out1, acc0_add, acc1_add, level, batch, ws};
+  return key_switch_multi(c, &job, 1, keys, ws + ks_layout(c, level, batch).ntt, s);
 }
 
-hipError_t rotate_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& in, uint32_t* out, const KeySet& keys,
-                       const GaloisSet& gs, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s) {
-  const uint64_t plane = (uint64_t)level * batch * c->n;
-  uint32_t* r1 = (uint32_t*)(ws + ks_layout(c, level, batch).d2);
-  hipError_t e = launch_frobenius_pair_ptrs(in, out, r1, gs, level, batch, c->log_n, s);
-  if (e == hipSuccess) e = key_switch(c, r1, keys, out, out + plane, true, false, level, batch, ws, s);
-  return e;
+// Level groups of a mixed-level batch: request indices sorted by level
+// (stable), and the workspace layout (per group its result staging
+// [2][level][B][N] and its own key-switching regions; then the transforms'
+// region shared by all groups).
+static_assert(TFHE_HMULT_LEVELS_MAX == kMaxRotBatch, "one bound for mixed-level batches");
+
+struct LvPlan {
+  std::vector<uint32_t> order;                 // request indices by level
+  std::vector<std::pair<uint32_t, uint32_t>> groups;  // [begin, end) in order
+  std::vector<size_t> staging, own;            // byte offsets per group
+  size_t ntt = 0, total = 0;
+};
+
+static LvPlan lv_plan(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count) {
+  LvPlan l;
+  l.order.resize(count);
+  for (uint32_t i = 0; i < count; ++i) l.order[i] = i;
+  std::stable_sort(l.order.begin(), l.order.end(),
+                   [&](uint32_t x, uint32_t y) { return r[x].level < r[y].level; });
+  for (uint32_t i = 0; i < count;) {
+    uint32_t j = i;
+    while (j < count && r[l.order[j]].level == r[l.order[i]].level) ++j;
+    l.groups.emplace_back(i, j);
+    i = j;
+  }
+  size_t off = 0, stage[4] = {0, 0, 0, 0};
+  for (auto& g : l.groups) {
+    const uint32_t level = r[l.order[g.first]].level, B = g.second - g.first;
+    const KsLayout lay = ks_layout(c, level, B);
+    l.staging.push_back(off);
+    off += align256((size_t)2 * level * B * c->n * sizeof(uint32_t));
+    l.own.push_back(off);
+    off += lay.own;
+    for (int k = 0; k < 4; ++k) stage[k] += lay.stage[k];
+  }
+  l.ntt = off;
+  l.total = off + align256(*std::max_element(stage, stage + 4));
+  return l;
+}
+
+size_t levels_ws_bytes(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count) {
+  return count ? lv_plan(c, r, count).total : 0;
+}
+
+hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uint32_t count,
+                      unsigned char* ws, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  if (count > kMaxRotBatch) return hipErrorInvalidValue;
+  const LvPlan l = lv_plan(c, r, count);
+  std::vector<KsJob> jobs;
+  ScatterSet sc{};
+  CtDescSet cs{};
+  KeySet keys{};
+  bool same = true;  // one key (and Galois element) for the whole batch
+  for (uint32_t i = 0; i < count; ++i)
+    same = same && r[i].key == r[0].key && (op == 0 || r[i].galois == r[0].galois);
+  keys.count = same ? 1 : count;
+  cs.count = count;
+  for (size_t g = 0; g < l.groups.size(); ++g) {
+    const uint32_t b0 = l.groups[g].first, B = l.groups[g].second - b0;
+    const uint32_t level = r[l.order[b0]].level;
+    const KsLayout lay = ks_layout(c, level, B);
+    uint32_t* stg = (uint32_t*)(ws + l.staging[g]);
+    unsigned char* own = ws + l.own[g];
+    uint32_t* d = (uint32_t*)(own + lay.d2);
+    const uint64_t plane = (uint64_t)level * B * c->n;
+    for (uint32_t k = 0; k < B; ++k) {
+      const LvReq& q = r[l.order[b0 + k]];
+      keys.k[same ? 0 : b0 + k] = q.key;
+      cs.c[b0 + k] = CtDesc{q.a, q.b, stg, d, level, B, k, q.galois};
+      sc.src[b0 + k] = stg;
+      sc.dst[b0 + k] = q.out;
+      sc.rows[b0 + k] = 2 * level;
+      sc.batch[b0 + k] = B;
+      sc.b[b0 + k] = k;
+    }
+    jobs.push_back(KsJob{d, b0, stg, stg + plane, true, op == 0, level, B, own});
+  }
+  hipError_t e = op == 0 ? launch_tensor_multi(cs, c->plan->d_mod, c->log_n, s) : launch_frobenius_multi(cs, c->log_n, s);
+  if (e != hipSuccess) return e;
+  if ((e = key_switch_multi(c, jobs.data(), (uint32_t)jobs.size(), keys, ws + l.ntt, s)) != hipSuccess) return e;
+  return launch_scatter(sc, count, c->log_n, s);
 }
 
 // RESCALE workspace: the top limbs in the coefficient domain [2][B][N], their
@@ -614,6 +737,77 @@ tfhe_status tfhe_hmult_noalloc(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const ui
   unsigned char* w = scratch_of(ctx->plan->device);
   if (!w) return fail(TFHE_EINVAL, "hmult_noalloc: scratch not bound on this device");
   return hmult_run(ctx, ct_a, ct_b, ct_out, evk, level, batch, w, stream);
+}
+
+tfhe_status tfhe_hmult_levels_workspace_size(tfhe_ckks_ctx ctx, const uint32_t* levels, uint32_t count,
+                                             size_t* bytes) {
+  if (!ctx || !bytes || (count && !levels)) return fail(TFHE_EINVAL, "hmult_levels_workspace_size: null argument");
+  if (count > kMaxRotBatch) return fail(TFHE_EINVAL, "hmult_levels: count exceeds TFHE_HMULT_LEVELS_MAX");
+  std::vector<LvReq> r(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    if (levels[i] < 1 || levels[i] > ctx->L) return fail(TFHE_EINVAL, "level must be in [1, L]");
+    r[i].level = levels[i];
+  }
+  *bytes = levels_ws_bytes(ctx, r.data(), count);
+  return TFHE_OK;
+}
+
+// Checks of a mixed-level call shared by tfhe_hmult_levels and
+// tfhe_rotate_levels (r filled in by the caller).
+static tfhe_status check_levels_call(tfhe_ckks_ctx ctx, const std::vector<LvReq>& r, void* ws, size_t ws_bytes,
+                                     const char* what) {
+  const uint32_t count = (uint32_t)r.size();
+  for (uint32_t i = 0; i < count; ++i) {
+    if (r[i].level < 1 || r[i].level > ctx->L) return fail(TFHE_EINVAL, "level must be in [1, L]");
+    if (!al16(r[i].a) || !al16(r[i].out) || !al16(r[i].key) || (r[i].b && !al16(r[i].b)))
+      return fail(TFHE_EINVAL, std::string(what) + ": null or unaligned ciphertext or key");
+  }
+  // results must not overlap one another (each may alias any input)
+  const size_t limb = (size_t)ctx->n * sizeof(uint32_t);
+  for (uint32_t i = 0; i < count; ++i)
+    for (uint32_t j = i + 1; j < count; ++j) {
+      const char *p = (const char*)r[i].out, *q = (const char*)r[j].out;
+      if (p < q + 2 * r[j].level * limb && q < p + 2 * r[i].level * limb)
+        return fail(TFHE_EINVAL, std::string(what) + ": result buffers overlap");
+    }
+  const size_t need = levels_ws_bytes(ctx, r.data(), count);
+  if (!ws || ws_bytes < need) return fail(TFHE_EINVAL, "workspace missing or too small");
+  if ((uintptr_t)ws % 256) return fail(TFHE_EINVAL, "workspace not 256-byte aligned");
+  return TFHE_OK;
+}
+
+tfhe_status tfhe_hmult_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_a, const uint32_t* const* ct_b,
+                              uint32_t* const* ct_out, const uint32_t* levels, uint32_t count,
+                              const uint32_t* evk, void* ws, size_t ws_bytes, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, 1, 1, nullptr, 0, false);
+  if (st != TFHE_OK || count == 0) return st;
+  if (count > kMaxRotBatch) return fail(TFHE_EINVAL, "hmult_levels: count exceeds TFHE_HMULT_LEVELS_MAX");
+  if (!ct_a || !ct_b || !ct_out || !levels) return fail(TFHE_EINVAL, "hmult_levels: null array");
+  if (!al16(evk)) return fail(TFHE_EINVAL, "hmult_levels: null or unaligned evk");
+  std::vector<LvReq> r(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!ct_b[i]) return fail(TFHE_EINVAL, "hmult_levels: null ciphertext");
+    r[i] = LvReq{ct_a[i], ct_b[i], ct_out[i], evk, levels[i], 0};
+  }
+  if ((st = check_levels_call(ctx, r, ws, ws_bytes, "hmult_levels")) != TFHE_OK) return st;
+  return hip_check(levels_run(ctx, 0, r.data(), count, (unsigned char*)ws, (hipStream_t)stream), "hmult_levels");
+}
+
+tfhe_status tfhe_rotate_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_in, uint32_t* const* ct_out,
+                               const uint32_t* const* rotkeys, const uint32_t* galois_elts, const uint32_t* levels,
+                               uint32_t count, void* ws, size_t ws_bytes, tfhe_stream_t stream) {
+  tfhe_status st = check_ct_call(ctx, 1, 1, nullptr, 0, false);
+  if (st != TFHE_OK || count == 0) return st;
+  if (count > kMaxRotBatch) return fail(TFHE_EINVAL, "rotate_levels: count exceeds TFHE_HMULT_LEVELS_MAX");
+  if (!ct_in || !ct_out || !rotkeys || !galois_elts || !levels) return fail(TFHE_EINVAL, "rotate_levels: null array");
+  std::vector<LvReq> r(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    if ((galois_elts[i] & 1) == 0 || galois_elts[i] >= 2 * ctx->n)
+      return fail(TFHE_EINVAL, "rotate_levels: galois elements must be odd and < 2N");
+    r[i] = LvReq{ct_in[i], nullptr, ct_out[i], rotkeys[i], levels[i], galois_elts[i]};
+  }
+  if ((st = check_levels_call(ctx, r, ws, ws_bytes, "rotate_levels")) != TFHE_OK) return st;
+  return hip_check(levels_run(ctx, 1, r.data(), count, (unsigned char*)ws, (hipStream_t)stream), "rotate_levels");
 }
 
 tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,

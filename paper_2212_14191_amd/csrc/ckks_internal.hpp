@@ -59,27 +59,37 @@ struct KeySet {
   const uint32_t* k[kMaxRotBatch];
 };
 
-// The ModUp forward transforms' second pass fused with the inner product
-// (ntt_fourstep.hip): for every extended-basis position t < level + K and
-// batch element b, acc_c[t][b] = sum_j y_j evk_j[c][t] with y_j the second
-// pass of digit j's tiled intermediate at (j, t, b) (t outside digit j) or
-// d2[t][b] (t in digit j, already in the NTT domain).  Layouts:
-//   inter [digits][level + K][batch][N] (pass-1 output, tiled per polynomial;
-//         slots of a digit's own limbs unused), d2 [level][batch][N],
-//   acc [2][level + K][batch][N], keys as KeySet (limb index t for q-limbs,
-//         L + t - level for the special ones).
-struct IpArgs {
-  const uint32_t* inter;
+// The key-switching inner product of one batch of one level (a level
+// group): for every extended-basis position t < level + K and batch element
+// b, acc_c[t][b] = sum_j y_j evk_j[c][t], with y_j = d2[t][b] where t is in
+// digit j (already in the NTT domain) and otherwise the ModUp result of
+// digit j at (j, t, b).  Layouts: src [digits][level + K][batch][N] (slots of
+// a digit's own limbs unused), d2 [level][batch][N], acc [2][level + K][batch][N];
+// keys as KeySet (limb index t for q-limbs, L + t - level for the special
+// ones).
+struct IpGroup {
+  const uint32_t* src;  // ip_run: the ModUp transforms' pass-1 intermediates
+                        // (tiled); launch_inner_product: the ModUp results
   const uint32_t* d2;
   uint32_t* acc;
-  uint32_t batch, level, L, K, alpha, digits;
-  KeySet keys;
+  uint32_t level, batch, digits;
+  uint32_t key0;   // keys.k index of the group's element 0 (keys.count > 1)
+  uint32_t item0;  // ip_run: the group's first work item (filled in by ip_run)
 };
-hipError_t ip_run(const tfhe_ntt_plan_s* p, const IpArgs& a, hipStream_t s);
-hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const KeySet& keys,
-                                uint32_t* acc0, uint32_t* acc1, const ModConst* mods,
-                                uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,
-                                uint32_t K, uint32_t batch, uint32_t log_n, hipStream_t s);
+constexpr int kMaxIpGroups = kMaxRotBatch;
+// The inner products of several level groups in one launch.
+struct IpSet {
+  uint32_t count, L, K, alpha;
+  KeySet keys;  // one key for every element, or one per element (group by group)
+  IpGroup g[kMaxIpGroups];
+};
+static_assert(sizeof(IpSet) <= 4096, "an IpSet is passed as a kernel argument");
+// The ModUp forward transforms' second pass fused with the inner product
+// (ntt_fourstep.hip): y_j of a position outside digit j is the second pass of
+// digit j's tiled intermediate.
+hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s);
+// The inner product over finished ModUp results (ckks_kernels.hip).
+hipError_t launch_inner_product(const IpSet& set, const ModConst* mods, uint32_t log_n, hipStream_t s);
 hipError_t launch_moddown_conv(const uint32_t* a, uint32_t* conv, const ModConst* mods,
                                const uint2* invp, const uint2* cp, uint32_t level, uint32_t L,
                                uint32_t K, uint32_t batch, uint32_t n, hipStream_t s);
@@ -107,18 +117,27 @@ hipError_t launch_frobenius_pair(const uint32_t* in0, uint32_t* out0, const uint
 hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst* mods,
                                 uint32_t top, uint32_t batch, uint32_t n, hipStream_t s);
 
-// A batch of separately allocated ciphertexts [2][level][N], read as one
-// [2][level][batch][N] array: element b lives at p[b].
-struct CtPtrs {
-  const uint32_t* p[kMaxRotBatch];
+// One ciphertext of a mixed-level batch for launch_tensor_multi /
+// launch_frobenius_multi: inputs [2][level][N] where they are; outputs at
+// element idx of its level group's [level][B][N] planes.
+struct CtDesc {
+  const uint32_t* a;  // input (HMULT: first operand)
+  const uint32_t* b;  // HMULT: second operand
+  uint32_t* out;      // group [2][level][B][N]: (d0, d1), or sigma(c0) and unused
+  uint32_t* d;        // group [level][B][N]: d2, or sigma(c1)
+  uint32_t level, B, idx, galois;
 };
-// launch_tensor / launch_frobenius_pair reading their inputs through CtPtrs
-// (outputs in the batch layout).
-hipError_t launch_tensor_ptrs(const CtPtrs& a, const CtPtrs& b, uint32_t* out, uint32_t* d2,
-                              const ModConst* mods, uint32_t level, uint32_t batch, uint32_t log_n,
-                              hipStream_t s);
-hipError_t launch_frobenius_pair_ptrs(const CtPtrs& in, uint32_t* out0, uint32_t* out1, const GaloisSet& gs,
-                                      uint32_t level, uint32_t batch, uint32_t log_n, hipStream_t s);
+struct CtDescSet {
+  uint32_t count;
+  CtDesc c[kMaxRotBatch];
+};
+static_assert(sizeof(CtDescSet) <= 4096, "a CtDescSet is passed as a kernel argument");
+// Tensor product of every ciphertext pair of the set in one launch:
+// d0 = c0c0', d1 = c0c1' + c1c0' into out, d2 = c1c1' into d.
+hipError_t launch_tensor_multi(const CtDescSet& set, const ModConst* mods, uint32_t log_n, hipStream_t s);
+// FrobeniusMap of both components of every ciphertext of the set (its own
+// Galois element) in one launch: sigma(c0) into out, sigma(c1) into d.
+hipError_t launch_frobenius_multi(const CtDescSet& set, uint32_t log_n, hipStream_t s);
 
 }  // namespace tfhe
 
@@ -129,8 +148,33 @@ namespace tfhe {
 // request dispatcher's batches), with the result in the batch layout
 // [2][level][batch][N] at out.  Arguments are not validated (the caller
 // has); ws holds at least tfhe_hmult_workspace_size bytes, 256-aligned.
-hipError_t hmult_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& a, const CtPtrs& b, uint32_t* out,
-                      const uint32_t* evk, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s);
-hipError_t rotate_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& in, uint32_t* out, const KeySet& keys,
-                       const GaloisSet& gs, uint32_t level, uint32_t batch, unsigned char* ws, hipStream_t s);
+// Per-ciphertext copies out of level-group results (launch_scatter): element
+// r reads row k (component, limb; k < rows[r]) of its group's [rows][batch][N]
+// result at src[r] + (k batch[r] + b[r]) N and writes dst[r] + k N.
+struct ScatterSet {
+  const uint32_t* src[kMaxRotBatch];
+  uint32_t* dst[kMaxRotBatch];
+  uint32_t rows[kMaxRotBatch], batch[kMaxRotBatch], b[kMaxRotBatch];
+};
+static_assert(sizeof(ScatterSet) <= 4096, "a ScatterSet is passed as a kernel argument");
+hipError_t launch_scatter(const ScatterSet& e, uint32_t count, uint32_t log_n, hipStream_t s);
+
+// One ciphertext of a batch of mixed levels (levels_run).
+struct LvReq {
+  const uint32_t* a;    // input [2][level][N] (HMULT: first operand)
+  const uint32_t* b;    // HMULT: second operand [2][level][N]
+  uint32_t* out;        // result [2][level][N]
+  const uint32_t* key;  // evk (HMULT) or the rotation key
+  uint32_t level, galois;
+};
+// Workspace bytes levels_run needs for these requests.
+size_t levels_ws_bytes(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count);
+// HMULT (op 0) or HROTATE (op 1) of count <= kMaxRotBatch requests of any
+// levels in one batched launch sequence: the requests are grouped by level;
+// each group's tensor product (or Frobenius map) and inner product run per
+// group, every transform and basis conversion once for all groups; the
+// results are copied out to each request's buffer.  Each result equals the
+// single call's.
+hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uint32_t count,
+                      unsigned char* ws, hipStream_t s);
 }  // namespace tfhe

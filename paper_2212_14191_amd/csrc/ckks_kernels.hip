@@ -4,6 +4,8 @@
 // and the ModDown finalisation (Ele-Sub, Hada-Mult).  All run over the
 // (limb, batch, N) layout, one thread per coefficient position, so each
 // limb-plane access is a coalesced stream.
+#include <algorithm>
+
 #include "ckks_internal.hpp"
 
 namespace tfhe {
@@ -85,36 +87,43 @@ modup_kernel(const uint4* __restrict__ x, uint4* __restrict__ up,
 }
 
 // acc_c[p] = sum_j dt_j[p] o key[j][c][t(p)] over the digits, where dt_j is
-// d2 (NTT domain) on the digit's own limbs and the ModUp result elsewhere.
+// d2 (NTT domain) on the digit's own limbs and the ModUp result elsewhere;
+// blockIdx.y selects the level group.  Products are summed as 64-bit values
+// below q 2^32 and reduced once per output.
 __global__ void __launch_bounds__(kThreads)
-inner_product_kernel(const uint4* __restrict__ d2, const uint4* __restrict__ up,
-                     const KeySet keys, uint4* __restrict__ acc0,
-                     uint4* __restrict__ acc1, const ModConst* __restrict__ mods,
-                     uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L, uint32_t K,
-                     uint32_t batch, uint32_t log_n) {
+inner_product_kernel(const IpSet set, const ModConst* __restrict__ mods, uint32_t log_n) {
+  const IpGroup& G = set.g[blockIdx.y];
   const uint32_t n4 = (1u << log_n) / 4;
-  const uint64_t bn4 = (uint64_t)batch * n4;
-  const uint64_t total = (uint64_t)(level + K) * bn4;
-  const uint64_t key_plane = (uint64_t)(L + K) * n4;  // one key component
+  const uint64_t bn4 = (uint64_t)G.batch * n4;
+  const uint64_t total = (uint64_t)(G.level + set.K) * bn4;
+  const uint64_t key_plane = (uint64_t)(set.L + set.K) * n4;  // one key component
+  const uint4* d2 = (const uint4*)G.d2;
+  const uint4* up = (const uint4*)G.src;
+  uint4* acc0 = (uint4*)G.acc;
+  uint4* acc1 = acc0 + total;
   for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
        i += (uint64_t)gridDim.x * kThreads) {
     const uint32_t p = (uint32_t)(i / bn4);
     const uint32_t coef = (uint32_t)(i % n4);
-    const uint32_t t = p < level ? p : L + (p - level);
+    const uint32_t t = p < G.level ? p : set.L + (p - G.level);
     const ModConst m = mods[t];
-    // the key of this element's batch entry (one key for all when count = 1)
-    const uint4* key = (const uint4*)keys.k[keys.count == 1 ? 0 : (uint32_t)((i % bn4) / n4)];
-    uint4 s0 = make_uint4(0, 0, 0, 0), s1 = s0;
-    for (uint32_t j = 0; j < ndigits; ++j) {
-      const bool own = p < level && p / alpha == j;
+    // the key of this element (one key for all when count = 1)
+    const uint32_t e = (uint32_t)((i % bn4) / n4);
+    const uint4* key = (const uint4*)set.keys.k[set.keys.count == 1 ? 0 : G.key0 + e];
+    uint64_t s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};  // below q 2^32
+    for (uint32_t j = 0; j < G.digits; ++j) {
+      const bool own = p < G.level && p / set.alpha == j;
       const uint4 v = own ? d2[i] : up[(uint64_t)j * total + i];
       const uint4* kj = key + (uint64_t)j * 2 * key_plane + (uint64_t)t * n4 + coef;
       const uint4 k0 = kj[0], k1 = kj[key_plane];
-      s0 = map4(s0, [&](uint32_t a, int c) { return add_mod(a, mul_mod(comp(v, c), comp(k0, c), m), m.q); });
-      s1 = map4(s1, [&](uint32_t a, int c) { return add_mod(a, mul_mod(comp(v, c), comp(k1, c), m), m.q); });
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        s0[c] = mac_lazy(s0[c], comp(v, c), comp(k0, c), m.q);
+        s1[c] = mac_lazy(s1[c], comp(v, c), comp(k1, c), m.q);
+      }
     }
-    acc0[i] = s0;
-    acc1[i] = s1;
+    acc0[i] = make_uint4(reduce_lazy(s0[0], m), reduce_lazy(s0[1], m), reduce_lazy(s0[2], m), reduce_lazy(s0[3], m));
+    acc1[i] = make_uint4(reduce_lazy(s1[0], m), reduce_lazy(s1[1], m), reduce_lazy(s1[2], m), reduce_lazy(s1[3], m));
   }
 }
 
@@ -300,45 +309,64 @@ frobenius_pair_kernel(const uint32_t* __restrict__ in0, uint32_t* __restrict__ o
   }
 }
 
-// tensor_kernel with the inputs read from separate ciphertexts [2][level][N]
-// (a.p[b], b.p[b]); output index i = (limb batch + b) N/4 + k.
+// Tensor product of the ciphertext pairs of a mixed-level batch, blockIdx.y
+// selecting the pair: element i = limb N/4 + k of its inputs goes to
+// (limb B + idx) N/4 + k of its group's planes.
 __global__ void __launch_bounds__(kThreads)
-tensor_ptrs_kernel(const CtPtrs a, const CtPtrs b, uint4* out, uint4* __restrict__ d2,
-                   const ModConst* __restrict__ mods, uint32_t level, uint32_t batch, uint32_t log_n4) {
-  const uint64_t n4 = 1ull << log_n4, plane4 = (uint64_t)level * batch * n4;
-  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < plane4;
+tensor_multi_kernel(const CtDescSet set, const ModConst* __restrict__ mods, uint32_t log_n4) {
+  const CtDesc& c = set.c[blockIdx.y];
+  const uint64_t n4 = 1ull << log_n4, per4 = (uint64_t)c.level << log_n4;
+  const uint64_t gplane4 = per4 * c.B;  // one component of the group
+  const uint4* A = (const uint4*)c.a;
+  const uint4* B = (const uint4*)c.b;
+  uint4* out = (uint4*)c.out;
+  uint4* d2 = (uint4*)c.d;
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < per4;
        i += (uint64_t)gridDim.x * kThreads) {
-    const uint32_t rb = (uint32_t)(i >> log_n4), limb = rb / batch, e = rb - limb * batch;
-    const uint64_t own = ((uint64_t)limb << log_n4) + (i & (n4 - 1)), comp1 = (uint64_t)level << log_n4;
-    const uint4* A = (const uint4*)a.p[e];
-    const uint4* B = (const uint4*)b.p[e];
+    const uint32_t limb = (uint32_t)(i >> log_n4);
+    const uint64_t o = (((uint64_t)limb * c.B + c.idx) << log_n4) + (i & (n4 - 1));
     const ModConst m = mods[limb];
-    const uint4 c0 = A[own], c1 = A[comp1 + own], e0 = B[own], e1 = B[comp1 + own];
-    d2[i] = map4(c1, [&](uint32_t x, int k) { return mul_mod(x, comp(e1, k), m); });
-    out[i] = map4(c0, [&](uint32_t x, int k) { return mul_mod(x, comp(e0, k), m); });
-    out[plane4 + i] = map4(c0, [&](uint32_t x, int k) {
+    const uint4 c0 = A[i], c1 = A[per4 + i], e0 = B[i], e1 = B[per4 + i];
+    d2[o] = map4(c1, [&](uint32_t x, int k) { return mul_mod(x, comp(e1, k), m); });
+    out[o] = map4(c0, [&](uint32_t x, int k) { return mul_mod(x, comp(e0, k), m); });
+    out[gplane4 + o] = map4(c0, [&](uint32_t x, int k) {
       return add_mod(mul_mod(x, comp(e1, k), m), mul_mod(comp(c1, k), comp(e0, k), m), m.q);
     });
   }
 }
 
-// frobenius_pair_kernel with the input components read from separate
-// ciphertexts [2][level][N] (in.p[b]); outputs [level][batch][N].
+// FrobeniusMap of both components of each ciphertext of a mixed-level batch
+// (blockIdx.y selects it, with its own Galois element): out_j = in_{pi(j)}
+// per limb; component 0 to out, component 1 to d, at (limb B + idx) N.
 __global__ void __launch_bounds__(kThreads)
-frobenius_pair_ptrs_kernel(const CtPtrs in, uint32_t* __restrict__ out0, uint32_t* __restrict__ out1,
-                           const GaloisSet gs, uint32_t level, uint32_t batch, uint32_t log_n) {
+frobenius_multi_kernel(const CtDescSet set, uint32_t log_n) {
+  const CtDesc& c = set.c[blockIdx.y];
   const uint32_t n = 1u << log_n, mask2n = 2 * n - 1;
-  const uint64_t per = ((uint64_t)level * batch) << log_n;
+  const uint64_t per = (uint64_t)c.level << log_n;
   for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < 2 * per;
        i += (uint64_t)gridDim.x * kThreads) {
     const bool second = i >= per;
     const uint64_t k = second ? i - per : i;
-    const uint32_t j = (uint32_t)(k & (n - 1)), row = (uint32_t)(k >> log_n);
-    const uint32_t limb = row / batch, e = row - limb * batch;
-    const uint32_t galois = gs.g[e % gs.batch];
-    const uint32_t src = (((2 * j + 1) * galois) & mask2n) >> 1;
-    const uint64_t base = ((uint64_t)(second ? level + limb : limb)) << log_n;
-    (second ? out1 : out0)[k] = in.p[e][base + src];
+    const uint32_t j = (uint32_t)(k & (n - 1)), limb = (uint32_t)(k >> log_n);
+    const uint32_t src = (((2 * j + 1) * c.galois) & mask2n) >> 1;
+    const uint64_t o = (((uint64_t)limb * c.B + c.idx) << log_n) + j;
+    (second ? c.d : c.out)[o] = c.a[(second ? per : 0) + ((uint64_t)limb << log_n) + src];
+  }
+}
+
+// Copies each ciphertext of a mixed-level batch out of its level group's
+// result [2][level][B][N] (element e.b[r]) to its own [2][level][N]
+// (e.dst[r]); blockIdx.y selects the ciphertext, 16 bytes per element.
+__global__ void __launch_bounds__(kThreads)
+scatter_kernel(const ScatterSet e, uint32_t log_n4) {
+  const uint32_t r = blockIdx.y;
+  const uint64_t n4 = 1ull << log_n4, total = (uint64_t)e.rows[r] << log_n4;
+  const uint4* src = (const uint4*)e.src[r];
+  uint4* dst = (uint4*)e.dst[r];
+  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * kThreads) {
+    const uint64_t row = i >> log_n4;
+    dst[i] = src[((row * e.batch[r] + e.b[r]) << log_n4) + (i & (n4 - 1))];
   }
 }
 
@@ -378,12 +406,18 @@ hipError_t launch_conv_mfma(const ConvSet& set, uint32_t num_cus, KernelId id, h
 }
 
 hipError_t ConvQueue::flush(uint32_t num_cus, KernelId id, hipStream_t s) {
-  for (size_t i = 0; i < q.size(); i += kConvPerLaunch) {
+  // a launch takes conversions of one plane size: queued order within each size
+  std::stable_sort(q.begin(), q.end(), [](const ConvArgs& x, const ConvArgs& y) { return x.plane < y.plane; });
+  for (size_t i = 0; i < q.size();) {
     ConvSet set{};
-    set.count = (uint32_t)std::min<size_t>(kConvPerLaunch, q.size() - i);
-    for (uint32_t k = 0; k < set.count; ++k) set.a[k] = q[i + k];
+    set.count = 0;
+    while (i < q.size() && set.count < (uint32_t)kConvPerLaunch && (set.count == 0 || q[i].plane == set.a[0].plane))
+      set.a[set.count++] = q[i++];
     hipError_t e = launch_conv_mfma(set, num_cus, id, s);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+      q.clear();
+      return e;
+    }
   }
   q.clear();
   return hipSuccess;
@@ -397,20 +431,34 @@ hipError_t launch_frobenius_pair(const uint32_t* in0, uint32_t* out0, const uint
   return hipGetLastError();
 }
 
-hipError_t launch_tensor_ptrs(const CtPtrs& a, const CtPtrs& b, uint32_t* out, uint32_t* d2,
-                              const ModConst* mods, uint32_t level, uint32_t batch, uint32_t log_n,
-                              hipStream_t s) {
-  const uint64_t plane4 = ((uint64_t)level * batch) << (log_n - 2);
-  TFHE_TIMED(K_TENSOR, s, hipLaunchKernelGGL(tensor_ptrs_kernel, dim3(grid_for(plane4)), dim3(kThreads), 0, s, a, b,
-                                             (uint4*)out, (uint4*)d2, mods, level, batch, log_n - 2));
+// blocks per ciphertext of a CtDescSet launch: the grid covers the largest
+uint32_t multi_grid(const CtDescSet& set, uint32_t per_level) {
+  uint32_t lv = 0;
+  for (uint32_t r = 0; r < set.count; ++r) lv = std::max(lv, set.c[r].level);
+  return std::max<uint32_t>(1, std::min<uint32_t>(grid_for((uint64_t)lv * per_level), 1024));
+}
+
+hipError_t launch_tensor_multi(const CtDescSet& set, const ModConst* mods, uint32_t log_n, hipStream_t s) {
+  if (set.count == 0) return hipSuccess;
+  TFHE_TIMED(K_TENSOR, s, hipLaunchKernelGGL(tensor_multi_kernel, dim3(multi_grid(set, (1u << log_n) / 4), set.count),
+                                             dim3(kThreads), 0, s, set, mods, log_n - 2));
   return hipGetLastError();
 }
 
-hipError_t launch_frobenius_pair_ptrs(const CtPtrs& in, uint32_t* out0, uint32_t* out1, const GaloisSet& gs,
-                                      uint32_t level, uint32_t batch, uint32_t log_n, hipStream_t s) {
-  const uint64_t per = ((uint64_t)level * batch) << log_n;
-  TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_pair_ptrs_kernel, dim3(grid_for(2 * per)), dim3(kThreads), 0,
-                                           s, in, out0, out1, gs, level, batch, log_n));
+hipError_t launch_frobenius_multi(const CtDescSet& set, uint32_t log_n, hipStream_t s) {
+  if (set.count == 0) return hipSuccess;
+  TFHE_TIMED(K_FROB, s, hipLaunchKernelGGL(frobenius_multi_kernel, dim3(multi_grid(set, 2u << log_n), set.count),
+                                           dim3(kThreads), 0, s, set, log_n));
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const ScatterSet& e, uint32_t count, uint32_t log_n, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  uint32_t rows = 0;
+  for (uint32_t r = 0; r < count; ++r) rows = std::max(rows, e.rows[r]);
+  const uint64_t per = ((uint64_t)rows << log_n) / 4;
+  const uint32_t gx = std::max<uint32_t>(1, std::min<uint32_t>(grid_for(per), 1024));
+  hipLaunchKernelGGL(scatter_kernel, dim3(gx, count), dim3(kThreads), 0, s, e, log_n - 2);
   return hipGetLastError();
 }
 
@@ -442,15 +490,15 @@ hipError_t launch_modup(const uint32_t* x, uint32_t* up, const ModConst* mods, c
   return hipGetLastError();
 }
 
-hipError_t launch_inner_product(const uint32_t* d2, const uint32_t* up, const KeySet& keys,
-                                uint32_t* acc0, uint32_t* acc1, const ModConst* mods,
-                                uint32_t alpha, uint32_t ndigits, uint32_t level, uint32_t L,
-                                uint32_t K, uint32_t batch, uint32_t log_n, hipStream_t s) {
-  const uint64_t total4 = ((uint64_t)(level + K) * batch << log_n) / 4;
-  TFHE_TIMED(K_INNER, s, hipLaunchKernelGGL(inner_product_kernel, dim3(grid_for(total4)), dim3(kThreads), 0, s,
-                                            (const uint4*)d2, (const uint4*)up, keys,
-                                            (uint4*)acc0, (uint4*)acc1, mods, alpha, ndigits, level, L, K,
-                                            batch, log_n));
+hipError_t launch_inner_product(const IpSet& set, const ModConst* mods, uint32_t log_n, hipStream_t s) {
+  if (set.count == 0) return hipSuccess;
+  uint64_t most = 0;  // the largest group's elements (16 bytes each)
+  for (uint32_t g = 0; g < set.count; ++g)
+    most = std::max<uint64_t>(most, ((uint64_t)(set.g[g].level + set.K) * set.g[g].batch << log_n) / 4);
+  // one block column per group; about 16384 blocks over the whole launch
+  const uint32_t gx = std::max<uint32_t>(1, std::min<uint32_t>(grid_for(most), std::max<uint32_t>(64, 16384 / set.count)));
+  TFHE_TIMED(K_INNER, s, hipLaunchKernelGGL(inner_product_kernel, dim3(gx, set.count), dim3(kThreads), 0, s, set,
+                                            mods, log_n));
   return hipGetLastError();
 }
 

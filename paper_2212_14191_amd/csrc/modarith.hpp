@@ -72,6 +72,24 @@ TFHE_HD uint32_t mul_mod(uint32_t a, uint32_t b, const ModConst& c) {
   return mul_shoup(mont_mul(a, b, c.q, c.qneg), c.r, c.rp, c.q);
 }
 
+// Sums of products of residues (a, b < q < 2^31) kept as 64-bit values
+// below q 2^32: s + a b < q 2^32 + q^2 < 2^64, and when the high word
+// reaches q (it is then below 2q) taking q off it restores the bound.
+TFHE_HD uint64_t mac_lazy(uint64_t s, uint32_t a, uint32_t b, uint32_t q) {
+  const uint64_t v = (uint64_t)a * b + s;
+  const uint32_t hi = (uint32_t)(v >> 32);
+  const uint32_t h2 = hi - q;
+  return ((uint64_t)(h2 < hi ? h2 : hi) << 32) | (uint32_t)v;
+}
+
+// s mod q for s < q 2^32: one Montgomery step (s + m q < 2q 2^32 is a
+// multiple of 2^32), then the factor 2^32 restored by Shoup.
+TFHE_HD uint32_t reduce_lazy(uint64_t s, const ModConst& c) {
+  const uint32_t m = (uint32_t)s * c.qneg;
+  const uint32_t t = (uint32_t)(((uint64_t)m * c.q + s) >> 32);
+  return mul_shoup(reduce_once(t, c.q), c.r, c.rp, c.q);
+}
+
 // Balanced digits of z in [-0x80808080, 0x7F7F7F7F], packed as 4 int8.
 TFHE_HD uint32_t balanced_digits(int32_t z) {
   return ((uint32_t)z + 0x80808080u) ^ 0x80808080u;

@@ -49,6 +49,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <atomic>
+
 #include "ckks_internal.hpp"
 #include "fourstep_dev.hpp"
 
@@ -460,35 +462,34 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 // ---------------------------------------------------------------------------
 // Second pass of the ModUp forward transforms fused with the key inner
 // product (Sec. IV-A, Table 2: NTT, then Inner-product): a workgroup takes
-// one extended-basis position t, batch element b and column block (an
-// "item"), and for every digit j (a "task") either runs the second pass
-// (the 256-point stage, narrow 16-vector item) on digit j's tiled
+// one level group's extended-basis position t, batch element b and column
+// block (an "item"), and for every digit j (a "task") either runs the second
+// pass (the 256-point stage, narrow 16-vector item) on digit j's tiled
 // intermediate of t, or, for the digit that holds t, takes d2[t] as it is;
 // it multiplies the result by evk_j[c][t] at its natural positions and, after
 // the last digit, writes acc_0 and acc_1 once.  The transformed limbs are
 // never written: the separate transform store and the inner product's re-read
-// of them disappear.  Products are summed as Montgomery residues
-// (x k 2^{-32}) and scaled by 2^32 once at the end; every quantity is exact,
-// so the result equals the unfused sequence bit for bit.
+// of them disappear.  Products are summed as 64-bit values kept below
+// q 2^32 and reduced once per output; every quantity is exact, so the
+// result equals the unfused sequence bit for bit.  Items of all level groups
+// form one sequence (group g from item0): one launch for a mixed-level batch.
 // Pipelining: the task's source (tile or d2) and its two key blocks arrive
 // by direct-to-LDS loads; the next task's source is issued into the other
 // buffer as soon as this task's has landed, so one load is always in flight
 // behind the arithmetic.  Keys and d2 are loaded into each wave's own slots
 // of the output layout (slot (4 wave + j, lane) = natural positions st_off).
 __global__ void __launch_bounds__(256, 2)
-ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* __restrict__ mods,
-        uint32_t log_n, uint32_t ipp) {
+ip_pass(const IpSet set, const FourStepLimb* __restrict__ limbs, const ModConst* __restrict__ mods,
+        uint32_t log_n, uint32_t ipp, uint32_t items) {
   using G = Geo<false, 16, false>;
   // two source buffers, then the key blocks of components 0 and 1
   __shared__ __attribute__((aligned(16))) uint32_t lds[4 * G::tile];
   uint32_t* const kbuf = lds + 2 * G::tile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g = lane >> 4;
-  const uint32_t ext = a.level + a.K;
   const uint64_t N = 1ull << log_n;
   const uint32_t S = (uint32_t)(N >> 8);  // second-pass columns (rows of the first)
-  const uint32_t items = ext * ipp * a.batch;
-  const uint64_t kplane = (uint64_t)(a.L + a.K) * N;  // one key component
+  const uint64_t kplane = (uint64_t)(set.L + set.K) * N;  // one key component
   // per-lane offsets within a polynomial for column block blk
   auto offsets = [&](uint32_t blk, uint32_t* ld, uint32_t* st) {
     const uint32_t c0 = blk * G::W;
@@ -500,16 +501,20 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
     }
   };
   struct Pos {
-    uint32_t b, blk, t, pl, own;
+    uint32_t grp, b, blk, t, pl, own;
   };
   auto pos_of = [&](uint32_t w) {
     Pos p;
-    p.b = w % a.batch;
-    const uint32_t tb = w / a.batch;
+    p.grp = 0;
+    while (p.grp + 1 < set.count && set.g[p.grp + 1].item0 <= w) ++p.grp;
+    const IpGroup& Gr = set.g[p.grp];
+    const uint32_t l = w - Gr.item0;
+    p.b = l % Gr.batch;
+    const uint32_t tb = l / Gr.batch;
     p.blk = tb % ipp;
     p.t = tb / ipp;
-    p.pl = p.t < a.level ? p.t : a.L + (p.t - a.level);  // plan limb
-    p.own = p.t < a.level ? p.t / a.alpha : 0xFFFFFFFFu;
+    p.pl = p.t < Gr.level ? p.t : set.L + (p.t - Gr.level);  // plan limb
+    p.own = p.t < Gr.level ? p.t / set.alpha : 0xFFFFFFFFu;
     return p;
   };
   // 16 bytes per lane into this wave's slot (4 wave + j) of `dst` (output layout)
@@ -525,23 +530,22 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
           : "memory", "m0");
     }
   };
-  // the source of task (item w, digit jd) into buffer buf: 4 loads per lane
-  auto issue_source = [&](uint32_t w, uint32_t jd, int buf) {
-    const Pos p = pos_of(w);
+  // the source of task (position p, digit jd) into buffer buf: 4 loads per lane
+  auto issue_source = [&](const Pos& p, uint32_t jd, int buf) {
+    const IpGroup& Gr = set.g[p.grp];
+    const uint32_t ext = Gr.level + set.K;
     uint32_t ld[4], st[4];
     offsets(p.blk, ld, st);
     if (jd == p.own)
-      load_slots(a.d2 + ((uint64_t)p.t * a.batch + p.b) * N, st, lds + buf * G::tile);
+      load_slots(Gr.d2 + ((uint64_t)p.t * Gr.batch + p.b) * N, st, lds + buf * G::tile);
     else
-      issue_tile<G::pitch>(a.inter + ((uint64_t)(jd * ext + p.t) * a.batch + p.b) * N, ld, lds + buf * G::tile,
+      issue_tile<G::pitch>(Gr.src + ((uint64_t)(jd * ext + p.t) * Gr.batch + p.b) * N, ld, lds + buf * G::tile,
                            wave);
   };
 
-  const uint32_t tasks_per_item = a.digits;
-  const uint32_t my_items = blockIdx.x < items ? (items - 1 - blockIdx.x) / gridDim.x + 1 : 0;
-  const uint32_t ntasks = my_items * tasks_per_item;
-  if (ntasks == 0) return;
-  auto task_item = [&](uint32_t k) { return blockIdx.x + (k / tasks_per_item) * gridDim.x; };
+  uint32_t w = blockIdx.x, jd = 0;
+  if (w >= items) return;
+  Pos p = pos_of(w);
 
   const FourStepLimb* cur = nullptr;
   v4i opA[4], opB[4];
@@ -550,13 +554,18 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
   uint64_t cq = 0;
   ModConst m{};
   uint64_t s0[4][4], s1[4][4];  // sums of products, kept below q 2^32
-  issue_source(task_item(0), 0, 0);
+  issue_source(p, 0, 0);
   bool stored_after = false;  // the previous task ended its item (8 stores after this source)
-  for (uint32_t k = 0; k < ntasks; ++k) {
-    const int cb = k & 1;
+  for (int cb = 0;; cb ^= 1) {
     uint32_t* const src = lds + cb * G::tile;
-    const uint32_t w = task_item(k), jd = k % tasks_per_item;
-    const Pos p = pos_of(w);
+    const IpGroup& Gr = set.g[p.grp];
+    // the task after this one: the next digit, else the next item
+    uint32_t nw = w, njd = jd + 1;
+    if (njd == Gr.digits) {
+      nw = w + gridDim.x;
+      njd = 0;
+    }
+    const bool next = nw < items;
     uint32_t ld[4], st[4];
     offsets(p.blk, ld, st);
     // this task's source: issued before the previous task's stores (if any)
@@ -583,12 +592,15 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
     }
     lds_barrier();  // the source is in LDS; every wave is done with the other buffer and the keys
     // this task's keys, then the next task's source
-    const uint32_t* key = a.keys.k[a.keys.count == 1 ? 0 : p.b];
+    const uint32_t* key = set.keys.k[set.keys.count == 1 ? 0 : Gr.key0 + p.b];
     const uint32_t* krow = key + (uint64_t)jd * 2 * kplane + (uint64_t)p.pl * N;
     load_slots(krow, st, kbuf);
     load_slots(krow + kplane, st, kbuf + G::tile);
-    const bool next = k + 1 < ntasks;
-    if (next) issue_source(task_item(k + 1), (k + 1) % tasks_per_item, cb ^ 1);
+    Pos np = p;
+    if (next) {
+      if (nw != w) np = pos_of(nw);
+      issue_source(np, njd, cb ^ 1);
+    }
     if (jd == 0) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
@@ -669,15 +681,16 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
       mac(s0[j], y, *(const v4u*)(kbuf + slot));
       mac(s1[j], y, *(const v4u*)(kbuf + G::tile + slot));
     }
-    stored_after = jd + 1 == tasks_per_item;
+    stored_after = jd + 1 == Gr.digits;
     if (stored_after) {
       // s mod q: one Montgomery step (s + m q < 2q 2^32), then times 2^32
       auto fin = [&](uint64_t v) {
         const uint32_t mm = (uint32_t)v * qneg;
         return mul_shoup(reduce_once((uint32_t)(mad_u64(mm, q, v) >> 32), q), m.r, m.rp, q);
       };
-      uint32_t* o0 = a.acc + ((uint64_t)p.t * a.batch + p.b) * N;
-      uint32_t* o1 = a.acc + ((uint64_t)(ext + p.t) * a.batch + p.b) * N;
+      const uint32_t ext = Gr.level + set.K;
+      uint32_t* o0 = Gr.acc + ((uint64_t)p.t * Gr.batch + p.b) * N;
+      uint32_t* o1 = Gr.acc + ((uint64_t)(ext + p.t) * Gr.batch + p.b) * N;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const v4u r0 = {fin(s0[j][0]), fin(s0[j][1]), fin(s0[j][2]), fin(s0[j][3])};
@@ -686,6 +699,10 @@ ip_pass(const IpArgs a, const FourStepLimb* __restrict__ limbs, const ModConst* 
         __builtin_nontemporal_store(r1, (v4u*)(o1 + st[j]));
       }
     }
+    if (!next) break;
+    w = nw;
+    jd = njd;
+    p = np;
   }
 }
 
@@ -948,19 +965,27 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
   return hipGetLastError();
 }
 
-hipError_t ip_run(const tfhe_ntt_plan_s* p, const IpArgs& a, hipStream_t s) {
-  if (!p->has_mfma || a.batch == 0) return a.batch == 0 ? hipSuccess : hipErrorInvalidValue;
+hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
+  if (set.count == 0) return hipSuccess;
+  if (!p->has_mfma) return hipErrorInvalidValue;
   using G = Geo<false, 16, false>;
   const uint32_t ipp = p->n / G::item;  // second-pass items per polynomial
-  static int occ = 0;
-  if (occ == 0) {
+  static std::atomic<int> occ{0};
+  if (occ.load() == 0) {
     int k = 0;
     occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, ip_pass, G::threads, 0) == hipSuccess && k > 0 ? k : 1;
   }
-  const uint64_t work = (uint64_t)(a.level + a.K) * ipp * a.batch;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(work, (uint64_t)p->num_cus * occ);
+  uint64_t items = 0;
+  for (uint32_t g = 0; g < set.count; ++g) {
+    set.g[g].item0 = (uint32_t)items;
+    items += (uint64_t)(set.g[g].level + set.K) * ipp * set.g[g].batch;
+  }
+  if (items == 0) return hipSuccess;
+  if (items >= (1ull << 32)) return hipErrorInvalidValue;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(items, (uint64_t)p->num_cus * occ.load());
   TFHE_TIMED(K_IP, s,
-             hipLaunchKernelGGL(ip_pass, dim3(grid), dim3(G::threads), 0, s, a, p->d_fs_fwd, p->d_mod, p->log_n, ipp));
+             hipLaunchKernelGGL(ip_pass, dim3(grid), dim3(G::threads), 0, s, set, p->d_fs_fwd, p->d_mod, p->log_n,
+                                ipp, (uint32_t)items));
   return hipGetLastError();
 }
 

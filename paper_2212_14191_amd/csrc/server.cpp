@@ -4,13 +4,13 @@
 //
 // Each of `slots` worker threads owns a HIP stream and an equal share of the
 // caller's memory pool.  Pending requests are indexed by batching key (op,
-// N, level); whenever a worker is free, the oldest request and up to
-// max_batch - 1 others of its key form a batch whose result buffer and
-// workspace fit the worker's share (otherwise the batch is halved until it
-// fits).  A batch of one runs in place on the request's own buffers; a
-// larger one reads its inputs where they are (through a table of
-// per-request pointers), computes into a result buffer in the (component,
-// limb, batch, coefficient) layout and is scattered back.  Rotations by
+// N, context): a batch may mix levels (operation-level batching across
+// levels, Sec. IV-D).  Whenever a worker is free, the oldest request and up
+// to max_batch - 1 later ones of its key form a batch whose workspace fits
+// the worker's share (otherwise the batch is halved until it fits).  A batch
+// of one runs in place on the request's own buffers; a larger one runs as
+// one mixed-level launch sequence (levels_run) that reads its inputs where
+// they are and copies each result out to its request.  Rotations by
 // different amounts share a batch (one key and Galois element per
 // ciphertext).  Every request waits for an event recorded on its
 // submitter's stream at submission.  Completed tags are collected by
@@ -31,32 +31,6 @@
 namespace tfhe {
 namespace {
 
-constexpr int kThreads = 256;
-
-// Copies a batch result [2][level][B][N] out to the requests' own
-// ciphertexts [2][level][N] (dst[b]); one element = 16 bytes, rows =
-// 2 level (component, limb).
-struct OutPtrs {
-  uint32_t* p[kMaxRotBatch];
-};
-
-__global__ void __launch_bounds__(kThreads)
-scatter_kernel(const uint4* __restrict__ src, const OutPtrs dst, uint32_t rows, uint32_t batch, uint32_t n4) {
-  const uint64_t total = (uint64_t)rows * batch * n4;
-  for (uint64_t i = blockIdx.x * (uint64_t)kThreads + threadIdx.x; i < total;
-       i += (uint64_t)gridDim.x * kThreads) {
-    const uint32_t k = (uint32_t)(i % n4);
-    const uint64_t rb = i / n4;
-    const uint32_t b = (uint32_t)(rb % batch), row = (uint32_t)(rb / batch);
-    ((uint4*)dst.p[b])[(uint64_t)row * n4 + k] = src[i];
-  }
-}
-
-uint32_t copy_grid(uint64_t items) {
-  const uint64_t blocks = (items + kThreads - 1) / kThreads;
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(blocks, 4096));
-}
-
 struct Req {
   uint32_t op, log_n, level, galois;
   const uint32_t *a, *b;
@@ -68,12 +42,12 @@ struct Req {
 };
 
 struct Key {
-  uint32_t op, log_n, level;
+  uint32_t op, log_n;
   tfhe_ckks_ctx ctx;  // requests submitted before a context was replaced batch apart
-  bool operator<(const Key& o) const {
-    return std::tie(op, log_n, level, ctx) < std::tie(o.op, o.log_n, o.level, o.ctx);
-  }
+  bool operator<(const Key& o) const { return std::tie(op, log_n, ctx) < std::tie(o.op, o.log_n, o.ctx); }
 };
+
+LvReq lv(const Req& r) { return LvReq{r.a, r.b, r.out, r.key, r.level, r.galois}; }
 
 struct Slot {
   hipStream_t s = nullptr;
@@ -112,13 +86,19 @@ struct tfhe_server_s {
   bool stop = false;
   std::vector<std::thread> workers;
 
-  // slot memory a batch of B requests like r needs
-  static size_t need(const Req& r, uint32_t B) {
-    const size_t ct = (size_t)2 * r.level * B * ((size_t)1 << r.log_n) * 4;
-    size_t ws = 0;
-    tfhe_hmult_workspace_size(r.ctx, r.level, B, &ws);
-    const size_t staging = B > 1 ? align256(ct) : 0;  // the batch result
-    return staging + align256(ws);
+  // slot memory the batch of the B requests from `first` needs: a batch of
+  // one runs in place with tfhe_hmult's workspace
+  template <typename It>
+  static size_t need(It first, uint32_t B) {
+    const tfhe_ckks_ctx ctx = first->ctx;
+    if (B == 1) {
+      size_t ws = 0;
+      tfhe_hmult_workspace_size(ctx, first->level, 1, &ws);
+      return align256(ws);
+    }
+    std::vector<LvReq> r;
+    for (uint32_t k = 0; k < B; ++k, ++first) r.push_back(lv(*first));
+    return align256(levels_ws_bytes(ctx, r.data(), B));
   }
   // a request holding e is done with it (caller holds mu)
   void release_event(hipEvent_t e) {
@@ -136,47 +116,29 @@ struct tfhe_server_s {
 
 int tfhe_server_s::launch(Slot& sl, std::vector<Req>& reqs) {
   const Req& r0 = reqs[0];
-  const uint32_t B = (uint32_t)reqs.size(), level = r0.level, n = 1u << r0.log_n;
+  const uint32_t B = (uint32_t)reqs.size();
   hipEvent_t waited = nullptr;  // requests submitted together share one event
   for (const Req& r : reqs) {
     if (r.ready == waited) continue;
     if (hipStreamWaitEvent(sl.s, r.ready, 0) != hipSuccess) return TFHE_EHIP;
     waited = r.ready;
   }
-  size_t ws_bytes = 0;
-  tfhe_hmult_workspace_size(r0.ctx, level, B, &ws_bytes);
-  bool same = true;  // one Galois element for the whole batch
-  for (const Req& r : reqs) same = same && r.galois == r0.galois;
   if (B == 1) {
     // in place on the request's own buffers, through the public entry points
+    size_t ws_bytes = 0;
+    tfhe_hmult_workspace_size(r0.ctx, r0.level, 1, &ws_bytes);
     void* ws = sl.mem;
     tfhe_status st = r0.op == 0
-        ? tfhe_hmult(r0.ctx, r0.a, r0.b, r0.out, r0.key, level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s)
-        : tfhe_rotate(r0.ctx, r0.a, r0.out, r0.key, r0.galois, level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s);
+        ? tfhe_hmult(r0.ctx, r0.a, r0.b, r0.out, r0.key, r0.level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s)
+        : tfhe_rotate(r0.ctx, r0.a, r0.out, r0.key, r0.galois, r0.level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s);
     if (st != TFHE_OK) return st;
   } else {
-    // inputs read where they are; the result goes to the slot's staging
-    // buffer in the batch layout, then out to each request
-    uint32_t* out = (uint32_t*)sl.mem;
-    unsigned char* ws = sl.mem + align256((size_t)2 * level * B * n * 4);
-    CtPtrs a{}, b{};
-    KeySet keys{};
-    GaloisSet gs{};
-    for (uint32_t k = 0; k < B; ++k) {
-      a.p[k] = reqs[k].a;
-      b.p[k] = reqs[k].b;
-      keys.k[k] = reqs[k].key;
-      gs.g[k] = reqs[k].galois;
-    }
-    keys.count = gs.batch = (r0.op == 1 && !same) ? B : 1;
-    const hipError_t e = r0.op == 0 ? hmult_ptrs(r0.ctx, a, b, out, r0.key, level, B, ws, sl.s)
-                                    : rotate_ptrs(r0.ctx, a, out, keys, gs, level, B, ws, sl.s);
-    if (e != hipSuccess) return fail(TFHE_EHIP, "server: batch launch failed");
-    OutPtrs dst{};
-    for (uint32_t k = 0; k < B; ++k) dst.p[k] = reqs[k].out;
-    const uint32_t rows = 2 * level, n4 = n / 4;
-    hipLaunchKernelGGL(scatter_kernel, dim3(copy_grid((uint64_t)rows * B * n4)), dim3(kThreads), 0, sl.s,
-                       (const uint4*)out, dst, rows, B, n4);
+    // one launch sequence for the whole batch, whatever its levels; the
+    // inputs are read where they are and each result is copied out
+    std::vector<LvReq> r;
+    for (const Req& q : reqs) r.push_back(lv(q));
+    if (levels_run(r0.ctx, r0.op, r.data(), B, sl.mem, sl.s) != hipSuccess)
+      return fail(TFHE_EHIP, "server: batch launch failed");
   }
   if (hipGetLastError() != hipSuccess) return TFHE_EHIP;
   if (hipEventRecord(sl.done, sl.s) != hipSuccess) return TFHE_EHIP;
@@ -198,13 +160,24 @@ bool tfhe_server_s::take(const Slot& sl, std::vector<Req>& reqs) {
   std::deque<Req>& q = pending[key];
   auto ci = ctxs.find(key.log_n);
   const uint32_t mb = ci != ctxs.end() && ci->second.max_batch ? ci->second.max_batch : max_batch;
-  uint32_t B = std::min<uint32_t>((uint32_t)q.size(), mb);
-  while (B > 1 && need(q.front(), B) > sl.bytes) B /= 2;
-  if (need(q.front(), B) > sl.bytes) return false;  // cannot happen: submission checks one request
-  reqs.assign(q.begin(), q.begin() + B);
-  q.erase(q.begin(), q.begin() + B);
+  // the oldest request, then the others of its level, then the rest (each
+  // group in arrival order): fewer level groups per batch, fewer launches
+  std::vector<size_t> pick{0};
+  const uint32_t lv = q.front().level;
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t i = 1; i < q.size() && pick.size() < mb; ++i)
+      if ((q[i].level == lv) == (pass == 0)) pick.push_back(i);
+  std::vector<Req> cand;
+  for (size_t i : pick) cand.push_back(q[i]);
+  uint32_t B = (uint32_t)cand.size();
+  while (B > 1 && need(cand.begin(), B) > sl.bytes) B /= 2;
+  if (need(cand.begin(), B) > sl.bytes) return false;  // cannot happen: submission checks one request
+  reqs.assign(cand.begin(), cand.begin() + B);
+  std::vector<size_t> gone(pick.begin(), pick.begin() + B);
+  std::sort(gone.rbegin(), gone.rend());
+  for (size_t i : gone) q.erase(q.begin() + i);
   if (q.empty()) pending.erase(key);
-  order.pop_front();
+  order.pop_front();  // the requests taken from further back leave stale entries
   return true;
 }
 
@@ -253,7 +226,7 @@ tfhe_status tfhe_server_s::check(const tfhe_server_request& q, Req& out) {
     key = k->second;
   }
   out = Req{q.op, q.log_n, q.level, q.galois_elt, q.ct_a, q.ct_b, q.ct_out, q.tag, 0, nullptr, c.ctx, key};
-  if (need(out, 1) > slots[0].bytes)
+  if (need(&out, 1) > slots[0].bytes)
     return fail(TFHE_ENOMEM, "server_submit: one request exceeds a slot's share of the pool");
   return TFHE_OK;
 }
@@ -359,7 +332,7 @@ tfhe_status tfhe_server_submit_many(tfhe_server s, const tfhe_server_request* re
     std::lock_guard<std::mutex> g(s->mu);
     s->ev_refs[ev] = count;
     for (Req& r : batch) {
-      const Key k{r.op, r.log_n, r.level, r.ctx};
+      const Key k{r.op, r.log_n, r.ctx};
       r.seq = s->next_seq++;
       r.ready = ev;
       s->pending[k].push_back(r);

@@ -3,9 +3,12 @@ Sec. IV-E: requests are collected, decomposed into batched kernel workflows
 and dispatched; keys and ciphertexts stay resident in HBM).
 
 A scheduler thread keeps up to `slots` batches in flight, each on its own
-HIP stream.  Pending requests are grouped by (op, N, level): rotations by
-different amounts share a batch (each ciphertext with its own Galois element
-and key, one batched launch sequence);
+HIP stream.  Pending requests are grouped by (op, N) when the backend runs
+batches of mixed levels (operation-level batching across levels, Sec. IV-D;
+the GPU backend does, through tfhe_hmult_levels / tfhe_rotate_levels), else
+by (op, N, level); rotations by different amounts share a batch (each
+ciphertext with its own Galois element and key, one batched launch
+sequence);
 whenever a slot is free, the oldest pending request and up to max_batch - 1
 compatible ones form a batch, provided its device memory (staged inputs,
 outputs, workspace) fits the remaining budget; otherwise admission waits
@@ -40,10 +43,10 @@ class Request:
         self.deadline = None if timeout_s is None else self.t_submit + timeout_s
         self.ready = None  # backend-specific readiness marker of the inputs
 
-    @property
-    def key(self):
-        """Batching key: rotations by different amounts batch together."""
-        return (self.op, self.log_n, self.level)
+    def key(self, mix_levels):
+        """Batching key: rotations by different amounts batch together, and
+        levels too where the backend mixes them."""
+        return (self.op, self.log_n) if mix_levels else (self.op, self.log_n, self.level)
 
 
 class Server:
@@ -56,6 +59,9 @@ class Server:
         self.max_batch = min(int(max_batch), cap)
         # per-N limits (the autotuner's choice, autotune.serving_batches)
         self.max_batch_by_n = {int(k): max(1, min(int(v), cap)) for k, v in (max_batch_by_n or {}).items()}
+        # a backend that runs batches of mixed levels says so and sizes them
+        # with batch_nbytes(requests)
+        self.mix = bool(getattr(backend, "mixes_levels", False))
         self.poll_s = poll_s
         self._pending = collections.OrderedDict()  # id -> Request (FIFO)
         self._by_key = {}                           # batching key -> deque of ids (FIFO)
@@ -92,7 +98,7 @@ class Server:
             if self._t0 is None:
                 self._t0 = req.t_submit
             self._pending[self._next_id] = req
-            self._by_key.setdefault(req.key, collections.deque()).append(self._next_id)
+            self._by_key.setdefault(req.key(self.mix), collections.deque()).append(self._next_id)
             if req.deadline is not None:
                 heapq.heappush(self._deadlines, (req.deadline, self._next_id))
             self._next_id += 1
@@ -143,10 +149,11 @@ class Server:
     def _drop(self, rid):
         """Remove a cancelled or timed-out request from the queue."""
         r = self._pending.pop(rid)
-        q = self._by_key[r.key]
+        k = r.key(self.mix)
+        q = self._by_key[k]
         q.remove(rid)
         if not q:
-            del self._by_key[r.key]
+            del self._by_key[k]
         if not r.future.cancelled():
             r.future.set_exception(TimeoutError("request timed out in the queue"))
 
@@ -169,13 +176,20 @@ class Server:
             return None
         ids = []
         limit = self.max_batch_by_n.get(head.log_n, self.max_batch)
-        for rid in self._by_key[head.key]:
-            if len(ids) == limit:
-                break
-            if not self._expired(self._pending[rid], now):
-                ids.append(rid)
+        # the oldest request, then the others of its level, then the rest
+        # (each in arrival order): fewer level groups per mixed batch
+        for same in ((True, False) if self.mix else (True,)):
+            for rid in self._by_key[head.key(self.mix)]:
+                if len(ids) == limit:
+                    break
+                r = self._pending[rid]
+                if (r.level == head.level) == same and not self._expired(r, now):
+                    ids.append(rid)
         while ids:
-            need = self.backend.nbytes(head.op, head.log_n, head.level, len(ids))
+            if self.mix:
+                need = self.backend.batch_nbytes([self._pending[i] for i in ids])
+            else:
+                need = self.backend.nbytes(head.op, head.log_n, head.level, len(ids))
             if self._used + need <= self.budget:
                 return ids, need
             if len(ids) == 1:
@@ -215,11 +229,12 @@ class Server:
                         break
                     ids, nbytes = fb
                     reqs = [self._pending.pop(rid) for rid in ids]
-                    q = self._by_key[reqs[0].key]
-                    for rid in ids:  # the batch is a FIFO prefix of its key's live ids
+                    k = reqs[0].key(self.mix)
+                    q = self._by_key[k]
+                    for rid in ids:
                         q.remove(rid)
                     if not q:
-                        del self._by_key[reqs[0].key]
+                        del self._by_key[k]
                     for r in reqs:
                         r.future.set_running_or_notify_cancel()
                     slot = self._free_slots.pop()
@@ -244,13 +259,15 @@ class Server:
 
 class GpuBackend:
     """Device backend: one CkksContext per N, resident keys, one HIP stream
-    per slot.  Inputs of a batch are staged into one [2][level][B][N] tensor
-    on the slot's stream (a single contiguous request is used in place);
-    HMULT / HROTATE run batched; the outputs are per-request views of the
-    batch output.  Each slot keeps one workspace, grown to the largest batch
-    it has run."""
+    per slot.  A request alone runs in place (tfhe_hmult / tfhe_rotate at
+    batch 1); a batch of several, whatever their levels, runs as one
+    mixed-level launch sequence (tfhe_hmult_levels / tfhe_rotate_levels) that
+    reads every input where it is and writes each request's own output
+    tensor.  Each slot keeps one workspace, grown to the largest batch it has
+    run."""
 
-    max_batch = 64  # tfhe_rotate_multi's limit
+    mixes_levels = True
+    max_batch = 64  # TFHE_HMULT_LEVELS_MAX
 
     def __init__(self, contexts, relin_keys, rot_keys, slots=4):
         import torch
@@ -295,37 +312,36 @@ class GpuBackend:
             b = self._wsb[k] = max(self.ctx[log_n].workspace_bytes(level, batch), 256)
         return b
 
-    def _workspace(self, slot, ctx, level, batch):
-        need = self._ws_bytes(ctx.log_n, level, batch)
+    def nbytes(self, op, log_n, level, batch):
+        """Device memory of a same-level batch of `batch` requests."""
+        n = 1 << log_n
+        ct = 2 * level * batch * n * 4
+        if batch == 1:  # in place: the output and the workspace
+            return ct + self._ws_bytes(log_n, level, 1)
+        return ct + max(self.ctx[log_n].levels_workspace_bytes([level] * batch), 256)
+
+    def batch_nbytes(self, reqs):
+        """Device memory of a batch of these requests (levels may differ):
+        their outputs and the workspace."""
+        r0 = reqs[0]
+        if len(reqs) == 1:
+            return self.nbytes(r0.op, r0.log_n, r0.level, 1)
+        levels = [r.level for r in reqs]
+        out = sum(2 * lv * (1 << r0.log_n) * 4 for lv in levels)
+        return out + max(self.ctx[r0.log_n].levels_workspace_bytes(levels), 256)
+
+    def _slot_ws(self, slot, need):
         w = self.ws[slot]
         if w is None or w.numel() < need:
             w = self.torch.empty(need, dtype=self.torch.uint8, device="cuda")
             self.ws[slot] = w
         return w
 
-    def _stage(self, reqs, attr, level, n):
-        """[2][level][B][N] input: a single contiguous request is used as is."""
-        torch = self.torch
-        if len(reqs) == 1:
-            t = getattr(reqs[0], attr)
-            if t.is_contiguous() and t.numel() == 2 * level * n:
-                return t.view(2, level, 1, n)
-        a = torch.empty((2, level, len(reqs), n), dtype=torch.int32, device="cuda")
-        for b, r in enumerate(reqs):
-            a[:, :, b].copy_(getattr(r, attr).reshape(2, level, n), non_blocking=True)
-        return a
-
-    def nbytes(self, op, log_n, level, batch):
-        n = 1 << log_n
-        ct = 2 * level * batch * n * 4
-        inputs = 2 * ct if op == HMULT else ct
-        return inputs + ct + self._ws_bytes(log_n, level, batch)
-
     def launch(self, slot, reqs):
         torch = self.torch
         r0 = reqs[0]
         ctx = self.ctx[r0.log_n]
-        B, level, n = len(reqs), r0.level, 1 << r0.log_n
+        B, n = len(reqs), 1 << r0.log_n
         s = self.streams[slot]
         # inputs ready: the latest submission event of each submitting stream
         # (events on one stream complete in order)
@@ -342,41 +358,46 @@ class GpuBackend:
                 s.wait_event(ev)
         # this thread only launches batches: allocations below belong to s
         torch.cuda.set_stream(s)
-        a = self._stage(reqs, "ct_a", level, n)
-        out = torch.empty((2, level, B, n), dtype=torch.int32, device="cuda")
-        ws = self._workspace(slot, ctx, level, B)
+        outs = [torch.empty((2, r.level, 1, n), dtype=torch.int32, device="cuda") for r in reqs]
         sp = self._sptr[slot]
-        # inputs were checked in prepare(): raw pointers into the C ABI
         tfhe = self.tfhe
-        if r0.op == HMULT:
-            bb = self._stage(reqs, "ct_b", level, n)
-            tfhe._call("tfhe_hmult", ctx.handle, a.data_ptr(), bb.data_ptr(), out.data_ptr(),
-                       self.evk[r0.log_n].data_ptr(), level, B, ws.data_ptr(), ws.numel(), sp)
-        else:
-            bb = None
-            gal = [r.galois for r in reqs]
-            if all(g == gal[0] for g in gal):
-                tfhe._call("tfhe_rotate", ctx.handle, a.data_ptr(), out.data_ptr(),
-                           self.rk[(r0.log_n, r0.galois)].data_ptr(), r0.galois, level, B, ws.data_ptr(),
-                           ws.numel(), sp)
+        # inputs were checked in prepare(): raw pointers into the C ABI
+        if B == 1:
+            level = r0.level
+            ws = self._slot_ws(slot, self._ws_bytes(r0.log_n, level, 1))
+            if r0.op == HMULT:
+                tfhe._call("tfhe_hmult", ctx.handle, r0.ct_a.data_ptr(), r0.ct_b.data_ptr(), outs[0].data_ptr(),
+                           self.evk[r0.log_n].data_ptr(), level, 1, ws.data_ptr(), ws.numel(), sp)
             else:
-                ctx.rotate_multi(a, [self.rk[(r0.log_n, g)] for g in gal], gal, level, out=out, ws=ws,
-                                 stream=s)
+                tfhe._call("tfhe_rotate", ctx.handle, r0.ct_a.data_ptr(), outs[0].data_ptr(),
+                           self.rk[(r0.log_n, r0.galois)].data_ptr(), r0.galois, level, 1, ws.data_ptr(),
+                           ws.numel(), sp)
+        else:
+            levels = [r.level for r in reqs]
+            ws = self._slot_ws(slot, max(ctx.levels_workspace_bytes(levels), 256))
+            view = lambda t, r: t.view(2, r.level, n)
+            if r0.op == HMULT:
+                ctx.hmult_levels([view(r.ct_a, r) for r in reqs], [view(r.ct_b, r) for r in reqs],
+                                 self.evk[r0.log_n], outs=[view(o, r) for o, r in zip(outs, reqs)], ws=ws, stream=s)
+            else:
+                ctx.rotate_levels([view(r.ct_a, r) for r in reqs], [self.rk[(r0.log_n, r.galois)] for r in reqs],
+                                  [r.galois for r in reqs], outs=[view(o, r) for o, r in zip(outs, reqs)], ws=ws,
+                                  stream=s)
         ev = self.events[slot]
         ev.record(s)
-        # the result block is allocated on s but read by the submitters on
-        # their streams: the caching allocator must not hand it out again on
-        # s before their work on it has finished
+        # the result tensors are allocated on s but read by the submitters on
+        # their streams: the caching allocator must not hand them out again
+        # on s before their work on them has finished
         users = {r.ready[0]: r.ready[2] for r in reqs if r.ready is not None}
         for st in users.values():
-            out.record_stream(st)
-        return {"event": ev, "out": out, "keep": (a, bb, ws), "B": B}
+            for o in outs:
+                o.record_stream(st)
+        return {"event": ev, "outs": outs, "keep": (ws, [(r.ct_a, r.ct_b) for r in reqs])}
 
     def done(self, h):
         return h["event"].query()
 
     def results(self, h):
-        """Per-request views of the batch output; the futures resolve after
-        the batch's device work has completed."""
-        out = h["out"]
-        return [out[:, :, b:b + 1] for b in range(h["B"])]
+        """Each request's own output [2][level][1][N]; the futures resolve
+        after the batch's device work has completed."""
+        return h["outs"]

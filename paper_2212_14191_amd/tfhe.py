@@ -86,6 +86,11 @@ def load():
         "tfhe_hmult_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
         "tfhe_hmult": ([vp, vp, vp, vp, vp, u32, u32, vp, sz, vp], i32),
         "tfhe_hmult_noalloc": ([vp, vp, vp, vp, vp, u32, u32, vp], i32),
+        "tfhe_hmult_levels_workspace_size": ([vp, pu32, u32, ctypes.POINTER(sz)], i32),
+        "tfhe_hmult_levels": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), pu32, u32, vp, vp, sz,
+                               vp], i32),
+        "tfhe_rotate_levels": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), pu32, pu32, u32, vp,
+                                sz, vp], i32),
         "tfhe_rotate": ([vp, vp, vp, vp, u32, u32, u32, vp, sz, vp], i32),
         "tfhe_rotate_multi": ([vp, vp, vp, ctypes.POINTER(vp), pu32, u32, u32, vp, sz, vp], i32),
         "tfhe_rescale_workspace_size": ([vp, u32, u32, ctypes.POINTER(sz)], i32),
@@ -395,6 +400,70 @@ class CkksContext:
         _call("tfhe_hmult", self.handle, _ptr(ct_a), _ptr(ct_b), _ptr(out), _ptr(evk), level, batch,
               _ptr(ws), ws.numel(), _stream(stream))
         return out
+
+    LEVELS_MAX = 64  # TFHE_HMULT_LEVELS_MAX
+
+    def levels_workspace_bytes(self, levels):
+        """Workspace of a mixed-level batch (tfhe_hmult_levels_workspace_size)."""
+        b = ctypes.c_size_t()
+        _call("tfhe_hmult_levels_workspace_size", self.handle, _u32_array(levels), len(levels), ctypes.byref(b))
+        return b.value
+
+    def levels_workspace(self, levels):
+        import torch
+        return torch.empty(max(self.levels_workspace_bytes(levels), 256), dtype=torch.uint8, device="cuda")
+
+    def hmult_levels(self, cts_a, cts_b, evk, outs=None, ws=None, stream=None):
+        """HMULT of pairs of different levels in one batched launch sequence
+        (tfhe_hmult_levels): cts_a[i], cts_b[i] are single ciphertexts, int32
+        [2][level_i][N]; returns the results (outs[i], same shapes)."""
+        if len(cts_a) != len(cts_b):
+            raise ValueError("one second operand per first operand")
+        levels = []
+        for a, b in zip(cts_a, cts_b):
+            if a.dim() != 3:
+                raise ValueError("hmult_levels takes single ciphertexts [2][level][N]")
+            lv = a.shape[1]
+            _check_residues(a, "ct_a", (2, lv, self.n))
+            _check_residues(b, "ct_b", (2, lv, self.n))
+            levels.append(lv)
+        _check_residues(evk, "evk", (self.dnum, 2, self.L + self.K, self.n))
+        if outs is None:
+            outs = [torch_empty_like(a) for a in cts_a]
+        for o, lv in zip(outs, levels):
+            _check_residues(o, "out", (2, lv, self.n))
+        if ws is None:
+            ws = self.levels_workspace(levels)
+        cnt = len(levels)
+        arr = lambda ts: (ctypes.c_void_p * max(cnt, 1))(*[t.data_ptr() for t in ts])
+        _call("tfhe_hmult_levels", self.handle, arr(cts_a), arr(cts_b), arr(outs), _u32_array(levels), cnt,
+              _ptr(evk), _ptr(ws), ws.numel(), _stream(stream))
+        return outs
+
+    def rotate_levels(self, cts, rotkeys, galois, outs=None, ws=None, stream=None):
+        """Ciphertext i (int32 [2][level_i][N]) rotated by galois[i] with
+        rotkeys[i], all in one batched launch sequence (tfhe_rotate_levels)."""
+        if len(rotkeys) != len(cts) or len(galois) != len(cts):
+            raise ValueError("one rotation key and one Galois element per ciphertext")
+        levels = []
+        for c in cts:
+            if c.dim() != 3:
+                raise ValueError("rotate_levels takes single ciphertexts [2][level][N]")
+            _check_residues(c, "ct", (2, c.shape[1], self.n))
+            levels.append(c.shape[1])
+        for k in rotkeys:
+            _check_residues(k, "rotkey", (self.dnum, 2, self.L + self.K, self.n))
+        if outs is None:
+            outs = [torch_empty_like(c) for c in cts]
+        for o, lv in zip(outs, levels):
+            _check_residues(o, "out", (2, lv, self.n))
+        if ws is None:
+            ws = self.levels_workspace(levels)
+        cnt = len(levels)
+        arr = lambda ts: (ctypes.c_void_p * max(cnt, 1))(*[t.data_ptr() for t in ts])
+        _call("tfhe_rotate_levels", self.handle, arr(cts), arr(outs), arr(rotkeys), _u32_array(galois),
+              _u32_array(levels), cnt, _ptr(ws), ws.numel(), _stream(stream))
+        return outs
 
     def rotate(self, ct, rotkey, galois, level, out=None, ws=None, stream=None):
         _, lv, batch, n = ct.shape

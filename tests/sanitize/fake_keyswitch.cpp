@@ -17,6 +17,7 @@ using namespace tfhe;
 // batched calls seen (B > 1), read by the driver; each call also takes a
 // little time, as a launch would, so that requests queue up into batches
 std::atomic<int> fake_batched_calls{0};
+std::atomic<int> fake_mixed_calls{0};  // batches holding more than one level
 static void pause() { std::this_thread::sleep_for(std::chrono::microseconds(50)); }
 
 extern "C" tfhe_status tfhe_hmult_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch, size_t* bytes) {
@@ -45,30 +46,27 @@ extern "C" tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* in, uint32
 
 namespace tfhe {
 
-// batch layout [2][level][batch][N]; request b's input [2][level][N]
-hipError_t hmult_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& a, const CtPtrs& b, uint32_t* out,
-                      const uint32_t* evk, uint32_t level, uint32_t batch, unsigned char*, hipStream_t) {
-  pause();
-  if (batch > 1) ++fake_batched_calls;
-  const size_t n = c->n;
-  for (uint32_t r = 0; r < 2 * level; ++r)
-    for (uint32_t k = 0; k < batch; ++k)
-      for (size_t i = 0; i < n; ++i)
-        out[((size_t)r * batch + k) * n + i] = a.p[k][r * n + i] + 2 * b.p[k][r * n + i] + evk[0];
-  return hipSuccess;
+size_t levels_ws_bytes(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count) {
+  size_t b = 256;
+  for (uint32_t k = 0; k < count; ++k) b += (size_t)2 * r[k].level * c->n * 4;
+  return b;
 }
 
-hipError_t rotate_ptrs(const tfhe_ckks_ctx_s* c, const CtPtrs& in, uint32_t* out, const KeySet& keys,
-                       const GaloisSet& gs, uint32_t level, uint32_t batch, unsigned char*, hipStream_t) {
+// each request's result written straight to its own buffer
+hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uint32_t count, unsigned char*,
+                      hipStream_t) {
   pause();
-  if (batch > 1) ++fake_batched_calls;
-  const size_t n = c->n;
-  for (uint32_t r = 0; r < 2 * level; ++r)
-    for (uint32_t k = 0; k < batch; ++k) {
-      const uint32_t key0 = keys.k[keys.count == 1 ? 0 : k][0];
-      for (size_t i = 0; i < n; ++i)
-        out[((size_t)r * batch + k) * n + i] = 3 * in.p[k][r * n + i] + gs.g[k % gs.batch] + key0;
+  if (count > 1) ++fake_batched_calls;
+  for (uint32_t k = 1; k < count; ++k)
+    if (r[k].level != r[0].level) {
+      ++fake_mixed_calls;
+      break;
     }
+  for (uint32_t k = 0; k < count; ++k) {
+    const size_t n = (size_t)2 * r[k].level * c->n;
+    for (size_t i = 0; i < n; ++i)
+      r[k].out[i] = op == 0 ? r[k].a[i] + 2 * r[k].b[i] + r[k].key[0] : 3 * r[k].a[i] + r[k].galois + r[k].key[0];
+  }
   return hipSuccess;
 }
 

@@ -43,24 +43,21 @@ hipError_t load_small_launch(const ModConst*, const int32_t*, uint32_t*, uint32_
                              hipStream_t) TFHE_STUB()
 hipError_t launch_tensor(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, const ModConst*, uint32_t,
                          uint32_t, uint32_t, hipStream_t) TFHE_STUB()
-hipError_t launch_tensor_ptrs(const CtPtrs&, const CtPtrs&, uint32_t*, uint32_t*, const ModConst*, uint32_t,
-                              uint32_t, uint32_t, hipStream_t) TFHE_STUB()
+hipError_t launch_tensor_multi(const CtDescSet&, const ModConst*, uint32_t, hipStream_t) TFHE_STUB()
 hipError_t launch_modup(const uint32_t*, uint32_t*, const ModConst*, const uint2*, const uint2*, uint32_t,
                         uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t) TFHE_STUB()
-hipError_t launch_inner_product(const uint32_t*, const uint32_t*, const KeySet&, uint32_t*, uint32_t*,
-                                const ModConst*, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
-                                uint32_t, hipStream_t) TFHE_STUB()
+hipError_t launch_inner_product(const IpSet&, const ModConst*, uint32_t, hipStream_t) TFHE_STUB()
 hipError_t launch_moddown_conv(const uint32_t*, uint32_t*, const ModConst*, const uint2*, const uint2*, uint32_t,
                                uint32_t, uint32_t, uint32_t, uint32_t, hipStream_t) TFHE_STUB()
 hipError_t launch_moddown_final(const uint32_t*, const uint32_t*, uint32_t*, const ModConst*, const uint2*,
                                 uint32_t, uint32_t, uint32_t, bool, hipStream_t, KernelId) TFHE_STUB()
 hipError_t launch_frobenius_pair(const uint32_t*, uint32_t*, const uint32_t*, uint32_t*, const GaloisSet&,
                                  uint32_t, uint32_t, hipStream_t) TFHE_STUB()
-hipError_t launch_frobenius_pair_ptrs(const CtPtrs&, uint32_t*, uint32_t*, const GaloisSet&, uint32_t, uint32_t,
-                                      uint32_t, hipStream_t) TFHE_STUB()
+hipError_t launch_frobenius_multi(const CtDescSet&, uint32_t, hipStream_t) TFHE_STUB()
 hipError_t launch_rescale_bcast(const uint32_t*, uint32_t*, const ModConst*, uint32_t, uint32_t, uint32_t,
                                 hipStream_t) TFHE_STUB()
 hipError_t ConvQueue::flush(uint32_t, KernelId, hipStream_t) TFHE_STUB()
-hipError_t ip_run(const tfhe_ntt_plan_s*, const IpArgs&, hipStream_t) TFHE_STUB()
+hipError_t ip_run(const tfhe_ntt_plan_s*, IpSet&, hipStream_t) TFHE_STUB()
+hipError_t launch_scatter(const ScatterSet&, uint32_t, uint32_t, hipStream_t) TFHE_STUB()
 
 }  // namespace tfhe

@@ -14,6 +14,7 @@
 #include "../../paper_2212_14191_amd/csrc/ckks_internal.hpp"
 
 extern std::atomic<int> fake_batched_calls;
+extern std::atomic<int> fake_mixed_calls;
 
 struct Request {
   uint32_t op, log_n, level, galois;
@@ -115,7 +116,7 @@ int main() {
       }
     }
   }
-  std::printf("server driver: %zu requests, %d wrong, %d batched calls\n", reqs.size(), bad,
-              fake_batched_calls.load());
-  return bad != 0 || fake_batched_calls.load() == 0;
+  std::printf("server driver: %zu requests, %d wrong, %d batched calls, %d of mixed levels\n", reqs.size(), bad,
+              fake_batched_calls.load(), fake_mixed_calls.load());
+  return bad != 0 || fake_batched_calls.load() == 0 || fake_mixed_calls.load() == 0;
 }

@@ -370,3 +370,81 @@ def test_fused_inner_product_equals_separate(tf, log_n, L, K, dnum, level, B):
     b0 = 0 if log_n < 16 else B - 1
     want = ckks.hmult(pr, ca[:, :, b0:b0 + 1], cb[:, :, b0:b0 + 1], evk, level)
     assert np.array_equal(to_host(got[1][0])[:, :, b0:b0 + 1], want)
+
+
+@pytest.mark.parametrize("log_n,ks_inner", [(13, 2), (13, 1), (14, 2)])
+def test_levels_batch_equals_single_calls_and_oracle(tf, log_n, ks_inner):
+    """tfhe_hmult_levels / tfhe_rotate_levels at the serving shapes (L = 24,
+    K = 8, dnum = 3): one batch of eight ciphertexts at levels 24, 1, 9, 17,
+    9, 24, 3, 24 (unsorted, groups of one to three) gives, for each, exactly
+    what tfhe_hmult / tfhe_rotate gives for it alone, and the oracle's
+    result; both inner-product kernels.  An output may alias its input."""
+    n = 1 << log_n
+    pr, s, evk, k, rk = serving_setup(log_n)
+    ctx = tf.CkksContext(log_n, 24, 8, 3, moduli=pr.moduli)
+    ctx.plan.set_param("ks_inner", ks_inner)
+    levels = [24, 1, 9, 17, 9, 24, 3, 24]
+    host_a, host_b = [], []
+    for i, lv in enumerate(levels):
+        m1 = inputs.small_messages(40 + i, (1, n))
+        m2 = inputs.small_messages(40 + i, (1, n), stream=1)
+        host_a.append(encrypt(pr, s, m1, lv, 50 + i)[:, :, 0])
+        host_b.append(encrypt(pr, s, m2, lv, 70 + i)[:, :, 0])
+    A = [to_dev(x) for x in host_a]
+    B = [to_dev(x) for x in host_b]
+    E, RK = to_dev(evk), to_dev(rk)
+    got = [to_host(o) for o in ctx.hmult_levels(A, B, E)]
+    rot = [to_host(o) for o in ctx.rotate_levels(A, [RK] * len(A), [k] * len(A))]
+    for i, lv in enumerate(levels):
+        single = to_host(ctx.hmult(A[i][:, :, None].contiguous(), B[i][:, :, None].contiguous(), E, lv))[:, :, 0]
+        assert np.array_equal(got[i], single), (i, lv)
+        single_r = to_host(ctx.rotate(A[i][:, :, None].contiguous(), RK, k, lv))[:, :, 0]
+        assert np.array_equal(rot[i], single_r), (i, lv)
+    for i in (0, 1, 2, 6):   # one per distinct level class (full, partial digits)
+        lv = levels[i]
+        want = ckks.hmult(pr, host_a[i][:, :, None], host_b[i][:, :, None], evk, lv)[:, :, 0]
+        assert np.array_equal(got[i], want), (i, lv)
+        want_r = ckks.rotate(pr, host_a[i][:, :, None], rk, k, lv)[:, :, 0]
+        assert np.array_equal(rot[i], want_r), (i, lv)
+    # results written over the first operands
+    outs = ctx.hmult_levels(A, B, E, outs=A)
+    for i in range(len(levels)):
+        assert np.array_equal(to_host(outs[i]), got[i])
+
+
+def test_levels_batch_errors(tf):
+    n = 1 << 10
+    pr, s, evk, _ = setup(n, 6, 2, 3)
+    ctx = tf.CkksContext(10, 6, 2, 3, moduli=pr.moduli)
+    E = to_dev(evk)
+    a = [torch.zeros((2, lv, n), dtype=torch.int32, device="cuda") for lv in (6, 3)]
+    shared = torch.zeros((2, 6, n), dtype=torch.int32, device="cuda")
+    with pytest.raises(tf.TfheError):      # two results in one buffer
+        ctx.hmult_levels(a, a, E, outs=[shared, shared.view(-1)[:2 * 3 * n].view(2, 3, n)])
+    with pytest.raises(tf.TfheError):      # workspace too small
+        ctx.hmult_levels(a, a, E, ws=torch.empty(256, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(tf.TfheError):      # level above L
+        ctx.levels_workspace_bytes([7])
+    with pytest.raises(tf.TfheError):      # even Galois element
+        ctx.rotate_levels(a, [E, E], [4, 5])
+    assert ctx.hmult_levels([], [], E) == []
+
+
+@pytest.mark.slow
+def test_levels_batch_full_size(tf):
+    """N = 2^16, L = 24: a batch at levels 24, 12, 24 equals the single calls,
+    and the level-12 result equals the oracle."""
+    log_n, n = 16, 1 << 16
+    pr, s, evk, _ = setup(n, 24, 8, 3)
+    ctx = tf.CkksContext(log_n, 24, 8, 3, moduli=pr.moduli)
+    levels = [24, 12, 24]
+    ha = [encrypt(pr, s, inputs.small_messages(i, (1, n)), lv, 90 + i)[:, :, 0] for i, lv in enumerate(levels)]
+    hb = [encrypt(pr, s, inputs.small_messages(i, (1, n), stream=1), lv, 95 + i)[:, :, 0]
+          for i, lv in enumerate(levels)]
+    A, B, E = [to_dev(x) for x in ha], [to_dev(x) for x in hb], to_dev(evk)
+    got = [to_host(o) for o in ctx.hmult_levels(A, B, E)]
+    for i, lv in enumerate(levels):
+        single = to_host(ctx.hmult(A[i][:, :, None].contiguous(), B[i][:, :, None].contiguous(), E, lv))[:, :, 0]
+        assert np.array_equal(got[i], single), (i, lv)
+    want = ckks.hmult(pr, ha[1][:, :, None], hb[1][:, :, None], evk, 12)[:, :, 0]
+    assert np.array_equal(got[1], want)

@@ -46,7 +46,7 @@ class OracleBackend:
             h["out"] = [out[:, :, i:i + 1] for i in range(len(reqs))]
             with self.lock:
                 self.inflight_bytes -= nb
-                self.launch_log.append((t0, time.perf_counter(), len(reqs), r0.key))
+                self.launch_log.append((t0, time.perf_counter(), len(reqs), [r.level for r in reqs]))
             h["done"] = True
 
         threading.Thread(target=work, daemon=True).start()
@@ -115,6 +115,58 @@ def test_alone_equals_mix(world):
     assert st["completed"] == len(reqs)
     assert st["p99_ms"] >= st["p50_ms"] > 0
     assert max(b for _, _, b, _ in be.launch_log) > 1   # some batching happened
+
+
+class MixingOracleBackend(OracleBackend):
+    """A backend that runs batches of mixed levels (as GpuBackend does):
+    each request of a batch at its own level."""
+
+    mixes_levels = True
+
+    def batch_nbytes(self, reqs):
+        return sum(self.nbytes(r.op, r.log_n, r.level, 1) for r in reqs)
+
+    def launch(self, slot, reqs):
+        nb = self.batch_nbytes(reqs)
+        with self.lock:
+            self.inflight_bytes += nb
+            self.peak = max(self.peak, self.inflight_bytes)
+        h = {"done": False, "out": None}
+
+        def work():
+            t0 = time.perf_counter()
+            time.sleep(self.delay)
+            h["out"] = [ckks.hmult(self.pr, r.ct_a, r.ct_b, self.evk, r.level) if r.op == HMULT
+                        else ckks.rotate(self.pr, r.ct_a, self.rks[r.galois], r.galois, r.level) for r in reqs]
+            with self.lock:
+                self.inflight_bytes -= nb
+                self.launch_log.append((t0, time.perf_counter(), len(reqs), [r.level for r in reqs]))
+            h["done"] = True
+
+        threading.Thread(target=work, daemon=True).start()
+        return h
+
+
+def test_mixed_level_batches(world):
+    """With a backend that mixes levels, requests batch on (op, N) alone:
+    batches hold several levels, every result equals the request alone, and
+    the memory budget (sized by the batch's own levels) holds."""
+    pr, evk, rks, _, _ = world
+    reqs = mix(world, count=30, seed=3)
+    alone = []
+    for r in reqs:
+        srv = Server(OracleBackend(pr, evk, rks), mem_budget_bytes=1 << 30, slots=1, max_batch=1)
+        alone.append(run(srv, [r])[0])
+        srv.close()
+    be = MixingOracleBackend(pr, evk, rks, delay_s=0.01)
+    budget = 6 * be.nbytes(HMULT, 6, 6, 1)
+    srv = Server(be, mem_budget_bytes=budget, slots=2, max_batch=8)
+    mixed = run(srv, reqs)
+    srv.close()
+    for x, y in zip(alone, mixed):
+        assert np.array_equal(x, y)
+    assert any(len(set(levels)) > 1 for _, _, _, levels in be.launch_log)
+    assert be.peak <= budget
 
 
 def test_budget_is_never_exceeded(world):
