@@ -119,7 +119,7 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *                            two), 2 = two (a transposed intermediate in the
  *                            workspace between two passes)
  *   TFHE_PARAM_KS_INNER      key switching with a four-step plan (the plan
- *                            of a CKKS context): 0 = library default (2),
+ *                            of a CKKS context): 0 = library default (1),
  *                            1 = the ModUp transforms' second pass fused
  *                            with the key inner product (Sec. IV-A: NTT,
  *                            then Inner-product, in one kernel), 2 = a

@@ -63,11 +63,10 @@ static hipError_t ntt_units(const tfhe_ntt_plan_s* p, const std::vector<NttUnit>
 }
 
 // Whether the ModUp transforms' second pass runs fused with the inner
-// product (ip_run): four-step plans that ask for it (TFHE_PARAM_KS_INNER =
-// 1; the separate kernels are the default, measured as fast or faster at
-// N = 2^15, 2^16).
+// product (ip_run): four-step plans unless TFHE_PARAM_KS_INNER asks for the
+// separate kernels (2).
 static bool fused_inner(const tfhe_ckks_ctx_s* c) {
-  return c->plan->algo == TFHE_NTT_FOURSTEP_MFMA && c->plan->ks_inner == 1;
+  return c->plan->algo == TFHE_NTT_FOURSTEP_MFMA && c->plan->ks_inner != 2;
 }
 
 // Workspace of one key-switching batch: its own regions (byte offsets from
