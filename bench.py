@@ -490,8 +490,8 @@ def main():
         tfhe.tfhe_timing_enable(True)
         dt = timed(hstep, args.hmult_steps, sync)
         kern = {}
-        for name in ("ntt_mfma_pass1", "ntt_mfma_pass2", "ckks_tensor", "ckks_modup", "ckks_inner",
-                     "ckks_moddown_conv", "ckks_moddown_final"):
+        for name in ("ntt_mfma_pass1", "ntt_mfma_pass2", "ntt_mfma_pass2_inner", "ckks_tensor", "ckks_modup",
+                     "ckks_inner", "ckks_moddown_conv", "ckks_moddown_final"):
             cnt, ms = tfhe.tfhe_timing_read(name)
             kern[name] = {"launches": cnt, "total_ms": ms}
         tfhe.tfhe_timing_enable(False)
