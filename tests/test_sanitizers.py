@@ -1,7 +1,9 @@
 """Host code under sanitizers, on the CPU (no GPU): the library's host-side
 table construction and C-ABI argument handling (plan.cpp, capi.cpp,
 ckks.cpp, timing.cpp) under AddressSanitizer + UndefinedBehaviorSanitizer
-(LeakSanitizer at exit), the request dispatcher's threads, queues, batching
+(LeakSanitizer at exit), a workspace audit of every CKKS operation
+(exactly sized buffers, kernel stand-ins that touch the ends of every range
+a launch uses), the request dispatcher's threads, queues, batching
 and event reference counts (server.cpp) under ThreadSanitizer with
 stand-in key switching, and the C oracle under ASan + UBSan.  The host
 sources are compiled against a stand-in HIP runtime (tests/sanitize/fakehip:
@@ -41,6 +43,18 @@ def test_host_tables_under_asan_ubsan(tmp_path):
                         + srcs + ["-lpthread"], str(tmp_path / "tables"),
                         {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=0"})
     assert "0 failures" in out
+
+
+def test_workspace_audit_under_asan(tmp_path):
+    """Every CKKS operation with buffers of exactly the size the C ABI asks
+    for, the kernel stand-ins touching the ends of every range the real
+    launches use: an undersized workspace region is a sanitizer report."""
+    srcs = [os.path.join(CSRC, f) for f in ("plan.cpp", "capi.cpp", "ckks.cpp", "timing.cpp")]
+    srcs += [os.path.join(SAN, "kernel_stubs.cpp"), os.path.join(SAN, "ws_audit_driver.cpp")]
+    out = build_and_run(CXX + ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-x", "c++"]
+                        + srcs + ["-lpthread"], str(tmp_path / "audit"),
+                        {"ASAN_OPTIONS": "detect_leaks=1:abort_on_error=0"})
+    assert " 0 failures" in out
 
 
 def test_dispatcher_under_tsan(tmp_path):
