@@ -87,10 +87,14 @@ tfhe_status tfhe_default_psi(uint32_t q, uint32_t log_n, uint32_t* psi);
 
 /* Create an immutable plan for N = 2^log_n over n_limbs primes.
  *   q[n_limbs], psi[n_limbs]: host arrays; psi may be NULL (default root).
- *   algo: transform used by tfhe_ntt_fwd/inv; AUTO picks per N.
+ *   algo: transform used by tfhe_ntt_fwd/inv; AUTO resolves to the
+ *     four-step MFMA transform where the plan supports it (log_n in [12, 16])
+ *     and to the butterfly elsewhere; tfhe_ntt_plan_info reports the choice.
  * Builds the twiddle tables of both algorithms on the device (Sec. IV-B:
  * "pre-computed in the initialization and reused").  Synchronous.
- * log_n in [4, 16]; the MFMA algorithm covers log_n in [12, 16] (N = N1 x 256).
+ * log_n in [4, 16].  The four-step split is fixed at N = N1 x 256 (N1 =
+ * 2^(log_n - 8), the 256-point stage a 16 x 16 matrix-core contraction,
+ * the N1-point stage 16 x N1/16); there is no split parameter.
  * Errors: TFHE_ENOTNTT for a bad modulus/root, TFHE_EINVAL, TFHE_ENOMEM. */
 tfhe_status tfhe_ntt_plan_create(tfhe_ntt_plan* out, uint32_t log_n, uint32_t n_limbs,
                                  const uint32_t* q, const uint32_t* psi, tfhe_ntt_algo algo);
