@@ -153,6 +153,22 @@ def serving_setup(log_n):
     return _KEYS[log_n]
 
 
+_ROT_KEYS = {}
+
+
+def serving_rotation_key(log_n, r):
+    """A second rotation key of the serving shapes (slots rotated by r)."""
+    if (log_n, r) not in _ROT_KEYS:
+        n = 1 << log_n
+        pr = ckks.Params(n, L=24, K=8, dnum=3)
+        s = inputs.ternary_secret(1, n, min(192, n // 2))
+        a = inputs.uniform_residues(1, pr.moduli, (3, n), stream=1).transpose(1, 0, 2)
+        e = inputs.gaussian_error(2, (3, n), stream=1)
+        k = ckks.galois_element(r, n)
+        _ROT_KEYS[(log_n, r)] = (k, ckks.rotation_key(pr, s, k, a, e))
+    return _ROT_KEYS[(log_n, r)]
+
+
 @pytest.mark.parametrize("level", [1, 9, 17, 24])
 @pytest.mark.parametrize("log_n", [14, 15])
 def test_hmult_rotate_serving_shapes_match_oracle(tf, log_n, level):
@@ -395,6 +411,17 @@ def test_levels_batch_equals_single_calls_and_oracle(tf, log_n, ks_inner):
     E, RK = to_dev(evk), to_dev(rk)
     got = [to_host(o) for o in ctx.hmult_levels(A, B, E)]
     rot = [to_host(o) for o in ctx.rotate_levels(A, [RK] * len(A), [k] * len(A))]
+    # rotations by two amounts in one batch (one key per ciphertext)
+    k2, rk2 = serving_rotation_key(log_n, 3)
+    RK2 = to_dev(rk2)
+    alt_k = [k if i % 2 else k2 for i in range(len(levels))]
+    alt = [to_host(o) for o in ctx.rotate_levels(A, [RK if i % 2 else RK2 for i in range(len(levels))], alt_k)]
+    for i in (1, 2):    # one of each amount
+        want_r = ckks.rotate(pr, host_a[i][:, :, None], rk if i % 2 else rk2, alt_k[i], levels[i])[:, :, 0]
+        assert np.array_equal(alt[i], want_r), (i, levels[i])
+    for i, lv in enumerate(levels):
+        single_r = to_host(ctx.rotate(A[i][:, :, None].contiguous(), RK if i % 2 else RK2, alt_k[i], lv))[:, :, 0]
+        assert np.array_equal(alt[i], single_r), (i, lv)
     for i, lv in enumerate(levels):
         single = to_host(ctx.hmult(A[i][:, :, None].contiguous(), B[i][:, :, None].contiguous(), E, lv))[:, :, 0]
         assert np.array_equal(got[i], single), (i, lv)
