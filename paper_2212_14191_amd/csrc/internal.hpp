@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -167,6 +168,19 @@ enum KernelId {
   K_FS_PASS1 = 0, K_FS_PASS2, K_BF_SINGLE, K_BF_COLS, K_BF_ROWS, K_EW, K_TENSOR, K_MODUP,
   K_INNER, K_MD_CONV, K_MD_FINAL, K_FROB, K_RS_BCAST, K_RS_FINAL, K_CO_PASS1, K_CO_PASS2, K_OP, K_IP
 };
+// Resident workgroups per CU of a kernel, queried once per process: the
+// dispatcher's workers may race to fill the cache; they store one value.
+template <typename K>
+int occupancy_cached(std::atomic<int>& cache, K kernel, int threads) {
+  int v = cache.load(std::memory_order_relaxed);
+  if (v == 0) {
+    int n = 0;
+    v = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) == hipSuccess && n > 0 ? n : 1;
+    cache.store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
 bool timing_on();
 void* timing_begin(int id, hipStream_t s);
 void timing_end(void* token, hipStream_t s);

@@ -49,8 +49,6 @@
 #include <algorithm>
 #include <type_traits>
 
-#include <atomic>
-
 #include "ckks_internal.hpp"
 #include "fourstep_dev.hpp"
 
@@ -406,14 +404,8 @@ fs_pass(const FsTable tab) {
 // Resident workgroups per CU of a pass kernel (queried once per process).
 template <bool kFirst, int kR, bool kWide, bool kEpi>
 uint32_t occupancy() {
-  static int occ = 0;
-  if (occ == 0) {
-    int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fs_pass<kFirst, kR, kWide, kEpi>,
-                                                                Geo<kFirst, kR, kWide>::threads, 0);
-    occ = (e == hipSuccess && n > 0) ? n : 1;
-  }
-  return (uint32_t)occ;
+  static std::atomic<int> occ{0};
+  return (uint32_t)occupancy_cached(occ, fs_pass<kFirst, kR, kWide, kEpi>, Geo<kFirst, kR, kWide>::threads);
 }
 
 // Persistent grid: a multiple of 16 workgroups, no more than the items need.
@@ -861,12 +853,8 @@ co_pass(const FsTable tab) {
 template <bool kFirst>
 void co_launch(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
   t.ipp_log = t.log_n - 12;
-  static int occ = 0;
-  if (occ == 0) {
-    int k = 0;
-    occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, co_pass<kFirst>, 256, 0) == hipSuccess && k > 0 ? k : 1;
-  }
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : (uint32_t)occ;
+  static std::atomic<int> occ{0};
+  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : (uint32_t)occupancy_cached(occ, co_pass<kFirst>, 256);
   const uint32_t items = t.total << t.ipp_log;
   const uint32_t grid = std::min(std::max(16u, (p->num_cus * w) / 16 * 16), (items + 15) / 16 * 16);
   TFHE_TIMED(kFirst ? K_CO_PASS1 : K_CO_PASS2, s,
@@ -971,10 +959,7 @@ hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
   using G = Geo<false, 16, false>;
   const uint32_t ipp = p->n / G::item;  // second-pass items per polynomial
   static std::atomic<int> occ{0};
-  if (occ.load() == 0) {
-    int k = 0;
-    occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, ip_pass, G::threads, 0) == hipSuccess && k > 0 ? k : 1;
-  }
+  const int resident = occupancy_cached(occ, ip_pass, G::threads);
   uint64_t items = 0;
   for (uint32_t g = 0; g < set.count; ++g) {
     set.g[g].item0 = (uint32_t)items;
@@ -982,7 +967,7 @@ hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
   }
   if (items == 0) return hipSuccess;
   if (items >= (1ull << 32)) return hipErrorInvalidValue;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(items, (uint64_t)p->num_cus * occ.load());
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(items, (uint64_t)p->num_cus * resident);
   TFHE_TIMED(K_IP, s,
              hipLaunchKernelGGL(ip_pass, dim3(grid), dim3(G::threads), 0, s, set, p->d_fs_fwd, p->d_mod, p->log_n,
                                 ipp, (uint32_t)items));

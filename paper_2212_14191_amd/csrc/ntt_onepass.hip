@@ -404,15 +404,9 @@ op_kernel(const FsTable tab) {
 template <int kLogN, bool kInv>
 void op_launch(const tfhe_ntt_plan_s* p, const FsTable& t, hipStream_t s) {
   using C = OpCfg<kLogN, kInv>;
-  static int occ = 0;
-  if (occ == 0) {
-    int k = 0;
-    occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, op_kernel<kLogN, kInv>, 64 * C::waves, 0) == hipSuccess &&
-                  k > 0
-              ? k
-              : 1;
-  }
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : (uint32_t)occ;
+  static std::atomic<int> occ{0};
+  const uint32_t w =
+      p->fs_wg_per_cu ? p->fs_wg_per_cu : (uint32_t)occupancy_cached(occ, op_kernel<kLogN, kInv>, 64 * C::waves);
   const uint32_t grid = std::min(std::max(1u, p->num_cus * w), t.total);
   TFHE_TIMED(K_OP, s, hipLaunchKernelGGL((op_kernel<kLogN, kInv>), dim3(grid), dim3(64 * C::waves), 0, s, t));
 }
