@@ -217,7 +217,7 @@ def sustainable_rate(fn, saturated, n_req, probes=7):
 
 
 def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "native"), native_slots=8,
-                table=None):
+                table=None, batch_ms=None):
     """Config 5: Poisson HMULT / rotate requests, N in {2^13..2^16}, levels
     uniform in 1..24, 8 rotation keys per N, keys and ciphertexts resident,
     memory-gated continuous batching.  Returns throughput and p50/p99."""
@@ -250,8 +250,9 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
     torch.cuda.synchronize()
     slots, budget = 4, 48 << 30
 
-    # per-N batch limits the autotuner chose (HMULT at level 24), else 16
-    by_n = autotune.serving_batches(table, log_ns, L) if table is not None else {}
+    # per-N batch limits from the autotuner's HMULT timings at level 24 (the
+    # largest batch within batch_ms, else its throughput choice), else 16
+    by_n = autotune.serving_batches(table, log_ns, L, batch_ms) if table is not None else {}
 
     # one long-lived backend: its streams, events and per-slot workspaces stay
     # warm across the runs, as in a running server
@@ -340,7 +341,7 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
 
     out = {"requests": n_req, "max_batch": 16, "max_batch_by_n": {str(k): v for k, v in by_n.items()},
-           "p99_bound_ms": P99_BOUND_MS}
+           "batch_ms": batch_ms, "p99_bound_ms": P99_BOUND_MS}
     for name, fn in (("python", run), ("native", run_native)):
         if name not in engines:
             continue
@@ -372,6 +373,8 @@ def main():
     ap.add_argument("--skip-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-engine", choices=["both", "python", "native"], default="both")
+    ap.add_argument("--serving-batch-ms", type=float, default=P99_BOUND_MS / 4,
+                    help="cap each N's serving batch at the largest whose measured HMULT time fits (0: no cap)")
     ap.add_argument("--native-slots", type=int, default=8,
                     help="worker threads (one stream each) of the native dispatcher")
     ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving"], default=None,
@@ -535,7 +538,8 @@ def main():
     if not args.skip_serving and args.only in (None, "serving"):
         engines = ("python", "native") if args.serving_engine == "both" else (args.serving_engine,)
         serving = serving_leg(args.serving_requests, args.serving_requests, (0.25, 0.5, 0.75, 0.9), torch, tfhe,
-                              inputs, engines, args.native_slots, table)
+                              inputs, engines, args.native_slots, table,
+                              args.serving_batch_ms if args.serving_batch_ms > 0 else None)
         tuning["serving_max_batch"] = serving.get("max_batch_by_n")
         log("serving", json.dumps(serving))
 

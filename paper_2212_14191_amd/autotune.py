@@ -112,13 +112,22 @@ def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     return {"ntt": e, "ks_inner": h.get("ks_inner") if h else None}
 
 
-def serving_batches(table, log_ns, level):
-    """{log_n: tuned HMULT batch at `level`} for the N the table covers."""
+def serving_batches(table, log_ns, level, batch_ms=None):
+    """{log_n: HMULT batch limit at `level`} for the N the table covers: the
+    tuned (throughput) batch, or with `batch_ms` the largest measured batch
+    whose time (batch / measured ops per second) stays within batch_ms, when
+    that is smaller (a request waits for at most about one batch ahead of it
+    and its own, so this bounds the latency a batch adds)."""
     out = {}
     for ln in log_ns:
         e = table.get(hmult_key(ln, level))
-        if e and "batch" in e:
-            out[ln] = int(e["batch"])
+        if not e or "batch" not in e:
+            continue
+        b = int(e["batch"])
+        if batch_ms is not None and e.get("ops_per_s"):
+            fit = [int(k) for k, v in e["ops_per_s"].items() if v > 0 and int(k) / v * 1e3 <= batch_ms]
+            b = min(b, max(fit)) if fit else 1
+        out[ln] = b
     return out
 
 

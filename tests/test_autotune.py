@@ -50,6 +50,11 @@ def test_apply_and_serving_batches():
     assert plan.params == {"auto_algo": 2, "fs_passes": 1, "fs_wide": 0, "fs_wg_per_cu": 0}
     assert autotune.apply(FakePlan(15), t, 24, 64) is None
     assert autotune.serving_batches(t, (13, 14, 15, 16), 24) == {14: 8, 16: 32}
+    # with a time budget per batch: the largest measured batch that fits
+    t.put(autotune.hmult_key(16, 24), {"batch": 32, "ops_per_s": {"8": 12000.0, "16": 13600.0, "32": 14400.0}})
+    assert autotune.serving_batches(t, (16,), 24, batch_ms=1.25) == {16: 16}
+    assert autotune.serving_batches(t, (16,), 24, batch_ms=0.1) == {16: 1}
+    assert autotune.serving_batches(t, (16,), 24, batch_ms=10.0) == {16: 32}
 
 
 def test_search_space_covers_passes():
