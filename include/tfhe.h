@@ -41,7 +41,7 @@ typedef enum {
                             or psi not a primitive 2N-th root of unity */
   TFHE_ENOMEM = -3,      /* device or host allocation failed */
   TFHE_EHIP = -4,        /* a HIP runtime call failed */
-  TFHE_EUNSUPPORTED = -5 /* valid request this build does not implement */
+  TFHE_EUNSUPPORTED = -5 /* valid request the library does not implement */
 } tfhe_status;
 
 typedef enum {
