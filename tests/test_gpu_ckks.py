@@ -388,7 +388,7 @@ def test_fused_inner_product_equals_separate(tf, log_n, L, K, dnum, level, B):
     assert np.array_equal(to_host(got[1][0])[:, :, b0:b0 + 1], want)
 
 
-@pytest.mark.parametrize("log_n,ks_inner", [(13, 2), (13, 1), (14, 2)])
+@pytest.mark.parametrize("log_n,ks_inner", [(13, 2), (13, 1), (14, 2), (14, 1), (15, 1)])
 def test_levels_batch_equals_single_calls_and_oracle(tf, log_n, ks_inner):
     """tfhe_hmult_levels / tfhe_rotate_levels at the serving shapes (L = 24,
     K = 8, dnum = 3): one batch of eight ciphertexts at levels 24, 1, 9, 17,
