@@ -10,10 +10,11 @@
 // (the second stage over its rows), whose results are held in registers
 // until every wave has read its rows, then written into LDS in natural output
 // order (position = pass-1 index + P1 x pass-2 index); 16-byte streaming
-// stores.  With N <= 2^14 the workgroup double-buffers: the next polynomial
-// loads while this one is transformed.  One workgroup of 8 waves per CU (two
-// of 4 waves at N = 2^12), so every wave keeps both passes' twiddle operands
-// in registers across polynomials of one limb.
+// stores.  For N <= 2^14 a workgroup has 4 waves and one polynomial buffer,
+// so that two or three workgroups share a CU: one's loads and stores overlap
+// the others' arithmetic (measured faster than one 8-wave workgroup that
+// double-buffers: 1.2-1.25 x at 2^13 and 2^14).  At 2^15 the polynomial
+// takes 128 KiB and one workgroup of 8 waves owns the CU.
 //
 // LDS layout: 1 KiB chunks of the polynomial in order; inside a chunk the
 // 16-byte quads are XOR-swizzled (quad Q at Q ^ X, X a function of the chunk
@@ -24,8 +25,9 @@
 // The output order uses its own swizzle.
 //
 // The first pass's post-twist P(column, output) is split into a factor fixed
-// per lane (Shoup form, in registers) and a factor per step (Montgomery form,
-// in registers), so no table is read inside the pipeline.
+// per lane (Shoup form, staged in LDS, or read through the caches at 2^14
+// where two workgroups' polynomials fill the LDS) and a factor per step
+// (Montgomery form, in registers).
 #include "fourstep_dev.hpp"
 
 namespace tfhe {
@@ -36,21 +38,22 @@ namespace {
 // X = (a c + b (Q >> sh)) & (2^sh - 1), with c the chunk and Q the quad.
 template <int kLogN, bool kInv>
 struct OpCfg;
-#define TFHE_OPCFG(LN, INV, W, B, IA, IB, OA, OB, OS)                       \
+#define TFHE_OPCFG(LN, INV, W, B, IA, IB, OA, OB, OS, PB)                   \
   template <>                                                              \
   struct OpCfg<LN, INV> {                                                  \
     static constexpr int waves = W, bufs = B;                              \
     static constexpr uint32_t in_a = IA, in_b = IB, out_a = OA, out_b = OB; \
     static constexpr uint32_t out_sh = OS;                                 \
+    static constexpr bool pb_lds = PB;                                     \
   };
-TFHE_OPCFG(12, false, 4, 2, 1, 4, 0, 1, 4)
-TFHE_OPCFG(13, false, 8, 2, 9, 4, 1, 1, 3)
-TFHE_OPCFG(14, false, 8, 2, 5, 4, 1, 4, 4)
-TFHE_OPCFG(15, false, 8, 1, 9, 4, 1, 4, 4)
-TFHE_OPCFG(12, true, 4, 2, 4, 1, 1, 0, 4)
-TFHE_OPCFG(13, true, 8, 2, 4, 1, 1, 0, 4)
-TFHE_OPCFG(14, true, 8, 2, 4, 1, 1, 0, 4)
-TFHE_OPCFG(15, true, 8, 1, 5, 4, 1, 0, 4)
+TFHE_OPCFG(12, false, 4, 1, 1, 4, 0, 1, 4, true)
+TFHE_OPCFG(13, false, 4, 1, 9, 4, 1, 1, 3, true)
+TFHE_OPCFG(14, false, 4, 1, 5, 4, 1, 4, 4, false)
+TFHE_OPCFG(15, false, 8, 1, 9, 4, 1, 4, 4, true)
+TFHE_OPCFG(12, true, 4, 1, 4, 1, 1, 0, 4, true)
+TFHE_OPCFG(13, true, 4, 1, 4, 1, 1, 0, 4, true)
+TFHE_OPCFG(14, true, 4, 1, 4, 1, 1, 0, 4, false)
+TFHE_OPCFG(15, true, 8, 1, 5, 4, 1, 0, 4, true)
 #undef TFHE_OPCFG
 
 template <uint32_t kA, uint32_t kB>
@@ -92,8 +95,11 @@ op_kernel(const FsTable tab) {
   static_assert(3 * CH <= 63, "vmcnt range");
   // polynomial buffers, then the limb's matrix-core operands and twists
   // (both passes) and the per-lane post-twist factors, staged once per limb
+  // (the post-twist factors stay in global memory, read per polynomial
+  // through the caches, where LDS must hold two workgroups' polynomials)
+  constexpr bool kPbLds = C::pb_lds;
   constexpr int kTabOpA1 = NB * N, kTabTw1 = kTabOpA1 + 1024, kTabOpA2 = kTabTw1 + 512;
-  constexpr int kTabTw2 = kTabOpA2 + 1024, kTabPb = kTabTw2 + 512, kLdsWords = kTabPb + 2048;
+  constexpr int kTabTw2 = kTabOpA2 + 1024, kTabPb = kTabTw2 + 512, kLdsWords = kTabPb + (kPbLds ? 2048 : 0);
   __shared__ __attribute__((aligned(16))) uint32_t lds[kLdsWords];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -128,6 +134,7 @@ op_kernel(const FsTable tab) {
 
   // per-limb values in registers (the rest of the limb's tables is in LDS)
   const FourStepLimb* cur_limb = nullptr;
+  const uint2* pb_src = nullptr;  // the limb's post-twist factors (global)
   uint32_t q = 0, qneg = 0, nq = 0;
   uint64_t cq = 0;
   uint2 lb1[4], lb2[16];  // level-B constants (uniform: scalar registers)
@@ -169,8 +176,9 @@ op_kernel(const FsTable tab) {
                                  (const uint32_t*)&O->p2.twist[0][0], (const uint32_t*)&O->post_b[0][0][0]};
       const int offs[5] = {kTabOpA1, kTabTw1, kTabOpA2, kTabTw2, kTabPb};
       const int lens[5] = {1024, 512, 1024, 512, 2048};
+      pb_src = &O->post_b[0][0][0];
 #pragma unroll
-      for (int k = 0; k < 5; ++k)
+      for (int k = 0; k < (kPbLds ? 5 : 4); ++k)
         for (int i = 4 * tid; i < lens[k]; i += 4 * 64 * W)
           *(uint4*)(lds + offs[k] + i) = *(const uint4*)(srcs[k] + i);
 #pragma unroll
@@ -204,7 +212,9 @@ op_kernel(const FsTable tab) {
         opA1[j] = *(const v4i*)(lds + kTabOpA1 + (j * 64 + lane) * 4);
         tw1[j] = *(const uint2*)(lds + kTabTw1 + (lane * 4 + j) * 2);
 #pragma unroll
-        for (int sg = 0; sg < 4; ++sg) pb[j][sg] = *(const uint2*)(lds + kTabPb + ((lane * 4 + j) * 4 + sg) * 2);
+        for (int sg = 0; sg < 4; ++sg)
+          pb[j][sg] = kPbLds ? *(const uint2*)(lds + kTabPb + ((lane * 4 + j) * 4 + sg) * 2)
+                             : pb_src[(lane * 4 + j) * 4 + sg];
       }
       uint32_t pa[4] = {pa0[0], pa0[1], pa0[2], pa0[3]};
 #pragma unroll

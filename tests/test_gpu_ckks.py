@@ -475,3 +475,26 @@ def test_levels_batch_full_size(tf):
         assert np.array_equal(got[i], single), (i, lv)
     want = ckks.hmult(pr, ha[1][:, :, None], hb[1][:, :, None], evk, 12)[:, :, 0]
     assert np.array_equal(got[1], want)
+
+
+@pytest.mark.parametrize("log_n,level,B", [(12, 8, 3), (13, 17, 3), (14, 24, 2), (15, 9, 2)])
+def test_hmult_one_pass_transforms_match_oracle(tf, log_n, level, B):
+    """HMULT with every transform of the key switch that can take it on the
+    one-pass kernel (TFHE_PARAM_FS_PASSES = 1; the ModUp transforms fused
+    with the inner product and ModDown's final transform keep their two
+    passes) equals the two-pass HMULT and the oracle."""
+    n = 1 << log_n
+    L = 8 if log_n == 12 else 24
+    K, dnum = (4, 2) if log_n == 12 else (8, 3)
+    pr, s, evk, _ = setup(n, L, K, dnum)
+    ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
+    m1 = inputs.small_messages(log_n, (B, n))
+    m2 = inputs.small_messages(log_n, (B, n), stream=3)
+    ca, cb = encrypt(pr, s, m1, level, 61), encrypt(pr, s, m2, level, 62)
+    A, Bt, E = to_dev(ca), to_dev(cb), to_dev(evk)
+    got = {}
+    for passes in (1, 2):
+        ctx.plan.set_param("fs_passes", passes)
+        got[passes] = to_host(ctx.hmult(A, Bt, E, level))
+    assert np.array_equal(got[1], got[2])
+    assert np.array_equal(got[1], ckks.hmult(pr, ca, cb, evk, level))
