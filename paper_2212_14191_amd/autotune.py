@@ -104,8 +104,14 @@ def apply(plan, table, limbs, batch):
 def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     """Tuned plan parameters of a CKKS context's transforms and its key
     switching variant (the inner product fused into the transforms or not).
+    The key switch keeps its transforms on two passes: the one-pass kernel
+    gains only 2-4 % of an HMULT at batch 16-64 (its fused ModUp and
+    ModDown transforms stay two-pass) and loses 10-20 % at batch 1-4 at
+    N = 2^14, where one workgroup per polynomial leaves most CUs idle.
     Returns the applied entries."""
     e = apply(ctx.plan, table, limbs, batch)
+    if e is not None and e.get("fs_passes") == 1:
+        ctx.plan.set_param("fs_passes", 2)
     h = table.get(hmult_key(ctx.log_n, level))
     if h and "ks_inner" in h:
         ctx.plan.set_param("ks_inner", int(h["ks_inner"]))

@@ -57,6 +57,25 @@ def test_apply_and_serving_batches():
     assert autotune.serving_batches(t, (16,), 24, batch_ms=10.0) == {16: 32}
 
 
+class FakeCtx:
+    def __init__(self, log_n):
+        self.log_n = log_n
+        self.plan = FakePlan(log_n)
+
+
+def test_apply_ckks_keeps_two_passes():
+    """A context's key switch takes the tuned launch shape and inner-product
+    variant but keeps two-pass transforms, whatever the NTT entry says."""
+    t = autotune.TuneTable()
+    t.put(autotune.ntt_key(14, 24, 64), {"algo": "mfma", "fs_passes": 1, "fs_wide": 1, "fs_wg_per_cu": 2})
+    t.put(autotune.hmult_key(14, 24), {"batch": 32, "ks_inner": 1})
+    ctx = FakeCtx(14)
+    got = autotune.apply_ckks(ctx, t)
+    assert got["ks_inner"] == 1 and got["ntt"]["fs_passes"] == 1
+    assert ctx.plan.params["fs_passes"] == 2 and ctx.plan.params["fs_wide"] == 1
+    assert ctx.plan.params["ks_inner"] == 1
+
+
 def test_search_space_covers_passes():
     c14 = autotune.ntt_candidates(14, True)
     assert ("mfma", 1, 0, 0) in c14 and ("mfma", 2, 2, 0) in c14 and ("butterfly", 0, 0, 0) in c14
