@@ -101,6 +101,21 @@ def apply(plan, table, limbs, batch):
     return e
 
 
+KS_INNER_MARGIN = 1.02
+
+
+def ks_inner_choice(entry):
+    """The key-switching variant an HMULT entry selects: the fused inner
+    product (1, the library default, with less HBM traffic) unless the
+    separate kernels (2) measured more than KS_INNER_MARGIN faster (the two
+    are within a few per cent of each other at N >= 2^15, so a smaller
+    difference is taken as noise)."""
+    ops = entry.get("ks_inner_ops_per_s")
+    if ops and "1" in ops and "2" in ops:
+        return 2 if ops["2"] > KS_INNER_MARGIN * ops["1"] else 1
+    return int(entry["ks_inner"]) if "ks_inner" in entry else None
+
+
 def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     """Tuned plan parameters of a CKKS context's transforms and its key
     switching variant (the inner product fused into the transforms or not).
@@ -113,9 +128,10 @@ def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     if e is not None and e.get("fs_passes") == 1:
         ctx.plan.set_param("fs_passes", 2)
     h = table.get(hmult_key(ctx.log_n, level))
-    if h and "ks_inner" in h:
-        ctx.plan.set_param("ks_inner", int(h["ks_inner"]))
-    return {"ntt": e, "ks_inner": h.get("ks_inner") if h else None}
+    choice = ks_inner_choice(h) if h else None
+    if choice is not None:
+        ctx.plan.set_param("ks_inner", choice)
+    return {"ntt": e, "ks_inner": choice}
 
 
 def serving_batches(table, log_ns, level, batch_ms=None):
@@ -295,8 +311,8 @@ def main(argv=None):
                     inner.setdefault(mode, []).append(t[b])
             ctx.plan.set_param("ks_inner", 0)
             med = {m: sorted(v)[1] for m, v in inner.items()}
-            entry["ks_inner"] = max(med, key=med.get)
             entry["ks_inner_ops_per_s"] = {str(m): round(v, 1) for m, v in med.items()}
+            entry["ks_inner"] = ks_inner_choice(entry)
             table.put(hmult_key(ln, level), entry)
             print("hmult", ln, level, b, entry["ks_inner"], flush=True)
         ctx.close()

@@ -76,6 +76,16 @@ def test_apply_ckks_keeps_two_passes():
     assert ctx.plan.params["ks_inner"] == 1
 
 
+def test_ks_inner_choice_margin():
+    """The fused inner product stays unless the separate kernels measured
+    more than 2 % faster."""
+    assert autotune.ks_inner_choice({"ks_inner_ops_per_s": {"1": 100.0, "2": 101.5}, "ks_inner": 2}) == 1
+    assert autotune.ks_inner_choice({"ks_inner_ops_per_s": {"1": 100.0, "2": 103.0}}) == 2
+    assert autotune.ks_inner_choice({"ks_inner_ops_per_s": {"1": 104.0, "2": 100.0}}) == 1
+    assert autotune.ks_inner_choice({"ks_inner": 2}) == 2
+    assert autotune.ks_inner_choice({"batch": 4}) is None
+
+
 def test_search_space_covers_passes():
     c14 = autotune.ntt_candidates(14, True)
     assert ("mfma", 1, 0, 0) in c14 and ("mfma", 2, 2, 0) in c14 and ("butterfly", 0, 0, 0) in c14
