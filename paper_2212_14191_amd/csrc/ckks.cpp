@@ -420,7 +420,9 @@ hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uin
 }
 
 // RESCALE workspace: the top limbs in the coefficient domain [2][B][N], their
-// broadcast to the remaining limbs [2][top][B][N], the transforms' workspace.
+// broadcast to the remaining limbs [2][top][B][N] (butterfly contexts; the
+// four-step transform reads the top limbs directly), the transforms'
+// workspace.
 struct RsLayout {
   size_t t, u, ntt, total;
 };
@@ -436,7 +438,7 @@ static RsLayout rs_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
   RsLayout l;
   size_t off = 0;
   l.t = off; off += align256(2 * plane);
-  l.u = off; off += align256(2 * plane * top);
+  l.u = off; off += mfma ? 0 : align256(2 * plane * top);  // the broadcast (butterfly path only)
   l.ntt = off; off += std::max(a, b);
   l.total = off;
   return l;
@@ -458,17 +460,20 @@ static hipError_t rescale(const tfhe_ckks_ctx_s* c, const uint32_t* ct, uint32_t
                          NttUnit{p, true, ct + (uint64_t)(level + top) * plane, t + plane, top, 1, batch}},
                      nws, s)) != hipSuccess)
     return e;
-  // reduce into every remaining limb, back to the NTT domain
-  if ((e = launch_rescale_bcast(t, u, p->d_mod, top, batch, c->n, s)) != hipSuccess) return e;
   if (p->algo == TFHE_NTT_FOURSTEP_MFMA) {
-    // NTT of the broadcast, finished in the store epilogue: (c_i - u_i) q_top^{-1}
-    NttUnit u0{p, false, u, out, 0, top, batch};
-    NttUnit u1{p, false, u + (uint64_t)top * plane, out + (uint64_t)top * plane, 0, top, batch};
+    // NTT of the top limb's coefficients modulo every remaining limb (each
+    // limb's first pass reads the same plane of t, whose values lie below
+    // 2^31), finished in the store epilogue: (c_i - NTT(t)_i) q_top^{-1}
+    NttUnit u0{p, false, t, out, 0, top, batch};
+    NttUnit u1{p, false, t + plane, out + (uint64_t)top * plane, 0, top, batch};
+    u0.in_bcast = u1.in_bcast = true;
     u0.acc = ct;
     u1.acc = ct + (uint64_t)level * plane;
     u0.epi_mult = u1.epi_mult = c->d_rs_qinv + (size_t)top * c->L;
     return ntt_units(p, {u0, u1}, nws, s);
   }
+  // reduce into every remaining limb, back to the NTT domain
+  if ((e = launch_rescale_bcast(t, u, p->d_mod, top, batch, c->n, s)) != hipSuccess) return e;
   if ((e = ntt_units(p, {NttUnit{p, false, u, u, 0, top, batch},
                          NttUnit{p, false, u + (uint64_t)top * plane, u + (uint64_t)top * plane, 0, top, batch}},
                      nws, s)) != hipSuccess)

@@ -26,6 +26,8 @@ struct FsUnit {
   const uint32_t* acc;
   const uint2* mult;
   uint32_t accumulate;
+  // first pass: every limb reads polynomial b of the one plane `in`
+  uint32_t in_bcast;
 };
 struct FsTable {
   uint32_t count, total;  // units, polynomials
@@ -149,6 +151,7 @@ __device__ __forceinline__ void level_b(uint32_t* y, const uint2* lb, const uint
 struct Item {
   uint32_t unit, limb;
   size_t poly_base;  // word offset of the polynomial within the unit's arrays
+  size_t in_base;    // its input's offset (the batch element's, for a broadcast input)
 };
 // Global polynomial p -> (unit, limb, offset); `k` is a running unit index
 // (p only increases along a walk).
@@ -159,6 +162,7 @@ __device__ __forceinline__ Item locate(const FsTable& t, uint32_t p, uint32_t& k
   it.unit = k;
   it.limb = local / t.u[k].batch;
   it.poly_base = (size_t)local << t.log_n;
+  it.in_base = t.u[k].in_bcast ? (size_t)(local % t.u[k].batch) << t.log_n : it.poly_base;
   return it;
 }
 

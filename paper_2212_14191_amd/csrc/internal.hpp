@@ -123,6 +123,11 @@ struct NttUnit {
   // tiled intermediate to `out` (the second pass is left to a fused
   // consumer, ip_run)
   bool pass1_only = false;
+  // Forward four-step transforms only: every limb of the unit reads the same
+  // input plane `in` ([batch][N], values below 2^31, not reduced by the
+  // limb's modulus), i.e. the transform of that integer polynomial modulo
+  // each of the unit's limbs
+  bool in_bcast = false;
 };
 // Runs every unit with the four-step algorithm (all units need has_mfma) or
 // the butterfly; ws must hold the sum of the units' workspaces.

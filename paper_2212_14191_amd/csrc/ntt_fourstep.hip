@@ -195,7 +195,7 @@ fs_pass(const FsTable tab) {
   uint32_t kf = 0, kc = 0;  // running unit indices of the load and compute walks
   auto issue = [&](uint32_t p, int stage) {
     const Item it = locate(tab, p, kf);
-    issue_tile<G::pitch>(tab.u[it.unit].in + it.poly_base, ld_off, ring + stage * G::tile, wave);
+    issue_tile<G::pitch>(tab.u[it.unit].in + it.in_base, ld_off, ring + stage * G::tile, wave);
   };
 #pragma unroll
   for (int j = 0; j < kStages - 1; ++j)
@@ -339,9 +339,11 @@ fs_pass(const FsTable tab) {
       }
     };
     // (the narrow first pass of the 256-point stage keeps one body: two
-    // would not fit its register budget without spilling)
+    // would not fit its register budget without spilling).  A broadcast
+    // input (below 2^31, not reduced by this limb's modulus) takes the body
+    // that maps its values into the digit window.
     constexpr bool kDual = !(kFirst && kR == 16 && !kWide);
-    if (!kDual || q > 0x7F7F7F7Fu) body(std::true_type{});
+    if (!kDual || q > 0x7F7F7F7Fu || (kFirst && tab.u[it.unit].in_bcast)) body(std::true_type{});
     else body(std::false_type{});
 
     if (kGather) {
@@ -905,7 +907,8 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     const bool inverse = units[lead].inverse;
     const bool epi = units[lead].acc != nullptr;
     const bool p1only = units[lead].pass1_only;
-    if ((epi || p1only) && inverse) return hipErrorInvalidValue;
+    const bool bcast = units[lead].in_bcast;
+    if ((epi || p1only || bcast) && inverse) return hipErrorInvalidValue;
     const tfhe_ntt_plan_s* p0 = units[lead].plan;
     const uint32_t N = 1u << log_n, N1 = N >> 8, r = N1 / 16;
     FsTable t1, t2;
@@ -914,7 +917,7 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     t2.cols = inverse ? 256 : N1;
     const uint32_t r1 = inverse ? 16 : r, r2 = inverse ? r : 16;
     // one HBM round trip where the one-pass kernel covers the shape
-    const bool one = !epi && !p1only && use_onepass(p0);
+    const bool one = !epi && !p1only && !bcast && use_onepass(p0);
     auto flush = [&]() {
       if (t1.total == 0) return;
       if (one) {
@@ -932,7 +935,7 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     for (uint32_t k = lead; k < count; ++k) {
       const NttUnit& u = units[k];
       if (done[k] || u.plan->log_n != log_n || u.inverse != inverse || (u.acc != nullptr) != epi ||
-          u.pass1_only != p1only)
+          u.pass1_only != p1only || u.in_bcast != bcast)
         continue;
       done[k] = true;
       const uint32_t polys = u.limb_count * u.batch;
@@ -943,8 +946,9 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
         t1.total = t2.total = 0;
       }
       const FourStepLimb* tabs = (u.inverse ? u.plan->d_fs_inv : u.plan->d_fs_fwd) + u.limb_begin;
-      t1.u[t1.count++] = FsUnit{u.in, one ? u.out : mids[k], tabs, u.batch, t1.total, nullptr, nullptr, 0};
-      t2.u[t2.count++] = FsUnit{mids[k], u.out, tabs, u.batch, t2.total, u.acc, u.epi_mult, u.epi_add ? 1u : 0u};
+      t1.u[t1.count++] = FsUnit{u.in, one ? u.out : mids[k], tabs, u.batch, t1.total, nullptr, nullptr, 0,
+                                u.in_bcast ? 1u : 0u};
+      t2.u[t2.count++] = FsUnit{mids[k], u.out, tabs, u.batch, t2.total, u.acc, u.epi_mult, u.epi_add ? 1u : 0u, 0};
       t1.total += polys;
       t2.total += polys;
     }
@@ -984,8 +988,8 @@ hipError_t co_transform(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* 
   t1.total = t2.total = limb_count * batch;
   t1.log_n = t2.log_n = p->log_n;
   t1.cols = t2.cols = 256;  // N = 2^16: both passes are 256 x 256
-  t1.u[0] = FsUnit{in, (uint32_t*)ws, tabs, batch, 0, nullptr, nullptr, 0};
-  t2.u[0] = FsUnit{(const uint32_t*)ws, out, tabs, batch, 0, nullptr, nullptr, 0};
+  t1.u[0] = FsUnit{in, (uint32_t*)ws, tabs, batch, 0, nullptr, nullptr, 0, 0};
+  t2.u[0] = FsUnit{(const uint32_t*)ws, out, tabs, batch, 0, nullptr, nullptr, 0, 0};
   co_launch<true>(p, t1, s);
   co_launch<false>(p, t2, s);
   return hipGetLastError();

@@ -41,7 +41,7 @@ static uint64_t words_of(const NttUnit& u) { return (uint64_t)u.limb_count * u.b
 static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static void unit_io(const NttUnit& u, uint32_t* mid, uint64_t mid_words) {
-  rd(u.in, words_of(u));
+  rd(u.in, u.in_bcast ? (uint64_t)u.batch * u.plan->n : words_of(u));
   if (u.pass1_only) {
     wr(u.out, (uint64_t)(unit_ws_bytes(u, true) / 4));
     return;
