@@ -257,11 +257,16 @@ fs_pass(const FsTable tab) {
     lds_barrier();  // the item's tile is complete; the oldest stage is free
     uint4 e_acc[4], e_out[4];  // epilogue operands at the item's store positions
     if (kEpi) {
+      // a unit that overwrites its output (RESCALE, the second component of
+      // a rotation) has no use for the old values: its second load re-reads
+      // the lines the first has just fetched, so the count of loads that the
+      // waits assume stays 8 per item without the output crossing HBM
       const FsUnit& U = tab.u[it.unit];
+      const uint32_t* const eo = U.accumulate ? U.out : U.acc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         e_acc[j] = *(const uint4*)(U.acc + it.poly_base + st_off[j]);
-        e_out[j] = *(const uint4*)(U.out + it.poly_base + st_off[j]);
+        e_out[j] = *(const uint4*)(eo + it.poly_base + st_off[j]);
       }
     }
     const bool issued = p + (kStages - 1) * walk.step < walk.p_end;
