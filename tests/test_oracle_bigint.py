@@ -1,0 +1,199 @@
+"""Pins of every bit of the oracle's HMULT and HROTATE against an exact
+big-integer model of the same definitions (CPU only).
+
+Decryption fixes an HMULT result only up to the key-switching noise; the
+invariants of the other pins fix ModUp and ModDown up to a small multiple of
+the digit modulus or of one.  This model fixes the rest.  It never works
+residue by residue: ciphertext components and keys are whole integers modulo
+Q_l (keys modulo Q_l P) rebuilt by the Chinese remainder theorem,
+polynomial products are schoolbook negacyclic sums of Python integers, and
+the two basis conversions of generalised key switching (Sec. II-B) are the
+exact integer sums their definitions name:
+  ModUp_j(x)  = sum_{i in D_j} [x (Q_j/q_i)^{-1}]_{q_i} (Q_j/q_i)
+  ModDown(a)  = (a - sum_k [a (P/p_k)^{-1}]_{p_k} (P/p_k)) / P
+(the division exact, no rounding offset), with D_j = [alpha j,
+min(alpha (j+1), l)).  The oracle's arrays are in the NTT domain; the
+conversions into and out of it use the oracle's transforms, which their
+own pins fix (Eq. 4 evaluated directly, schoolbook products).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import ckks
+from paper_2212_14191_amd import inputs
+
+
+# ------------------------------------------------------------ the model
+def _prod(xs):
+    r = 1
+    for x in xs:
+        r *= x
+    return r
+
+
+def _crt(res, mods):
+    """The integer in [0, prod(mods)) with these residues."""
+    M = _prod(mods)
+    return sum(r * (M // m) * pow(M // m, -1, m) for r, m in zip(res, mods)) % M
+
+
+def _negacyclic(a, b, m):
+    """a(X) b(X) mod (X^N + 1), coefficients mod m (schoolbook)."""
+    n = len(a)
+    out = [0] * n
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            if i + j < n:
+                out[i + j] += x * y
+            else:
+                out[i + j - n] -= x * y
+    return [v % m for v in out]
+
+
+def _sigma(a, k, m):
+    """X^i -> X^{i k mod 2N}, negated where i k mod 2N >= N."""
+    n = len(a)
+    out = [0] * n
+    for i, x in enumerate(a):
+        e = i * k % (2 * n)
+        out[e % n] = x % m if e < n else (-x) % m
+    return out
+
+
+def _key_switch(d, keys, q, p, alpha, level):
+    """(ModDown(sum_j ModUp_j(d) keys[j][0]), ModDown(... keys[j][1])) of the
+    integer polynomial d (mod Q_l); keys[j][c]: integer polynomials mod Q_l P."""
+    Q, P = _prod(q[:level]), _prod(p)
+    M = Q * P
+    n = len(d)
+    acc = [[0] * n, [0] * n]
+    for j in range((level + alpha - 1) // alpha):
+        digit = q[alpha * j:min(alpha * (j + 1), level)]
+        Qj = _prod(digit)
+        up = [sum((x * pow(Qj // qi, -1, qi) % qi) * (Qj // qi) for qi in digit) for x in d]
+        for c in range(2):
+            prod = _negacyclic(up, keys[j][c], M)
+            acc[c] = [(u + v) % M for u, v in zip(acc[c], prod)]
+    out = []
+    for c in range(2):
+        res = []
+        for a in acc[c]:
+            t = sum((a * pow(P // pk, -1, pk) % pk) * (P // pk) for pk in p)
+            assert (a - t) % P == 0
+            res.append((a - t) // P % Q)
+        out.append(res)
+    return out
+
+
+def model_hmult(pr, level, a, b, keys):
+    """a, b: [2][B] integer polynomials mod Q_l; keys[j][c]: mod Q_l P."""
+    Q = _prod(pr.q[:level])
+    outs = []
+    for bi in range(len(a[0])):
+        a0, a1, b0, b1 = a[0][bi], a[1][bi], b[0][bi], b[1][bi]
+        d0 = _negacyclic(a0, b0, Q)
+        d1 = [(x + y) % Q for x, y in zip(_negacyclic(a0, b1, Q), _negacyclic(a1, b0, Q))]
+        d2 = _negacyclic(a1, b1, Q)
+        o0, o1 = _key_switch(d2, keys, pr.q, pr.p, pr.alpha, level)
+        outs.append(([(x + y) % Q for x, y in zip(d0, o0)], [(x + y) % Q for x, y in zip(d1, o1)]))
+    return outs
+
+
+def model_rotate(pr, level, a, keys, k):
+    Q = _prod(pr.q[:level])
+    outs = []
+    for bi in range(len(a[0])):
+        r0, r1 = _sigma(a[0][bi], k, Q), _sigma(a[1][bi], k, Q)
+        o0, o1 = _key_switch(r1, keys, pr.q, pr.p, pr.alpha, level)
+        outs.append(([(x + y) % Q for x, y in zip(r0, o0)], o1))
+    return outs
+
+
+# ------------------------------------------- inputs and the oracle's view
+def _setup(pr, level, batch, seed):
+    """Coefficient-domain residues of two ciphertexts and of a key (random:
+    the pin is about arithmetic, not about what a valid key encrypts), the
+    same as integers, and the oracle's NTT-domain arrays."""
+    n = pr.n
+    idx = list(range(level))
+    qs, ps = pr.mods(idx), pr.psis(idx)
+    cts = [inputs.uniform_residues(seed + i, qs, (2, batch, n)).transpose(1, 0, 2, 3) for i in range(2)]
+    key = inputs.uniform_residues(seed + 2, pr.moduli, (pr.dnum, 2, n)).transpose(1, 2, 0, 3)
+    ext = pr.ext_limbs(level)
+    ext_mods = pr.mods(ext)
+    ints = [[[[_crt([int(ct[c, i, bi, x]) for i in range(level)], qs) for x in range(n)]
+               for bi in range(batch)] for c in range(2)] for ct in cts]
+    key_ints = [[[_crt([int(key[j, c, t, x]) for t in ext], ext_mods) for x in range(n)] for c in range(2)]
+                for j in range(pr.dnum)]
+    nts = [np.stack([oracle.ntt_fwd(np.ascontiguousarray(ct[c]), qs, ps) for c in range(2)]) for ct in cts]
+    key_ntt = np.stack([np.stack([oracle.ntt_fwd(np.ascontiguousarray(key[j, c]), pr.moduli, pr.psi)
+                                  for c in range(2)]) for j in range(pr.dnum)])
+    return ints, key_ints, nts, key_ntt
+
+
+def _coeffs(pr, ct_ntt, level):
+    idx = list(range(level))
+    return np.stack([oracle.ntt_inv(np.ascontiguousarray(ct_ntt[c]), pr.mods(idx), pr.psis(idx))
+                     for c in range(2)])
+
+
+def _assert_equal(pr, got, want, level):
+    """got: oracle coefficients [2][level][B][N]; want: model [B](c0, c1)."""
+    for bi, comps in enumerate(want):
+        for c in range(2):
+            for i in range(level):
+                qi = pr.q[i]
+                assert [int(v) for v in got[c, i, bi]] == [v % qi for v in comps[c]], (bi, c, i)
+
+
+# ---------------------------------------------------------------- pins
+SHAPES = {
+    # (N, L, K, dnum, level): full and partial digits, K < alpha
+    "l6": (16, 6, 2, 3, 6),
+    "l5": (16, 6, 2, 3, 5),
+    "l1": (16, 6, 2, 3, 1),
+    "k1": (16, 6, 1, 2, 5),
+}
+
+
+def check_hmult(shape="l5", seed=7):
+    n, L, K, dnum, level = SHAPES[shape]
+    pr = ckks.Params(n, L, K, dnum)
+    ints, key_ints, nts, key_ntt = _setup(pr, level, 2, seed)
+    got = _coeffs(pr, ckks.hmult(pr, nts[0], nts[1], key_ntt, level), level)
+    _assert_equal(pr, got, model_hmult(pr, level, ints[0], ints[1], key_ints), level)
+
+
+def check_rotate(k=5, shape="l5", seed=11):
+    n, L, K, dnum, level = SHAPES[shape]
+    pr = ckks.Params(n, L, K, dnum)
+    ints, key_ints, nts, key_ntt = _setup(pr, level, 2, seed)
+    got = _coeffs(pr, ckks.rotate(pr, nts[0], key_ntt, k, level), level)
+    _assert_equal(pr, got, model_rotate(pr, level, ints[0], key_ints, k), level)
+
+
+@pytest.mark.parametrize("shape", sorted(SHAPES))
+def test_hmult_equals_bigint_model(shape):
+    check_hmult(shape)
+
+
+@pytest.mark.parametrize("k", [5, 25, 31])
+@pytest.mark.parametrize("shape", ["l6", "l1", "k1"])
+def test_rotate_equals_bigint_model(k, shape):
+    check_rotate(k, shape)
+
+
+def test_model_reduces_to_schoolbook_without_key_switching():
+    """The model's own anchor: with c1 = c1' = 0, HMULT is (c0 c0', 0), the
+    product of the CRT values taken modulo X^N + 1 and Q_l."""
+    pr = ckks.Params(16, 6, 2, 3)
+    level = 4
+    ints, key_ints, _, _ = _setup(pr, level, 1, 3)
+    zero = [[0] * pr.n]
+    out = model_hmult(pr, level, [ints[0][0], zero], [ints[1][0], zero], key_ints)
+    Q = _prod(pr.q[:level])
+    a, b = ints[0][0][0], ints[1][0][0]
+    want = [sum(a[i] * b[(x - i) % pr.n] * (1 if i <= x else -1) for i in range(pr.n)) % Q
+            for x in range(pr.n)]
+    assert out[0][0] == want and out[0][1] == [0] * pr.n

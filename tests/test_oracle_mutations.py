@@ -3,14 +3,16 @@ mutant is a plausible slip in one step of RESCALE (a swapped operand, a
 wrong constant, an off-by-one limb, the rounding reading in place of the
 floor) or of key switching, the tensor product and the automorphism (a
 dropped inverse in ModUp, a flipped sign in ModDown, exchanged tensor
-operands, a missing negation); the pin tests run with the mutant in place
-of the oracle's function and must fail."""
+operands, a missing negation, ModDown with a rounding offset); the pin
+tests run with the mutant in place of the oracle's function and must
+fail."""
 import numpy as np
 import pytest
 
 import oracle
 from oracle import ckks
 
+import test_oracle_bigint as bigint
 import test_oracle_ckks as pins
 
 
@@ -60,11 +62,13 @@ def test_rescale_unmutated_passes_pins():
 
 
 # ------------------------------------------------------------ key switching
-# Four slips in the key switch and the operations around it, each planted
+# Five slips in the key switch and the operations around it, each planted
 # in place of one oracle function: ModUp without the (Q_j/q_i)^{-1} factor,
 # ModDown with the subtraction's sign flipped, the tensor product with the
-# second ciphertext's components exchanged in d1, and the automorphism
-# without the negation of wrapped coefficients (X^N = -1).
+# second ciphertext's components exchanged in d1, the automorphism without
+# the negation of wrapped coefficients (X^N = -1), and ModDown with the
+# rounding offset P/2 that another reading adds (a result that still
+# decrypts correctly: the decryption pins miss it).
 
 def _mod_up_without_inverse(pr, x, digit, level):
     ext = pr.ext_limbs(level)
@@ -111,6 +115,16 @@ def _automorphism_without_negation(x, k, qs):
     return out
 
 
+def _mod_down_rounded(pr, acc_ntt, level):
+    # ModDown(acc + floor(P/2)) instead of ModDown(acc)
+    ext = pr.ext_limbs(level)
+    mods = pr.mods(ext)
+    half = np.array([(pr.P // 2) % m for m in mods], dtype=np.uint32).reshape(-1, 1, 1)
+    h = np.ascontiguousarray(np.broadcast_to(half, acc_ntt.shape))
+    h_ntt = oracle.ntt_fwd(h, mods, pr.psis(ext))
+    return _ORIG["mod_down"](pr, oracle.add(acc_ntt, h_ntt, mods), level)
+
+
 _ORIG = {"mod_down": ckks.mod_down}
 
 KS_PINS = {
@@ -121,15 +135,20 @@ KS_PINS = {
     "hmult_dec": lambda: pins.test_hmult_decrypts_to_product(5),
     "automorphism": lambda: pins.test_automorphism_is_ntt_permutation(),
     "rotate_dec": lambda: pins.test_rotate_decrypts_to_rotated_message("rot5"),
+    "hmult_bigint": lambda: bigint.check_hmult("l5"),
+    "rotate_bigint": lambda: bigint.check_rotate(5, "l5"),
 }
 
 KS_MUTANTS = {
     # mutant: (oracle function replaced, replacement, pins it must fail)
-    "modup_inverse": ("mod_up", _mod_up_without_inverse, {"mod_up", "hmult_dec", "rotate_dec"}),
-    "moddown_sign": ("mod_down", _mod_down_sign_flipped, {"mod_down", "hmult_dec", "rotate_dec"}),
-    "tensor_exchanged": ("tensor", _tensor_exchanged, {"trivial", "hmult_dec"}),
+    "modup_inverse": ("mod_up", _mod_up_without_inverse,
+                      {"mod_up", "hmult_dec", "rotate_dec", "hmult_bigint", "rotate_bigint"}),
+    "moddown_sign": ("mod_down", _mod_down_sign_flipped,
+                     {"mod_down", "hmult_dec", "rotate_dec", "hmult_bigint", "rotate_bigint"}),
+    "tensor_exchanged": ("tensor", _tensor_exchanged, {"trivial", "hmult_dec", "hmult_bigint"}),
     "automorphism_sign": ("automorphism_coeff", _automorphism_without_negation,
-                          {"automorphism", "rotate_dec"}),
+                          {"automorphism", "rotate_dec", "rotate_bigint"}),
+    "moddown_rounded": ("mod_down", _mod_down_rounded, {"hmult_bigint", "rotate_bigint"}),
 }
 
 
