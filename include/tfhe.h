@@ -129,13 +129,20 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *                            then Inner-product, in one kernel), 2 = a
  *                            separate inner-product kernel.  Same results;
  *                            tfhe_hmult_workspace_size depends on it.
+ *   TFHE_PARAM_FS_RING       LDS ring depth (work items in flight per
+ *                            workgroup) of the two-pass four-step kernels
+ *                            with 8-wave items (the 256-point stage, see
+ *                            TFHE_PARAM_FS_WIDE): 0 = library default (2),
+ *                            2 or 3; the 4-wave items always use 3.  Same
+ *                            results.
  * Not thread-safe against concurrent compute calls on the same plan. */
 typedef enum {
   TFHE_PARAM_FS_WG_PER_CU = 1,
   TFHE_PARAM_AUTO_ALGO = 2,
   TFHE_PARAM_FS_WIDE = 3,
   TFHE_PARAM_FS_PASSES = 4,
-  TFHE_PARAM_KS_INNER = 5
+  TFHE_PARAM_KS_INNER = 5,
+  TFHE_PARAM_FS_RING = 6
 } tfhe_plan_param;
 tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t value);
 tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, int64_t* value);

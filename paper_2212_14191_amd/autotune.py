@@ -33,6 +33,7 @@ TABLE_PATH = os.path.join(HERE, "tune_mi355x.json")
 
 NTT_WG_CANDIDATES = (0, 1, 2, 3, 4, 6, 8)
 NTT_WIDE_CANDIDATES = (1, 2)   # narrow / wide 256-point items (0 = library default)
+NTT_RING_CANDIDATES = (2, 3)   # LDS ring stages of the wide-item passes
 HMULT_BATCHES = (1, 2, 4, 8, 16, 32, 64)
 
 
@@ -86,7 +87,7 @@ def load_default():
     return TuneTable(TABLE_PATH)
 
 
-PLAN_PARAMS = ("fs_passes", "fs_wide", "fs_wg_per_cu")
+PLAN_PARAMS = ("fs_passes", "fs_wide", "fs_wg_per_cu", "fs_ring")
 
 
 def apply(plan, table, limbs, batch):
@@ -154,12 +155,16 @@ def serving_batches(table, log_ns, level, batch_ms=None):
 
 
 def ntt_candidates(log_n, mfma):
-    """(algo, fs_passes, fs_wide, fs_wg_per_cu) tuples to time."""
-    cands = [("butterfly", 0, 0, 0)]
+    """(algo, fs_passes, fs_wide, fs_wg_per_cu, fs_ring) tuples to time: the
+    LDS ring depth is searched where the 256-point stage takes wide items
+    (fs_wide 2 at N >= 2^13); narrow items have one depth."""
+    cands = [("butterfly", 0, 0, 0, 0)]
     if mfma:
-        cands += [("mfma", 2, wide, w) for wide in NTT_WIDE_CANDIDATES for w in NTT_WG_CANDIDATES]
+        for wide in NTT_WIDE_CANDIDATES:
+            rings = NTT_RING_CANDIDATES if wide == 2 and log_n >= 13 else (0,)
+            cands += [("mfma", 2, wide, w, ring) for w in NTT_WG_CANDIDATES for ring in rings]
         if 12 <= log_n <= 15:
-            cands += [("mfma", 1, 0, 0)]
+            cands += [("mfma", 1, 0, 0, 0)]
     return cands
 
 
@@ -169,10 +174,11 @@ def _time_candidate(plan, cand, x, y, z, ws, reps, trials):
     the round trip is the identity."""
     import statistics
     import torch
-    algo, passes, wide, w = cand
+    algo, passes, wide, w, ring = cand
     plan.set_param("fs_passes", passes)
     plan.set_param("fs_wide", wide)
     plan.set_param("fs_wg_per_cu", w)
+    plan.set_param("fs_ring", ring)
     for _ in range(2):
         plan.fwd(x, out=y, algo=algo, ws=ws)
         plan.inv(y, out=z, algo=algo, ws=ws)
@@ -186,7 +192,7 @@ def _time_candidate(plan, cand, x, y, z, ws, reps, trials):
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) / reps)
     if not torch.equal(z, x):
-        raise RuntimeError(f"autotune: {algo}/{passes}/{wide}/{w} failed the round trip")
+        raise RuntimeError(f"autotune: {algo}/{passes}/{wide}/{w}/{ring} failed the round trip")
     return statistics.median(times)
 
 
@@ -206,7 +212,7 @@ def tune_ntt(plan, x, reps=5, trials=3, finalists=3, rounds=3):
     ws = plan.workspace(limbs, batch, "mfma" if mfma else "butterfly")
     old = {name: plan.get_param(name) for name in PLAN_PARAMS}
     first = [(c, _time_candidate(plan, c, x, y, z, ws, reps, trials)) for c in cands]
-    default = ("mfma", 0, 0, 0) if mfma else ("butterfly", 0, 0, 0)
+    default = ("mfma", 0, 0, 0, 0) if mfma else ("butterfly", 0, 0, 0, 0)
     top = [c for c, _ in sorted(first, key=lambda r: r[1])[:finalists]]
     if default not in top:
         top.append(default)
@@ -220,7 +226,7 @@ def tune_ntt(plan, x, reps=5, trials=3, finalists=3, rounds=3):
     kops = lambda t: units / t / 1e3
     scored = {c: statistics.median(ts) for c, ts in final.items()}
     best_c = min(scored, key=scored.get)
-    as_cfg = lambda c: {"algo": c[0], "fs_passes": c[1], "fs_wide": c[2], "fs_wg_per_cu": c[3]}
+    as_cfg = lambda c: {"algo": c[0], "fs_passes": c[1], "fs_wide": c[2], "fs_wg_per_cu": c[3], "fs_ring": c[4]}
     best = dict(as_cfg(best_c), kops=kops(scored[best_c]), default_kops=kops(scored[default]))
     return best, [dict(as_cfg(c), kops=kops(t)) for c, t in first]
 

@@ -196,6 +196,10 @@ tfhe_status tfhe_ntt_plan_set_param(tfhe_ntt_plan plan, tfhe_plan_param param, i
       if (value < 0 || value > 2) return fail(TFHE_EINVAL, "ks_inner must be 0, 1 or 2");
       plan->ks_inner = (uint32_t)value;
       return TFHE_OK;
+    case TFHE_PARAM_FS_RING:
+      if (value != 0 && value != 2 && value != 3) return fail(TFHE_EINVAL, "fs_ring must be 0, 2 or 3");
+      plan->fs_ring = (uint32_t)value;
+      return TFHE_OK;
   }
   return fail(TFHE_EINVAL, "unknown plan parameter");
 }
@@ -208,6 +212,7 @@ tfhe_status tfhe_ntt_plan_get_param(tfhe_ntt_plan plan, tfhe_plan_param param, i
     case TFHE_PARAM_FS_WIDE: *value = plan->fs_wide; return TFHE_OK;
     case TFHE_PARAM_FS_PASSES: *value = plan->fs_passes; return TFHE_OK;
     case TFHE_PARAM_KS_INNER: *value = plan->ks_inner; return TFHE_OK;
+    case TFHE_PARAM_FS_RING: *value = plan->fs_ring; return TFHE_OK;
   }
   return fail(TFHE_EINVAL, "unknown plan parameter");
 }

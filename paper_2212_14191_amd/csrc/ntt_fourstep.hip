@@ -32,8 +32,9 @@
 //
 // Data movement.  A work item is P rows x W columns (vectors) of one
 // polynomial, 1024 words per wave (4 waves, or 8 for the wide items of the
-// 256-point stage).  Items are staged through a three-deep LDS ring by
-// direct-to-LDS loads issued two items ahead.  Each wave transforms four
+// 256-point stage).  Items are staged through an LDS ring of three stages
+// (two by default for the wide items, a plan parameter) by direct-to-LDS
+// loads issued two (one) items ahead.  Each wave transforms four
 // sets of vectors; a set fills the 16 rows of one MFMA tile with 16 / r
 // vectors.  The intermediate array between the passes is tiled: block kb of
 // 16 consecutive pass-1 outputs holds, for every pass-1 column c, the 16
@@ -54,8 +55,6 @@
 
 namespace tfhe {
 namespace {
-
-constexpr int kStages = 3;   // LDS ring depth (items)
 
 // Geometry of a pass with P = 16 kR points.  A work item is P rows x W
 // vectors (columns) of one polynomial, 1024 words per wave; each wave
@@ -130,29 +129,30 @@ __device__ __forceinline__ void issue_tile(const uint32_t* src, const uint32_t* 
 // Wait until this wave's loads of the current item have landed.  Vector
 // memory operations of a wave complete in issue order, so it suffices that at
 // most as many operations remain outstanding as were issued after those
-// loads: in steady state the stores of the two previous items (kSt each:
-// 16 in the narrow first passes, 4 otherwise) and the loads of the next item
-// (4); fewer near the start; without a next item everything is awaited.
-// Table loads issued in between only make the wait stricter.
-template <int kSt>
+// loads.  With a ring of kRing stages the loads of item n are issued kRing - 1
+// items ahead; each item then issues, in order, its epilogue loads (kE: 8
+// with the store epilogue, else 0), the 4 ring loads of the item kRing - 1
+// ahead and its kSt stores (16 in the narrow first passes, 4 otherwise).  In
+// steady state that leaves the stores of item n - kRing + 1 and everything of
+// the kRing - 2 items after it; near the start, the prologue's later loads
+// and the first items' operations.  Without a next item everything is
+// awaited.  Table loads issued in between only make the wait stricter.
+template <int kRing, int kSt, int kE>
 __device__ __forceinline__ void wait_item(uint32_t n, bool has_next) {
-  constexpr int st = kSt;
+  static_assert(kRing == 2 || kRing == 3, "ring depth");
+  constexpr int per = kE + 4 + kSt;  // operations of one item
   if (!has_next) wait_vmcnt<0>();
-  else if (n == 0) wait_vmcnt<4>();
-  else if (n == 1) wait_vmcnt<4 + st>();
-  else wait_vmcnt<4 + 2 * st>();
+  else if (kRing == 2) {
+    if (n == 0) wait_vmcnt<0>();
+    else wait_vmcnt<kSt>();
+  } else {
+    if (n == 0) wait_vmcnt<4>();
+    else if (n == 1) wait_vmcnt<per>();
+    else wait_vmcnt<kSt + per>();
+  }
 }
 
-// Like wait_item, for the second pass with the epilogue: each item also
-// issues its 8 epilogue loads (before the ring loads of item n + 2).
-__device__ __forceinline__ void wait_item_epi(uint32_t n, bool has_next) {
-  if (!has_next) wait_vmcnt<0>();
-  else if (n == 0) wait_vmcnt<4>();
-  else if (n == 1) wait_vmcnt<4 + 4 + 8>();
-  else wait_vmcnt<4 + 2 * 4 + 8>();
-}
-
-template <bool kFirst, int kR, bool kWide, bool kEpi = false>
+template <bool kFirst, int kR, bool kWide, bool kEpi = false, int kRing = 3>
 __global__ void __launch_bounds__(kWide ? 512 : 256, (kWide || kEpi) ? 2 : 3)
 fs_pass(const FsTable tab) {
   static_assert(!kEpi || (!kFirst && kR == 16), "the epilogue belongs to the forward second pass");
@@ -162,9 +162,9 @@ fs_pass(const FsTable tab) {
   // contiguous 256-byte run of the tiled array) and stores them with
   // 16-byte stores; the narrow first passes store 64-byte runs directly.
   constexpr bool kGather = kFirst && kWide;
-  __shared__ __attribute__((aligned(16))) uint32_t ring[kStages * G::tile + (kGather ? G::waves * 1024 : 0)];
+  __shared__ __attribute__((aligned(16))) uint32_t ring[kRing * G::tile + (kGather ? G::waves * 1024 : 0)];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  uint32_t* const gather = kGather ? ring + kStages * G::tile + wave * 1024 : ring;
+  uint32_t* const gather = kGather ? ring + kRing * G::tile + wave * 1024 : ring;
   const int i16 = lane & 15, g = lane >> 4;
   const Walk walk = make_walk(tab.total, tab.ipp_log);
   if (walk.p >= walk.p_end) return;
@@ -198,7 +198,7 @@ fs_pass(const FsTable tab) {
     issue_tile<G::pitch>(tab.u[it.unit].in + it.in_base, ld_off, ring + stage * G::tile, wave);
   };
 #pragma unroll
-  for (int j = 0; j < kStages - 1; ++j)
+  for (int j = 0; j < kRing - 1; ++j)
     if (walk.p + j * walk.step < walk.p_end) issue(walk.p + j * walk.step, j);
 
   const FourStepLimb* cur_limb = nullptr;
@@ -212,7 +212,7 @@ fs_pass(const FsTable tab) {
   uint2 pf[4];     // kR < 16, pass 2: per-output factor
   int st = 0;
   uint32_t n = 0;
-  for (uint32_t p = walk.p; p < walk.p_end; p += walk.step, ++n, st = (st + 1 == kStages) ? 0 : st + 1) {
+  for (uint32_t p = walk.p; p < walk.p_end; p += walk.step, ++n, st = (st + 1 == kRing) ? 0 : st + 1) {
     const Item it = locate(tab, p, kc);
     const FourStepLimb* limb = tab.u[it.unit].limbs + it.limb;
     if (limb != cur_limb) {
@@ -252,8 +252,7 @@ fs_pass(const FsTable tab) {
       cur_limb = limb;
     }
     const bool has_next = p + walk.step < walk.p_end;
-    if (kEpi) wait_item_epi(n, has_next);
-    else wait_item<kFirst && !kWide ? 16 : 4>(n, has_next);
+    wait_item<kRing, kFirst && !kWide ? 16 : 4, kEpi ? 8 : 0>(n, has_next);
     lds_barrier();  // the item's tile is complete; the oldest stage is free
     uint4 e_acc[4], e_out[4];  // epilogue operands at the item's store positions
     if (kEpi) {
@@ -269,8 +268,8 @@ fs_pass(const FsTable tab) {
         e_out[j] = *(const uint4*)(eo + it.poly_base + st_off[j]);
       }
     }
-    const bool issued = p + (kStages - 1) * walk.step < walk.p_end;
-    if (issued) issue(p + (kStages - 1) * walk.step, (st + kStages - 1) % kStages);
+    const bool issued = p + (kRing - 1) * walk.step < walk.p_end;
+    if (issued) issue(p + (kRing - 1) * walk.step, (st + kRing - 1) % kRing);
 
     // lane (i, g) of wave w reads row kR (4g + c) + i % kR of the quad
     // w Mt + i / kR (four vectors, one per set): for 16 lanes either 256
@@ -409,30 +408,46 @@ fs_pass(const FsTable tab) {
 }
 
 // Resident workgroups per CU of a pass kernel (queried once per process).
-template <bool kFirst, int kR, bool kWide, bool kEpi>
+template <bool kFirst, int kR, bool kWide, bool kEpi, int kRing>
 uint32_t occupancy() {
   static std::atomic<int> occ{0};
-  return (uint32_t)occupancy_cached(occ, fs_pass<kFirst, kR, kWide, kEpi>, Geo<kFirst, kR, kWide>::threads);
+  return (uint32_t)occupancy_cached(occ, fs_pass<kFirst, kR, kWide, kEpi, kRing>, Geo<kFirst, kR, kWide>::threads);
 }
 
 // Persistent grid: a multiple of 16 workgroups, no more than the items need.
-template <bool kFirst, int kR, bool kWide, bool kEpi>
+template <bool kFirst, int kR, bool kWide, bool kEpi, int kRing>
 uint32_t grid_size(const tfhe_ntt_plan_s* p, uint32_t items) {
-  // default: the resident count; twice that for the wide kernels (one
-  // resident workgroup per CU), whose tail balances better with the second
-  // half of the grid scheduled as the first half drains (measured)
-  const uint32_t w = p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide, kEpi>() * (kWide ? 2 : 1);
+  // default: the resident count; twice that for the wide kernels (one or
+  // two resident workgroups per CU), whose tail balances better with the
+  // second half of the grid scheduled as the first half drains (measured)
+  const uint32_t w =
+      p->fs_wg_per_cu ? p->fs_wg_per_cu : occupancy<kFirst, kR, kWide, kEpi, kRing>() * (kWide ? 2 : 1);
   const uint32_t g = std::max(16u, (p->num_cus * w) / 16 * 16);
   return std::min(g, (items + 15) / 16 * 16);
 }
 
-template <bool kFirst, int kR, bool kWide, bool kEpi = false>
-void launch_pass(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
+template <bool kFirst, int kR, bool kWide, bool kEpi, int kRing>
+void launch_ring(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
   using G = Geo<kFirst, kR, kWide>;
   t.ipp_log = t.log_n - (kWide ? 13 : 12);  // items per polynomial: N / item words
-  const uint32_t grid = grid_size<kFirst, kR, kWide, kEpi>(p, t.total << t.ipp_log);
+  const uint32_t grid = grid_size<kFirst, kR, kWide, kEpi, kRing>(p, t.total << t.ipp_log);
   TFHE_TIMED(kFirst ? K_FS_PASS1 : K_FS_PASS2, s,
-             hipLaunchKernelGGL((fs_pass<kFirst, kR, kWide, kEpi>), dim3(grid), dim3(G::threads), 0, s, t));
+             hipLaunchKernelGGL((fs_pass<kFirst, kR, kWide, kEpi, kRing>), dim3(grid), dim3(G::threads), 0, s, t));
+}
+
+// LDS ring depth of a pass: for the wide items of the 256-point stage the
+// plan's fs_ring, by default 2 (measured 1-2 % faster than 3 at N = 2^15
+// and 2^16); narrow items keep 3 (2 measured 5-20 % slower at N = 2^12..
+// 2^14, and the narrow first passes would spill registers).
+template <bool kFirst, int kR, bool kWide, bool kEpi = false>
+void launch_pass(const tfhe_ntt_plan_s* p, FsTable t, hipStream_t s) {
+  if constexpr (kWide) {
+    if (p->fs_ring != 3) {
+      launch_ring<kFirst, kR, kWide, kEpi, 2>(p, t, s);
+      return;
+    }
+  }
+  launch_ring<kFirst, kR, kWide, kEpi, 3>(p, t, s);
 }
 
 // The 256-point stage uses wide items by default when the pass has >= 128

@@ -192,7 +192,7 @@ class NttPlan:
             self.q.append(a.value)
             self.psi.append(b.value)
 
-    PARAMS = {"fs_wg_per_cu": 1, "auto_algo": 2, "fs_wide": 3, "fs_passes": 4, "ks_inner": 5}
+    PARAMS = {"fs_wg_per_cu": 1, "auto_algo": 2, "fs_wide": 3, "fs_passes": 4, "ks_inner": 5, "fs_ring": 6}
 
     def set_param(self, name, value):
         _call("tfhe_ntt_plan_set_param", self.handle, self.PARAMS[name], int(value))

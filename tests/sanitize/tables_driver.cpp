@@ -26,12 +26,17 @@ int main() {
     uint32_t ln = 0, nl = 0;
     tfhe_ntt_algo a;
     EXPECT(tfhe_ntt_plan_info(p, &ln, &nl, &a) == TFHE_OK && ln == log_n && nl == 3);
-    for (int param = 1; param <= 4; ++param) {
+    for (int param = 1; param <= 6; ++param) {
       int64_t v = -1;
       EXPECT(tfhe_ntt_plan_get_param(p, (tfhe_plan_param)param, &v) == TFHE_OK);
     }
     EXPECT(tfhe_ntt_plan_set_param(p, TFHE_PARAM_FS_PASSES, 1) == TFHE_OK);
     EXPECT(tfhe_ntt_plan_set_param(p, TFHE_PARAM_FS_PASSES, 3) == TFHE_EINVAL);
+    EXPECT(tfhe_ntt_plan_set_param(p, TFHE_PARAM_FS_RING, 2) == TFHE_OK);
+    EXPECT(tfhe_ntt_plan_set_param(p, TFHE_PARAM_FS_RING, 1) == TFHE_EINVAL);
+    EXPECT(tfhe_ntt_plan_set_param(p, TFHE_PARAM_FS_RING, 4) == TFHE_EINVAL);
+    int64_t ring = 0;
+    EXPECT(tfhe_ntt_plan_get_param(p, TFHE_PARAM_FS_RING, &ring) == TFHE_OK && ring == 2);
     size_t ws = 0;
     EXPECT(tfhe_ntt_workspace_size(p, TFHE_NTT_BUTTERFLY, 3, 5, &ws) == TFHE_OK);
     uint32_t qq = 0, psi = 0;

@@ -47,7 +47,7 @@ def test_apply_and_serving_batches():
     plan = FakePlan(14)
     e = autotune.apply(plan, t, 24, 64)
     assert e["fs_passes"] == 1
-    assert plan.params == {"auto_algo": 2, "fs_passes": 1, "fs_wide": 0, "fs_wg_per_cu": 0}
+    assert plan.params == {"auto_algo": 2, "fs_passes": 1, "fs_wide": 0, "fs_wg_per_cu": 0, "fs_ring": 0}
     assert autotune.apply(FakePlan(15), t, 24, 64) is None
     assert autotune.serving_batches(t, (13, 14, 15, 16), 24) == {14: 8, 16: 32}
     # with a time budget per batch: the largest measured batch that fits
@@ -86,11 +86,14 @@ def test_ks_inner_choice_margin():
     assert autotune.ks_inner_choice({"batch": 4}) is None
 
 
-def test_search_space_covers_passes():
+def test_search_space_covers_passes_and_ring_depth():
     c14 = autotune.ntt_candidates(14, True)
-    assert ("mfma", 1, 0, 0) in c14 and ("mfma", 2, 2, 0) in c14 and ("butterfly", 0, 0, 0) in c14
-    assert all(p == 2 for a, p, _, _ in autotune.ntt_candidates(16, True) if a == "mfma")
-    assert autotune.ntt_candidates(10, False) == [("butterfly", 0, 0, 0)]
+    assert ("mfma", 1, 0, 0, 0) in c14 and ("butterfly", 0, 0, 0, 0) in c14
+    assert ("mfma", 2, 2, 0, 2) in c14 and ("mfma", 2, 2, 0, 3) in c14 and ("mfma", 2, 1, 0, 0) in c14
+    assert all(p == 2 for a, p, _, _, _ in autotune.ntt_candidates(16, True) if a == "mfma")
+    # ring depth only where the 256-point stage can take wide items
+    assert {c[4] for c in autotune.ntt_candidates(12, True)} == {0}
+    assert autotune.ntt_candidates(10, False) == [("butterfly", 0, 0, 0, 0)]
 
 
 def test_shipped_table_is_well_formed():

@@ -194,6 +194,27 @@ def test_hmult_rotate_serving_shapes_match_oracle(tf, log_n, level):
     assert np.array_equal(got_r, ckks.rotate(pr, ca, rk, k, level))
 
 
+@pytest.mark.parametrize("level", [9, 24])
+def test_ring_depth_three_matches_oracle(tf, level):
+    """HMULT, HROTATE and RESCALE at N = 2^15 (wide items) with the
+    three-stage LDS ring instead of the default two: bit-exact against the
+    oracle (the key switch's fused and epilogue passes included)."""
+    log_n = 15
+    n = 1 << log_n
+    pr, s, evk, k, rk = serving_setup(log_n)
+    ctx = tf.CkksContext(log_n, 24, 8, 3, moduli=pr.moduli)
+    ctx.plan.set_param("fs_ring", 3)
+    assert ctx.plan.get_param("fs_ring") == 3
+    m1 = inputs.small_messages(log_n, (2, n))
+    m2 = inputs.small_messages(log_n, (2, n), stream=1)
+    ca, cb = encrypt(pr, s, m1, level, 11), encrypt(pr, s, m2, level, 12)
+    got = to_host(ctx.hmult(to_dev(ca), to_dev(cb), to_dev(evk), level))
+    assert np.array_equal(got, ckks.hmult(pr, ca, cb, evk, level))
+    got_r = to_host(ctx.rotate(to_dev(ca), to_dev(rk), k, level))
+    assert np.array_equal(got_r, ckks.rotate(pr, ca, rk, k, level))
+    assert np.array_equal(to_host(ctx.rescale(to_dev(ca), level)), ckks.rescale(pr, ca, level))
+
+
 @pytest.mark.slow
 def test_rotate_full_size_level24(tf):
     """HROTATE at N = 2^16, level 24 (L = 24, K = 8, dnum = 3) on a batch of

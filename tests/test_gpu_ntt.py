@@ -95,18 +95,21 @@ def test_mfma_matches_oracle_per_prime_window(tf, log_n, window):
     assert np.array_equal(to_host(plan.inv(to_dev(x), algo="mfma")), oracle.ntt_inv(x, qs, plan.psi))
 
 
-@pytest.mark.parametrize("log_n,wide", [(12, 0), (13, 0), (14, 0), (15, 0), (13, 2), (14, 2),
-                                         (15, 1), (16, 1), (16, 2)])
-def test_mfma_equals_butterfly_ragged(tf, log_n, wide):
+@pytest.mark.parametrize("log_n,wide,ring", [(12, 0, 0), (13, 0, 0), (14, 0, 0), (15, 0, 0), (13, 2, 0),
+                                              (14, 2, 0), (15, 1, 0), (16, 1, 0), (16, 2, 0), (13, 2, 3),
+                                              (15, 0, 3), (16, 2, 3), (16, 1, 2)])
+def test_mfma_equals_butterfly_ragged(tf, log_n, wide, ring):
     """Batches whose polynomial count is not a multiple of the workgroup
     grouping (5 limbs x 37 polynomials), with the default, narrow (1) and
-    wide (2) items of the 256-point stage: MFMA == butterfly bit for bit,
-    and the MFMA round trip is the identity."""
+    wide (2) items of the 256-point stage and the two LDS ring depths of the
+    wide items (0 = default 2, 3; narrow items ignore it): MFMA == butterfly
+    bit for bit, and the MFMA round trip is the identity."""
     n = 1 << log_n
     qs = PRIMES31[:5]
     plan = tf.NttPlan(log_n, qs)
     plan.set_param("fs_wide", wide)
-    assert plan.get_param("fs_wide") == wide
+    plan.set_param("fs_ring", ring)
+    assert plan.get_param("fs_wide") == wide and plan.get_param("fs_ring") == ring
     x = to_dev(inputs.uniform_residues(7 * log_n, qs, (37, n)))
     f_m = plan.fwd(x, algo="mfma")
     f_b = plan.fwd(x, algo="butterfly")
