@@ -196,11 +196,14 @@ def cpu_baseline(qs, psis, budget_s=10.0):
 P99_BOUND_MS = 5.0
 
 
-def sustainable_rate(fn, saturated, n_req, probes=7):
+def sustainable_rate(fn, saturated, n_req, probes=7, keep_up=0.95):
     """Highest Poisson arrival rate (requests/s) whose p99 submit-to-done
-    latency stays at or below P99_BOUND_MS, by bisection on the fraction of
-    the saturated rate (each probe serves min(n_req, 4000) requests of the
-    same mix; the arrivals' seed differs from the load points')."""
+    latency stays at or below P99_BOUND_MS while the measured throughput
+    keeps up with it (at least keep_up x the rate: a backlog that grows, or
+    a submitting loop that falls behind the schedule, is not sustained), by
+    bisection on the fraction of the saturated rate (each probe serves
+    min(n_req, 4000) requests of the same mix; the arrivals' seed differs
+    from the load points')."""
     count = min(n_req, 4000)
     lo, hi, best = 0.0, 1.0, None
     for _ in range(probes):
@@ -208,11 +211,11 @@ def sustainable_rate(fn, saturated, n_req, probes=7):
         st = fn(count, 4, frac * saturated)
         rec = {"rate_per_s": round(frac * saturated, 1), "throughput_per_s": round(st["throughput_per_s"], 1),
                "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)}
-        if st["p99_ms"] <= P99_BOUND_MS:
+        if st["p99_ms"] <= P99_BOUND_MS and st["throughput_per_s"] >= keep_up * frac * saturated:
             lo, best = frac, rec
         else:
             hi = frac
-    return {"p99_bound_ms": P99_BOUND_MS, "requests_per_probe": count, "probes": probes,
+    return {"p99_bound_ms": P99_BOUND_MS, "keep_up": keep_up, "requests_per_probe": count, "probes": probes,
             "rate_per_s": best["rate_per_s"] if best else 0.0, "at_rate": best}
 
 
