@@ -235,13 +235,22 @@ def test_deterministic(tf):
 
 
 @pytest.mark.slow
-def test_full_size_44x128_sampled(tf):
+@pytest.mark.parametrize("launch", ["tuned", "default"])
+def test_full_size_44x128_sampled(tf, launch):
     """Config 2/3 shape (N=2^16, 44 limbs, 128 polynomials) in the launch
-    configuration the benchmark times: MFMA == butterfly everywhere, round
-    trip everywhere, and sampled (limb, poly) units equal the oracle."""
+    configuration the benchmark times (the shipped tune table applied to the
+    plan, as bench.py does) and in the library default: MFMA == butterfly
+    everywhere, round trip everywhere, and sampled (limb, poly) units equal
+    the oracle."""
+    from paper_2212_14191_amd import autotune
     n = 1 << 16
     qs = oracle.ntt_primes(44, 31, 1 << 17)
+    assert list(qs) == list(tf.tfhe_find_primes(31, 1 << 17, 44))  # bench.py's primes
     plan = tf.NttPlan(16, qs)
+    if launch == "tuned":
+        table = autotune.load_default()
+        if autotune.apply(plan, table, 44, 128) is None:
+            pytest.skip("no tune table entry for this shape")
     x_host = inputs.uniform_residues(0, qs, (128, n))
     x = to_dev(x_host)
     ws = plan.workspace(44, 128, "mfma")
