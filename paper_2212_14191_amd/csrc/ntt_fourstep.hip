@@ -478,8 +478,8 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 // product (Sec. IV-A, Table 2: NTT, then Inner-product): a workgroup takes
 // one level group's extended-basis position t, batch element b and column
 // block (an "item"), and for every digit j (a "task") either runs the second
-// pass (the 256-point stage, narrow 16-vector item) on digit j's tiled
-// intermediate of t, or, for the digit that holds t, takes d2[t] as it is;
+// pass (the 256-point stage) on digit j's tiled intermediate of t, or, for
+// the digit that holds t, takes d2[t] as it is;
 // it multiplies the result by evk_j[c][t] at its natural positions and, after
 // the last digit, writes acc_0 and acc_1 once.  The transformed limbs are
 // never written: the separate transform store and the inner product's re-read
@@ -492,10 +492,15 @@ void launch_pass_r(const tfhe_ntt_plan_s* p, uint32_t r, const FsTable& t, hipSt
 // buffer as soon as this task's has landed, so one load is always in flight
 // behind the arithmetic.  Keys and d2 are loaded into each wave's own slots
 // of the output layout (slot (4 wave + j, lane) = natural positions st_off).
-__global__ void __launch_bounds__(256, 2)
+// Items are the wide ones of the 256-point stage (8 waves, 32 vectors: every
+// load and store a whole 128-byte line, 144 KiB of LDS, one workgroup per
+// CU) wherever N >= 2^13, else the narrow ones (4 waves, 16 vectors, two
+// workgroups per CU); wide measured 2 % faster for this kernel at 2^16.
+template <bool kWide>
+__global__ void __launch_bounds__(kWide ? 512 : 256, kWide ? 1 : 2)
 ip_pass(const IpSet set, const FourStepLimb* __restrict__ limbs, const ModConst* __restrict__ mods,
         uint32_t log_n, uint32_t ipp, uint32_t items) {
-  using G = Geo<false, 16, false>;
+  using G = Geo<false, 16, kWide>;
   // two source buffers, then the key blocks of components 0 and 1
   __shared__ __attribute__((aligned(16))) uint32_t lds[4 * G::tile];
   uint32_t* const kbuf = lds + 2 * G::tile;
@@ -977,13 +982,12 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
   return hipGetLastError();
 }
 
-hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
-  if (set.count == 0) return hipSuccess;
-  if (!p->has_mfma) return hipErrorInvalidValue;
-  using G = Geo<false, 16, false>;
-  const uint32_t ipp = p->n / G::item;  // second-pass items per polynomial
+template <bool kWide>
+static hipError_t ip_launch(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
+  using G = Geo<false, 16, kWide>;
+  const uint32_t ipp = p->n / G::item;  // second-pass items per polynomial (>= 1)
   static std::atomic<int> occ{0};
-  const int resident = occupancy_cached(occ, ip_pass, G::threads);
+  const int resident = occupancy_cached(occ, ip_pass<kWide>, G::threads);
   uint64_t items = 0;
   for (uint32_t g = 0; g < set.count; ++g) {
     set.g[g].item0 = (uint32_t)items;
@@ -993,9 +997,18 @@ hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
   if (items >= (1ull << 32)) return hipErrorInvalidValue;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(items, (uint64_t)p->num_cus * resident);
   TFHE_TIMED(K_IP, s,
-             hipLaunchKernelGGL(ip_pass, dim3(grid), dim3(G::threads), 0, s, set, p->d_fs_fwd, p->d_mod, p->log_n,
-                                ipp, (uint32_t)items));
+             hipLaunchKernelGGL(ip_pass<kWide>, dim3(grid), dim3(G::threads), 0, s, set, p->d_fs_fwd, p->d_mod,
+                                p->log_n, ipp, (uint32_t)items));
   return hipGetLastError();
+}
+
+hipError_t ip_run(const tfhe_ntt_plan_s* p, IpSet& set, hipStream_t s) {
+  if (set.count == 0) return hipSuccess;
+  if (!p->has_mfma) return hipErrorInvalidValue;
+  // wide items need 32 columns of the 256-point stage (N >= 2^13); a plan
+  // that asks for narrow items (fs_wide 1) keeps them here too
+  if (p->fs_wide != 1 && (p->n >> 8) >= 32) return ip_launch<true>(p, set, s);
+  return ip_launch<false>(p, set, s);
 }
 
 hipError_t co_transform(const tfhe_ntt_plan_s* p, bool inverse, const uint32_t* in, uint32_t* out,

@@ -393,7 +393,8 @@ def test_rotate_multi_at_the_batch_limit(tf):
     (12, 8, 4, 2, 8, 3), (13, 24, 8, 3, 17, 2), (14, 12, 2, 6, 11, 2), (16, 24, 8, 3, 24, 3), (12, 8, 1, 1, 8, 2)])
 def test_fused_inner_product_equals_separate(tf, log_n, L, K, dnum, level, B):
     """Key switching with the ModUp transforms' second pass fused with the
-    inner product (the default) and with the separate kernels: HMULT and a
+    inner product (the default; wide items from N = 2^13, and narrow ones
+    when the plan asks for them) and with the separate kernels: HMULT and a
     mixed-amount HROTATE batch give the same bits, and the fused HMULT equals
     the oracle (including K < alpha, where digits outnumber special primes)."""
     n = 1 << log_n
@@ -406,11 +407,14 @@ def test_fused_inner_product_equals_separate(tf, log_n, L, K, dnum, level, B):
     gal = [ckks.galois_element(1 + b, n) for b in range(B)]
     rks = [to_dev(ckks.rotation_key(pr, s, k, a, e)) for k in gal]
     got = {}
-    for mode in (1, 2):
+    for mode, wide in ((1, 0), (2, 0), (1, 1)):
         ctx.plan.set_param("ks_inner", mode)
-        got[mode] = (ctx.hmult(A, Bt, E, level).clone(), ctx.rotate_multi(A, rks, gal, level).clone())
-    assert torch.equal(got[1][0], got[2][0])
-    assert torch.equal(got[1][1], got[2][1])
+        ctx.plan.set_param("fs_wide", wide)
+        got[mode, wide] = (ctx.hmult(A, Bt, E, level).clone(), ctx.rotate_multi(A, rks, gal, level).clone())
+    for k in ((2, 0), (1, 1)):
+        assert torch.equal(got[1, 0][0], got[k][0]), k
+        assert torch.equal(got[1, 0][1], got[k][1]), k
+    got[1] = got[1, 0]
     b0 = 0 if log_n < 16 else B - 1
     want = ckks.hmult(pr, ca[:, :, b0:b0 + 1], cb[:, :, b0:b0 + 1], evk, level)
     assert np.array_equal(to_host(got[1][0])[:, :, b0:b0 + 1], want)
