@@ -117,11 +117,15 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *                            (8 waves) whenever N >= 2^13
  *   TFHE_PARAM_FS_PASSES     HBM round trips of a four-step transform
  *                            (the paper's Stages 1-5 as one pipeline,
- *                            Sec. IV-C): 0 = library default, 1 = one (the
- *                            polynomial stays in LDS; N = 2^12..2^15, and not
- *                            for the ModDown / RESCALE epilogue, which keep
- *                            two), 2 = two (a transposed intermediate in the
- *                            workspace between two passes)
+ *                            Sec. IV-C): 1 = one (the polynomial stays in
+ *                            LDS; N = 2^12..2^15, not for the key switch's
+ *                            fused passes or the ModDown / RESCALE
+ *                            epilogue, which keep two), 2 = two (a
+ *                            transposed intermediate in the workspace
+ *                            between two passes), 0 = library default: one
+ *                            at N = 2^12..2^14 for launches of at least two
+ *                            polynomials per compute unit, else two.  Same
+ *                            results.
  *   TFHE_PARAM_KS_INNER      key switching with a four-step plan (the plan
  *                            of a CKKS context): 0 = library default (1),
  *                            1 = the ModUp transforms' second pass fused

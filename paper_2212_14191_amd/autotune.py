@@ -120,14 +120,15 @@ def ks_inner_choice(entry):
 def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     """Tuned plan parameters of a CKKS context's transforms and its key
     switching variant (the inner product fused into the transforms or not).
-    The key switch keeps its transforms on two passes: the one-pass kernel
-    gains only 2-4 % of an HMULT at batch 16-64 (its fused ModUp and
-    ModDown transforms stay two-pass) and loses 10-20 % at batch 1-4 at
-    N = 2^14, where one workgroup per polynomial leaves most CUs idle.
-    Returns the applied entries."""
+    A one-pass choice becomes the library default (fs_passes 0) here: the
+    key switch's plain transforms (the INTT of d2 and of the special limbs)
+    then take one pass for launches with at least two polynomials per CU,
+    which measured 2-8 % faster HMULT at N = 2^12..2^14 and batch 8-64,
+    and two below, where one pass would leave CUs idle (10-20 % slower at
+    batch 1-4).  Returns the applied entries."""
     e = apply(ctx.plan, table, limbs, batch)
     if e is not None and e.get("fs_passes") == 1:
-        ctx.plan.set_param("fs_passes", 2)
+        ctx.plan.set_param("fs_passes", 0)
     h = table.get(hmult_key(ctx.log_n, level))
     choice = ks_inner_choice(h) if h else None
     if choice is not None:

@@ -83,7 +83,7 @@ struct tfhe_plan_impl {
   uint32_t num_cus = 256;         // compute units of the device
   uint32_t fs_wg_per_cu = 0;      // persistent four-step workgroups per CU (0: occupancy)
   uint32_t fs_wide = 0;           // 256-point stage items: 0 auto, 1 narrow, 2 wide when possible
-  uint32_t fs_passes = 0;         // four-step HBM passes: 0 auto, 1 one pass (N = 2^12..2^15), 2 two
+  uint32_t fs_passes = 0;         // four-step HBM passes: 0 auto (one at 2^12..2^14 for large launches), 1 one, 2 two
   uint32_t fs_ring = 0;           // LDS ring stages of the wide-item passes: 0 auto (2), 2, 3
   uint32_t ks_inner = 0;          // key switching: 0 default (fused), 1 fused second pass + inner product, 2 separate
   std::vector<uint32_t> q, psi;

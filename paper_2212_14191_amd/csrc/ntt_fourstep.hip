@@ -912,10 +912,17 @@ size_t fs_workspace_bytes(const tfhe_ntt_plan_s* p, uint32_t limb_count, uint32_
   return (size_t)limb_count * batch * p->n * sizeof(uint32_t);
 }
 
-// Whether four-step transforms of this plan take the one-pass kernel.
-static bool use_onepass(const tfhe_ntt_plan_s* p) {
+// Whether a launch of `polys` four-step transforms of this plan takes the
+// one-pass kernel: always with fs_passes 1, never with 2; by default at
+// N = 2^12..2^14 when the launch gives every CU at least two polynomials
+// (one workgroup holds one whole polynomial, so a smaller launch leaves CUs
+// idle: HMULT at N = 2^14, batch 1-4, ran 10-20 % slower with every
+// transform on it; with the rule HMULT at batch 8-64 is 2-8 % faster at
+// 2^12..2^14 and unchanged below; at 2^15 the kernel is slower).
+static bool use_onepass(const tfhe_ntt_plan_s* p, uint64_t polys) {
   if (!op_supported(p->log_n) || p->fs_passes == 2) return false;
-  return p->fs_passes == 1;
+  if (p->fs_passes == 1) return true;
+  return p->log_n <= 14 && polys >= 2ull * p->num_cus;
 }
 
 // Fused launches: units are grouped by (N, direction), in order of first
@@ -952,8 +959,16 @@ hipError_t fs_run_units(const NttUnit* units, uint32_t count, void* ws, hipStrea
     t1.cols = inverse ? N1 : 256;  // N / P of pass 1
     t2.cols = inverse ? 256 : N1;
     const uint32_t r1 = inverse ? 16 : r, r2 = inverse ? r : 16;
-    // one HBM round trip where the one-pass kernel covers the shape
-    const bool one = !epi && !p1only && !bcast && use_onepass(p0);
+    // one HBM round trip where the one-pass kernel covers the shape and
+    // the group's polynomials fill the CUs
+    uint64_t group_polys = 0;
+    for (uint32_t k = lead; k < count; ++k) {
+      const NttUnit& u = units[k];
+      if (!done[k] && u.plan->log_n == log_n && u.inverse == inverse && (u.acc != nullptr) == epi &&
+          u.pass1_only == p1only && u.in_bcast == bcast)
+        group_polys += (uint64_t)u.limb_count * u.batch;
+    }
+    const bool one = !epi && !p1only && !bcast && use_onepass(p0, group_polys);
     auto flush = [&]() {
       if (t1.total == 0) return;
       if (one) {

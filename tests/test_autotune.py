@@ -63,16 +63,17 @@ class FakeCtx:
         self.plan = FakePlan(log_n)
 
 
-def test_apply_ckks_keeps_two_passes():
+def test_apply_ckks_takes_tuned_shape():
     """A context's key switch takes the tuned launch shape and inner-product
-    variant but keeps two-pass transforms, whatever the NTT entry says."""
+    variant; a one-pass choice becomes the library default, which takes one
+    pass only for launches that fill the CUs."""
     t = autotune.TuneTable()
     t.put(autotune.ntt_key(14, 24, 64), {"algo": "mfma", "fs_passes": 1, "fs_wide": 1, "fs_wg_per_cu": 2})
     t.put(autotune.hmult_key(14, 24), {"batch": 32, "ks_inner": 1})
     ctx = FakeCtx(14)
     got = autotune.apply_ckks(ctx, t)
     assert got["ks_inner"] == 1 and got["ntt"]["fs_passes"] == 1
-    assert ctx.plan.params["fs_passes"] == 2 and ctx.plan.params["fs_wide"] == 1
+    assert ctx.plan.params["fs_passes"] == 0 and ctx.plan.params["fs_wide"] == 1
     assert ctx.plan.params["ks_inner"] == 1
 
 

@@ -374,6 +374,10 @@ def test_mfma_one_pass_large_batch_equals_two_pass(tf, log_n):
     f1, i1 = plan.fwd(x, algo="mfma"), plan.inv(x, algo="mfma")
     assert torch.equal(f1, f2)
     assert torch.equal(i1, i2)
+    # the library default (one pass at N <= 2^14 for launches this large)
+    plan.set_param("fs_passes", 0)
+    assert torch.equal(plan.fwd(x, algo="mfma"), f2)
+    assert torch.equal(plan.inv(x, algo="mfma"), i2)
     xs = to_host(x)
     for l, b in ((0, 0), (3, 128), (7, 64)):
         got = to_host(f1)[l:l + 1, b:b + 1]
