@@ -44,6 +44,9 @@ I8_OPS_PER_COEFF_PASS = 8 * 16 * 16 * 64 * 2 // 256
 TRAFFIC_SOURCES = ("csrc/ntt_fourstep.hip", "csrc/fourstep_dev.hpp", "csrc/internal.hpp", "csrc/modarith.hpp",
                    "csrc/plan.cpp", "tune_mi355x.json")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ntt_mfma_n16_44x128.md")
+# the HMULT benchmark's kernels: the transforms plus the key-switching code
+HMULT_SOURCES = TRAFFIC_SOURCES + ("csrc/ckks.cpp", "csrc/ckks_kernels.hip", "csrc/ckks_internal.hpp")
+HMULT_PROFILE = os.path.join(ROOT, "profiles", "hmult_n16_l24_b64.md")
 
 
 def _code_only(text):
@@ -54,9 +57,9 @@ def _code_only(text):
     return "\n".join(l for l in lines if l.strip())
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=TRAFFIC_SOURCES):
     h = hashlib.sha256()
-    for rel in TRAFFIC_SOURCES:
+    for rel in sources:
         path = os.path.join(ROOT, "paper_2212_14191_amd", rel)
         if os.path.exists(path):
             with open(path) as f:
@@ -64,18 +67,37 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profile_record(key):
-    """The JSON record `key: {...}` of the committed rocprofv3 summary, or
+def profile_record(key, path=TRAFFIC_PROFILE, sources=TRAFFIC_SOURCES):
+    """The JSON record `key: {...}` of a committed rocprofv3 summary, or
     None when it is missing or was taken from different kernel sources."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(path) as f:
             m = re.search(r"^" + key + r": (\{.*\})$", f.read(), re.M)
         d = json.loads(m.group(1)) if m else None
     except (OSError, ValueError):
         return None
-    if not d or d.get("source_sha256") != kernel_source_hash():
+    if not d or d.get("source_sha256") != kernel_source_hash(sources):
         return None
     return d
+
+
+def hmult_roofline(ops_per_s, n, L, K, dnum, batch):
+    """HMULT against the 8 TB/s HBM peak, two ways: with the algorithmic
+    bytes of one HMULT (the two input ciphertexts and the output, [2][L][N]
+    words each, and a 1/batch share of the key, [dnum][2][L+K][N]), and with
+    the bytes its kernels move, as the committed counter summary records
+    them (None when missing or stale)."""
+    alg = 4 * n * (6 * L) + 4 * n * 2 * dnum * (L + K) / batch
+    rec = profile_record("hmult_traffic", HMULT_PROFILE, HMULT_SOURCES)
+    meas = rec.get("bytes_per_hmult") if rec else None
+    out = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "algorithmic_bytes_per_op": round(alg),
+           "achieved_algorithmic": round(ops_per_s * alg / 1e9, 1),
+           "frac_algorithmic": round(ops_per_s * alg / 1e9 / HBM_PEAK_GBS, 4),
+           "measured_bytes_per_op": meas, "achieved_measured": None, "frac_measured": None}
+    if meas:
+        out["achieved_measured"] = round(ops_per_s * meas / 1e9, 1)
+        out["frac_measured"] = round(ops_per_s * meas / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def measured_traffic(kernel):
@@ -503,6 +525,7 @@ def main():
         tfhe.tfhe_timing_enable(False)
         hmult = {"ops_per_s": HM_BATCH * args.hmult_steps / dt, "ms_per_batch": 1e3 * dt / args.hmult_steps,
                  "batch": HM_BATCH, "level": level, "kernels": kern}
+        hmult["roofline"] = hmult_roofline(hmult["ops_per_s"], n, HM_L, HM_K, HM_DNUM, HM_BATCH)
         log("hmult", json.dumps(hmult))
         # RESCALE of the HMULT results (level 24 -> 23), same batch
         rs_out = torch.empty((2, level - 1, HM_BATCH, n), dtype=torch.int32, device="cuda")
