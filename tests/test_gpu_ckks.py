@@ -509,6 +509,28 @@ def test_levels_batch_full_size(tf):
     assert np.array_equal(got[1], want)
 
 
+@pytest.mark.parametrize("log_n", [13, 14])
+def test_hmult_default_one_pass_at_large_batch(tf, log_n):
+    """HMULT at a batch large enough (24 limbs x 24 ciphertexts, at least two
+    polynomials per CU) for the library default to put the key switch's plain
+    transforms on the one-pass kernel: equal to the all-two-pass HMULT, and
+    the first and last ciphertexts equal the oracle."""
+    n, level, B = 1 << log_n, 24, 24
+    pr, s, evk, _ = setup(n, 24, 8, 3)
+    ctx = tf.CkksContext(log_n, 24, 8, 3, moduli=pr.moduli)
+    m1 = inputs.small_messages(log_n, (B, n))
+    m2 = inputs.small_messages(log_n, (B, n), stream=5)
+    ca, cb = encrypt(pr, s, m1, level, 71), encrypt(pr, s, m2, level, 72)
+    A, Bt, E = to_dev(ca), to_dev(cb), to_dev(evk)
+    assert ctx.plan.get_param("fs_passes") == 0
+    auto = to_host(ctx.hmult(A, Bt, E, level))
+    ctx.plan.set_param("fs_passes", 2)
+    assert np.array_equal(auto, to_host(ctx.hmult(A, Bt, E, level)))
+    for b in (0, B - 1):
+        want = ckks.hmult(pr, ca[:, :, b:b + 1], cb[:, :, b:b + 1], evk, level)
+        assert np.array_equal(auto[:, :, b:b + 1], want), b
+
+
 @pytest.mark.parametrize("log_n,level,B", [(12, 8, 3), (13, 17, 3), (14, 24, 2), (15, 9, 2)])
 def test_hmult_one_pass_transforms_match_oracle(tf, log_n, level, B):
     """HMULT with every transform of the key switch that can take it on the
