@@ -197,3 +197,23 @@ def test_model_reduces_to_schoolbook_without_key_switching():
     want = [sum(a[i] * b[(x - i) % pr.n] * (1 if i <= x else -1) for i in range(pr.n)) % Q
             for x in range(pr.n)]
     assert out[0][0] == want and out[0][1] == [0] * pr.n
+
+
+def test_cmult_hadd_equal_bigint_model():
+    """CMULT and HADD (Sec. II-B; element-wise in the NTT domain) equal the
+    negacyclic product with the plaintext and the sum of the integer
+    polynomials modulo Q_l."""
+    pr = ckks.Params(16, 6, 2, 3)
+    level = 5
+    ints, _, nts, _ = _setup(pr, level, 2, 23)
+    Q = _prod(pr.q[:level])
+    # the second ciphertext's first component serves as the plaintext
+    got_c = _coeffs(pr, ckks.cmult(pr, nts[0], nts[1][0], level), level)
+    got_h = _coeffs(pr, ckks.hadd(pr, nts[0], nts[1], level), level)
+    want_c, want_h = [], []
+    for bi in range(2):
+        p = ints[1][0][bi]
+        want_c.append(tuple(_negacyclic(ints[0][c][bi], p, Q) for c in range(2)))
+        want_h.append(tuple([(x + y) % Q for x, y in zip(ints[0][c][bi], ints[1][c][bi])] for c in range(2)))
+    _assert_equal(pr, got_c, want_c, level)
+    _assert_equal(pr, got_h, want_h, level)
