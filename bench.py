@@ -386,6 +386,38 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
     return out
 
 
+def onepass_leg(args, torch, tfhe, inputs, sync, log_n=14, limbs=24, batch=64):
+    """Profiling leg: forward + inverse on the one-pass kernel (each
+    polynomial crosses HBM once per transform) at one serving shape; the
+    algorithmic bytes of a launch are one read and one write of every
+    residue."""
+    n = 1 << log_n
+    qs = tfhe.tfhe_find_primes(31, 1 << 17, limbs)
+    plan = tfhe.NttPlan(log_n, qs)
+    plan.set_param("fs_passes", 1)
+    x = torch.from_numpy(inputs.uniform_residues(0, qs, (batch, n)).view(np.int32)).cuda()
+    y, z = torch.empty_like(x), torch.empty_like(x)
+    ws = plan.workspace(limbs, batch, "mfma")
+
+    def step():
+        plan.fwd(x, out=y, algo="mfma", ws=ws)
+        plan.inv(y, out=z, algo="mfma", ws=ws)
+    for _ in range(args.warmup):
+        step()
+    sync()
+    assert torch.equal(z, x), "one-pass INTT(NTT(x)) != x"
+    tfhe.tfhe_timing_enable(True)
+    dt = timed(step, args.steps, sync)
+    cnt, ms = tfhe.tfhe_timing_read("ntt_mfma_onepass")
+    tfhe.tfhe_timing_enable(False)
+    units = limbs * batch
+    per_launch = ms / max(cnt, 1)
+    nbytes = 2 * units * n * 4
+    return {"log_n": log_n, "limbs": limbs, "batch": batch, "kops": 2 * units * args.steps / dt / 1e3,
+            "launches": cnt, "avg_launch_ms": round(per_launch, 4), "algorithmic_bytes_per_launch": nbytes,
+            "achieved_gbs": round(nbytes / (per_launch * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,8 +434,9 @@ def main():
                     help="cap each N's serving batch at the largest whose measured HMULT time fits (0: no cap)")
     ap.add_argument("--native-slots", type=int, default=8,
                     help="worker threads (one stream each) of the native dispatcher")
-    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving"], default=None,
-                    help="time one leg only (for profiling runs)")
+    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving", "onepass"], default=None,
+                    help="time one leg only (for profiling runs; onepass: the one-HBM-round-trip "
+                         "transform at N = 2^14, 24 limbs x 64 polynomials, the serving shape)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of the input batch (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -418,6 +451,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     sync = torch.cuda.synchronize
+    if args.only == "onepass":
+        print(json.dumps({"onepass": onepass_leg(args, torch, tfhe, inputs, sync)}), flush=True)
+        return
     n = 1 << LOG_N
 
     qs = tfhe.tfhe_find_primes(31, 1 << 17, LIMBS)
