@@ -1,6 +1,7 @@
 // Per-kernel timing: when enabled, every launcher brackets its kernel with a
 // pair of HIP events recorded on the launch stream; tfhe_timing_read resolves
 // them.  Off by default (no events are recorded).
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -15,7 +16,7 @@ struct Rec {
   hipEvent_t a, b;
 };
 std::mutex g_mu;
-bool g_on = false;
+std::atomic<bool> g_on{false};  // read without the lock by every launcher
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -45,7 +46,11 @@ void* timing_begin(int id, hipStream_t s) {
   if (!g_on) return nullptr;
   std::lock_guard<std::mutex> lk(g_mu);
   Rec r{id, take(), take()};
-  if (!r.a || !r.b) return nullptr;
+  if (!r.a || !r.b) {  // event creation failed: this launch goes untimed
+    if (r.a) g_pool.push_back(r.a);
+    if (r.b) g_pool.push_back(r.b);
+    return nullptr;
+  }
   (void)hipEventRecord(r.a, s);
   g_recs.push_back(r);
   return &g_recs.back() - &g_recs[0] + (char*)1;  // index + 1 as an opaque token
