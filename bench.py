@@ -44,8 +44,10 @@ I8_OPS_PER_COEFF_PASS = 8 * 16 * 16 * 64 * 2 // 256
 TRAFFIC_SOURCES = ("csrc/ntt_fourstep.hip", "csrc/fourstep_dev.hpp", "csrc/internal.hpp", "csrc/modarith.hpp",
                    "csrc/plan.cpp", "tune_mi355x.json")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ntt_mfma_n16_44x128.md")
-# the HMULT benchmark's kernels: the transforms plus the key-switching code
-HMULT_SOURCES = TRAFFIC_SOURCES + ("csrc/ckks.cpp", "csrc/ckks_kernels.hip", "csrc/ckks_internal.hpp")
+# the HMULT benchmark's kernels: the transforms plus the key-switching code,
+# and the rules that set its context's launch shape
+HMULT_SOURCES = TRAFFIC_SOURCES + ("csrc/ckks.cpp", "csrc/ckks_kernels.hip", "csrc/ckks_internal.hpp",
+                                   "autotune.py")
 HMULT_PROFILE = os.path.join(ROOT, "profiles", "hmult_n16_l24_b64.md")
 
 

@@ -125,10 +125,16 @@ def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     then take one pass for launches with at least two polynomials per CU,
     which measured 2-8 % faster HMULT at N = 2^12..2^14 and batch 8-64,
     and two below, where one pass would leave CUs idle (10-20 % slower at
-    batch 1-4).  Returns the applied entries."""
+    batch 1-4).  The persistent grid stays the library's (fs_wg_per_cu 0):
+    the transform-tuned 4 workgroups per CU measured 0.6-2.4 % slower for
+    HMULT at N = 2^15 and 2^16 (levels 12 and 24), whose many launches of
+    other shapes balance better on the resident-count grid.  Returns the
+    applied entries."""
     e = apply(ctx.plan, table, limbs, batch)
     if e is not None and e.get("fs_passes") == 1:
         ctx.plan.set_param("fs_passes", 0)
+    if e is not None:
+        ctx.plan.set_param("fs_wg_per_cu", 0)
     h = table.get(hmult_key(ctx.log_n, level))
     choice = ks_inner_choice(h) if h else None
     if choice is not None:

@@ -64,9 +64,10 @@ class FakeCtx:
 
 
 def test_apply_ckks_takes_tuned_shape():
-    """A context's key switch takes the tuned launch shape and inner-product
-    variant; a one-pass choice becomes the library default, which takes one
-    pass only for launches that fill the CUs."""
+    """A context's key switch takes the tuned item width, ring depth and
+    inner-product variant; a one-pass choice becomes the library default,
+    which takes one pass only for launches that fill the CUs, and the
+    persistent grid stays the library's."""
     t = autotune.TuneTable()
     t.put(autotune.ntt_key(14, 24, 64), {"algo": "mfma", "fs_passes": 1, "fs_wide": 1, "fs_wg_per_cu": 2})
     t.put(autotune.hmult_key(14, 24), {"batch": 32, "ks_inner": 1})
@@ -74,6 +75,7 @@ def test_apply_ckks_takes_tuned_shape():
     got = autotune.apply_ckks(ctx, t)
     assert got["ks_inner"] == 1 and got["ntt"]["fs_passes"] == 1
     assert ctx.plan.params["fs_passes"] == 0 and ctx.plan.params["fs_wide"] == 1
+    assert ctx.plan.params["fs_wg_per_cu"] == 0  # the library's grid for HMULT's launches
     assert ctx.plan.params["ks_inner"] == 1
 
 
