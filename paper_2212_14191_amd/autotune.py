@@ -131,10 +131,13 @@ def apply_ckks(ctx, table, limbs=24, batch=64, level=24):
     other shapes balance better on the resident-count grid.  Returns the
     applied entries."""
     e = apply(ctx.plan, table, limbs, batch)
-    if e is not None and e.get("fs_passes") == 1:
-        ctx.plan.set_param("fs_passes", 0)
     if e is not None:
-        ctx.plan.set_param("fs_wg_per_cu", 0)
+        e = dict(e)  # the parameters as applied to this context
+        if e.get("fs_passes") == 1:
+            e["fs_passes"] = 0
+        e["fs_wg_per_cu"] = 0
+        for name in ("fs_passes", "fs_wg_per_cu"):
+            ctx.plan.set_param(name, e[name])
     h = table.get(hmult_key(ctx.log_n, level))
     choice = ks_inner_choice(h) if h else None
     if choice is not None:

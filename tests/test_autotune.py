@@ -73,7 +73,9 @@ def test_apply_ckks_takes_tuned_shape():
     t.put(autotune.hmult_key(14, 24), {"batch": 32, "ks_inner": 1})
     ctx = FakeCtx(14)
     got = autotune.apply_ckks(ctx, t)
-    assert got["ks_inner"] == 1 and got["ntt"]["fs_passes"] == 1
+    # the returned entry is what the context got
+    assert got["ks_inner"] == 1 and got["ntt"]["fs_passes"] == 0 and got["ntt"]["fs_wg_per_cu"] == 0
+    assert t.get(autotune.ntt_key(14, 24, 64))["fs_passes"] == 1  # the table itself is unchanged
     assert ctx.plan.params["fs_passes"] == 0 and ctx.plan.params["fs_wide"] == 1
     assert ctx.plan.params["fs_wg_per_cu"] == 0  # the library's grid for HMULT's launches
     assert ctx.plan.params["ks_inner"] == 1
