@@ -114,7 +114,9 @@ tfhe_status tfhe_ntt_plan_modulus(tfhe_ntt_plan plan, uint32_t limb, uint32_t* q
  *   TFHE_PARAM_FS_WIDE       work items of the four-step 256-point stage:
  *                            0 = library default (wide for N >= 2^15),
  *                            1 = always 16 vectors (4 waves), 2 = 32 vectors
- *                            (8 waves) whenever N >= 2^13
+ *                            (8 waves) whenever N >= 2^13.  The key switch's
+ *                            fused second pass takes wide items whenever
+ *                            N >= 2^13 unless this is 1.
  *   TFHE_PARAM_FS_PASSES     HBM round trips of a four-step transform
  *                            (the paper's Stages 1-5 as one pipeline,
  *                            Sec. IV-C): 1 = one (the polynomial stays in
