@@ -105,6 +105,55 @@ class Server:
             self._lock.notify()
         return req.future
 
+    def submit_many(self, reqs, timeout_s=None):
+        """Queue several requests at once: reqs is a list of (op, log_n,
+        level, ct_a, ct_b, galois) tuples (ct_b None for a rotation, galois
+        None for HMULT).  One lock acquisition and, on the GPU backend, one
+        readiness event for the whole group.  Returns their Futures, in
+        order; a request that fails its checks gets a failed Future and the
+        others are queued."""
+        out, ok = [], []
+        for op, log_n, level, ct_a, ct_b, galois in reqs:
+            req = Request(op, log_n, level, galois, ct_a, ct_b, timeout_s)
+            out.append(req.future)
+            if op == HMULT and ct_b is None:
+                req.future.set_exception(ValueError("HMULT needs two ciphertexts"))
+                continue
+            if op == ROTATE and galois is None:
+                req.future.set_exception(ValueError("rotation needs a Galois element"))
+                continue
+            need = self.backend.nbytes(op, log_n, level, 1)
+            if need > self.budget:
+                req.future.set_exception(MemoryError(f"request needs {need} B > budget {self.budget} B"))
+                continue
+            ok.append(req)
+        prepare_many = getattr(self.backend, "prepare_many", None)
+        prepare = getattr(self.backend, "prepare", None)
+        if prepare_many is not None:
+            bad = prepare_many(ok)
+        else:
+            bad = set()
+            for i, r in enumerate(ok):
+                try:
+                    if prepare is not None:
+                        prepare(r)
+                except Exception as e:  # noqa: BLE001 - surfaced on the request's future
+                    r.future.set_exception(e)
+                    bad.add(i)
+        with self._lock:
+            for i, req in enumerate(ok):
+                if i in bad:
+                    continue
+                if self._t0 is None:
+                    self._t0 = req.t_submit
+                self._pending[self._next_id] = req
+                self._by_key.setdefault(req.key(self.mix), collections.deque()).append(self._next_id)
+                if req.deadline is not None:
+                    heapq.heappush(self._deadlines, (req.deadline, self._next_id))
+                self._next_id += 1
+            self._lock.notify()
+        return out
+
     def stats(self):
         with self._lock:
             lat = np.array([t1 - t0 for t0, t1 in self._done])
@@ -290,6 +339,13 @@ class GpuBackend:
         """Called in the submitting thread: checks the inputs (so that the
         scheduler can pass raw pointers) and records an event on the
         submitter's current stream that marks when they are ready."""
+        self._check(req)
+        st = self.torch.cuda.current_stream()
+        ev = self.torch.cuda.Event()
+        ev.record(st)
+        req.ready = (st.cuda_stream, ev, st)
+
+    def _check(self, req):
         ctx = self.ctx.get(req.log_n)
         if ctx is None:
             raise ValueError(f"no context for N = 2^{req.log_n}")
@@ -300,10 +356,27 @@ class GpuBackend:
                 raise ValueError(f"ciphertexts must be contiguous int32 device tensors of {shape} elements")
         if req.op == ROTATE and (req.log_n, req.galois) not in self.rk:
             raise ValueError(f"no rotation key for Galois element {req.galois}")
+
+    def prepare_many(self, reqs):
+        """prepare() for a group submitted together: every request is
+        checked and all share one readiness event, recorded once on the
+        submitter's current stream.  Returns the indices of the requests
+        that failed their checks (their futures carry the error)."""
+        bad = set()
         st = self.torch.cuda.current_stream()
-        ev = self.torch.cuda.Event()
-        ev.record(st)
-        req.ready = (st.cuda_stream, ev, st)
+        ev = None
+        for i, req in enumerate(reqs):
+            try:
+                self._check(req)
+            except Exception as e:  # noqa: BLE001 - surfaced on the request's future
+                req.future.set_exception(e)
+                bad.add(i)
+                continue
+            if ev is None:
+                ev = self.torch.cuda.Event()
+                ev.record(st)
+            req.ready = (st.cuda_stream, ev, st)
+        return bad
 
     def _ws_bytes(self, log_n, level, batch):
         k = (log_n, level, batch)

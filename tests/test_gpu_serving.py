@@ -66,9 +66,11 @@ def test_alone_equals_mix_on_gpu(world):
     futs = [srv.submit(op, ln, lv, a, b, g) for op, ln, lv, a, b, g in reqs]
     mixed = [f.result(timeout=60) for f in futs]
     st = srv.stats()
+    # the same requests as one group (one readiness event for all)
+    grouped = [f.result(timeout=60) for f in srv.submit_many(reqs)]
     srv.close()
-    for x, y in zip(alone, mixed):
-        assert torch.equal(x, y)
+    for x, y, z in zip(alone, mixed, grouped):
+        assert torch.equal(x, y) and torch.equal(x, z)
     assert st["completed"] == len(reqs) and st["p99_ms"] is not None
 
 

@@ -117,6 +117,29 @@ def test_alone_equals_mix(world):
     assert max(b for _, _, b, _ in be.launch_log) > 1   # some batching happened
 
 
+def test_submit_many_equals_submit(world):
+    """A group submitted in one call gives each request the result it gets
+    when submitted alone; a request that fails its checks gets a failed
+    future while the rest of the group is served."""
+    pr, evk, rks, _, cts = world
+    reqs = mix(world, count=12, seed=3)
+    srv = Server(OracleBackend(pr, evk, rks), mem_budget_bytes=1 << 30, slots=1, max_batch=1)
+    one = run(srv, reqs)
+    srv.close()
+    be = OracleBackend(pr, evk, rks, delay_s=0.005)
+    srv = Server(be, mem_budget_bytes=1 << 30, slots=2, max_batch=8)
+    group = [(op, 6, lv, a, b, g) for op, lv, a, b, g in reqs]
+    group.insert(5, (HMULT, 6, 4, cts[(4, 0)], None, None))   # no second ciphertext
+    futs = srv.submit_many(group)
+    with pytest.raises(ValueError):
+        futs[5].result(timeout=60)
+    got = [f.result(timeout=60) for i, f in enumerate(futs) if i != 5]
+    srv.close()
+    for x, y in zip(one, got):
+        assert np.array_equal(x, y)
+    assert max(b for _, _, b, _ in be.launch_log) > 1
+
+
 class MixingOracleBackend(OracleBackend):
     """A backend that runs batches of mixed levels (as GpuBackend does):
     each request of a batch at its own level."""
