@@ -364,8 +364,11 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
                 raise RuntimeError("native serving run did not finish")
         del outs
         lat = t_done - t_sub
+        by_n = {str(ln): round(float(np.percentile(lat[mix["log_n"] == ln], 99) * 1e3), 3)
+                for ln in log_ns if (mix["log_n"] == ln).any()}
         return {"throughput_per_s": count / (np.max(t_done) - t_sub[0]),
-                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "p99_ms_by_log_n": by_n}
 
     out = {"requests": n_req, "max_batch": 16, "max_batch_by_n": {str(k): v for k, v in by_n.items()},
            "batch_ms": batch_ms, "p99_bound_ms": P99_BOUND_MS}
@@ -379,9 +382,11 @@ def serving_leg(n_sat, n_req, fracs, torch, tfhe, inputs, engines=("python", "na
         for frac in fracs:
             rate = frac * sat["throughput_per_s"]
             st = fn(n_req, 3, rate)
-            res["runs"].append({"load": frac, "rate_per_s": round(rate, 1),
-                                "throughput_per_s": round(st["throughput_per_s"], 1),
-                                "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)})
+            rec = {"load": frac, "rate_per_s": round(rate, 1), "throughput_per_s": round(st["throughput_per_s"], 1),
+                   "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3)}
+            if "p99_ms_by_log_n" in st:
+                rec["p99_ms_by_log_n"] = st["p99_ms_by_log_n"]
+            res["runs"].append(rec)
         res["sustainable"] = sustainable_rate(fn, sat["throughput_per_s"], n_req)
         out[name] = res
     native.close()
