@@ -382,11 +382,13 @@ tfhe_status tfhe_frobenius_map(tfhe_ntt_plan plan, const uint32_t* in, uint32_t*
 /* Request dispatcher (the API layer of Sec. IV-E with operation-level
  * batching, Sec. IV-D): callers submit single-ciphertext HMULT and HROTATE
  * requests; `slots` worker threads, each with its own stream, group
- * requests of equal (operation, N) into batches of up to max_batch, whatever
- * their levels, run each batch as one mixed-level launch sequence (as
- * tfhe_hmult_levels does; a batch of one with tfhe_hmult / tfhe_rotate on
- * the request's own buffers), and report each request's completion through
- * tfhe_server_poll.
+ * requests of equal N into batches of up to max_batch, whatever their levels
+ * and operations, run each batch as one launch sequence (as
+ * tfhe_hmult_levels does, with the tensor products of its HMULTs and the
+ * Frobenius maps of its rotations each in one launch and every kernel of the
+ * key switch, which the two operations share, once for the whole batch; a
+ * batch of one with tfhe_hmult / tfhe_rotate on the request's own buffers),
+ * and report each request's completion through tfhe_server_poll.
  * The result of a request is exactly what tfhe_hmult / tfhe_rotate computes
  * for it alone.
  *

@@ -335,10 +335,10 @@ static hipError_t key_switch(const tfhe_ckks_ctx_s* c, const uint32_t* d, const 
   return key_switch_multi(c, &job, 1, keys, ws + ks_layout(c, level, batch).ntt, s);
 }
 
-// Level groups of a mixed-level batch: request indices sorted by level
-// (stable), and the workspace layout (per group its result staging
-// [2][level][B][N] and its own key-switching regions; then the transforms'
-// region shared by all groups).
+// Groups of a mixed batch: request indices sorted by (level, op) (stable),
+// and the workspace layout (per group its result staging [2][level][B][N]
+// and its own key-switching regions; then the transforms' region shared by
+// all groups).
 static_assert(TFHE_HMULT_LEVELS_MAX == kMaxRotBatch, "one bound for mixed-level batches");
 
 struct LvPlan {
@@ -352,11 +352,12 @@ static LvPlan lv_plan(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count) 
   LvPlan l;
   l.order.resize(count);
   for (uint32_t i = 0; i < count; ++i) l.order[i] = i;
-  std::stable_sort(l.order.begin(), l.order.end(),
-                   [&](uint32_t x, uint32_t y) { return r[x].level < r[y].level; });
+  std::stable_sort(l.order.begin(), l.order.end(), [&](uint32_t x, uint32_t y) {
+    return r[x].level != r[y].level ? r[x].level < r[y].level : r[x].op < r[y].op;
+  });
   for (uint32_t i = 0; i < count;) {
     uint32_t j = i;
-    while (j < count && r[l.order[j]].level == r[l.order[i]].level) ++j;
+    while (j < count && r[l.order[j]].level == r[l.order[i]].level && r[l.order[j]].op == r[l.order[i]].op) ++j;
     l.groups.emplace_back(i, j);
     i = j;
   }
@@ -379,23 +380,22 @@ size_t levels_ws_bytes(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count)
   return count ? lv_plan(c, r, count).total : 0;
 }
 
-hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uint32_t count,
-                      unsigned char* ws, hipStream_t s) {
+hipError_t levels_run(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count, unsigned char* ws,
+                      hipStream_t s) {
   if (count == 0) return hipSuccess;
   if (count > kMaxRotBatch) return hipErrorInvalidValue;
   const LvPlan l = lv_plan(c, r, count);
   std::vector<KsJob> jobs;
   ScatterSet sc{};
-  CtDescSet cs{};
+  CtDescSet cs[2] = {};  // the HMULTs' tensor products, the rotations' Frobenius maps
   KeySet keys{};
-  bool same = true;  // one key (and Galois element) for the whole batch
+  bool same = true;  // one operation and key (and Galois element) for the whole batch
   for (uint32_t i = 0; i < count; ++i)
-    same = same && r[i].key == r[0].key && (op == 0 || r[i].galois == r[0].galois);
+    same = same && r[i].op == r[0].op && r[i].key == r[0].key && (r[i].op == 0 || r[i].galois == r[0].galois);
   keys.count = same ? 1 : count;
-  cs.count = count;
   for (size_t g = 0; g < l.groups.size(); ++g) {
     const uint32_t b0 = l.groups[g].first, B = l.groups[g].second - b0;
-    const uint32_t level = r[l.order[b0]].level;
+    const uint32_t level = r[l.order[b0]].level, op = r[l.order[b0]].op ? 1 : 0;
     const KsLayout lay = ks_layout(c, level, B);
     uint32_t* stg = (uint32_t*)(ws + l.staging[g]);
     unsigned char* own = ws + l.own[g];
@@ -404,7 +404,7 @@ hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uin
     for (uint32_t k = 0; k < B; ++k) {
       const LvReq& q = r[l.order[b0 + k]];
       keys.k[same ? 0 : b0 + k] = q.key;
-      cs.c[b0 + k] = CtDesc{q.a, q.b, stg, d, level, B, k, q.galois};
+      cs[op].c[cs[op].count++] = CtDesc{q.a, q.b, stg, d, level, B, k, q.galois};
       sc.src[b0 + k] = stg;
       sc.dst[b0 + k] = q.out;
       sc.rows[b0 + k] = 2 * level;
@@ -413,7 +413,10 @@ hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uin
     }
     jobs.push_back(KsJob{d, b0, stg, stg + plane, true, op == 0, level, B, own});
   }
-  hipError_t e = op == 0 ? launch_tensor_multi(cs, c->plan->d_mod, c->log_n, s) : launch_frobenius_multi(cs, c->log_n, s);
+  // every input is read here, before any result is written (by the final
+  // copies): a result may alias any request's input
+  hipError_t e = launch_tensor_multi(cs[0], c->plan->d_mod, c->log_n, s);
+  if (e == hipSuccess) e = launch_frobenius_multi(cs[1], c->log_n, s);
   if (e != hipSuccess) return e;
   if ((e = key_switch_multi(c, jobs.data(), (uint32_t)jobs.size(), keys, ws + l.ntt, s)) != hipSuccess) return e;
   return launch_scatter(sc, count, c->log_n, s);
@@ -791,10 +794,10 @@ tfhe_status tfhe_hmult_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_a, co
   std::vector<LvReq> r(count);
   for (uint32_t i = 0; i < count; ++i) {
     if (!ct_b[i]) return fail(TFHE_EINVAL, "hmult_levels: null ciphertext");
-    r[i] = LvReq{ct_a[i], ct_b[i], ct_out[i], evk, levels[i], 0};
+    r[i] = LvReq{ct_a[i], ct_b[i], ct_out[i], evk, levels[i], 0, 0};
   }
   if ((st = check_levels_call(ctx, r, ws, ws_bytes, "hmult_levels")) != TFHE_OK) return st;
-  return hip_check(levels_run(ctx, 0, r.data(), count, (unsigned char*)ws, (hipStream_t)stream), "hmult_levels");
+  return hip_check(levels_run(ctx, r.data(), count, (unsigned char*)ws, (hipStream_t)stream), "hmult_levels");
 }
 
 tfhe_status tfhe_rotate_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_in, uint32_t* const* ct_out,
@@ -808,10 +811,10 @@ tfhe_status tfhe_rotate_levels(tfhe_ckks_ctx ctx, const uint32_t* const* ct_in, 
   for (uint32_t i = 0; i < count; ++i) {
     if ((galois_elts[i] & 1) == 0 || galois_elts[i] >= 2 * ctx->n)
       return fail(TFHE_EINVAL, "rotate_levels: galois elements must be odd and < 2N");
-    r[i] = LvReq{ct_in[i], nullptr, ct_out[i], rotkeys[i], levels[i], galois_elts[i]};
+    r[i] = LvReq{ct_in[i], nullptr, ct_out[i], rotkeys[i], levels[i], galois_elts[i], 1};
   }
   if ((st = check_levels_call(ctx, r, ws, ws_bytes, "rotate_levels")) != TFHE_OK) return st;
-  return hip_check(levels_run(ctx, 1, r.data(), count, (unsigned char*)ws, (hipStream_t)stream), "rotate_levels");
+  return hip_check(levels_run(ctx, r.data(), count, (unsigned char*)ws, (hipStream_t)stream), "rotate_levels");
 }
 
 tfhe_status tfhe_rotate(tfhe_ckks_ctx ctx, const uint32_t* ct_in, uint32_t* ct_out,

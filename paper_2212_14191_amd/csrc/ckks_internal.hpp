@@ -159,22 +159,24 @@ struct ScatterSet {
 static_assert(sizeof(ScatterSet) <= 4096, "a ScatterSet is passed as a kernel argument");
 hipError_t launch_scatter(const ScatterSet& e, uint32_t count, uint32_t log_n, hipStream_t s);
 
-// One ciphertext of a batch of mixed levels (levels_run).
+// One request of a batch of mixed levels and operations (levels_run).
 struct LvReq {
   const uint32_t* a;    // input [2][level][N] (HMULT: first operand)
   const uint32_t* b;    // HMULT: second operand [2][level][N]
   uint32_t* out;        // result [2][level][N]
   const uint32_t* key;  // evk (HMULT) or the rotation key
   uint32_t level, galois;
+  uint32_t op;          // 0: HMULT, 1: HROTATE
 };
 // Workspace bytes levels_run needs for these requests.
 size_t levels_ws_bytes(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count);
-// HMULT (op 0) or HROTATE (op 1) of count <= kMaxRotBatch requests of any
-// levels in one batched launch sequence: the requests are grouped by level;
-// each group's tensor product (or Frobenius map) and inner product run per
-// group, every transform and basis conversion once for all groups; the
-// results are copied out to each request's buffer.  Each result equals the
-// single call's.
-hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uint32_t count,
-                      unsigned char* ws, hipStream_t s);
+// count <= kMaxRotBatch HMULT and HROTATE requests (r[i].op) of any levels
+// in one batched launch sequence: the requests are grouped by (level, op);
+// one launch forms every HMULT's tensor product and one every rotation's
+// Frobenius map, and every transform, basis conversion and inner product of
+// the key switch (the part the two operations share) runs once for all
+// groups; the results are copied out to each request's buffer.  Each result
+// equals the single call's.
+hipError_t levels_run(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count, unsigned char* ws,
+                      hipStream_t s);
 }  // namespace tfhe

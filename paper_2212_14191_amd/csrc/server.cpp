@@ -3,18 +3,18 @@
 // and dispatched; keys and ciphertexts stay resident in device memory).
 //
 // Each of `slots` worker threads owns a HIP stream and an equal share of the
-// caller's memory pool.  Pending requests are indexed by batching key (op,
-// N, context): a batch may mix levels (operation-level batching across
-// levels, Sec. IV-D).  Whenever a worker is free, the oldest request and up
-// to max_batch - 1 later ones of its key form a batch whose workspace fits
-// the worker's share (otherwise the batch is halved until it fits).  A batch
-// of one runs in place on the request's own buffers; a larger one runs as
-// one mixed-level launch sequence (levels_run) that reads its inputs where
-// they are and copies each result out to its request.  Rotations by
-// different amounts share a batch (one key and Galois element per
-// ciphertext).  Every request waits for an event recorded on its
-// submitter's stream at submission.  Completed tags are collected by
-// tfhe_server_poll.
+// caller's memory pool.  Pending requests are indexed by batching key (N,
+// context): a batch may mix levels and operations (operation-level
+// batching, Sec. IV-D: HMULT and HROTATE share every kernel of the key
+// switch).  Whenever a worker is free, the oldest request and up to
+// max_batch - 1 later ones of its key form a batch whose workspace fits the
+// worker's share (otherwise the batch is halved until it fits).  A batch of
+// one runs in place on the request's own buffers; a larger one runs as one
+// launch sequence (levels_run) that reads its inputs where they are and
+// copies each result out to its request.  Rotations by different amounts
+// share a batch (one key and Galois element per ciphertext).  Every request
+// waits for an event recorded on its submitter's stream at submission.
+// Completed tags are collected by tfhe_server_poll.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,12 +42,12 @@ struct Req {
 };
 
 struct Key {
-  uint32_t op, log_n;
+  uint32_t log_n;
   tfhe_ckks_ctx ctx;  // requests submitted before a context was replaced batch apart
-  bool operator<(const Key& o) const { return std::tie(op, log_n, ctx) < std::tie(o.op, o.log_n, o.ctx); }
+  bool operator<(const Key& o) const { return std::tie(log_n, ctx) < std::tie(o.log_n, o.ctx); }
 };
 
-LvReq lv(const Req& r) { return LvReq{r.a, r.b, r.out, r.key, r.level, r.galois}; }
+LvReq lv(const Req& r) { return LvReq{r.a, r.b, r.out, r.key, r.level, r.galois, r.op}; }
 
 struct Slot {
   hipStream_t s = nullptr;
@@ -133,11 +133,12 @@ int tfhe_server_s::launch(Slot& sl, std::vector<Req>& reqs) {
         : tfhe_rotate(r0.ctx, r0.a, r0.out, r0.key, r0.galois, r0.level, 1, ws, ws_bytes, (tfhe_stream_t)sl.s);
     if (st != TFHE_OK) return st;
   } else {
-    // one launch sequence for the whole batch, whatever its levels; the
-    // inputs are read where they are and each result is copied out
+    // one launch sequence for the whole batch, whatever its levels and
+    // operations; the inputs are read where they are and each result is
+    // copied out
     std::vector<LvReq> r;
     for (const Req& q : reqs) r.push_back(lv(q));
-    if (levels_run(r0.ctx, r0.op, r.data(), B, sl.mem, sl.s) != hipSuccess)
+    if (levels_run(r0.ctx, r.data(), B, sl.mem, sl.s) != hipSuccess)
       return fail(TFHE_EHIP, "server: batch launch failed");
   }
   if (hipGetLastError() != hipSuccess) return TFHE_EHIP;
@@ -160,13 +161,13 @@ bool tfhe_server_s::take(const Slot& sl, std::vector<Req>& reqs) {
   std::deque<Req>& q = pending[key];
   auto ci = ctxs.find(key.log_n);
   const uint32_t mb = ci != ctxs.end() && ci->second.max_batch ? ci->second.max_batch : max_batch;
-  // the oldest request, then the others of its level, then the rest (each
-  // group in arrival order): fewer level groups per batch, fewer launches
+  // the oldest request, then the others of its level and operation, then
+  // the rest (each group in arrival order): fewer groups per batch
   std::vector<size_t> pick{0};
-  const uint32_t lv = q.front().level;
+  const uint32_t lv = q.front().level, op = q.front().op;
   for (int pass = 0; pass < 2; ++pass)
     for (size_t i = 1; i < q.size() && pick.size() < mb; ++i)
-      if ((q[i].level == lv) == (pass == 0)) pick.push_back(i);
+      if ((q[i].level == lv && q[i].op == op) == (pass == 0)) pick.push_back(i);
   std::vector<Req> cand;
   for (size_t i : pick) cand.push_back(q[i]);
   uint32_t B = (uint32_t)cand.size();
@@ -332,7 +333,7 @@ tfhe_status tfhe_server_submit_many(tfhe_server s, const tfhe_server_request* re
     std::lock_guard<std::mutex> g(s->mu);
     s->ev_refs[ev] = count;
     for (Req& r : batch) {
-      const Key k{r.op, r.log_n, r.ctx};
+      const Key k{r.log_n, r.ctx};
       r.seq = s->next_seq++;
       r.ready = ev;
       s->pending[k].push_back(r);

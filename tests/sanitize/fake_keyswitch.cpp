@@ -17,7 +17,8 @@ using namespace tfhe;
 // batched calls seen (B > 1), read by the driver; each call also takes a
 // little time, as a launch would, so that requests queue up into batches
 std::atomic<int> fake_batched_calls{0};
-std::atomic<int> fake_mixed_calls{0};  // batches holding more than one level
+std::atomic<int> fake_mixed_calls{0};     // batches holding more than one level
+std::atomic<int> fake_mixed_op_calls{0};  // batches holding HMULTs and rotations
 static void pause() { std::this_thread::sleep_for(std::chrono::microseconds(50)); }
 
 extern "C" tfhe_status tfhe_hmult_workspace_size(tfhe_ckks_ctx ctx, uint32_t level, uint32_t batch, size_t* bytes) {
@@ -53,8 +54,7 @@ size_t levels_ws_bytes(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count)
 }
 
 // each request's result written straight to its own buffer
-hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uint32_t count, unsigned char*,
-                      hipStream_t) {
+hipError_t levels_run(const tfhe_ckks_ctx_s* c, const LvReq* r, uint32_t count, unsigned char*, hipStream_t) {
   pause();
   if (count > 1) ++fake_batched_calls;
   for (uint32_t k = 1; k < count; ++k)
@@ -62,10 +62,15 @@ hipError_t levels_run(const tfhe_ckks_ctx_s* c, uint32_t op, const LvReq* r, uin
       ++fake_mixed_calls;
       break;
     }
+  for (uint32_t k = 1; k < count; ++k)
+    if (r[k].op != r[0].op) {
+      ++fake_mixed_op_calls;
+      break;
+    }
   for (uint32_t k = 0; k < count; ++k) {
     const size_t n = (size_t)2 * r[k].level * c->n;
     for (size_t i = 0; i < n; ++i)
-      r[k].out[i] = op == 0 ? r[k].a[i] + 2 * r[k].b[i] + r[k].key[0] : 3 * r[k].a[i] + r[k].galois + r[k].key[0];
+      r[k].out[i] = r[k].op == 0 ? r[k].a[i] + 2 * r[k].b[i] + r[k].key[0] : 3 * r[k].a[i] + r[k].galois + r[k].key[0];
   }
   return hipSuccess;
 }

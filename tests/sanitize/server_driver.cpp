@@ -15,6 +15,7 @@
 
 extern std::atomic<int> fake_batched_calls;
 extern std::atomic<int> fake_mixed_calls;
+extern std::atomic<int> fake_mixed_op_calls;
 
 struct Request {
   uint32_t op, log_n, level, galois;
@@ -116,7 +117,8 @@ int main() {
       }
     }
   }
-  std::printf("server driver: %zu requests, %d wrong, %d batched calls, %d of mixed levels\n", reqs.size(), bad,
-              fake_batched_calls.load(), fake_mixed_calls.load());
-  return bad != 0 || fake_batched_calls.load() == 0 || fake_mixed_calls.load() == 0;
+  std::printf("server driver: %zu requests, %d wrong, %d batched calls, %d of mixed levels, %d of mixed operations\n",
+              reqs.size(), bad, fake_batched_calls.load(), fake_mixed_calls.load(), fake_mixed_op_calls.load());
+  return bad != 0 || fake_batched_calls.load() == 0 || fake_mixed_calls.load() == 0 ||
+         fake_mixed_op_calls.load() == 0;
 }
