@@ -121,59 +121,25 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
 
 // ModUp conversion of digit [d0, d0 + nd) on the matrix cores: every
 // extended-basis position outside the digit, in launches of <= 32 targets.
-static void modup_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* x, uint32_t* up, uint32_t key_idx,
-                       uint32_t d0, uint32_t nd, uint32_t level, uint64_t plane, ConvQueue& cq) {
-  ConvArgs a;
-  a.in = x + (uint64_t)d0 * plane;
-  a.out = up;
-  a.plane = plane;
-  a.nin = nd;
-  for (uint32_t r = 0; r < nd; ++r) {
-    a.in_q[r] = c->h_mod[d0 + r].q;
-    a.in_mult[r] = c->h_up_inv[(size_t)key_idx * kMaxAlpha + r];
-  }
-  a.nout = 0;
-  for (uint32_t pos = 0; pos < level + c->K; ++pos) {
-    if (pos >= d0 && pos < d0 + nd) continue;
-    const uint32_t t = pos < level ? pos : c->L + (pos - level);
-    a.out_plane[a.nout] = pos;
-    a.out_q[a.nout] = c->h_mod[t].q;
-    a.out_qneg[a.nout] = c->h_mod[t].qneg;
-    a.out_k[a.nout] = c->h_up_k[(size_t)key_idx * (c->L + c->K) + t];
-    a.a_tab[a.nout] = c->d_up_mfma + ((size_t)key_idx * (c->L + c->K) + t) * 32;
-    if (++a.nout == kConvMaxOut) {
-      cq.q.push_back(a);
-      a.nout = 0;
-    }
-  }
-  if (a.nout) cq.q.push_back(a);
+static void modup_mfma(const uint32_t* x, uint32_t* up, uint32_t key_idx, uint32_t d0, uint32_t nd,
+                       uint32_t level, uint32_t K, uint64_t plane, ConvQueue& cq) {
+  const uint32_t targets = level + K - nd;  // every extended-basis position outside the digit
+  for (uint32_t first = 0; first < targets; first += kConvMaxOut)
+    cq.q.push_back(ConvDesc{x + (uint64_t)d0 * plane, up, plane, nd,
+                            std::min<uint32_t>(kConvMaxOut, targets - first), first, key_idx, d0, level});
 }
 
 // ModDown conversion of the K special limbs to the level q-limbs.
-static void moddown_conv_mfma(const tfhe_ckks_ctx_s* c, const uint32_t* tp, uint32_t* conv,
-                              uint32_t level, uint64_t plane, ConvQueue& cq) {
-  ConvArgs a;
-  a.in = tp;
-  a.out = conv;
-  a.plane = plane;
-  a.nin = c->K;
-  for (uint32_t k = 0; k < c->K; ++k) {
-    a.in_q[k] = c->h_mod[c->L + k].q;
-    a.in_mult[k] = c->h_dn_invp[k];
-  }
-  a.nout = 0;
-  for (uint32_t i = 0; i < level; ++i) {
-    a.out_plane[a.nout] = i;
-    a.out_q[a.nout] = c->h_mod[i].q;
-    a.out_qneg[a.nout] = c->h_mod[i].qneg;
-    a.out_k[a.nout] = c->h_dn_k[i];
-    a.a_tab[a.nout] = c->d_dn_mfma + (size_t)i * 32;
-    if (++a.nout == kConvMaxOut) {
-      cq.q.push_back(a);
-      a.nout = 0;
-    }
-  }
-  if (a.nout) cq.q.push_back(a);
+static void moddown_conv_mfma(const uint32_t* tp, uint32_t* conv, uint32_t level, uint32_t K, uint64_t plane,
+                              ConvQueue& cq) {
+  for (uint32_t first = 0; first < level; first += kConvMaxOut)
+    cq.q.push_back(ConvDesc{tp, conv, plane, K, std::min<uint32_t>(kConvMaxOut, level - first), first, kConvDown,
+                            0, level});
+}
+
+static ConvTabs conv_tabs(const tfhe_ckks_ctx_s* c) {
+  return ConvTabs{c->plan->d_mod, c->d_up_inv, c->d_dn_invp, c->d_up_k, c->d_dn_k, c->d_up_mfma, c->d_dn_mfma,
+                  c->L, c->K};
 }
 
 // One batch of a key switch: d (NTT domain, [level][batch][N]);
@@ -229,6 +195,7 @@ static hipError_t key_switch_multi(const tfhe_ckks_ctx_s* c, const KsJob* jobs, 
   // inter + (j ext + pos) plane; ip_run finishes them.
   units.clear();
   ConvQueue cq;  // the matrix-core conversions, launched together
+  cq.tabs = conv_tabs(c);
   for (uint32_t g = 0; g < nj; ++g) {
     const uint32_t level = jobs[g].level, batch = jobs[g].batch, ext = w[g].ext;
     const uint64_t plane = w[g].plane;
@@ -237,7 +204,7 @@ static hipError_t key_switch_multi(const tfhe_ckks_ctx_s* c, const KsJob* jobs, 
       const uint32_t key_idx = d0 + nd - 1;
       uint32_t* upj = w[g].up + (uint64_t)j * ext * plane;
       if (mfma_conv)
-        modup_mfma(c, w[g].x, upj, key_idx, d0, nd, level, plane, cq);
+        modup_mfma(w[g].x, upj, key_idx, d0, nd, level, c->K, plane, cq);
       else if ((e = launch_modup(w[g].x, upj, p->d_mod, c->d_up_inv + (size_t)key_idx * kMaxAlpha,
                                  c->d_up_conv + (size_t)key_idx * (c->L + c->K) * kMaxAlpha, d0, nd, level,
                                  c->L, c->K, batch, c->n, s)) != hipSuccess)
@@ -282,7 +249,7 @@ static hipError_t key_switch_multi(const tfhe_ckks_ctx_s* c, const KsJob* jobs, 
       const uint32_t* tpc = w[g].tp + (comp ? (uint64_t)c->K * plane : 0);
       uint32_t* convc = w[g].conv + (comp ? (uint64_t)level * plane : 0);
       if (mfma_conv)
-        moddown_conv_mfma(c, tpc, convc, level, plane, cq);
+        moddown_conv_mfma(tpc, convc, level, c->K, plane, cq);
       else if ((e = launch_moddown_conv(tpc, convc, p->d_mod, c->d_dn_invp, c->d_dn_conv, level, c->L, c->K,
                                         jobs[g].batch, c->n, s)) != hipSuccess)
         return e;
@@ -565,26 +532,21 @@ static tfhe_status ctx_build(tfhe_ckks_ctx_s* c) {
       for (uint32_t k = 0; k < K; ++k) dn_mfma[(size_t)i * 32 + 8 * j + k] = pack(dconv[(size_t)i * kMaxK + k].x, m[i], j);
   // offset corrections: 2^30 sum_r C[t][r] mod m_t
   const auto k30 = [&](uint32_t mt) { return (uint32_t)((1ull << 30) % mt); };
-  c->h_up_k.assign((size_t)L * (L + K), 0);
+  std::vector<uint32_t> up_k((size_t)L * (L + K), 0), dn_k(L, 0);
   for (uint32_t e = 1; e <= L; ++e) {
     const uint32_t d0 = A * ((e - 1) / A), nd = e - d0;
     for (uint32_t t = 0; t < L + K; ++t) {
       uint32_t sum = 0;
       for (uint32_t r = 0; r < nd; ++r)
         sum = (uint32_t)(((uint64_t)sum + up_conv[((size_t)(e - 1) * (L + K) + t) * kMaxAlpha + r].x) % m[t]);
-      c->h_up_k[(size_t)(e - 1) * (L + K) + t] = mulm(sum, k30(m[t]), m[t]);
+      up_k[(size_t)(e - 1) * (L + K) + t] = mulm(sum, k30(m[t]), m[t]);
     }
   }
-  c->h_dn_k.assign(L, 0);
   for (uint32_t i = 0; i < L; ++i) {
     uint32_t sum = 0;
     for (uint32_t k = 0; k < K; ++k) sum = (uint32_t)(((uint64_t)sum + dconv[(size_t)i * kMaxK + k].x) % m[i]);
-    c->h_dn_k[i] = mulm(sum, k30(m[i]), m[i]);
+    dn_k[i] = mulm(sum, k30(m[i]), m[i]);
   }
-  c->h_up_inv = up_inv;
-  c->h_dn_invp = invp;
-  c->h_mod.resize(L + K);
-  for (uint32_t t = 0; t < L + K; ++t) c->h_mod[t] = make_modconst(m[t]);
   std::vector<uint2> rsq((size_t)L * L, make_uint2(0, 0));
   for (uint32_t t = 1; t < L; ++t)
     for (uint32_t i = 0; i < t; ++i)
@@ -593,6 +555,8 @@ static tfhe_status ctx_build(tfhe_ckks_ctx_s* c) {
   if ((e = upload(&c->d_rs_qinv, rsq, c->owned)) != hipSuccess ||
       (e = upload(&c->d_up_mfma, up_mfma, c->owned)) != hipSuccess ||
       (e = upload(&c->d_dn_mfma, dn_mfma, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_up_k, up_k, c->owned)) != hipSuccess ||
+      (e = upload(&c->d_dn_k, dn_k, c->owned)) != hipSuccess ||
       (e = upload(&c->d_up_inv, up_inv, c->owned)) != hipSuccess ||
       (e = upload(&c->d_up_conv, up_conv, c->owned)) != hipSuccess ||
       (e = upload(&c->d_dn_invp, invp, c->owned)) != hipSuccess ||

@@ -19,13 +19,12 @@ struct CkksCtxImpl {
   uint2* d_dn_pinv = nullptr;  // [L]                   [P^{-1}]_{q_i}
   // RESCALE constants:
   uint2* d_rs_qinv = nullptr;  // [L][L]                [q_t^{-1}]_{q_i} at row t
-  // Matrix-core basis conversion operands (ConvArgs::a_tab layout):
+  // Matrix-core basis conversion operands (32 dwords per target):
   uint32_t* d_up_mfma = nullptr;  // [L (digit end - 1)][L+K (target)][4][8]
   uint32_t* d_dn_mfma = nullptr;  // [L (target)][4][8]
-  // host copies of the per-input multipliers and per-limb Montgomery constants
-  std::vector<uint2> h_up_inv, h_dn_invp;  // as d_up_inv, d_dn_invp
-  std::vector<uint32_t> h_up_k, h_dn_k;    // [L][L+K], [L]: ConvArgs::out_k
-  std::vector<ModConst> h_mod;             // [L+K]
+  // their offset constants 2^30 sum_r C[t][r] mod m_t
+  uint32_t* d_up_k = nullptr;     // [L (digit end - 1)][L+K (target)]
+  uint32_t* d_dn_k = nullptr;     // [L (target)]
   std::vector<void*> owned;
 };
 
@@ -33,18 +32,24 @@ struct CkksCtxImpl {
 // with y_r = in_r * mult_r mod q_r in [0, q_r) (the integer itself matters:
 // q_r != m_t), for up to 8 inputs and 32 targets.
 constexpr int kConvMaxIn = 8, kConvMaxOut = 32;
-struct ConvArgs {
-  const uint32_t* in;   // input plane r at in + r * plane
-  uint32_t* out;        // target t written to out + out_plane[t] * plane
-  uint64_t plane;       // words per plane (batch * N), a multiple of 64
-  uint32_t nin, nout;
-  uint32_t in_q[kConvMaxIn];
-  uint2 in_mult[kConvMaxIn];       // Shoup pair of mult_r
-  uint32_t out_plane[kConvMaxOut];
-  uint32_t out_q[kConvMaxOut], out_qneg[kConvMaxOut];
-  uint32_t out_k[kConvMaxOut];         // 2^30 sum_r C[t][r] mod m_t (offset correction)
-  const uint32_t* a_tab[kConvMaxOut];  // 32 dwords per target: [plane j][8]
+constexpr uint32_t kConvDown = 0xFFFFFFFFu;  // ConvDesc::key_idx of a ModDown conversion
+// One conversion: inputs at in + r plane (r < nin); targets u = first ..
+// first + nout - 1 (nout <= kConvMaxOut) of its list, target u written to
+// out + conv_pos(u) plane.  ModUp of the digit [d0, d0 + nin) (key_idx: the
+// row of its constants, the digit's last limb): the list is the extended-
+// basis positions 0 .. level + K - 1 without the digit.  ModDown (key_idx
+// kConvDown): the positions 0 .. level - 1, from the K special limbs.  The
+// moduli, multipliers and matrix operands come from the context's tables
+// (ConvSet), so a descriptor is small and one launch takes many.
+struct ConvDesc {
+  const uint32_t* in;
+  uint32_t* out;
+  uint64_t plane;  // words per plane (batch * N), a multiple of 64
+  uint32_t nin, nout, first, key_idx, d0, level;
 };
+TFHE_HD uint32_t conv_pos(const ConvDesc& a, uint32_t u) {
+  return a.key_idx != kConvDown && u >= a.d0 ? u + a.nin : u;
+}
 
 hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
                          const ModConst* mods, uint32_t level, uint32_t batch, uint32_t n,
@@ -97,17 +102,26 @@ hipError_t launch_moddown_final(const uint32_t* acc, const uint32_t* conv, uint3
                                 const ModConst* mods, const uint2* pinv, uint32_t level,
                                 uint32_t batch, uint32_t n, bool accumulate, hipStream_t s,
                                 KernelId id = K_MD_FINAL);
-// Several conversions of one plane size in one launch (blockIdx.y selects).
-constexpr int kConvPerLaunch = 3;
+// Conversions of any plane sizes in one launch (blockIdx.y selects), with
+// the context's constant tables.
+constexpr int kConvPerLaunch = 64;
+struct ConvTabs {
+  const ModConst* mods;                        // [L+K]
+  const uint2 *up_inv, *dn_invp;               // as CkksCtxImpl::d_up_inv, d_dn_invp
+  const uint32_t *up_k, *dn_k, *up_mfma, *dn_mfma;
+  uint32_t L, K;
+};
 struct ConvSet {
+  ConvTabs tabs;
   uint32_t count;
-  ConvArgs a[kConvPerLaunch];
+  ConvDesc d[kConvPerLaunch];
 };
 static_assert(sizeof(ConvSet) <= 4096, "a ConvSet is passed as a kernel argument");
 hipError_t launch_conv_mfma(const ConvSet& set, uint32_t num_cus, KernelId id, hipStream_t s);
 // Collects conversions and launches them kConvPerLaunch at a time.
 struct ConvQueue {
-  std::vector<ConvArgs> q;
+  ConvTabs tabs;
+  std::vector<ConvDesc> q;
   hipError_t flush(uint32_t num_cus, KernelId id, hipStream_t s);
 };
 // FrobeniusMap of both ciphertext components (in0 -> out0, in1 -> out1, each

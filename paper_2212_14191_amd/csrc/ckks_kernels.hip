@@ -207,33 +207,52 @@ __device__ __forceinline__ uint32_t conv_fuse(int c0, int c1, int c2, int c3, ui
 }
 
 // The per-target constants (A operands, moduli, Montgomery and offset
-// constants) sit in LDS and are read per use, which keeps the kernel at four
-// resident waves per SIMD for latency hiding; targets beyond nout have zero
-// operands and modulus 1 (their results are not stored).
+// constants) are read from the context's tables into LDS and read there per
+// use, which keeps the kernel at four resident waves per SIMD for latency
+// hiding; targets beyond nout have zero operands and modulus 1 (their
+// results are not stored).  Conversions of one launch may differ in plane
+// size: the grid covers the largest, and the workgroups beyond a smaller
+// one's chunks leave at once.
 __global__ void __launch_bounds__(kThreads, 4)
 conv_mfma_kernel(const ConvSet set) {
-  const ConvArgs& a = set.a[blockIdx.y];
+  const ConvDesc& a = set.d[blockIdx.y];
+  const ConvTabs& tb = set.tabs;
+  const uint64_t chunks = a.plane / 64;
+  if ((uint64_t)blockIdx.x * (kThreads / 64) >= chunks) return;  // the whole workgroup
+  const bool up = a.key_idx != kConvDown;
+  // plan limb of target t of this descriptor
+  auto limb_of = [&](uint32_t t) {
+    const uint32_t pos = conv_pos(a, a.first + t);
+    return pos < a.level ? pos : tb.L + (pos - a.level);
+  };
   __shared__ __attribute__((aligned(16))) uint32_t s_a[kConvMaxOut * 32];
   __shared__ __attribute__((aligned(16))) uint32_t s_q[kConvMaxOut], s_qn[kConvMaxOut], s_k[kConvMaxOut];
   for (int i = threadIdx.x; i < kConvMaxOut * 32; i += kThreads) {
     const uint32_t t = i / 32;
-    s_a[i] = t < a.nout ? a.a_tab[t][i % 32] : 0u;
+    const uint32_t* row = t < a.nout ? (up ? tb.up_mfma + ((size_t)a.key_idx * (tb.L + tb.K) + limb_of(t)) * 32
+                                           : tb.dn_mfma + (size_t)limb_of(t) * 32)
+                                     : nullptr;
+    s_a[i] = row ? row[i % 32] : 0u;
   }
   if (threadIdx.x < kConvMaxOut) {
     const uint32_t t = threadIdx.x;
-    s_q[t] = t < a.nout ? a.out_q[t] : 1u;
-    s_qn[t] = t < a.nout ? a.out_qneg[t] : 0u;
-    s_k[t] = t < a.nout ? a.out_k[t] : 0u;
+    const bool live = t < a.nout;
+    const uint32_t l = live ? limb_of(t) : 0;
+    s_q[t] = live ? tb.mods[l].q : 1u;
+    s_qn[t] = live ? tb.mods[l].qneg : 0u;
+    s_k[t] = live ? (up ? tb.up_k[(size_t)a.key_idx * (tb.L + tb.K) + l] : tb.dn_k[l]) : 0u;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
-  const uint64_t chunks = a.plane / 64;
   const uint64_t wave_id = (blockIdx.x * (uint64_t)kThreads + threadIdx.x) / 64;
   const uint64_t waves = (uint64_t)gridDim.x * (kThreads / 64);
   const int r0 = 2 * g, r1 = 2 * g + 1;
   const bool h0 = r0 < (int)a.nin, h1 = r1 < (int)a.nin;
-  const uint32_t q0 = h0 ? a.in_q[r0] : 1, q1 = h1 ? a.in_q[r1] : 1;
-  const uint2 m0 = h0 ? a.in_mult[r0] : make_uint2(0, 0), m1 = h1 ? a.in_mult[r1] : make_uint2(0, 0);
+  // input r: ModUp q-limb d0 + r with [(Q_D/q_r)^{-1}]; ModDown p-limb r with [(P/p_r)^{-1}]
+  auto in_q = [&](int r) { return tb.mods[up ? a.d0 + r : tb.L + r].q; };
+  auto in_mult = [&](int r) { return up ? tb.up_inv[(size_t)a.key_idx * kMaxAlpha + r] : tb.dn_invp[r]; };
+  const uint32_t q0 = h0 ? in_q(r0) : 1, q1 = h1 ? in_q(r1) : 1;
+  const uint2 m0 = h0 ? in_mult(r0) : make_uint2(0, 0), m1 = h1 ? in_mult(r1) : make_uint2(0, 0);
   const int blocks = a.nout > 16 ? 2 : 1;
   const v4i zero = {0, 0, 0, 0};
   // the next chunk's inputs are loaded while this one is converted
@@ -282,7 +301,7 @@ conv_mfma_kernel(const ConvSet set) {
       for (int i = 0; i < 4; ++i) {
         const uint32_t t = t0 + i, q = comp(tq, i), k = comp(tk, i);
         if (t < a.nout)
-          *(uint4*)(a.out + (uint64_t)a.out_plane[t] * a.plane + pos) =
+          *(uint4*)(a.out + (uint64_t)conv_pos(a, a.first + t) * a.plane + pos) =
               make_uint4(add_mod(res[i][0], k, q), add_mod(res[i][1], k, q), add_mod(res[i][2], k, q),
                          add_mod(res[i][3], k, q));
       }
@@ -395,7 +414,8 @@ rescale_bcast_kernel(const uint4* __restrict__ t, uint4* __restrict__ u,
 }  // namespace
 
 hipError_t launch_conv_mfma(const ConvSet& set, uint32_t num_cus, KernelId id, hipStream_t s) {
-  const uint64_t chunks = set.a[0].plane / 64;  // every conversion of a set has one plane size
+  uint64_t chunks = 0;  // the largest conversion's
+  for (uint32_t k = 0; k < set.count; ++k) chunks = std::max<uint64_t>(chunks, set.d[k].plane / 64);
   const uint64_t blocks = (chunks + 3) / 4;  // 4 waves per block, one chunk each per round
   // about one resident round (four workgroups per CU): each wave then
   // converts several chunks with its next inputs in flight
@@ -406,13 +426,11 @@ hipError_t launch_conv_mfma(const ConvSet& set, uint32_t num_cus, KernelId id, h
 }
 
 hipError_t ConvQueue::flush(uint32_t num_cus, KernelId id, hipStream_t s) {
-  // a launch takes conversions of one plane size: queued order within each size
-  std::stable_sort(q.begin(), q.end(), [](const ConvArgs& x, const ConvArgs& y) { return x.plane < y.plane; });
   for (size_t i = 0; i < q.size();) {
     ConvSet set{};
+    set.tabs = tabs;
     set.count = 0;
-    while (i < q.size() && set.count < (uint32_t)kConvPerLaunch && (set.count == 0 || q[i].plane == set.a[0].plane))
-      set.a[set.count++] = q[i++];
+    while (i < q.size() && set.count < (uint32_t)kConvPerLaunch) set.d[set.count++] = q[i++];
     hipError_t e = launch_conv_mfma(set, num_cus, id, s);
     if (e != hipSuccess) {
       q.clear();

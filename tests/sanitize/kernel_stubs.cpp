@@ -224,9 +224,9 @@ hipError_t launch_rescale_bcast(const uint32_t* t, uint32_t* u, const ModConst*,
   return hipSuccess;
 }
 hipError_t ConvQueue::flush(uint32_t, KernelId, hipStream_t) {
-  for (const ConvArgs& a : q) {
+  for (const ConvDesc& a : q) {
     rd(a.in, a.nin * a.plane);
-    for (uint32_t t = 0; t < a.nout; ++t) wr(a.out + a.out_plane[t] * a.plane, a.plane);
+    for (uint32_t t = 0; t < a.nout; ++t) wr(a.out + conv_pos(a, a.first + t) * a.plane, a.plane);
   }
   q.clear();
   return hipSuccess;
