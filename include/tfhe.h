@@ -288,10 +288,10 @@ tfhe_status tfhe_hmult_noalloc(tfhe_ckks_ctx ctx, const uint32_t* ct_a, const ui
 /* HMULT of ciphertext pairs of different levels in one batched launch
  * sequence (operation-level batching across levels, Sec. IV-D): pair i is
  * multiplied at levels[i] exactly as tfhe_hmult would do for it alone (same
- * result, bit for bit).  The pairs are grouped by level; each group's tensor
- * product and key inner product are launched per group, and every NTT/INTT
- * and basis conversion of all groups shares one launch per key-switching
- * step (the transforms run over a descriptor table of the groups' limbs).
+ * result, bit for bit).  The pairs are grouped by level; one launch forms
+ * every pair's tensor product, and every NTT/INTT, basis conversion and key
+ * inner product of all groups shares one launch per key-switching step (the
+ * transforms run over a descriptor table of the groups' limbs).
  *   ct_a, ct_b, ct_out: host arrays [count] of device pointers, each a
  *     single ciphertext [2][levels[i]][N], NTT domain, 16-byte aligned.  An
  *     output may alias any input (results are written after every input has
