@@ -269,6 +269,39 @@ def test_native_server_full_pointer_table(world):
     srv.close()
 
 
+def test_native_server_mixed_operation_batch(world):
+    """HMULTs and rotations of one N and three levels submitted in one call
+    form one batch (one worker, a batch limit and pool that hold them all):
+    one tensor-product launch, one Frobenius launch and one key switch for
+    both operations.  Every result equals its single call, and one HMULT and
+    one rotation of the batch equal the oracle."""
+    from oracle import ckks
+    ctxs, evks, rks, cts = world
+    ln = 12
+    reqs = []
+    for k in range(12):
+        lv = (2, 5, 6)[k % 3]
+        if k % 2 == 0:
+            reqs.append((0, ln, lv, cts[(ln, lv, 0)], cts[(ln, lv, 1)], None))
+        else:
+            g = pow(5, (1, 3)[(k // 2) % 2], 2 << ln)
+            reqs.append((1, ln, lv, cts[(ln, lv, (k // 2) % 2)], None, g))
+    alone = alone_results(world, reqs)
+    srv = native_server(world, slots=1, max_batch=64, pool_bytes=256 << 20)
+    outs = srv.submit_many([(op, a, b, g or 0, None) for op, _, lv, a, b, g in reqs])
+    done = drain(srv, len(reqs))
+    assert all(st is None for st in done.values()), done
+    for (tag, out), want in zip(outs, alone):
+        assert torch.equal(out, want), tag
+    srv.close()
+    to_np = lambda t: t.cpu().numpy().view(np.uint32)
+    pr = ckks.Params(1 << ln, L=6, K=2, dnum=3, moduli=list(ctxs[ln].moduli))
+    _, _, lv, a, b, _ = reqs[2]
+    assert np.array_equal(to_np(outs[2][1]), ckks.hmult(pr, to_np(a), to_np(b), to_np(evks[ln]), lv))
+    _, _, lv, a, _, g = reqs[3]
+    assert np.array_equal(to_np(outs[3][1]), ckks.rotate(pr, to_np(a), to_np(rks[(ln, g)]), g, lv))
+
+
 @pytest.fixture(scope="module")
 def serving_world():
     """The serving mix's smaller shapes: N = 2^13, 2^14, 2^15 with L = 24,
