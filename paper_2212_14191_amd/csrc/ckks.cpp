@@ -120,7 +120,7 @@ static KsLayout ks_layout(const tfhe_ckks_ctx_s* c, uint32_t level, uint32_t bat
 }
 
 // ModUp conversion of digit [d0, d0 + nd) on the matrix cores: every
-// extended-basis position outside the digit, in launches of <= 32 targets.
+// extended-basis position outside the digit, in descriptors of <= 32 targets.
 static void modup_mfma(const uint32_t* x, uint32_t* up, uint32_t key_idx, uint32_t d0, uint32_t nd,
                        uint32_t level, uint32_t K, uint64_t plane, ConvQueue& cq) {
   const uint32_t targets = level + K - nd;  // every extended-basis position outside the digit
