@@ -5,7 +5,8 @@
 // write.  An undersized workspace region, a slice laid out past the end of
 // its buffer or a wrong extent of an input or output is therefore reported
 // by the sanitizer.  Covers HMULT, HROTATE (one and several Galois
-// elements), RESCALE, the allocation-free HMULT and the mixed-level batches,
+// elements), RESCALE, the allocation-free HMULT and the mixed-level batches
+// (one operation, and HMULTs with rotations),
 // for four-step and butterfly contexts (fewer special primes than a digit
 // has limbs included) and both inner-product paths.  Exit status 0 when
 // every call succeeded.
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "tfhe.h"
+#include "../../paper_2212_14191_amd/csrc/ckks_internal.hpp"
 
 static int failures = 0;
 #define EXPECT(cond)                                                                            \
@@ -111,7 +113,15 @@ int main() {
       // a result written over an input (allowed)
       EXPECT(tfhe_hmult_levels(c, ins_a.data(), ins_b.data(), (uint32_t* const*)ins_a.data(), mix.data(),
                                (uint32_t)mix.size(), evk.u(), ws.p, wsb, nullptr) == TFHE_OK);
-      calls += 3;
+      // HMULTs and rotations in one batch (as the request dispatcher runs
+      // them), in a workspace of exactly the size it asks for
+      std::vector<tfhe::LvReq> both;
+      for (size_t i = 0; i < mix.size(); ++i)
+        both.push_back(tfhe::LvReq{ins_a[i], i % 2 ? nullptr : ins_b[i], outs[i], keys[i], mix[i],
+                                   i % 2 ? gal[i] : 0u, (uint32_t)(i % 2)});
+      Buf ws2(tfhe::levels_ws_bytes(c, both.data(), (uint32_t)both.size()));
+      EXPECT(tfhe::levels_run(c, both.data(), (uint32_t)both.size(), (unsigned char*)ws2.p, nullptr) == hipSuccess);
+      calls += 4;
       for (Buf* p : bufs) delete p;
     }
     EXPECT(tfhe_ckks_ctx_destroy(c) == TFHE_OK);
