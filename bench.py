@@ -425,6 +425,46 @@ def onepass_leg(args, torch, tfhe, inputs, sync, log_n=14, limbs=24, batch=64):
             "achieved_gbs": round(nbytes / (per_launch * 1e-3) / 1e9, 1)}
 
 
+# 16 requests at 16 different levels (mean 12.5) against 16 at level 12
+MIXED_LEVELS = (2, 3, 5, 6, 8, 9, 11, 12, 13, 14, 16, 17, 19, 20, 22, 23)
+
+
+def levels_leg(args, torch, tfhe, inputs, sync, log_ns=(16, 14), L=24, K=8, dnum=3):
+    """Profiling leg: one HMULT batch of 16 requests at 16 different levels
+    (one request per level group, as the serving mix forms them) against a
+    batch of 16 at one level, at the serving shapes (tfhe_hmult_levels;
+    the key switch's launches are shared by every group either way)."""
+    out = {}
+    for ln in log_ns:
+        n = 1 << ln
+        ctx = tfhe.CkksContext(ln, L, K, dnum)
+        ev = inputs.uniform_residues(ln, ctx.moduli, (dnum, 2, n)).transpose(1, 2, 0, 3)
+        evk = torch.from_numpy(np.ascontiguousarray(ev).view(np.int32)).cuda()
+        res = {}
+        for name, levels in (("single_level", (12,) * 16), ("mixed_levels", MIXED_LEVELS)):
+            def ct(seed, lv):
+                c = inputs.uniform_residues(seed, ctx.moduli[:lv], (2, n)).transpose(1, 0, 2)
+                return torch.from_numpy(np.ascontiguousarray(c).view(np.int32)).cuda()
+            A = [ct(2 * k, lv) for k, lv in enumerate(levels)]
+            B = [ct(2 * k + 1, lv) for k, lv in enumerate(levels)]
+            outs = [torch.empty_like(a) for a in A]
+            ws = ctx.levels_workspace(list(levels))
+
+            def step():
+                ctx.hmult_levels(A, B, evk, outs=outs, ws=ws)
+            for _ in range(args.warmup):
+                step()
+            sync()
+            k = len(levels) - 1
+            one = ctx.hmult(A[k][:, :, None], B[k][:, :, None], evk, levels[k])  # [2][level][1][N]
+            assert torch.equal(outs[k], one[:, :, 0]), "batched HMULT != single call"
+            dt = timed(step, args.steps, sync)
+            res[name] = {"levels": list(levels), "ms_per_batch": round(dt / args.steps * 1e3, 4)}
+        res["mixed_over_single"] = round(res["mixed_levels"]["ms_per_batch"] / res["single_level"]["ms_per_batch"], 3)
+        out[str(ln)] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,9 +481,10 @@ def main():
                     help="cap each N's serving batch at the largest whose measured HMULT time fits (0: no cap)")
     ap.add_argument("--native-slots", type=int, default=8,
                     help="worker threads (one stream each) of the native dispatcher")
-    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving", "onepass"], default=None,
+    ap.add_argument("--only", choices=["mfma", "butterfly", "co", "hmult", "serving", "onepass", "levels"], default=None,
                     help="time one leg only (for profiling runs; onepass: the one-HBM-round-trip "
-                         "transform at N = 2^14, 24 limbs x 64 polynomials, the serving shape)")
+                         "transform at N = 2^14, 24 limbs x 64 polynomials, the serving shape; levels: "
+                         "an HMULT batch of 16 levels against one of a single level, N = 2^16 and 2^14)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one plain device copy of the input batch (a known-size "
                          "kernel for scaling hardware byte counters)")
@@ -460,6 +501,9 @@ def main():
     sync = torch.cuda.synchronize
     if args.only == "onepass":
         print(json.dumps({"onepass": onepass_leg(args, torch, tfhe, inputs, sync)}), flush=True)
+        return
+    if args.only == "levels":
+        print(json.dumps({"levels": levels_leg(args, torch, tfhe, inputs, sync)}), flush=True)
         return
     n = 1 << LOG_N
 
