@@ -47,12 +47,15 @@ def encrypt(pr, s, m, level, seed):
 
 @pytest.mark.parametrize("log_n,L,K,dnum,level", [
     (10, 6, 2, 3, 6), (10, 6, 2, 3, 5), (10, 6, 2, 3, 1), (12, 8, 4, 2, 8), (12, 8, 4, 2, 3),
-    (13, 24, 8, 3, 24), (13, 24, 8, 3, 17), (5, 6, 2, 3, 6), (10, 12, 2, 12, 12), (10, 12, 2, 12, 9)])
+    (13, 24, 8, 3, 24), (13, 24, 8, 3, 17), (5, 6, 2, 3, 6), (10, 12, 2, 12, 12), (10, 12, 2, 12, 9),
+    (10, 40, 4, 10, 40), (10, 40, 4, 10, 37)])
 def test_hmult_matches_oracle(tf, log_n, L, K, dnum, level):
     """Bit-exact HMULT.  The basis conversions run on the matrix cores,
     except at N = 2^5 (3 x 32-word planes are not whole 64-word chunks),
     which takes the VALU conversion; dnum = 12 runs the inner product in
-    two digit groups."""
+    two digit groups; L = 40 gives conversions of more than 32 targets
+    (ModUp 40 and 37-40, ModDown 40 and 37), each split over two
+    descriptors."""
     n = 1 << log_n
     pr, s, evk, _ = setup(n, L, K, dnum)
     ctx = tf.CkksContext(log_n, L, K, dnum, moduli=pr.moduli)
