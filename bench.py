@@ -646,6 +646,12 @@ def main():
                            "gb_per_s": nbytes * args.hmult_steps / dt / 1e9}
             log(name, json.dumps(hmult[name]))
         del cts, out, hws, evk, ctx, rs_out, rws, pt, ew_out
+        if args.only is None:
+            # the serving mix's batches hold one request per level group:
+            # such a batch against one of a single level (same size)
+            hmult["levels"] = levels_leg(argparse.Namespace(steps=min(args.steps, 20), warmup=min(args.warmup, 5)),
+                                         torch, tfhe, inputs, sync)
+            log("levels", json.dumps({k: v["mixed_over_single"] for k, v in hmult["levels"].items()}))
 
     serving = None
     if not args.skip_serving and args.only in (None, "serving"):
